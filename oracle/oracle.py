@@ -1,0 +1,211 @@
+"""ctypes front end of the FP64 C oracle (``sal_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the CPU-baseline leg of
+``bench.py`` may import this module.  It shares no code with the GPU path.
+
+Every function takes and returns NumPy arrays; volumes are float32 ``[n0][n1][n2]`` (axis 0
+is t), results are float64.  Each wrapper names the passage of the paper its C function
+follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sal_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_lp = ctypes.POINTER(ctypes.c_long)
+_up = ctypes.POINTER(ctypes.c_uint32)
+_L = ctypes.c_long
+
+# rays: bit 2a enables the ray along +axis a, bit 2a+1 the ray along -axis a
+RAY_PT, RAY_MT, RAY_PX, RAY_MX, RAY_PY, RAY_MY = 1, 2, 4, 8, 16, 32
+RAYS_AXIS = (RAY_PT | RAY_MT, RAY_PX | RAY_MX, RAY_PY | RAY_MY)  # S_t: +-t, S_x: +-x, S_y: +-y
+RAYS_ALL = (63, 63, 63)
+
+
+def build(force: bool = False) -> str:
+    """Compile ``sal_oracle.c`` with gcc (FP64, OpenMP) into ``liboracle.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        build()
+        l = ctypes.CDLL(_LIB)
+        l.oracle_window_spectrum.argtypes = [_fp, _L, _L, _L, _L, _L, _L, _L, _dp]
+        l.oracle_project.argtypes = [_dp, _L, _dp]
+        l.oracle_local_spectra.argtypes = [_fp, _L, _L, _L, _L, _lp, _lp, _dp]
+        l.oracle_energy_box.argtypes = [_fp, _L, _L, _L, _L, _lp, _lp, _dp]
+        l.oracle_energy.argtypes = [_fp, _L, _L, _L, _L, _dp]
+        l.oracle_dcs.argtypes = [_dp, _L, _L, _L, _L, ctypes.c_double, _up, _dp]
+        l.oracle_dcs.restype = ctypes.c_int
+        l.oracle_combine.argtypes = [_dp, _L, _dp, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, _dp, _dp]
+        l.oracle_combine_with_stats.argtypes = [_dp, _L, _dp, ctypes.c_int, ctypes.c_double,
+                                                ctypes.c_double, _dp, _dp]
+        l.oracle_absmax.argtypes = [_fp, _L]
+        l.oracle_absmax.restype = ctypes.c_double
+        l.oracle_saliency.argtypes = [_fp, _L, _L, _L, _L, _L, ctypes.c_double, _up, _dp,
+                                      ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
+        l.oracle_raw_box.argtypes = [_fp, _L, _L, _L, _L, _L, ctypes.c_double, _up, _lp, _lp,
+                                     _dp, _dp]
+        l.oracle_raw_box.restype = ctypes.c_int
+        _lib = l
+    return _lib
+
+
+@dataclass
+class Params:
+    """Method parameters (Sec. 2 and Eq. (5)-(6)); defaults are the declared readings."""
+    L: int = 8                      # cube side (first step of Sec. 2; the paper uses 5)
+    d: int | None = None            # DCS line length, defaults to L (after Fig. 3)
+    sigma: float | None = None      # Gaussian width of the DCS weights, defaults to d/4
+    rays: tuple = RAYS_AXIS         # rays used by S_t, S_x, S_y
+    abc: tuple = (1.0 / 3, 1.0 / 3, 1.0 / 3)  # Eq. (6) weights, equal (Sec. 2, last para.)
+    normalize: int = 1
+    zero_range: float = 1e-6
+
+    @property
+    def r(self) -> int:
+        return (self.d if self.d is not None else self.L) // 2
+
+    @property
+    def sig(self) -> float:
+        return self.sigma if self.sigma is not None else (self.d if self.d is not None else self.L) / 4.0
+
+
+def _f32(V):
+    V = np.ascontiguousarray(V, dtype=np.float32)
+    return V, V.ctypes.data_as(_fp)
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _longs(x):
+    return (ctypes.c_long * 3)(*[int(v) for v in x])
+
+
+def _rays(r):
+    return (ctypes.c_uint32 * 3)(*[int(v) for v in r])
+
+
+def window_spectrum(V, t, x, y, L) -> np.ndarray:
+    """Local spectrum F[mu,nu,om] (complex128) of voxel (t,x,y): DFT definition after Eq. (2)."""
+    V, pV = _f32(V)
+    F = np.zeros((L, L, L, 2), np.float64)
+    lib().oracle_window_spectrum(pV, *V.shape, t, x, y, L, _d(F))
+    return F[..., 0] + 1j * F[..., 1]
+
+
+def project(F) -> np.ndarray:
+    """(E_t, E_x, E_y) of one spectrum: Eqs. (1)-(4), DC excluded, absolute mean (Sec. 2)."""
+    F = np.asarray(F, np.complex128)
+    L = F.shape[0]
+    buf = np.ascontiguousarray(np.stack([F.real, F.imag], -1))
+    E = np.zeros(3, np.float64)
+    lib().oracle_project(_d(buf), L, _d(E))
+    return E
+
+
+def local_spectra(V, L, lo, bn) -> np.ndarray:
+    """Spectra of every voxel of box [lo, lo+bn): complex128 [bn0][bn1][bn2][L][L][L]."""
+    V, pV = _f32(V)
+    out = np.zeros(tuple(bn) + (L, L, L, 2), np.float64)
+    lib().oracle_local_spectra(pV, *V.shape, L, _longs(lo), _longs(bn), _d(out))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def energy(V, L) -> np.ndarray:
+    """E[3][n0][n1][n2]: Sec. 2 steps one to three over the whole volume."""
+    V, pV = _f32(V)
+    E = np.zeros((3,) + V.shape, np.float64)
+    lib().oracle_energy(pV, *V.shape, L, _d(E))
+    return E
+
+
+def energy_box(V, L, lo, bn) -> np.ndarray:
+    V, pV = _f32(V)
+    E = np.zeros((3,) + tuple(bn), np.float64)
+    lib().oracle_energy_box(pV, *V.shape, L, _longs(lo), _longs(bn), _d(E))
+    return E
+
+
+def dcs(E, r, sigma, rays=RAYS_AXIS) -> np.ndarray:
+    """Raw S_m[3][...] from E[3][...]: Eq. (5), reflect at the volume edges."""
+    E = np.ascontiguousarray(E, np.float64)
+    S = np.zeros_like(E)
+    bad = lib().oracle_dcs(_d(E), *E.shape[1:], r, float(sigma), _rays(rays), _d(S))
+    assert bad == 0
+    return S
+
+
+def combine(S_raw, abc=(1 / 3, 1 / 3, 1 / 3), normalize=1, zero_range=1e-6, vmax=1.0):
+    """Eq. (6) after per-component volume-wide min-max normalisation.  Returns (S, stats)."""
+    S_raw = np.ascontiguousarray(S_raw, np.float64)
+    n = S_raw[0].size
+    S = np.zeros(S_raw.shape[1:], np.float64)
+    stats = np.zeros(6, np.float64)
+    w = np.asarray(abc, np.float64)
+    lib().oracle_combine(_d(S_raw), n, _d(w), int(normalize), float(zero_range), float(vmax),
+                         _d(S), _d(stats))
+    return S, stats
+
+
+def combine_with_stats(S_raw, stats, abc=(1 / 3, 1 / 3, 1 / 3), normalize=1, zero_range=1e-6,
+                       vmax=1.0):
+    S_raw = np.ascontiguousarray(S_raw, np.float64)
+    stats = np.ascontiguousarray(stats, np.float64)
+    S = np.zeros(S_raw.shape[1:], np.float64)
+    w = np.asarray(abc, np.float64)
+    lib().oracle_combine_with_stats(_d(S_raw), S_raw[0].size, _d(w), int(normalize),
+                                    float(zero_range), float(vmax), _d(stats), _d(S))
+    return S
+
+
+def absmax(V) -> float:
+    V, pV = _f32(V)
+    return lib().oracle_absmax(pV, V.size)
+
+
+def saliency(V, p: Params = Params()):
+    """Whole method (Sec. 2 steps one to five).  Returns dict with S, E, S_raw, stats."""
+    V, pV = _f32(V)
+    S = np.zeros(V.shape, np.float64)
+    E = np.zeros((3,) + V.shape, np.float64)
+    Sr = np.zeros((3,) + V.shape, np.float64)
+    stats = np.zeros(6, np.float64)
+    w = np.asarray(p.abc, np.float64)
+    lib().oracle_saliency(pV, *V.shape, p.L, p.r, float(p.sig), _rays(p.rays), _d(w),
+                          int(p.normalize), float(p.zero_range), _d(S), _d(E), _d(Sr), _d(stats))
+    return {"S": S, "E": E, "S_raw": Sr, "stats": stats}
+
+
+def raw_box(V, p: Params, lo, bn):
+    """E and raw S_m on the box [lo, lo+bn) of a large volume (energies on box + r halo)."""
+    V, pV = _f32(V)
+    E = np.zeros((3,) + tuple(bn), np.float64)
+    S = np.zeros((3,) + tuple(bn), np.float64)
+    bad = lib().oracle_raw_box(pV, *V.shape, p.L, p.r, float(p.sig), _rays(p.rays),
+                               _longs(lo), _longs(bn), _d(E), _d(S))
+    assert bad == 0
+    return E, S

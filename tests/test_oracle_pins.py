@@ -1,0 +1,273 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+None of these checks re-types the oracle's own formulas: they use brute-force sums, a
+library FFT, Parseval's identity, closed forms of plane waves and deltas, symmetry
+invariants and hand-derived values of Eq. (5).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1901_11095_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _window(V, t, x, y, L):
+    """Window of voxel (t,x,y): start v - floor(L/2), numpy 'reflect' padding."""
+    P = np.pad(V.astype(np.float64), L, mode="reflect")
+    h = L // 2
+    return P[t - h + L:t - h + 2 * L, x - h + L:x - h + 2 * L, y - h + L:y - h + 2 * L]
+
+
+def _dft_bruteforce(f):
+    """The triple sum after Eq. (2), every bin summed directly."""
+    L = f.shape[0]
+    p = np.arange(L)
+    P, Q, R = np.meshgrid(p, p, p, indexing="ij")
+    F = np.zeros((L, L, L), np.complex128)
+    for mu in range(L):
+        for nu in range(L):
+            for om in range(L):
+                F[mu, nu, om] = np.sum(f * np.exp(-2j * np.pi * (P * mu + Q * nu + R * om) / L))
+    return F / L ** 3
+
+
+def _signed(u, L):
+    return u if u <= L // 2 else u - L
+
+
+VOXELS = [(0, 0, 0), (8, 9, 10), (4, 5, 6), (1, 8, 3), (7, 0, 10), (3, 4, 2)]
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 8])
+def test_dft_bruteforce(oracle_mod, L):
+    V = synth.random_volume((9, 10, 11), seed=L)
+    for (t, x, y) in VOXELS:
+        F = oracle_mod.window_spectrum(V, t, x, y, L)
+        ref = _dft_bruteforce(_window(V, t, x, y, L))
+        assert np.abs(F - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 8, 16])
+def test_dft_library_fft(oracle_mod, L):
+    V = synth.random_volume((17, 18, 19), seed=100 + L)
+    for (t, x, y) in VOXELS + [(16, 17, 18), (15, 1, 9)]:
+        F = oracle_mod.window_spectrum(V, t, x, y, L)
+        ref = np.fft.fftn(_window(V, t, x, y, L)) / L ** 3
+        assert np.abs(F - ref).max() <= 1e-13
+
+
+@pytest.mark.parametrize("L", [3, 4, 8])
+def test_dc_is_window_mean_and_parseval(oracle_mod, L):
+    V = synth.random_volume((12, 12, 12), seed=7)
+    for (t, x, y) in VOXELS[:4]:
+        f = _window(V, t, x, y, L)
+        F = oracle_mod.window_spectrum(V, t, x, y, L)
+        assert abs(F[0, 0, 0] - f.mean()) <= 1e-14
+        assert abs(np.sum(np.abs(F) ** 2) - np.sum(f ** 2) / L ** 3) <= 1e-13
+
+
+def test_local_spectra_box_layout(oracle_mod):
+    V = synth.random_volume((9, 10, 11), seed=3)
+    L = 4
+    lo, bn = (2, 3, 4), (3, 2, 5)
+    Fb = oracle_mod.local_spectra(V, L, lo, bn)
+    for a in range(bn[0]):
+        for b in range(bn[1]):
+            for c in range(bn[2]):
+                ref = np.fft.fftn(_window(V, lo[0] + a, lo[1] + b, lo[2] + c, L)) / L ** 3
+                assert np.abs(Fb[a, b, c] - ref).max() <= 1e-13
+
+
+@pytest.mark.parametrize("L,abc", [(8, (1, 2, 3)), (8, (0, 1, 0)), (8, (3, 0, 5)), (8, (4, 0, 4)),
+                                   (8, (2, 6, 1)), (5, (1, 2, 0)), (5, (2, 1, 3)), (4, (1, 1, 2)),
+                                   (16, (3, 7, 1))])
+def test_plane_wave_closed_form(oracle_mod, L, abc):
+    """cos(2 pi (a t + b x + c y)/L) puts |F| = 1/2 on the bins +-(a,b,c) (or 1 on a single
+    self-conjugate bin), so E_m = w_m(i,j,k)/(L^3-1) with the projection weights of
+    Eqs. (1)-(4): w_t = sqrt(j^2+k^2)/rho, w_x = sqrt(i^2+k^2)/rho, w_y = sqrt(i^2+j^2)/rho."""
+    a, b, c = abc
+    n = 2 * L + 2
+    t, x, y = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    V = np.cos(2 * np.pi * (a * t + b * x + c * y) / L).astype(np.float32)
+    i, j, k = _signed(a, L), _signed(b, L), _signed(c, L)
+    rho = math.sqrt(i * i + j * j + k * k)
+    expect = np.array([math.sqrt(j * j + k * k), math.sqrt(i * i + k * k),
+                       math.sqrt(i * i + j * j)]) / rho / (L ** 3 - 1)
+    # interior voxels: the window lies inside the volume
+    for v in [(L // 2, L // 2, L // 2), (L, L + 1, L - 1), (n - L + L // 2, L // 2 + 1, L)]:
+        F = oracle_mod.window_spectrum(V, *v, L)
+        E = oracle_mod.project(F)
+        # float32 rounding of the cosine samples bounds the agreement
+        assert np.abs(E - expect).max() <= 2e-7 * max(expect.max(), 1e-3), (v, E, expect)
+
+
+def test_projection_weights_sum_of_squares(oracle_mod):
+    """sum_m w_m^2 = 2 for every non-DC bin, so the projected spectra of one bin in
+    isolation give E_t^2 + E_x^2 + E_y^2 = 2 (|F|/(L^3-1))^2."""
+    L = 8
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        F = np.zeros((L, L, L), np.complex128)
+        mu, nu, om = rng.integers(0, L, 3)
+        if mu == nu == om == 0:
+            continue
+        F[mu, nu, om] = 0.75 - 0.5j
+        E = oracle_mod.project(F)
+        assert abs(np.sum(E ** 2) - 2 * (abs(F[mu, nu, om]) / (L ** 3 - 1)) ** 2) <= 1e-18
+
+
+def test_dc_bin_excluded(oracle_mod):
+    L = 4
+    F = np.zeros((L, L, L), np.complex128)
+    F[0, 0, 0] = 123.0
+    assert np.all(oracle_mod.project(F) == 0.0)
+
+
+def test_axis_permutation(oracle_mod):
+    """Swapping axes t and x of V swaps E_t and E_x and leaves E_y; a cyclic permutation
+    (t,x,y) -> (x,y,t) maps E_t->E_y... as the definitions of the projections imply."""
+    V = synth.random_volume((10, 12, 11), seed=11)
+    L = 4
+    p = oracle_mod.Params(L=L)
+    R = oracle_mod.saliency(V, p)
+    # t <-> x
+    Vp = np.ascontiguousarray(V.transpose(1, 0, 2))
+    Rp = oracle_mod.saliency(Vp, p)
+    for m, mp in [(0, 1), (1, 0), (2, 2)]:
+        assert np.abs(Rp["E"][mp] - R["E"][m].transpose(1, 0, 2)).max() <= 1e-13
+        assert np.abs(Rp["S_raw"][mp] - R["S_raw"][m].transpose(1, 0, 2)).max() <= 1e-13
+    assert np.abs(Rp["S"] - R["S"].transpose(1, 0, 2)).max() <= 1e-12
+    # cyclic: new axes (x, y, t)
+    Vc = np.ascontiguousarray(V.transpose(1, 2, 0))
+    Rc = oracle_mod.saliency(Vc, p)
+    for m, mc in [(0, 2), (1, 0), (2, 1)]:
+        assert np.abs(Rc["E"][mc] - R["E"][m].transpose(1, 2, 0)).max() <= 1e-13
+        assert np.abs(Rc["S_raw"][mc] - R["S_raw"][m].transpose(1, 2, 0)).max() <= 1e-13
+
+
+def test_dc_shift_invariance(oracle_mod):
+    """Adding a constant only changes the DC bin, which is excluded (paragraph after Fig. 2)."""
+    V = (synth.integer_volume((9, 9, 10), seed=2) / 8.0).astype(np.float32)
+    p = oracle_mod.Params(L=4)
+    R0 = oracle_mod.saliency(V, p)
+    R1 = oracle_mod.saliency((V + 3.0).astype(np.float32), p)
+    assert np.abs(R0["E"] - R1["E"]).max() <= 1e-13
+    assert np.abs(R0["S_raw"] - R1["S_raw"]).max() <= 1e-13
+
+
+def test_constant_volume(oracle_mod):
+    V = np.full((9, 8, 10), 2.5, np.float32)
+    R = oracle_mod.saliency(V, oracle_mod.Params(L=4))
+    assert np.abs(R["E"]).max() <= 1e-13 * 2.5
+    assert np.abs(R["S_raw"]).max() <= 1e-13 * 2.5
+    assert np.all(R["S"] == 0.0)
+
+
+def test_homogeneity(oracle_mod):
+    V = synth.random_volume((9, 10, 8), seed=4)
+    p = oracle_mod.Params(L=4)
+    R0 = oracle_mod.saliency(V, p)
+    R1 = oracle_mod.saliency((-2.0 * V).astype(np.float32), p)
+    assert np.abs(R1["E"] - 2.0 * R0["E"]).max() <= 1e-13
+    assert np.abs(R1["S_raw"] - 2.0 * R0["S_raw"]).max() <= 1e-13
+    assert np.abs(R1["S"] - R0["S"]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_mirror_odd_L(oracle_mod, axis):
+    """For odd L the window is centred, the weights depend on squares and the rays come in
+    +- pairs, so flipping V along an axis flips E and S."""
+    V = synth.random_volume((9, 10, 11), seed=9)
+    p = oracle_mod.Params(L=5)
+    R = oracle_mod.saliency(V, p)
+    Rf = oracle_mod.saliency(np.ascontiguousarray(np.flip(V, axis)), p)
+    assert np.abs(Rf["E"] - np.flip(R["E"], axis + 1)).max() <= 1e-13
+    assert np.abs(Rf["S"] - np.flip(R["S"], axis)).max() <= 1e-12
+
+
+def test_integer_dc_exact(oracle_mod):
+    """With small integer samples the DC bin times L^3 is the integer window sum."""
+    V = synth.integer_volume((10, 9, 11), seed=1)
+    L = 4
+    for (t, x, y) in [(0, 0, 0), (9, 8, 10), (5, 4, 3)]:
+        F = oracle_mod.window_spectrum(V, t, x, y, L)
+        assert F[0, 0, 0].real * L ** 3 == _window(V, t, x, y, L).sum()
+
+
+# ---------------------------------------------------------------- Eq. (5): DCS ----------
+
+def _g(s, sigma):
+    return math.exp(-s * s / (2.0 * sigma * sigma))
+
+
+@pytest.mark.parametrize("rays", ["axis", "all"])
+def test_dcs_constant_energy(oracle_mod, rays):
+    """E = e everywhere: every term is e (1 - g(s)), so S_m = e (1/r) sum_s (1 - g(s))."""
+    r, sigma, e = 4, 2.0, 0.37
+    E = np.full((3, 9, 10, 11), e)
+    rr = oracle_mod.RAYS_AXIS if rays == "axis" else oracle_mod.RAYS_ALL
+    S = oracle_mod.dcs(E, r, sigma, rr)
+    expect = e * sum(1.0 - _g(s, sigma) for s in range(1, r + 1)) / r
+    assert np.abs(S - expect).max() <= 1e-15
+
+
+def test_dcs_delta_golden(oracle_mod):
+    """Hand-derived values of Eq. (5) around a unit spike of E (tests/golden/dcs_delta.json):
+    the spike itself sees |1 - g 0| = 1 on every term (S = 1); a voxel s steps away along
+    the ray axis sees one term |0 - g(s) 1|, so S = g(s)/Q; at the volume edge the reflected
+    ray meets the spike a second time."""
+    with open(os.path.join(GOLDEN, "dcs_delta.json")) as fh:
+        cases = json.load(fh)["cases"]
+    for case in cases:
+        shape, r, sigma = tuple(case["shape"]), case["r"], case["sigma"]
+        E = np.zeros((3,) + shape)
+        m = case["map"]
+        E[m][tuple(case["spike"])] = 1.0
+        rays = [0, 0, 0]
+        rays[m] = case["rays"]
+        S = oracle_mod.dcs(E, r, sigma, tuple(rays))
+        for item in case["expect"]:
+            got = S[m][tuple(item["at"])]
+            want = eval(item["value"], {"g": lambda s: _g(s, sigma)})
+            assert abs(got - want) <= 1e-15, (case["name"], item, got, want)
+
+
+# ------------------------------------------------------- Eq. (6) and normalisation -------
+
+def test_combine_closed_form(oracle_mod):
+    n = 7
+    ramp = np.arange(n, dtype=np.float64)
+    S_raw = np.stack([2.0 + 3.0 * ramp / (n - 1), 5.0 - ramp, np.full(n, 4.0)])
+    S, stats = oracle_mod.combine(S_raw, abc=(0.5, 0.25, 0.25), vmax=10.0)
+    assert list(stats) == [2.0, 5.0, -1.0, 5.0, 4.0, 4.0]
+    expect = 0.5 * ramp / (n - 1) + 0.25 * (1.0 - ramp / (n - 1)) + 0.0  # flat map -> 0
+    assert np.abs(S - expect).max() <= 1e-15
+    S2 = oracle_mod.combine_with_stats(S_raw, stats, abc=(0.5, 0.25, 0.25), vmax=10.0)
+    assert np.array_equal(S, S2)
+    S3, _ = oracle_mod.combine(S_raw, abc=(1.0, 1.0, 1.0), normalize=0)
+    assert np.abs(S3 - S_raw.sum(0)).max() <= 1e-15
+
+
+def test_saliency_normalised_range(oracle_mod):
+    V = synth.workload("vol64")[:24, :20, :22].copy()
+    R = oracle_mod.saliency(V, oracle_mod.Params(L=4))
+    assert abs(R["S"].min()) <= 1.0 and R["S"].max() <= 1.0 + 1e-15
+    for m in range(3):
+        lo, hi = R["stats"][2 * m], R["stats"][2 * m + 1]
+        assert lo == R["S_raw"][m].min() and hi == R["S_raw"][m].max()
+
+
+def test_raw_box_matches_full_volume(oracle_mod):
+    V = synth.random_volume((14, 13, 15), seed=21)
+    p = oracle_mod.Params(L=4)
+    R = oracle_mod.saliency(V, p)
+    for lo, bn in [((0, 0, 0), (5, 4, 6)), ((9, 8, 10), (5, 5, 5)), ((3, 2, 4), (6, 7, 5))]:
+        E, S = oracle_mod.raw_box(V, p, lo, bn)
+        sl = tuple(slice(a, a + b) for a, b in zip(lo, bn))
+        assert np.abs(E - R["E"][(slice(None),) + sl]).max() <= 1e-15
+        assert np.abs(S - R["S_raw"][(slice(None),) + sl]).max() <= 1e-15
