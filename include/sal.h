@@ -1,0 +1,158 @@
+/*
+ * sal.h -- C ABI of the MI355X (gfx950) seismic saliency library.
+ *
+ * The library computes the saliency map of Shafiq, Long, Alshawi and AlRegib, "Saliency
+ * detection for seismic applications using multi-dimensional spectral projections and
+ * directional comparisons" (ICIP 2017), Sec. 2:
+ *   step 1  local 3D DFT of a sliding cube of side L around every voxel (DFT definition
+ *           after Eq. (2), including the 1/L^3 factor);
+ *   step 2  projection of each local spectrum along f_t, f_x, f_y (Eqs. (1)-(4)), with
+ *           the DC bin excluded (paragraph after Fig. 2);
+ *   step 3  spectral energies E_t, E_x, E_y: absolute mean of each projected spectrum;
+ *   step 4  directional center-surround comparison (Eq. (5)) with Gaussian weights;
+ *   step 5  weighted combination S = a S_t + b S_x + c S_y (Eq. (6)).
+ *
+ * Conventions shared by every entry point:
+ *   - Volumes are contiguous C-order arrays [n0][n1][n2]; axis 0 is t (time/depth),
+ *     axis 1 is x, axis 2 is y (fastest).  Sec. 2 calls the volume "T x X x Y".
+ *   - Every pointer named V, E, S, spectra or workspace is DEVICE memory on the context's
+ *     device, owned by the caller; the library never frees or retains it beyond the call.
+ *     Pointers must be 16-byte aligned.
+ *   - Per-component maps are stored as [3][n0][n1][n2] in the order t, x, y.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the default
+ *     stream).  Nothing synchronises unless stated.  A device fault of an earlier call is
+ *     reported as SAL_E_DEVICE by a later call.
+ *   - Every call returns a sal_status; no exception or abort crosses the ABI.  On an error
+ *     nothing is enqueued and sal_last_error() describes it.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Window boundaries: samples outside the volume are reflected without repeating the
+ *     edge sample (-1 -> 1, n -> n-2).  Every dimension must exceed max(floor(L/2), r).
+ */
+#ifndef SAL_H
+#define SAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sal_ctx sal_ctx;
+
+typedef enum {
+    SAL_OK = 0,
+    SAL_E_INVAL = 1,        /* bad argument: null/misaligned pointer, bad size or parameter */
+    SAL_E_UNSUPPORTED = 2,  /* valid method parameters this GPU build does not implement */
+    SAL_E_DEVICE = 3,       /* HIP runtime or device error */
+    SAL_E_WORKSPACE = 4     /* workspace smaller than sal_workspace_size() */
+} sal_status;
+
+/* Arithmetic of the DFT contractions (steps 1-3).  Everything after step 3 is FP32 with
+ * FP64 normalisation statistics and combination in every mode. */
+typedef enum {
+    SAL_FP32 = 0,        /* FP32 operands, FP32 accumulation (MFMA f32) */
+    SAL_BF16 = 1,        /* BF16 data and DFT matrix, FP32 accumulation */
+    SAL_BF16_SPLIT = 2,  /* BF16 data times DFT matrix split hi + lo (two BF16 terms) */
+    SAL_FP16 = 3,        /* FP16 data and DFT matrix, FP32 accumulation */
+    SAL_FP16_SPLIT = 4   /* FP16 data times DFT matrix split hi + lo */
+} sal_precision;
+
+/* Rays of the directional comparison of Eq. (5): +t, -t, +x, -x, +y, -y. */
+enum {
+    SAL_RAY_PT = 1, SAL_RAY_MT = 2, SAL_RAY_PX = 4,
+    SAL_RAY_MX = 8, SAL_RAY_PY = 16, SAL_RAY_MY = 32
+};
+
+/* Length of the statistics vector written by sal_saliency:
+ * {lo_t, hi_t, lo_x, hi_x, lo_y, hi_y, max|V|}. */
+#define SAL_STATS_LEN 7
+
+typedef struct {
+    int32_t L;          /* cube side of the local DFT (Sec. 2 step 1; the paper uses 5).
+                           GPU build: 8 or 16. */
+    int32_t d;          /* length of the d x 1 comparison line (after Fig. 3), default L;
+                           the line is r = floor(d/2) neighbours on each enabled ray. */
+    double sigma;       /* width of the Gaussian neighbour weight w(s) = exp(-s^2/(2 sigma^2))
+                           of Eq. (5); the paper gives none, default d/4. */
+    uint32_t rays[3];   /* SAL_RAY_* masks used by S_t, S_x, S_y; default {+-t, +-x, +-y}
+                           ("along t, x and y respectively", after Fig. 3). */
+    double a, b, c;     /* weights of Eq. (6); default 1/3 each ("equal weights"). */
+    int32_t normalize;  /* 1: map each S_m to [0,1] by its volume-wide min and max before
+                           Eq. (6) (default); 0: combine the raw maps. */
+    double zero_range;  /* a component whose range is <= zero_range * max|V| has no
+                           contrast and contributes 0 (default 1e-6). */
+    int32_t precision;  /* sal_precision, default SAL_FP32 */
+} sal_params;
+
+/* Fill *p with the defaults above for cube side L. */
+void sal_default_params(sal_params *p, int32_t L);
+
+/* Validate *p (copied) and create a context on HIP device `device`.  Builds the DFT
+ * matrices and projection weight tables on that device.  Errors: SAL_E_INVAL (null out,
+ * L < 2, d < 2, sigma <= 0, a ray mask with bits above 63 or empty, bad precision),
+ * SAL_E_UNSUPPORTED (L not in {8, 16}), SAL_E_DEVICE. */
+sal_status sal_create(const sal_params *p, int device, sal_ctx **out);
+
+/* Free the context and its device tables (waits for nothing; the caller must ensure no
+ * enqueued work still uses the context). NULL is ignored. */
+void sal_destroy(sal_ctx *ctx);
+
+/* Text of the last error of this context (or of sal_create when ctx is NULL). */
+const char *sal_last_error(const sal_ctx *ctx);
+
+/* Bytes of device workspace sal_saliency needs for an n0 x n1 x n2 volume. */
+sal_status sal_workspace_size(sal_ctx *ctx, int64_t n0, int64_t n1, int64_t n2, size_t *bytes);
+
+/*
+ * Local spectra of the voxels of the box [lo, lo + bn) of V (Sec. 2 step 1, DFT definition
+ * after Eq. (2)).  spectra: device complex64 (re, im float pairs)
+ * [bn0][bn1][bn2][L][L][L] in unshifted order mu, nu, om = 0..L-1 along (t, x, y),
+ * including the 1/L^3 factor.  The box must lie inside the volume.  Meant for checks on
+ * small boxes: the output is L^3 complex values per voxel.
+ */
+sal_status sal_local_spectra(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                             const int64_t lo[3], const int64_t bn[3], void *spectra,
+                             void *stream);
+
+/*
+ * Spectral energies from given spectra (Sec. 2 steps 2-3, Eqs. (1)-(4)):
+ *   E_m = (1/(L^3-1)) sum over the bins other than DC of w_m(i,j,k) |F[mu,nu,om]|,
+ *   w_t = sqrt(j^2+k^2)/rho, w_x = sqrt(i^2+k^2)/rho, w_y = sqrt(i^2+j^2)/rho,
+ *   rho = sqrt(i^2+j^2+k^2), (i,j,k) the signed frequencies of (mu,nu,om).
+ * spectra: device complex64 [nvox][L][L][L] (layout of sal_local_spectra);
+ * E: device float [3][nvox].
+ */
+sal_status sal_project(sal_ctx *ctx, const void *spectra, int64_t nvox, float *E, void *stream);
+
+/*
+ * Directional center-surround comparison (Eq. (5)) on given energies:
+ *   S_m[v] = (1/Q_m) sum over enabled rays e of m, s = 1..r, of |E_m[v] - w(s) E_m[v + s e]|,
+ *   Q_m = (enabled rays of m) * r, w(s) = exp(-s^2 / (2 sigma^2)), reflected at the edges.
+ * E, S_raw: device float [3][n0][n1][n2]; they must not overlap.
+ */
+sal_status sal_directional_compare(sal_ctx *ctx, const float *E, int64_t n0, int64_t n1,
+                                   int64_t n2, float *S_raw, void *stream);
+
+/*
+ * The whole method, steps 1-5, on a device-resident volume.
+ *   V          device float [n0][n1][n2], input
+ *   S          device float [n0][n1][n2], output saliency map (Eq. (6))
+ *   E_out      optional device float [3][n0][n1][n2]: energies (NULL: not written)
+ *   S_raw_out  optional device float [3][n0][n1][n2]: maps of Eq. (5) before
+ *              normalisation (NULL: not written)
+ *   stats_out  optional DEVICE double [SAL_STATS_LEN]: {lo_t, hi_t, lo_x, hi_x, lo_y, hi_y,
+ *              max|V|}, the volume-wide FP64 statistics used by the normalisation
+ *   workspace  device scratch of at least sal_workspace_size() bytes, ws_bytes its size
+ * The normalisation statistics are reduced in FP64 and Eq. (6) is evaluated in FP64 per
+ * voxel, then stored as FP32.  Errors: SAL_E_INVAL, SAL_E_WORKSPACE, SAL_E_DEVICE.
+ */
+sal_status sal_saliency(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                        float *S, float *E_out, float *S_raw_out, double *stats_out,
+                        void *workspace, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAL_H */

@@ -1,0 +1,443 @@
+// C-ABI front end of libsal: argument checks, per-context device tables, workspace
+// layout and the launch sequence of the method (Shafiq et al., ICIP 2017, Sec. 2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sal_internal.h"
+
+namespace {
+
+thread_local std::string g_create_err;
+
+// exp(-2 pi i k / L) in FP64 with the quarter-turn values exact (0, +-1).
+void twiddle(long k, long L, double *c, double *s)
+{
+    k %= L;
+    if (k < 0) k += L;
+    if ((4 * k) % L == 0) {
+        static const double C4[4] = {1.0, 0.0, -1.0, 0.0}, S4[4] = {0.0, -1.0, 0.0, 1.0};
+        const long q = 4 * k / L;
+        *c = C4[q];
+        *s = S4[q];
+        return;
+    }
+    const double a = 2.0 * M_PI * (double)k / (double)L;
+    *c = std::cos(a);
+    *s = -std::sin(a);
+}
+
+long sfreq(long u, long L) { return u <= L / 2 ? u : u - L; }
+
+// projection weights (t, x, y) of bin with signed frequencies (i, j, k); DC -> 0
+void proj_w(long i, long j, long k, double w[3])
+{
+    const double rho = std::sqrt((double)(i * i + j * j + k * k));
+    if (rho == 0.0) {
+        w[0] = w[1] = w[2] = 0.0;
+        return;
+    }
+    w[0] = std::sqrt((double)(j * j + k * k)) / rho;
+    w[1] = std::sqrt((double)(i * i + k * k)) / rho;
+    w[2] = std::sqrt((double)(i * i + j * j)) / rho;
+}
+
+uint16_t to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;  // round to nearest even (inputs are finite)
+    return (uint16_t)(u >> 16);
+}
+float from_bf16(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+uint16_t to_f16(float f)
+{
+    _Float16 h = (_Float16)f;  // RNE
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+float from_f16(uint16_t b)
+{
+    _Float16 h;
+    std::memcpy(&h, &b, 2);
+    return (float)h;
+}
+
+struct DevScope {
+    int prev = -1;
+    bool ok = false;
+    explicit DevScope(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DevScope()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+sal_status fail(sal_ctx *c, sal_status s, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_create_err = msg;
+    return s;
+}
+
+sal_status dev_fail(sal_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, SAL_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src)
+{
+    hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t build_tables(sal_ctx *c)
+{
+    const long L = c->L, h = c->h;
+    const long L3 = L * L * L;
+    const long MT = 2 * L / 16, MTA = (2 * h + 15) / 16;
+    // w_c[(f, co)][(tap, ci)]: F = sum_tap e^{-2 pi i f tap / L} a_tap in real form
+    std::vector<double> wc((size_t)(2 * L) * (2 * L));
+    for (long f = 0; f < L; ++f)
+        for (long tp = 0; tp < L; ++tp) {
+            double cs, sn;
+            twiddle(f * tp, L, &cs, &sn);
+            wc[(2 * f) * 2 * L + 2 * tp] = cs;
+            wc[(2 * f) * 2 * L + 2 * tp + 1] = -sn;
+            wc[(2 * f + 1) * 2 * L + 2 * tp] = sn;
+            wc[(2 * f + 1) * 2 * L + 2 * tp + 1] = cs;
+        }
+    std::vector<double> wa((size_t)16 * MTA * L, 0.0);
+    for (long mu = 0; mu < h; ++mu)
+        for (long p = 0; p < L; ++p) {
+            double cs, sn;
+            twiddle(mu * p, L, &cs, &sn);
+            wa[(2 * mu) * L + p] = cs;
+            wa[(2 * mu + 1) * L + p] = sn;
+        }
+    // weights of the two bins lane group g owns in M tile mt of row (mu, nu)
+    std::vector<float> wb;
+    const double scale = 1.0 / ((double)L3 * (double)(L3 - 1));
+    for (long mu = 0; mu < h; ++mu) {
+        const bool self = (mu == 0 || mu == L / 2);
+        const long nuc = self ? L / 2 + 1 : L;
+        for (long nu = 0; nu < nuc; ++nu) {
+            const double mult = (self && (nu == 0 || nu == L / 2)) ? 1.0 : 2.0;
+            for (long mt = 0; mt < MT; ++mt)
+                for (long g = 0; g < 4; ++g) {
+                    float ent[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    for (long bb = 0; bb < 2; ++bb) {
+                        const long om = 8 * mt + 2 * g + bb;
+                        double w[3];
+                        proj_w(sfreq(mu, L), sfreq(nu, L), sfreq(om, L), w);
+                        for (int m = 0; m < 3; ++m) ent[3 * bb + m] = (float)(w[m] * mult * scale);
+                    }
+                    wb.insert(wb.end(), ent, ent + 8);
+                }
+        }
+    }
+    std::vector<float> tw(2 * L);
+    for (long k = 0; k < L; ++k) {
+        double cs, sn;
+        twiddle(k, L, &cs, &sn);
+        tw[2 * k] = (float)cs;
+        tw[2 * k + 1] = (float)sn;
+    }
+    std::vector<float> wp((size_t)4 * L3, 0.f);
+    for (long mu = 0; mu < L; ++mu)
+        for (long nu = 0; nu < L; ++nu)
+            for (long om = 0; om < L; ++om) {
+                double w[3];
+                proj_w(sfreq(mu, L), sfreq(nu, L), sfreq(om, L), w);
+                const long b = (mu * L + nu) * L + om;
+                for (int m = 0; m < 3; ++m) wp[4 * b + m] = (float)(w[m] / (double)(L3 - 1));
+            }
+    std::vector<float> wcf(wc.size()), waf(wa.size());
+    for (size_t i = 0; i < wc.size(); ++i) wcf[i] = (float)wc[i];
+    for (size_t i = 0; i < wa.size(); ++i) waf[i] = (float)wa[i];
+    // 16-bit forms: hi = RNE(w), lo = RNE(w - hi)
+    std::vector<uint16_t> c16[4], a16[4];
+    for (int k = 0; k < 4; ++k) {
+        c16[k].resize(wc.size());
+        a16[k].resize(wa.size());
+    }
+    for (size_t i = 0; i < wc.size(); ++i) {
+        const uint16_t bh = to_bf16((float)wc[i]), fh = to_f16((float)wc[i]);
+        c16[0][i] = bh;
+        c16[1][i] = to_bf16((float)(wc[i] - (double)from_bf16(bh)));
+        c16[2][i] = fh;
+        c16[3][i] = to_f16((float)(wc[i] - (double)from_f16(fh)));
+    }
+    for (size_t i = 0; i < wa.size(); ++i) {
+        const uint16_t bh = to_bf16((float)wa[i]), fh = to_f16((float)wa[i]);
+        a16[0][i] = bh;
+        a16[1][i] = to_bf16((float)(wa[i] - (double)from_bf16(bh)));
+        a16[2][i] = fh;
+        a16[3][i] = to_f16((float)(wa[i] - (double)from_f16(fh)));
+    }
+    hipError_t e;
+    if ((e = upload(&c->t.w_c, wcf)) != hipSuccess) return e;
+    if ((e = upload(&c->t.w_a, waf)) != hipSuccess) return e;
+    if ((e = upload(&c->t.w_bin, wb)) != hipSuccess) return e;
+    if ((e = upload(&c->t.twiddle, tw)) != hipSuccess) return e;
+    if ((e = upload(&c->t.w_proj, wp)) != hipSuccess) return e;
+    for (int k = 0; k < 4; ++k) {
+        if ((e = upload(&c->t.w_c16[k], c16[k])) != hipSuccess) return e;
+        if ((e = upload(&c->t.w_a16[k], a16[k])) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void free_tables(sal_tables *t)
+{
+    float **fp[] = {&t->w_c, &t->w_a, &t->w_bin, &t->twiddle, &t->w_proj};
+    for (float **p : fp)
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+    for (int k = 0; k < 4; ++k) {
+        if (t->w_c16[k]) (void)hipFree(t->w_c16[k]);
+        if (t->w_a16[k]) (void)hipFree(t->w_a16[k]);
+        t->w_c16[k] = t->w_a16[k] = nullptr;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t e, s_raw, vmax, mm, stats, total;
+};
+
+WsLayout ws_layout(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
+{
+    const size_t N = (size_t)n0 * n1 * n2;
+    WsLayout w;
+    w.e = 0;
+    w.s_raw = w.e + align256(3 * N * sizeof(float));
+    w.vmax = w.s_raw + align256(3 * N * sizeof(float));
+    w.mm = w.vmax + align256((size_t)energy_num_blocks(c, n0, n1, n2) * sizeof(float));
+    w.stats = w.mm + align256((size_t)dcs_num_blocks(n0, n1, n2) * 6 * sizeof(float));
+    w.total = w.stats + align256(8 * sizeof(double));
+    return w;
+}
+
+sal_status check_dims(sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
+{
+    const int64_t need = (c->H > c->r ? c->H : c->r);
+    if (n0 <= need || n1 <= need || n2 <= need)
+        return fail(c, SAL_E_INVAL, "every dimension must exceed max(floor(L/2), r) = " +
+                                        std::to_string(need));
+    if (n0 > (1 << 30) || n1 > (1 << 30) || n2 > (1 << 30) ||
+        n0 * n1 * n2 > ((int64_t)1 << 31) - 1 || n1 * n2 > ((int64_t)1 << 31) - 1)
+        return fail(c, SAL_E_INVAL, "volume too large (at most 2^31-1 voxels)");
+    return SAL_OK;
+}
+
+sal_status sticky(sal_ctx *c)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return dev_fail(c, e, "earlier device error");
+    return SAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sal_default_params(sal_params *p, int32_t L)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->L = L;
+    p->d = L;
+    p->sigma = (double)L / 4.0;
+    p->rays[0] = SAL_RAY_PT | SAL_RAY_MT;
+    p->rays[1] = SAL_RAY_PX | SAL_RAY_MX;
+    p->rays[2] = SAL_RAY_PY | SAL_RAY_MY;
+    p->a = p->b = p->c = 1.0 / 3.0;
+    p->normalize = 1;
+    p->zero_range = 1e-6;
+    p->precision = SAL_FP32;
+}
+
+sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
+{
+    if (!p || !out) return fail(nullptr, SAL_E_INVAL, "null params or output pointer");
+    *out = nullptr;
+    if (p->L < 2) return fail(nullptr, SAL_E_INVAL, "L must be >= 2");
+    if (p->d < 2 || p->d > 64) return fail(nullptr, SAL_E_INVAL, "d must be in [2, 64]");
+    if (!(p->sigma > 0.0)) return fail(nullptr, SAL_E_INVAL, "sigma must be > 0 (may be inf)");
+    for (int m = 0; m < 3; ++m)
+        if (p->rays[m] == 0 || p->rays[m] > 63u)
+            return fail(nullptr, SAL_E_INVAL, "each ray mask must be a nonempty subset of 6 rays");
+    if (p->precision < SAL_FP32 || p->precision > SAL_FP16_SPLIT)
+        return fail(nullptr, SAL_E_INVAL, "unknown precision");
+    if (!(p->zero_range >= 0.0)) return fail(nullptr, SAL_E_INVAL, "zero_range must be >= 0");
+    if (p->L != 8 && p->L != 16)
+        return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements L = 8 and L = 16");
+    if (p->precision != SAL_FP32)
+        return fail(nullptr, SAL_E_UNSUPPORTED, "precision form not built yet");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, SAL_E_DEVICE, "no such HIP device");
+    DevScope ds(device);
+    if (!ds.ok) return fail(nullptr, SAL_E_DEVICE, "hipSetDevice failed");
+    sal_ctx *c = new (std::nothrow) sal_ctx();
+    if (!c) return fail(nullptr, SAL_E_DEVICE, "out of host memory");
+    c->p = *p;
+    c->device = device;
+    c->L = p->L;
+    c->H = p->L / 2;
+    c->h = p->L / 2 + 1;
+    c->r = p->d / 2;
+    c->nrows = (c->h - 2) * c->L + 2 * (c->L / 2 + 1);
+    for (int s = 0; s < 32; ++s)
+        c->g[s] = (s < c->r) ? (float)std::exp(-(double)((s + 1) * (s + 1)) / (2.0 * p->sigma * p->sigma)) : 0.f;
+    for (int m = 0; m < 3; ++m) {
+        int nr = 0;
+        for (int b = 0; b < 6; ++b) nr += (p->rays[m] >> b) & 1;
+        c->Q[m] = (float)(nr * c->r);
+        c->q_inv[m] = 1.0f / c->Q[m];
+    }
+    hipError_t e = build_tables(c);
+    if (e != hipSuccess) {
+        free_tables(&c->t);
+        delete c;
+        return fail(nullptr, SAL_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return SAL_OK;
+}
+
+void sal_destroy(sal_ctx *c)
+{
+    if (!c) return;
+    DevScope ds(c->device);
+    free_tables(&c->t);
+    delete c;
+}
+
+const char *sal_last_error(const sal_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+sal_status sal_workspace_size(sal_ctx *c, int64_t n0, int64_t n1, int64_t n2, size_t *bytes)
+{
+    if (!c || !bytes) return fail(c, SAL_E_INVAL, "null argument");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    *bytes = ws_layout(c, n0, n1, n2).total;
+    return SAL_OK;
+}
+
+sal_status sal_local_spectra(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                             const int64_t lo[3], const int64_t bn[3], void *spectra, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!V || !lo || !bn || !spectra) return fail(c, SAL_E_INVAL, "null pointer");
+    if (!aligned16(V) || !aligned16(spectra)) return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    const int64_t n[3] = {n0, n1, n2};
+    for (int a = 0; a < 3; ++a)
+        if (lo[a] < 0 || bn[a] < 0 || lo[a] + bn[a] > n[a])
+            return fail(c, SAL_E_INVAL, "box outside the volume");
+    if (bn[0] * bn[1] * bn[2] > (int64_t)1 << 24) return fail(c, SAL_E_INVAL, "box too large");
+    DevScope ds(c->device);
+    if ((st = sticky(c)) != SAL_OK) return st;
+    hipError_t e = launch_local_spectra(c, V, n0, n1, n2, lo, bn, (float *)spectra, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(c, e, "local spectra launch");
+    return SAL_OK;
+}
+
+sal_status sal_project(sal_ctx *c, const void *spectra, int64_t nvox, float *E, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!spectra || !E) return fail(c, SAL_E_INVAL, "null pointer");
+    if (!aligned16(spectra) || !aligned16(E)) return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    if (nvox < 0 || nvox > ((int64_t)1 << 31) - 1) return fail(c, SAL_E_INVAL, "bad voxel count");
+    DevScope ds(c->device);
+    sal_status st;
+    if ((st = sticky(c)) != SAL_OK) return st;
+    hipError_t e = launch_project(c, (const float *)spectra, nvox, E, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(c, e, "project launch");
+    return SAL_OK;
+}
+
+sal_status sal_directional_compare(sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
+                                   float *S_raw, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!E || !S_raw) return fail(c, SAL_E_INVAL, "null pointer");
+    if (!aligned16(E) || !aligned16(S_raw)) return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    const size_t bytes = (size_t)3 * n0 * n1 * n2 * sizeof(float);
+    const char *a = (const char *)E, *b = (const char *)S_raw;
+    if (a < b + bytes && b < a + bytes) return fail(c, SAL_E_INVAL, "E and S_raw overlap");
+    DevScope ds(c->device);
+    if ((st = sticky(c)) != SAL_OK) return st;
+    hipError_t e = launch_dcs(c, E, n0, n1, n2, S_raw, nullptr, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
+    return SAL_OK;
+}
+
+sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, float *S,
+                        float *E_out, float *S_raw_out, double *stats_out, void *workspace,
+                        size_t ws_bytes, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!V || !S || !workspace) return fail(c, SAL_E_INVAL, "null pointer");
+    if (!aligned16(V) || !aligned16(S) || !aligned16(workspace) || (E_out && !aligned16(E_out)) ||
+        (S_raw_out && !aligned16(S_raw_out)) || (stats_out && !aligned16(stats_out)))
+        return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    const WsLayout w = ws_layout(c, n0, n1, n2);
+    if (ws_bytes < w.total)
+        return fail(c, SAL_E_WORKSPACE, "workspace too small: need " + std::to_string(w.total) + " bytes");
+    DevScope ds(c->device);
+    if ((st = sticky(c)) != SAL_OK) return st;
+    char *ws = (char *)workspace;
+    float *E = E_out ? E_out : (float *)(ws + w.e);
+    float *Sr = S_raw_out ? S_raw_out : (float *)(ws + w.s_raw);
+    float *vmax = (float *)(ws + w.vmax);
+    float *mm = (float *)(ws + w.mm);
+    double *stats = stats_out ? stats_out : (double *)(ws + w.stats);
+    const int64_t N = n0 * n1 * n2;
+    hipStream_t s = (hipStream_t)stream;
+    int nv = 0;
+    hipError_t e = launch_energy(c, V, n0, n1, n2, E, vmax, &nv, s);
+    if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    e = launch_dcs(c, E, n0, n1, n2, Sr, mm, s);
+    if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
+    e = launch_stats(vmax, nv, mm, dcs_num_blocks(n0, n1, n2), stats, s);
+    if (e != hipSuccess) return dev_fail(c, e, "stats launch");
+    e = launch_combine(Sr, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);
+    if (e != hipSuccess) return dev_fail(c, e, "combine launch");
+    return SAL_OK;
+}
+
+}  // extern "C"

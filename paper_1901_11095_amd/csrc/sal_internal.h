@@ -1,0 +1,67 @@
+// Internal declarations shared by the C-ABI front end and the gfx950 kernels of libsal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "sal.h"
+
+// Device tables built once per context from FP64 values rounded to the kernel's type.
+struct sal_tables {
+    float *w_c;      // [2L][2L] real form of the L-point DFT matrix: row (freq, re|im),
+                     // column (tap, re|im); used by the x and y contractions
+    float *w_a;      // [16*MTA][L] real-input DFT along t: row (mu, re|im) for mu <= L/2,
+                     // zero rows above
+    float *w_bin;    // per reduced-spectrum row, M tile, lane group: 8 floats holding the
+                     // projection weights (t, x, y) of the two bins a lane owns, times the
+                     // Hermitian multiplicity and 1/(L^3 (L^3-1)); DC has weight 0
+    float *twiddle;  // [L][2] exp(-2 pi i k / L), for the per-voxel spectra kernel
+    float *w_proj;   // [L^3][4] projection weights / (L^3 - 1) of bin (mu,nu,om), DC = 0
+    uint16_t *w_c16[4];  // [2L][2L] DFT matrix as bf16 hi, bf16 lo, fp16 hi, fp16 lo
+    uint16_t *w_a16[4];  // [16*MTA][L] likewise for the t contraction
+};
+
+struct sal_ctx {
+    sal_params p;
+    int device;
+    int L, H, h, r, nrows;
+    float g[32];       // Gaussian neighbour weights w(s), s = 1..r (index s-1)
+    float q_inv[3];    // unused by the kernels (kept for diagnostics)
+    float Q[3];        // number of terms of Eq. (5) per component
+    sal_tables t;
+    std::string err;
+};
+
+// Arguments of the directional comparison kernel.
+struct dcs_args {
+    int r;
+    uint32_t rays[3];
+    float Q[3];
+    float g[32];
+};
+
+// ------------------------------------------------------------------ launchers
+// All return hipSuccess or the launch error.
+hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                         float *E, float *vmax_part, int *nparts, hipStream_t s);
+int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
+
+hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
+                      float *S_raw, float *minmax_part, hipStream_t s);
+int64_t dcs_num_blocks(int64_t n0, int64_t n1, int64_t n2);
+
+hipError_t launch_stats(const float *vmax_part, int64_t nv, const float *minmax_part,
+                        int64_t nm, double *stats, hipStream_t s);
+
+hipError_t launch_combine(const float *S_raw, int64_t nvox, const double *stats, double a,
+                          double b, double c, int normalize, double zero_range, float *S,
+                          hipStream_t s);
+
+hipError_t launch_local_spectra(const sal_ctx *c, const float *V, int64_t n0, int64_t n1,
+                                int64_t n2, const int64_t lo[3], const int64_t bn[3],
+                                float *out, hipStream_t s);
+
+hipError_t launch_project(const sal_ctx *c, const float *spectra, int64_t nvox, float *E,
+                          hipStream_t s);

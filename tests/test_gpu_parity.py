@@ -1,0 +1,236 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: max|gpu - oracle| / max|oracle| <= 1e-5 for every FP32 map; bit-exact where the
+arithmetic is exact (integer windows, unweighted comparisons, min/max statistics).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1901_11095_amd import sal, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def relmax(got, ref):
+    """max |got - ref| / max |ref| (complex values compared as complex numbers)."""
+    dt = np.complex128 if (np.iscomplexobj(got) or np.iscomplexobj(ref)) else np.float64
+    got = np.asarray(got, dt)
+    ref = np.asarray(ref, dt)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def ctx8():
+    return sal.Saliency(L=8)
+
+
+@pytest.fixture(scope="module")
+def ctx16():
+    return sal.Saliency(L=16)
+
+
+def gpu(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+# ------------------------------------------------------------------ step 1 ------------
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_local_spectra_vs_oracle(dev, L):
+    ctx = sal.Saliency(L=L)
+    V = synth.random_volume((20, 19, 23), seed=L)
+    for lo, bn in [((0, 0, 0), (2, 3, 4)), ((17, 15, 19), (3, 4, 4)), ((8, 7, 9), (2, 2, 3))]:
+        print("local_spectra L=%d lo=%s bn=%s" % (L, lo, bn), flush=True)
+        F = ctx.local_spectra(gpu(V, dev), lo, bn)
+        torch.cuda.synchronize()
+        ref = O.local_spectra(V, L, lo, bn)
+        got = F.cpu().numpy().astype(np.complex128)
+        assert relmax(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_local_spectra_dc_bit_exact(dev, L):
+    """Integer windows: the DC bin is an integer sum times 2^-3k, exact in any order."""
+    ctx = sal.Saliency(L=L)
+    V = synth.integer_volume((19, 18, 21), seed=3)
+    lo, bn = (0, 0, 0), (19, 18, 21) if L == 8 else (10, 18, 21)
+    F = ctx.local_spectra(gpu(V, dev), lo, bn).cpu().numpy()
+    dc_gpu = F[..., 0, 0, 0]
+    ref = O.local_spectra(V, L, lo, (bn[0], bn[1], bn[2]))[..., 0, 0, 0]
+    assert np.array_equal(dc_gpu.real.astype(np.float64), ref.real)
+    assert np.all(dc_gpu.imag == 0.0)
+
+
+# --------------------------------------------------------------- steps 2-3 -----------
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_project_vs_oracle(dev, L):
+    ctx = sal.Saliency(L=L)
+    V = synth.random_volume((18, 17, 19), seed=5)
+    spec = O.local_spectra(V, L, (1, 2, 3), (3, 2, 4)).astype(np.complex64)
+    E = ctx.project(gpu(spec, dev)).cpu().numpy()
+    flat = spec.reshape(-1, L, L, L)
+    ref = np.stack([O.project(f.astype(np.complex128)) for f in flat], 1)
+    assert relmax(E, ref) <= TOL
+
+
+# ------------------------------------------------------------------ step 4 -----------
+
+def test_dcs_vs_oracle(dev, ctx8):
+    E = (np.abs(synth.random_volume((3, 21, 22, 23), seed=8)) + 0.1).astype(np.float32)
+    S = ctx8.directional_compare(gpu(E, dev)).cpu().numpy()
+    ref = O.dcs(E.astype(np.float64), 4, 2.0, O.RAYS_AXIS)
+    assert relmax(S, ref) <= TOL
+
+
+def test_dcs_all_rays_vs_oracle(dev):
+    ctx = sal.Saliency(L=8, rays=sal.RAYS_ALL)
+    E = (np.abs(synth.random_volume((3, 12, 11, 13), seed=9)) + 0.1).astype(np.float32)
+    S = ctx.directional_compare(gpu(E, dev)).cpu().numpy()
+    ref = O.dcs(E.astype(np.float64), 4, 2.0, O.RAYS_ALL)
+    assert relmax(S, ref) <= TOL
+
+
+def test_dcs_bit_exact_unweighted(dev):
+    """sigma = inf: integer E, Q = 2r = 8, every partial sum exact -> bit-exact."""
+    ctx = sal.Saliency(L=8, sigma=math.inf)
+    E = np.abs(synth.integer_volume((3, 9, 10, 11), seed=4)).astype(np.float32)
+    S = ctx.directional_compare(gpu(E, dev)).cpu().numpy().astype(np.float64)
+    ref = O.dcs(E.astype(np.float64), 4, math.inf, O.RAYS_AXIS)
+    assert np.array_equal(S, ref)
+
+
+# ----------------------------------------------------------------- whole path ----------
+
+def _check_full(ctx, V, L, dev, rays=O.RAYS_AXIS, sigma=None):
+    p = O.Params(L=L, rays=rays, sigma=sigma)
+    ref = O.saliency(V, p)
+    S, E, Sr, st = ctx.saliency_maps(gpu(V, dev))
+    torch.cuda.synchronize()
+    E, Sr, S, st = E.cpu().numpy(), Sr.cpu().numpy(), S.cpu().numpy(), st.cpu().numpy()
+    for m in range(3):
+        assert relmax(E[m], ref["E"][m]) <= TOL, ("E", m, relmax(E[m], ref["E"][m]))
+        assert relmax(Sr[m], ref["S_raw"][m]) <= TOL, ("S_raw", m)
+    assert relmax(S, ref["S"]) <= TOL, ("S", relmax(S, ref["S"]))
+    # statistics: exact min/max of the GPU's own raw maps and of |V|
+    for m in range(3):
+        assert st[2 * m] == Sr[m].min() and st[2 * m + 1] == Sr[m].max()
+    assert st[6] == np.abs(V).max()
+    return E, Sr, S, st
+
+
+@pytest.mark.parametrize("shape", [(24, 20, 40), (33, 17, 45), (9, 9, 9), (40, 5, 70)])
+def test_saliency_small_L8(dev, ctx8, shape):
+    print("saliency L=8 shape", shape, flush=True)
+    V = synth.make_volume(shape, seed=sum(shape), n_faults=1)
+    _check_full(ctx8, V, 8, dev)
+
+
+@pytest.mark.parametrize("shape", [(20, 18, 33), (17, 40, 9)])
+def test_saliency_small_L16(dev, ctx16, shape):
+    print("saliency L=16 shape", shape, flush=True)
+    V = synth.make_volume(shape, seed=sum(shape), n_faults=1)
+    _check_full(ctx16, V, 16, dev)
+
+
+def test_saliency_all_rays(dev):
+    ctx = sal.Saliency(L=8, rays=sal.RAYS_ALL)
+    V = synth.make_volume((21, 22, 35), seed=2)
+    _check_full(ctx, V, 8, dev, rays=O.RAYS_ALL)
+
+
+def test_saliency_vol64_full(dev, ctx8):
+    """64^3 volume, one fault, 10 dB: the whole volume against the oracle."""
+    V = synth.workload("vol64")
+    _check_full(ctx8, V, 8, dev)
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_saliency_survey_subblock(dev, L):
+    """256 x 512 x 512 survey volume on the GPU; oracle on seeded 32^3 sub-blocks (raw maps
+    with the halo the comparison needs; the final map with the GPU's volume statistics)."""
+    ctx = sal.Saliency(L=L)
+    V = synth.workload("survey256x512x512")
+    Vg = gpu(V, dev)
+    S, E, Sr, st = ctx.saliency_maps(Vg)
+    torch.cuda.synchronize()
+    stats = st.cpu().numpy()
+    rng = np.random.default_rng(1234 + L)
+    los = [(0, 0, 0), (V.shape[0] - 32, V.shape[1] - 32, V.shape[2] - 32)]
+    los.append(tuple(int(rng.integers(0, n - 32 + 1)) for n in V.shape))
+    p = O.Params(L=L)
+    for lo in los:
+        print("sub-block", lo, flush=True)
+        sl = tuple(slice(a, a + 32) for a in lo)
+        Eo, So = O.raw_box(V, p, lo, (32, 32, 32))
+        Eg = E[(slice(None),) + sl].cpu().numpy()
+        Sg = Sr[(slice(None),) + sl].cpu().numpy()
+        for m in range(3):
+            assert relmax(Eg[m], Eo[m]) <= TOL
+            assert relmax(Sg[m], So[m]) <= TOL
+        Sref = O.combine_with_stats(So, stats[:6], vmax=stats[6])
+        assert relmax(S[sl].cpu().numpy(), Sref) <= TOL
+    # statistics are the exact min/max of the GPU raw maps
+    Srn = Sr.cpu().numpy()
+    for m in range(3):
+        assert stats[2 * m] == Srn[m].min() and stats[2 * m + 1] == Srn[m].max()
+    assert stats[6] == np.abs(V).max()
+
+
+# ------------------------------------------------------------ invariants on GPU --------
+
+def test_constant_volume(dev, ctx8):
+    V = np.full((20, 21, 33), 2.5, np.float32)
+    S, E, Sr, st = ctx8.saliency_maps(gpu(V, dev))
+    assert float(E.abs().max()) <= 1e-6 * 2.5
+    assert torch.all(S == 0)
+
+
+def test_dc_shift(dev, ctx8):
+    V = (synth.integer_volume((20, 19, 35), seed=6) / 8.0).astype(np.float32)
+    _, E0, S0, _ = ctx8.saliency_maps(gpu(V, dev))
+    _, E1, S1, _ = ctx8.saliency_maps(gpu(V + 3.0, dev))
+    assert relmax(E1.cpu().numpy(), E0.cpu().numpy()) <= TOL
+    assert relmax(S1.cpu().numpy(), S0.cpu().numpy()) <= TOL
+
+
+def test_axis_permutation(dev, ctx8):
+    V = synth.random_volume((18, 26, 37), seed=12)
+    _, E, Sr, _ = ctx8.saliency_maps(gpu(V, dev))
+    Vp = np.ascontiguousarray(V.transpose(1, 0, 2))
+    _, Ep, Srp, _ = ctx8.saliency_maps(gpu(Vp, dev))
+    E, Ep = E.cpu().numpy(), Ep.cpu().numpy()
+    for m, mp in [(0, 1), (1, 0), (2, 2)]:
+        assert relmax(Ep[mp], E[m].transpose(1, 0, 2)) <= TOL
+
+
+# ------------------------------------------------------------------ errors -------------
+
+def test_error_paths(dev, ctx8):
+    V = torch.zeros((4, 20, 20), device=dev)
+    with pytest.raises(sal.SalError) as ei:
+        ctx8.saliency(V)
+    assert ei.value.status == sal.SAL_E_INVAL
+    V = torch.zeros((20, 20, 20), device=dev)
+    ws = torch.empty(16, dtype=torch.uint8, device=dev)
+    with pytest.raises(sal.SalError) as ei:
+        ctx8.saliency(V, workspace=ws)
+    assert ei.value.status == sal.SAL_E_WORKSPACE
+    big = torch.zeros(20 * 20 * 20 + 1, device=dev)
+    with pytest.raises(sal.SalError) as ei:
+        ctx8.saliency(big[1:].view(20, 20, 20))
+    assert ei.value.status == sal.SAL_E_INVAL
+    with pytest.raises(sal.SalError) as ei:
+        sal.Saliency(L=5)
+    assert ei.value.status == sal.SAL_E_UNSUPPORTED
