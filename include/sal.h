@@ -151,6 +151,18 @@ sal_status sal_saliency(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, in
                         float *S, float *E_out, float *S_raw_out, double *stats_out,
                         void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Per-kernel timing of sal_saliency.  While enabled (on != 0), every sal_saliency call
+ * records HIP events on its stream around each of its kernels: [0] the fused steps 1-3
+ * kernel, [1] the comparison of Eq. (5), [2] the FP64 statistics, [3] the FP64
+ * combination.  sal_profile_read waits for the recorded events, returns the summed
+ * durations in milliseconds in ms[4] and the number of timed calls in *calls, and forgets
+ * them when reset != 0.  Disabling also forgets them.  Timing adds four event records
+ * per call and no synchronisation until read.
+ */
+sal_status sal_profile_enable(sal_ctx *ctx, int on);
+sal_status sal_profile_read(sal_ctx *ctx, double ms[4], int64_t *calls, int reset);
+
 #ifdef __cplusplus
 }
 #endif

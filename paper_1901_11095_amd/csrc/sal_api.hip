@@ -257,6 +257,27 @@ sal_status check_dims(sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
     return SAL_OK;
 }
 
+void release_events(sal_ctx *c)
+{
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    c->ev_pool.clear();
+    c->ev_used = 0;
+}
+
+// Events for one timed call (5 marks), or nullptr if profiling is off or creation fails.
+hipEvent_t *take_events(sal_ctx *c)
+{
+    if (!c->profiling) return nullptr;
+    while (c->ev_pool.size() < c->ev_used + 5) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    hipEvent_t *ev = &c->ev_pool[c->ev_used];
+    c->ev_used += 5;
+    return ev;
+}
+
 sal_status sticky(sal_ctx *c)
 {
     hipError_t e = hipGetLastError();
@@ -337,6 +358,7 @@ void sal_destroy(sal_ctx *c)
 {
     if (!c) return;
     DevScope ds(c->device);
+    release_events(c);
     free_tables(&c->t);
     delete c;
 }
@@ -428,15 +450,52 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     double *stats = stats_out ? stats_out : (double *)(ws + w.stats);
     const int64_t N = n0 * n1 * n2;
     hipStream_t s = (hipStream_t)stream;
+    hipEvent_t *ev = take_events(c);
     int nv = 0;
+    if (ev) (void)hipEventRecord(ev[0], s);
     hipError_t e = launch_energy(c, V, n0, n1, n2, E, vmax, &nv, s);
     if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    if (ev) (void)hipEventRecord(ev[1], s);
     e = launch_dcs(c, E, n0, n1, n2, Sr, mm, s);
     if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
+    if (ev) (void)hipEventRecord(ev[2], s);
     e = launch_stats(vmax, nv, mm, dcs_num_blocks(n0, n1, n2), stats, s);
     if (e != hipSuccess) return dev_fail(c, e, "stats launch");
+    if (ev) (void)hipEventRecord(ev[3], s);
     e = launch_combine(Sr, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);
     if (e != hipSuccess) return dev_fail(c, e, "combine launch");
+    if (ev) (void)hipEventRecord(ev[4], s);
+    return SAL_OK;
+}
+
+sal_status sal_profile_enable(sal_ctx *c, int on)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    DevScope ds(c->device);
+    c->profiling = on != 0;
+    if (!c->profiling) release_events(c);
+    return SAL_OK;
+}
+
+sal_status sal_profile_read(sal_ctx *c, double ms[4], int64_t *calls, int reset)
+{
+    if (!c || !ms || !calls) return fail(c, SAL_E_INVAL, "null argument");
+    DevScope ds(c->device);
+    for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+    const size_t n = c->ev_used / 5;
+    for (size_t i = 0; i < n; ++i) {
+        hipEvent_t *ev = &c->ev_pool[5 * i];
+        hipError_t e = hipEventSynchronize(ev[4]);
+        if (e != hipSuccess) return dev_fail(c, e, "event synchronize");
+        for (int k = 0; k < 4; ++k) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            if (e != hipSuccess) return dev_fail(c, e, "event elapsed time");
+            ms[k] += (double)t;
+        }
+    }
+    *calls = (int64_t)n;
+    if (reset) c->ev_used = 0;
     return SAL_OK;
 }
 

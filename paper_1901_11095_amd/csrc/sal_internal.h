@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "sal.h"
 
@@ -32,6 +33,10 @@ struct sal_ctx {
     float Q[3];        // number of terms of Eq. (5) per component
     sal_tables t;
     std::string err;
+    // per-kernel timing of sal_saliency (sal_profile_enable / sal_profile_read)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;  // 5 events per timed call
+    size_t ev_used = 0;
 };
 
 // Arguments of the directional comparison kernel.

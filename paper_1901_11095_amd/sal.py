@@ -23,7 +23,8 @@ STATS_LEN = 7
 
 EXPORTS = ("sal_default_params", "sal_create", "sal_destroy", "sal_last_error",
            "sal_workspace_size", "sal_local_spectra", "sal_project", "sal_directional_compare",
-           "sal_saliency")
+           "sal_saliency", "sal_profile_enable", "sal_profile_read")
+KERNELS = ("energy", "dcs", "stats", "combine")
 
 
 class SalError(RuntimeError):
@@ -69,8 +70,12 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
                                           ctypes.c_int64, vp, vp]
     l.sal_saliency.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, vp, vp,
                                vp, vp, vp, ctypes.c_size_t, vp]
+    l.sal_profile_enable.argtypes = [vp, ctypes.c_int]
+    l.sal_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     for f in ("sal_create", "sal_workspace_size", "sal_local_spectra", "sal_project",
-              "sal_directional_compare", "sal_saliency"):
+              "sal_directional_compare", "sal_saliency", "sal_profile_enable",
+              "sal_profile_read"):
         getattr(l, f).restype = ctypes.c_int
     _lib = l
     return l
@@ -199,6 +204,17 @@ class Saliency:
                                            _ptr(S_raw_out), _ptr(stats_out), _ptr(ws),
                                            ws.numel() * ws.element_size(), _stream(V.device)))
         return S
+
+    def profile(self, on: bool = True):
+        """Enable/disable per-kernel HIP-event timing of saliency()."""
+        self._raise(self._lib.sal_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self, reset: bool = True):
+        """(dict kernel -> summed ms, number of timed calls)."""
+        ms = (ctypes.c_double * 4)()
+        n = ctypes.c_int64()
+        self._raise(self._lib.sal_profile_read(self._h, ms, ctypes.byref(n), int(bool(reset))))
+        return dict(zip(KERNELS, list(ms))), n.value
 
     def saliency_maps(self, V: torch.Tensor):
         """(S, E, S_raw, stats) with every intermediate map returned."""
