@@ -51,12 +51,17 @@ typedef enum {
 /* Arithmetic of the DFT contractions (steps 1-3).  Everything after step 3 is FP32 with
  * FP64 normalisation statistics and combination in every mode. */
 typedef enum {
-    SAL_FP32 = 0,        /* FP32 operands, FP32 accumulation (MFMA f32) */
-    SAL_BF16 = 1,        /* BF16 data and DFT matrix, FP32 accumulation */
-    SAL_BF16_SPLIT = 2,  /* BF16 data times DFT matrix split hi + lo (two BF16 terms) */
-    SAL_FP16 = 3,        /* FP16 data and DFT matrix, FP32 accumulation */
-    SAL_FP16_SPLIT = 4   /* FP16 data times DFT matrix split hi + lo */
+    SAL_FP32 = 0,         /* FP32 operands, FP32 accumulation (MFMA f32) */
+    SAL_BF16 = 1,         /* BF16 data and DFT matrix, FP32 accumulation */
+    SAL_BF16_SPLIT = 2,   /* DFT matrix and data each split into BF16 hi + lo parts; the
+                             four products are accumulated in FP32 */
+    SAL_FP16 = 3,         /* FP16 data and DFT matrix, FP32 accumulation */
+    SAL_FP16_SPLIT = 4,   /* as SAL_BF16_SPLIT with FP16 parts */
+    SAL_BF16_SPLITW = 5,  /* BF16 data times the DFT matrix split hi + lo (two products) */
+    SAL_FP16_SPLITW = 6   /* FP16 data times the DFT matrix split hi + lo */
 } sal_precision;
+/* In every 16-bit form each contraction stage rounds its input to the 16-bit type and
+ * scales its FP32 output by 1/L (exact), so FP16 forms need |V| < 65504. */
 
 /* Rays of the directional comparison of Eq. (5): +t, -t, +x, -x, +y, -y. */
 enum {

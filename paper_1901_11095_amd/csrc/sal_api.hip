@@ -138,13 +138,18 @@ hipError_t build_tables(sal_ctx *c)
             wa[(2 * mu) * L + p] = cs;
             wa[(2 * mu + 1) * L + p] = sn;
         }
-    // weights of the two bins lane group g owns in M tile mt of row (mu, nu)
+    // Weights of the two bins lane group g owns in M tile mt, for every group (mu, k),
+    // k = 0..L/2: the row nu = k, joined by its mirror row nu = L - k when mu is not 0 or
+    // L/2 (same squared frequencies, so same weights).  The multiplicity counts the
+    // conjugate bins (-mu, -nu, -om) that the half spectrum leaves out; 1/L^3 of the DFT and
+    // 1/(L^3 - 1) of the mean are folded in.
     std::vector<float> wb;
-    const double scale = 1.0 / ((double)L3 * (double)(L3 - 1));
+    // the 16-bit forms scale the t and x stage outputs by 1/L each (range of FP16)
+    const double stage_gain = c->p.precision == SAL_FP32 ? 1.0 : (double)(L * L);
+    const double scale = stage_gain / ((double)L3 * (double)(L3 - 1));
     for (long mu = 0; mu < h; ++mu) {
         const bool self = (mu == 0 || mu == L / 2);
-        const long nuc = self ? L / 2 + 1 : L;
-        for (long nu = 0; nu < nuc; ++nu) {
+        for (long nu = 0; nu <= L / 2; ++nu) {
             const double mult = (self && (nu == 0 || nu == L / 2)) ? 1.0 : 2.0;
             for (long mt = 0; mt < MT; ++mt)
                 for (long g = 0; g < 4; ++g) {
@@ -178,25 +183,41 @@ hipError_t build_tables(sal_ctx *c)
     std::vector<float> wcf(wc.size()), waf(wa.size());
     for (size_t i = 0; i < wc.size(); ++i) wcf[i] = (float)wc[i];
     for (size_t i = 0; i < wa.size(); ++i) waf[i] = (float)wa[i];
-    // 16-bit forms: hi = RNE(w), lo = RNE(w - hi)
-    std::vector<uint16_t> c16[4], a16[4];
-    for (int k = 0; k < 4; ++k) {
-        c16[k].resize(wc.size());
-        a16[k].resize(wa.size());
-    }
-    for (size_t i = 0; i < wc.size(); ++i) {
-        const uint16_t bh = to_bf16((float)wc[i]), fh = to_f16((float)wc[i]);
-        c16[0][i] = bh;
-        c16[1][i] = to_bf16((float)(wc[i] - (double)from_bf16(bh)));
-        c16[2][i] = fh;
-        c16[3][i] = to_f16((float)(wc[i] - (double)from_f16(fh)));
-    }
-    for (size_t i = 0; i < wa.size(); ++i) {
-        const uint16_t bh = to_bf16((float)wa[i]), fh = to_f16((float)wa[i]);
-        a16[0][i] = bh;
-        a16[1][i] = to_bf16((float)(wa[i] - (double)from_bf16(bh)));
-        a16[2][i] = fh;
-        a16[3][i] = to_f16((float)(wa[i] - (double)from_f16(fh)));
+    // 16-bit forms: hi = RNE(w), lo = RNE(w - hi) (lo = 0 when the matrix is not split),
+    // laid out as the per-lane A operands of the 16x16x32 MFMAs (see sal_energy16.hip)
+    const int prec = c->p.precision;
+    const bool bf = prec == SAL_BF16 || prec == SAL_BF16_SPLIT || prec == SAL_BF16_SPLITW;
+    const bool split = prec != SAL_BF16 && prec != SAL_FP16;
+    auto r16 = [&](double v) -> uint16_t { return bf ? to_bf16((float)v) : to_f16((float)v); };
+    auto f16v = [&](uint16_t b) -> double { return bf ? (double)from_bf16(b) : (double)from_f16(b); };
+    auto part = [&](double v, int s) -> uint16_t {
+        const uint16_t hi = r16(v);
+        if (s == 0) return hi;
+        return split ? r16(v - f16v(hi)) : (uint16_t)0;
+    };
+    const long J = L / 8;
+    std::vector<uint32_t> c16((size_t)MT * J * 64 * 4, 0u), a16((size_t)MTA * 64 * 4, 0u);
+    if (prec != SAL_FP32) {
+        for (long mt = 0; mt < MT; ++mt)
+            for (long j = 0; j < J; ++j)
+                for (long lane = 0; lane < 64; ++lane) {
+                    const long g = lane / 16, i = lane % 16;
+                    for (long e = 0; e < 8; ++e) {
+                        const long q = 8 * j + 4 * (g & 1) + e / 2, ci = e & 1;
+                        const uint16_t v = part(wc[(16 * mt + i) * 2 * L + 2 * q + ci], (int)(g >> 1));
+                        c16[((mt * J + j) * 64 + lane) * 4 + e / 2] |= (uint32_t)v << (16 * (e & 1));
+                    }
+                }
+        for (long mt = 0; mt < MTA; ++mt)
+            for (long lane = 0; lane < 64; ++lane) {
+                const long g = lane / 16, i = lane % 16;
+                for (long e = 0; e < 8; ++e) {
+                    const long p = 4 * g + e / 2;
+                    const double w = (p < L) ? wa[(16 * mt + i) * L + p] : 0.0;
+                    const uint16_t v = part(w, (int)(e & 1));
+                    a16[(mt * 64 + lane) * 4 + e / 2] |= (uint32_t)v << (16 * (e & 1));
+                }
+            }
     }
     hipError_t e;
     if ((e = upload(&c->t.w_c, wcf)) != hipSuccess) return e;
@@ -204,10 +225,8 @@ hipError_t build_tables(sal_ctx *c)
     if ((e = upload(&c->t.w_bin, wb)) != hipSuccess) return e;
     if ((e = upload(&c->t.twiddle, tw)) != hipSuccess) return e;
     if ((e = upload(&c->t.w_proj, wp)) != hipSuccess) return e;
-    for (int k = 0; k < 4; ++k) {
-        if ((e = upload(&c->t.w_c16[k], c16[k])) != hipSuccess) return e;
-        if ((e = upload(&c->t.w_a16[k], a16[k])) != hipSuccess) return e;
-    }
+    if ((e = upload(&c->t.w_c16, c16)) != hipSuccess) return e;
+    if ((e = upload(&c->t.w_a16, a16)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -219,11 +238,9 @@ void free_tables(sal_tables *t)
             (void)hipFree(*p);
             *p = nullptr;
         }
-    for (int k = 0; k < 4; ++k) {
-        if (t->w_c16[k]) (void)hipFree(t->w_c16[k]);
-        if (t->w_a16[k]) (void)hipFree(t->w_a16[k]);
-        t->w_c16[k] = t->w_a16[k] = nullptr;
-    }
+    if (t->w_c16) (void)hipFree(t->w_c16);
+    if (t->w_a16) (void)hipFree(t->w_a16);
+    t->w_c16 = t->w_a16 = nullptr;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -240,7 +257,7 @@ WsLayout ws_layout(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
     w.s_raw = w.e + align256(3 * N * sizeof(float));
     w.vmax = w.s_raw + align256(3 * N * sizeof(float));
     w.mm = w.vmax + align256((size_t)energy_num_blocks(c, n0, n1, n2) * sizeof(float));
-    w.stats = w.mm + align256((size_t)dcs_num_blocks(n0, n1, n2) * 6 * sizeof(float));
+    w.stats = w.mm + align256((size_t)dcs_num_blocks(c, n0, n1, n2) * 6 * sizeof(float));
     w.total = w.stats + align256(8 * sizeof(double));
     return w;
 }
@@ -315,13 +332,11 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
     for (int m = 0; m < 3; ++m)
         if (p->rays[m] == 0 || p->rays[m] > 63u)
             return fail(nullptr, SAL_E_INVAL, "each ray mask must be a nonempty subset of 6 rays");
-    if (p->precision < SAL_FP32 || p->precision > SAL_FP16_SPLIT)
+    if (p->precision < SAL_FP32 || p->precision > SAL_FP16_SPLITW)
         return fail(nullptr, SAL_E_INVAL, "unknown precision");
     if (!(p->zero_range >= 0.0)) return fail(nullptr, SAL_E_INVAL, "zero_range must be >= 0");
     if (p->L != 8 && p->L != 16)
         return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements L = 8 and L = 16");
-    if (p->precision != SAL_FP32)
-        return fail(nullptr, SAL_E_UNSUPPORTED, "precision form not built yet");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(nullptr, SAL_E_DEVICE, "no such HIP device");
@@ -459,7 +474,7 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     e = launch_dcs(c, E, n0, n1, n2, Sr, mm, s);
     if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
     if (ev) (void)hipEventRecord(ev[2], s);
-    e = launch_stats(vmax, nv, mm, dcs_num_blocks(n0, n1, n2), stats, s);
+    e = launch_stats(vmax, nv, mm, dcs_num_blocks(c, n0, n1, n2), stats, s);
     if (e != hipSuccess) return dev_fail(c, e, "stats launch");
     if (ev) (void)hipEventRecord(ev[3], s);
     e = launch_combine(Sr, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);

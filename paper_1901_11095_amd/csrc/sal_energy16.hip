@@ -1,0 +1,359 @@
+// Steps 1-3 of the saliency method (Shafiq et al., ICIP 2017, Sec. 2) with 16-bit MFMA
+// operands: BF16 or FP16 data, and the DFT matrix either rounded once or split into a
+// high and a low 16-bit part (W = W_hi + W_lo) whose two products are summed by the same
+// MFMA in FP32.  With DS (data split) every stage input is also split, d = d_hi + d_lo,
+// and a second MFMA adds the products with d_lo: four products W_{hi,lo} d_{hi,lo}, about
+// 16 significant bits per operand.  Everything else matches the FP32 kernel: three separable contractions
+// (t real -> half spectrum, x, y), the spectrum of each voxel kept in the accumulators,
+// projections and energies in FP32.
+//
+// Every stage rounds its input to 16 bits, so the data passed between stages lives in LDS
+// as packed 16-bit complex values (re in the low half).  Each stage output is scaled by
+// 1/L (exact, L a power of two) before rounding so FP16 keeps the input's range; the
+// projection weights carry the matching factor L^2.
+//
+// K order of a complex contraction (16x16x32 MFMA j covers taps 8j..8j+7):
+//   element e of lane group g: part s = g >> 1 (0: W_hi, 1: W_lo), tap 8j + 4(g & 1) + e/2,
+//   re|im = e & 1, so each lane's data operand is four consecutive complex taps, i.e. 16
+//   contiguous bytes of LDS, identical for the hi and lo halves.
+// K order of the t contraction: element e of lane group g: tap p = 4g + e/2, part e & 1.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cstdint>
+
+#include "sal_device.h"
+#include "sal_internal.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+template <typename T>
+struct Half16;
+template <>
+struct Half16<__bf16> {
+    static __device__ __forceinline__ f4 mma(u32x4 a, u32x4 b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    }
+    // round-to-nearest-even of both values, lo in bits 0..15
+    static __device__ __forceinline__ uint32_t pack(float lo, float hi)
+    {
+        const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    // the 16-bit value in bits 0..15 / 16..31 of a packed pair, as float
+    static __device__ __forceinline__ float lo_f(uint32_t p) { return __uint_as_float(p << 16); }
+    static __device__ __forceinline__ float hi_f(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+};
+template <>
+struct Half16<_Float16> {
+    static __device__ __forceinline__ f4 mma(u32x4 a, u32x4 b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ uint32_t pack(float lo, float hi)
+    {
+        const f16x2 v = {(_Float16)lo, (_Float16)hi};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    static __device__ __forceinline__ float lo_f(uint32_t p) { return (float)__builtin_bit_cast(f16x2, p)[0]; }
+    static __device__ __forceinline__ float hi_f(uint32_t p) { return (float)__builtin_bit_cast(f16x2, p)[1]; }
+};
+
+// Store the complex value (re, im) as packed 16-bit parts: hi = round(v), and with DS
+// also lo = round(v - hi) in the second array.
+template <bool DS, typename T>
+__device__ __forceinline__ void store_c(uint32_t *hi_arr, uint32_t *lo_arr, int idx, float re, float im)
+{
+    const uint32_t hi = Half16<T>::pack(re, im);
+    hi_arr[idx] = hi;
+    if (DS) lo_arr[idx] = Half16<T>::pack(re - Half16<T>::lo_f(hi), im - Half16<T>::hi_f(hi));
+}
+
+__device__ __forceinline__ u32x4 lds4(const uint32_t *p) { return u32x4{p[0], p[1], p[2], p[3]}; }
+
+}  // namespace
+
+template <int L, typename T, bool DS>
+__global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
+    const float *__restrict__ V, int n0, int n1, int n2, int tt_len, int nby, int nbx,
+    const uint32_t *__restrict__ w_c16, const uint32_t *__restrict__ w_a16,
+    const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
+{
+    using G = Geo<L>;
+    using C = TileCfg<L>;
+    using HT = Half16<T>;
+    constexpr int H = G::H, h = G::h, MT = G::MT, MTA = G::MTA;
+    constexpr int J = L / 8;  // 16x16x32 MFMAs per split complex contraction (K = 4L)
+    constexpr int NW = C::NW, TY = C::TY;
+    constexpr int PX = NW + L - 1, PY = TY + L - 1;
+    constexpr int NTB = (PY + 15) / 16, PYB = NTB * 16, NTC = TY / 16;
+    constexpr int NPOS = PX * PY, NTA = (NPOS + 15) / 16, NJ = (NTA + NW - 1) / NW;
+    constexpr int NGK = L / 2 + 1;
+    constexpr int NWB = C::W_LDS ? h * NGK * MT * 32 : 1;
+    constexpr float invL = 1.0f / (float)L;
+
+    constexpr int NP = DS ? 2 : 1;  // 16-bit parts stored per value
+    __shared__ uint32_t A_s[NP][h * PY * PX];
+    __shared__ uint32_t B_s[NW][NP][L * PYB];
+    __shared__ float wb_s[NWB];
+    __shared__ float red_s[NW];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
+    const int y_base = ty * TY, x_base = tx * NW;
+    const int t_begin = tb * tt_len;
+    const int t_end = min(n0, t_begin + tt_len);
+
+    u32x4 wc[MT][J], wa[MTA];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < J; ++j) wc[mt][j] = reinterpret_cast<const u32x4 *>(w_c16)[(mt * J + j) * 64 + lane];
+#pragma unroll
+    for (int mt = 0; mt < MTA; ++mt) wa[mt] = reinterpret_cast<const u32x4 *>(w_a16)[mt * 64 + lane];
+    if (C::W_LDS)
+        for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
+
+    int off_xy[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
+        const int xp = pos / PY, yp = pos - xp * PY;
+        off_xy[jj] = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
+    }
+    const int64_t plane = (int64_t)n1 * n2;
+    const int64_t nvox = plane * n0;
+    float vmax = 0.0f;
+    uint32_t *Bw = B_s[wave][0];
+    uint32_t *Bw_lo = B_s[wave][NP - 1];
+    const int qoff = 4 * (g & 1);
+
+    float vnext[NJ][4];
+    auto load_a = [&](int t0) {
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = 4 * g + e;
+                const int tr = refl_idx(t0 - H + p, n0);
+                vnext[jj][e] = (wave + NW * jj < NTA && p < L) ? V[tr * plane + off_xy[jj]] : 0.f;
+            }
+    };
+    load_a(t_begin);
+
+    for (int t0 = t_begin; t0 < t_end; ++t0) {
+        __syncthreads();
+        float vcur[NJ][4];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) vcur[jj][e] = vnext[jj][e];
+        if (t0 + 1 < t_end) load_a(t0 + 1);
+        // ---------------- stage A: real DFT along t -------------------------------------
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int tl = wave + NW * jj;
+            if (tl < NTA) {
+                u32x4 b, bl;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    vmax = fmaxf(vmax, fabsf(vcur[jj][e]));
+                    b[e] = HT::pack(vcur[jj][e], vcur[jj][e]);
+                    if (DS) {
+                        const float lo = vcur[jj][e] - HT::lo_f(b[e]);
+                        bl[e] = HT::pack(lo, lo);
+                    }
+                }
+                f4 acc[MTA];
+#pragma unroll
+                for (int mt = 0; mt < MTA; ++mt) {
+                    acc[mt] = HT::mma(wa[mt], b, f4{0.f, 0.f, 0.f, 0.f});
+                    if (DS) acc[mt] = HT::mma(wa[mt], bl, acc[mt]);
+                }
+                const int pos = tl * 16 + n;
+                if (pos < NPOS) {
+                    const int xp = pos / PY, yp = pos - xp * PY;
+#pragma unroll
+                    for (int mt = 0; mt < MTA; ++mt) {
+                        const int mu0 = 8 * mt + 2 * g;
+                        if (mu0 < h)
+                            store_c<DS, T>(A_s[0], A_s[NP - 1], (mu0 * PY + yp) * PX + xp, acc[mt][0] * invL, acc[mt][1] * invL);
+                        if (mu0 + 1 < h)
+                            store_c<DS, T>(A_s[0], A_s[NP - 1], ((mu0 + 1) * PY + yp) * PX + xp, acc[mt][2] * invL, acc[mt][3] * invL);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        float e[NTC][3];
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) e[c][0] = e[c][1] = e[c][2] = 0.f;
+        int grp = 0;
+#pragma unroll 1
+        for (int mu = 0; mu < h; ++mu) {
+            const bool self = (mu == 0 || mu == L / 2);
+            // ---------------- stage B: complex DFT along x for this mu ------------------
+#pragma unroll
+            for (int nb = 0; nb < NTB; ++nb) {
+                const int yp = min(nb * 16 + n, PY - 1);
+                f4 acc[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int ao = (mu * PY + yp) * PX + wave + 8 * j + qoff;
+                    const u32x4 b = lds4(&A_s[0][ao]);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
+                    if (DS) {
+                        const u32x4 bl = lds4(&A_s[NP - 1][ao]);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], bl, acc[mt]);
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int nu0 = 8 * mt + 2 * g;
+                    store_c<DS, T>(Bw, Bw_lo, nu0 * PYB + nb * 16 + n, acc[mt][0] * invL, acc[mt][1] * invL);
+                    store_c<DS, T>(Bw, Bw_lo, (nu0 + 1) * PYB + nb * 16 + n, acc[mt][2] * invL, acc[mt][3] * invL);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // ---------------- stage C: complex DFT along y, projections, energies -------
+#pragma unroll 1
+            for (int k = 0; k < NGK; ++k, ++grp) {
+                const bool pair = !self && k > 0 && k < L / 2;
+                float wv[MT][6];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int wo = ((grp * MT + mt) * 4 + g) * 8;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
+                }
+#pragma unroll
+                for (int c = 0; c < NTC; ++c) {
+                    const int y0 = c * 16 + n;
+                    f4 acc[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const int bo = k * PYB + y0 + 8 * j + qoff;
+                        const u32x4 b = lds4(&Bw[bo]);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
+                        if (DS) {
+                            const u32x4 bl = lds4(&Bw_lo[bo]);
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], bl, acc[mt]);
+                        }
+                    }
+                    float m0[MT], m1[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        m0[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
+                        m1[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                    }
+                    if (pair) {
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int j = 0; j < J; ++j) {
+                            const int bo = (L - k) * PYB + y0 + 8 * j + qoff;
+                            const u32x4 b = lds4(&Bw[bo]);
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
+                            if (DS) {
+                                const u32x4 bl = lds4(&Bw_lo[bo]);
+#pragma unroll
+                                for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], bl, acc[mt]);
+                            }
+                        }
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            m0[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
+                            m1[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                        }
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int m = 0; m < 3; ++m)
+                            e[c][m] = fmaf(wv[mt][3 + m], m1[mt], fmaf(wv[mt][m], m0[mt], e[c][m]));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        const int x = x_base + wave;
+#pragma unroll
+        for (int c = 0; c < NTC; ++c) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                float s = e[c][m];
+                s += __shfl_xor(s, 16);
+                s += __shfl_xor(s, 32);
+                e[c][m] = s;
+            }
+            const int y = y_base + c * 16 + n;
+            if (g == 0 && x < n1 && y < n2) {
+                const int64_t o = ((int64_t)t0 * n1 + x) * n2 + y;
+                E[o] = e[c][0];
+                E[nvox + o] = e[c][1];
+                E[2 * nvox + o] = e[c][2];
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    if (lane == 0) red_s[wave] = vmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = red_s[0];
+        for (int w = 1; w < NW; ++w) m = fmaxf(m, red_s[w]);
+        vmax_part[blockIdx.x] = m;
+    }
+}
+
+template <int L, typename T, bool DS>
+static hipError_t launch_h(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                           float *E, float *vmax_part, int nby, int nbx, int tt, int64_t nb,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL((k_energy_h<L, T, DS>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s,
+                       V, (int)n0, (int)n1, (int)n2, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
+                       c->t.w_bin, E, vmax_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy16(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                           float *E, float *vmax_part, int nby, int nbx, int tt, int64_t nb,
+                           hipStream_t s)
+{
+    const int p = c->p.precision;
+    const bool bf = p == SAL_BF16 || p == SAL_BF16_SPLIT || p == SAL_BF16_SPLITW;
+    const bool ds = p == SAL_BF16_SPLIT || p == SAL_FP16_SPLIT;
+#define SAL_LAUNCH_H(LL, TT, DD) launch_h<LL, TT, DD>(c, V, n0, n1, n2, E, vmax_part, nby, nbx, tt, nb, s)
+    if (c->L == 8) {
+        if (bf) return ds ? SAL_LAUNCH_H(8, __bf16, true) : SAL_LAUNCH_H(8, __bf16, false);
+        return ds ? SAL_LAUNCH_H(8, _Float16, true) : SAL_LAUNCH_H(8, _Float16, false);
+    }
+    if (bf) return ds ? SAL_LAUNCH_H(16, __bf16, true) : SAL_LAUNCH_H(16, __bf16, false);
+    return ds ? SAL_LAUNCH_H(16, _Float16, true) : SAL_LAUNCH_H(16, _Float16, false);
+#undef SAL_LAUNCH_H
+}

@@ -15,13 +15,14 @@ struct sal_tables {
                      // column (tap, re|im); used by the x and y contractions
     float *w_a;      // [16*MTA][L] real-input DFT along t: row (mu, re|im) for mu <= L/2,
                      // zero rows above
-    float *w_bin;    // per reduced-spectrum row, M tile, lane group: 8 floats holding the
-                     // projection weights (t, x, y) of the two bins a lane owns, times the
-                     // Hermitian multiplicity and 1/(L^3 (L^3-1)); DC has weight 0
+    float *w_bin;    // per weight group (mu, k <= L/2), M tile, lane group: 8 floats holding
+                     // the projection weights (t, x, y) of the two bins a lane owns, times
+                     // the Hermitian multiplicity and 1/(L^3 (L^3-1)); DC has weight 0
     float *twiddle;  // [L][2] exp(-2 pi i k / L), for the per-voxel spectra kernel
     float *w_proj;   // [L^3][4] projection weights / (L^3 - 1) of bin (mu,nu,om), DC = 0
-    uint16_t *w_c16[4];  // [2L][2L] DFT matrix as bf16 hi, bf16 lo, fp16 hi, fp16 lo
-    uint16_t *w_a16[4];  // [16*MTA][L] likewise for the t contraction
+    uint32_t *w_c16;  // 16-bit forms: per M tile, MFMA and lane, the eight 16-bit A-operand
+                      // values (W_hi | W_lo halves) of the x and y contractions
+    uint32_t *w_a16;  // likewise for the t contraction
 };
 
 struct sal_ctx {
@@ -52,10 +53,13 @@ struct dcs_args {
 hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
                          float *E, float *vmax_part, int *nparts, hipStream_t s);
 int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
+hipError_t launch_energy16(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                           float *E, float *vmax_part, int nby, int nbx, int tt, int64_t nb,
+                           hipStream_t s);
 
 hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
                       float *S_raw, float *minmax_part, hipStream_t s);
-int64_t dcs_num_blocks(int64_t n0, int64_t n1, int64_t n2);
+int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
 
 hipError_t launch_stats(const float *vmax_part, int64_t nv, const float *minmax_part,
                         int64_t nm, double *stats, hipStream_t s);

@@ -11,82 +11,35 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <climits>
 #include <cstdint>
 
+#include "sal_device.h"
 #include "sal_internal.h"
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-namespace {
-
-__device__ __forceinline__ f4 mfma4(float a, float b, f4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Reflect u into [0, n) without repeating the edge sample; exact for -(n-1) <= u <= 2(n-1).
-// The final clamp only matters for padding positions of edge tiles, whose results are
-// never stored.
-__device__ __forceinline__ int refl_idx(int u, int n)
-{
-    u = u < 0 ? -u : u;
-    u = u >= n ? 2 * (n - 1) - u : u;
-    return u < 0 ? 0 : (u >= n ? n - 1 : u);
-}
-
-// Workgroup -> tile order that keeps neighbouring tiles on one XCD: workgroups are
-// dispatched round-robin over the 8 XCDs, so workgroup b runs on XCD b % 8; giving each XCD
-// a contiguous range of tiles lets halo re-reads hit that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nblk)
-{
-    const int q = nblk >> 3;
-    if (bid >= (q << 3)) return bid;
-    return (bid & 7) * q + (bid >> 3);
-}
-
-template <int L>
-struct Geo {
-    static constexpr int H = L / 2;                         // window start = v - H
-    static constexpr int h = L / 2 + 1;                     // t frequencies kept (Hermitian half)
-    static constexpr int KS = (2 * L) / 4;                  // 16x16x4 steps of a complex contraction
-    static constexpr int MT = (2 * L) / 16;                 // 16-row tiles of (freq, re|im)
-    static constexpr int KSA = L / 4;                       // steps of the real t contraction
-    static constexpr int MTA = (2 * h + 15) / 16;           // row tiles of the t contraction
-    static constexpr int NR = (h - 2) * L + 2 * (L / 2 + 1);  // (mu, nu) rows kept
-};
-
-template <int L>
-struct TileCfg;
-template <>
-struct TileCfg<8> {
-    static constexpr int NW = 4, TY = 32;
-    static constexpr bool W_LDS = true;
-};
-template <>
-struct TileCfg<16> {
-    static constexpr int NW = 4, TY = 16;
-    static constexpr bool W_LDS = false;
-};
-
-}  // namespace
 
 // ------------------------------------------------------------------------------------
 // Steps 1-3, FP32.  One workgroup = NW waves owns a tile of NW x-rows by TY y-columns and
 // walks t over [t_begin, t_end).  For every t0:
 //   stage A (all waves): A[x', y', mu] = sum_p W[mu, p] V[t0 - H + p, x', y'] for the whole
-//            (NW + L - 1) x (TY + L - 1) patch, mu <= L/2, MFMA with N = 16 positions;
+//            (NW + L - 1) x (TY + L - 1) patch, mu <= L/2, MFMA with N = 16 positions (the
+//            volume samples of the next t0 are already in flight while this one computes);
 //   stage B (wave w, x-row x0 = w): per mu, B[nu, y'] = sum_q W[nu, q] A[x0 + q, y', mu];
+//            for mu in {0, L/2} the input is real and the imaginary K steps are skipped;
 //   stage C (wave w): per kept (mu, nu) row, F[om, y0] = sum_r W[om, r] B[nu, y0 + r], the
-//            window sum of 16 consecutive voxels as one 16x16 tile (y0 on N, (om, re|im)
-//            on M), never leaving the accumulators; each lane turns its two complex bins
+//            window sums of 16 consecutive voxels as one 16x16 tile (y0 on N, (om, re|im)
+//            on M) that never leaves the accumulators; each lane turns its two complex bins
 //            into magnitudes and folds them with the projection weights into E_t, E_x, E_y.
-// Rows (mu, nu) with mu in {0, L/2} keep nu <= L/2 only: the remaining bins are complex
-// conjugates of kept ones, and the weights carry the multiplicity.
+// Rows (mu, nu) with mu in {0, L/2} keep nu <= L/2 only: the other bins are complex
+// conjugates of kept ones; the weights carry the multiplicity.  For other mu, rows nu and
+// L - nu have identical projection weights (they depend on squared frequencies), so their
+// magnitudes are summed before weighting: one "group" per (mu, k), k = 0..L/2.
+// Floating-point MFMA and VALU work serialise on a SIMD on this chip, so the per-bin VALU
+// count (|F|^2, sqrt, three weighted sums) is kept minimal.
 template <int L>
 __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     const float *__restrict__ V, int n0, int n1, int n2, int tt_len, int nby, int nbx,
     const float *__restrict__ w_c, const float *__restrict__ w_a,
-    const float *__restrict__ w_bin, float *__restrict__ E, float *__restrict__ vmax_part)
+    const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
 {
     using G = Geo<L>;
     using C = TileCfg<L>;
@@ -95,7 +48,8 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     constexpr int PX = NW + L - 1, PY = TY + L - 1;
     constexpr int NTB = (PY + 15) / 16, PYB = NTB * 16, NTC = TY / 16;
     constexpr int NPOS = PX * PY, NTA = (NPOS + 15) / 16, NJ = (NTA + NW - 1) / NW;
-    constexpr int NWB = C::W_LDS ? G::NR * MT * 32 : 1;
+    constexpr int NGK = L / 2 + 1;  // groups per mu
+    constexpr int NWB = C::W_LDS ? h * NGK * MT * 32 : 1;
 
     __shared__ float2 A_s[NPOS * h];
     __shared__ float2 B_s[NW][L * PYB];
@@ -123,7 +77,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
 #pragma unroll
         for (int kk = 0; kk < KSA; ++kk) wa[mt][kk] = w_a[(16 * mt + n) * L + KSA * g + kk];
     if (C::W_LDS)
-        for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_bin[i];
+        for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
     // stage-A positions of this wave (fixed for the whole t walk)
     int off_xy[NJ];
@@ -139,8 +93,26 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     float vmax = 0.0f;
     float2 *Bw = B_s[wave];
 
+    float vnext[NJ][KSA];
+    auto load_a = [&](int t0) {
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+            for (int kk = 0; kk < KSA; ++kk) {
+                const int tr = refl_idx(t0 - H + KSA * g + kk, n0);
+                vnext[jj][kk] = (wave + NW * jj < NTA) ? V[tr * plane + off_xy[jj]] : 0.f;
+            }
+    };
+    load_a(t_begin);
+
     for (int t0 = t_begin; t0 < t_end; ++t0) {
         __syncthreads();  // previous t0 is done with A_s
+        float vcur[NJ][KSA];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+            for (int kk = 0; kk < KSA; ++kk) vcur[jj][kk] = vnext[jj][kk];
+        if (t0 + 1 < t_end) load_a(t0 + 1);
         // ---------------- stage A: real DFT along t -------------------------------------
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
@@ -151,8 +123,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
                 for (int mt = 0; mt < MTA; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kk = 0; kk < KSA; ++kk) {
-                    const int tr = refl_idx(t0 - H + KSA * g + kk, n0);
-                    const float v = V[tr * plane + off_xy[jj]];
+                    const float v = vcur[jj][kk];
                     vmax = fmaxf(vmax, fabsf(v));
 #pragma unroll
                     for (int mt = 0; mt < MTA; ++mt) acc[mt] = mfma4(wa[mt][kk], v, acc[mt]);
@@ -173,9 +144,10 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
         float e[NTC][3];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) e[c][0] = e[c][1] = e[c][2] = 0.f;
-        int row = 0;
+        int grp = 0;
 #pragma unroll 1
         for (int mu = 0; mu < h; ++mu) {
+            const bool self = (mu == 0 || mu == L / 2);  // real stage-A output
             // ---------------- stage B: complex DFT along x for this mu ------------------
 #pragma unroll
             for (int nb = 0; nb < NTB; ++nb) {
@@ -183,14 +155,22 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
                 f4 acc[MT];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+                if (self) {
 #pragma unroll
-                for (int kk = 0; kk < KS; kk += 2) {
-                    const int q = (KS * g + kk) >> 1;
-                    const float2 a = A_s[((wave + q) * PY + yp) * h + mu];
+                    for (int kk = 0; kk < KS; kk += 2) {
+                        const float a = A_s[((wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu].x;
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) {
-                        acc[mt] = mfma4(wc[mt][kk], a.x, acc[mt]);
-                        acc[mt] = mfma4(wc[mt][kk + 1], a.y, acc[mt]);
+                        for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma4(wc[mt][kk], a, acc[mt]);
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KS; kk += 2) {
+                        const float2 a = A_s[((wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu];
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            acc[mt] = mfma4(wc[mt][kk], a.x, acc[mt]);
+                            acc[mt] = mfma4(wc[mt][kk + 1], a.y, acc[mt]);
+                        }
                     }
                 }
 #pragma unroll
@@ -204,15 +184,15 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // ---------------- stage C: complex DFT along y, projections, energies -------
-            const int nuc = (mu == 0 || mu == L / 2) ? L / 2 + 1 : L;
 #pragma unroll 1
-            for (int nu = 0; nu < nuc; ++nu, ++row) {
+            for (int k = 0; k < NGK; ++k, ++grp) {
+                const bool pair = !self && k > 0 && k < L / 2;
                 float wv[MT][6];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
-                    const int wo = ((row * MT + mt) * 4 + g) * 8;
+                    const int wo = ((grp * MT + mt) * 4 + g) * 8;
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) wv[mt][k] = C::W_LDS ? wb_s[wo + k] : w_bin[wo + k];
+                    for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
                 }
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
@@ -222,24 +202,42 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
                     for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int kk = 0; kk < KS; kk += 2) {
-                        const int rr = (KS * g + kk) >> 1;
-                        const float2 b = Bw[nu * PYB + y0 + rr];
+                        const float2 b = Bw[k * PYB + y0 + ((KS * g + kk) >> 1)];
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
                             acc[mt] = mfma4(wc[mt][kk], b.x, acc[mt]);
                             acc[mt] = mfma4(wc[mt][kk + 1], b.y, acc[mt]);
                         }
                     }
+                    float m0[MT], m1[MT];
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) {
-                        const float m0 = __builtin_amdgcn_sqrtf(
-                            fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
-                        const float m1 = __builtin_amdgcn_sqrtf(
-                            fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                        m0[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
+                        m1[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                    }
+                    if (pair) {
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int kk = 0; kk < KS; kk += 2) {
+                            const float2 b = Bw[(L - k) * PYB + y0 + ((KS * g + kk) >> 1)];
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) {
+                                acc[mt] = mfma4(wc[mt][kk], b.x, acc[mt]);
+                                acc[mt] = mfma4(wc[mt][kk + 1], b.y, acc[mt]);
+                            }
+                        }
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            m0[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
+                            m1[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                        }
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                         for (int m = 0; m < 3; ++m)
-                            e[c][m] = fmaf(wv[mt][3 + m], m1, fmaf(wv[mt][m], m0, e[c][m]));
-                    }
+                            e[c][m] = fmaf(wv[mt][3 + m], m1[mt], fmaf(wv[mt][m], m0[mt], e[c][m]));
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -279,22 +277,22 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
 }
 
 // ------------------------------------------------------------------------------------
-// Step 4, Eq. (5): one thread per voxel; neighbours are read through the caches.
+// Step 4, Eq. (5): grid-stride over voxels, one voxel per thread and trip; neighbours are
+// read through the caches.  The bounded grid keeps the min/max partials few.
 __global__ __launch_bounds__(256) void k_dcs(const float *__restrict__ E, int n0, int n1, int n2,
                                              dcs_args a, float *__restrict__ S,
                                              float *__restrict__ mm_part)
 {
     const int64_t N = (int64_t)n0 * n1 * n2;
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-    if (v < N) {
+    const int dims[3] = {n0, n1, n2};
+    const int64_t stride[3] = {(int64_t)n1 * n2, n2, 1};
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256) {
         const int y = (int)(v % n2);
         const int64_t rest = v / n2;
         const int x = (int)(rest % n1);
         const int t = (int)(rest / n1);
         const int pos[3] = {t, x, y};
-        const int dims[3] = {n0, n1, n2};
-        const int64_t stride[3] = {(int64_t)n1 * n2, n2, 1};
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const float *Em = E + m * N;
@@ -312,8 +310,8 @@ __global__ __launch_bounds__(256) void k_dcs(const float *__restrict__ E, int n0
             }
             const float sv = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
             S[m * N + v] = sv;
-            mn[m] = sv;
-            mx[m] = sv;
+            mn[m] = fminf(mn[m], sv);
+            mx[m] = fmaxf(mx[m], sv);
         }
     }
     if (mm_part == nullptr) return;
@@ -339,6 +337,182 @@ __global__ __launch_bounds__(256) void k_dcs(const float *__restrict__ E, int n0
         mm_part[(int64_t)blockIdx.x * 6 + k] = r;
     }
 }
+
+// ------------------------------------------------------------------------------------
+// Step 4, Eq. (5), tiled: a workgroup owns DTX x DTY voxels in (x, y) and walks DTT values
+// of t.  For every component m it keeps in LDS a ring of 2*ht+1 planes of E_m (ht = r if
+// m has rays along t, else 0), each plane DTX x DTY plus a halo of r along x (y) when m has
+// rays along x (y).  Planes are stored at logical coordinates with the reflection applied
+// when they are loaded, so every neighbour of Eq. (5) is a plain LDS read.  With the
+// default rays each E value is read from memory about 1.4 times instead of 2r+1 times.
+constexpr int DTX = 8, DTY = 32, DTT = 32, DMAXE = 4;
+
+// R = r at compile time (unrolled neighbour loops), or 0 for any r.
+template <int R>
+__global__ __launch_bounds__(256) void k_dcs_tiled(const float *__restrict__ E, int n0, int n1,
+                                                   int n2, dcs_args a, int nbx, int nby,
+                                                   float *__restrict__ S,
+                                                   float *__restrict__ mm_part)
+{
+    extern __shared__ float lds[];
+    const int64_t plane = (int64_t)n1 * n2, N = plane * n0;
+    const int bid = blockIdx.x;
+    const int ty = bid % nby, tx = (bid / nby) % nbx, tb = bid / (nby * nbx);
+    const int x_base = tx * DTX, y_base = ty * DTY;
+    const int t_begin = tb * DTT, t_end = min(n0, t_begin + DTT);
+    const int tid = threadIdx.x, lx = tid / DTY, ly = tid % DTY;
+    const int x = x_base + lx, y = y_base + ly;
+    const bool valid = x < n1 && y < n2;
+    const int r = R > 0 ? R : a.r;
+    float g[R > 0 ? R : 32];
+#pragma unroll
+    for (int s = 0; s < (R > 0 ? R : 32); ++s) g[s] = a.g[s];
+
+    int ht[3], hx[3], hy[3], W[3], HW[3], depth[3], off[3];
+    int o = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        ht[m] = (a.rays[m] & 3u) ? r : 0;
+        hx[m] = (a.rays[m] & 12u) ? r : 0;
+        hy[m] = (a.rays[m] & 48u) ? r : 0;
+        W[m] = DTY + 2 * hy[m];
+        HW[m] = (DTX + 2 * hx[m]) * W[m];
+        depth[m] = 2 * ht[m] + 1;
+        off[m] = o;
+        o += depth[m] * HW[m];
+    }
+    // this thread's share of every plane: LDS offset and (reflected) volume offset
+    int gofs[3][DMAXE];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int e = 0; e < DMAXE; ++e) {
+            const int i = tid + 256 * e;
+            const int ix = i / W[m], iy = i - ix * W[m];
+            gofs[m][e] = i < HW[m] ? refl_idx(x_base - hx[m] + ix, n1) * n2 + refl_idx(y_base - hy[m] + iy, n2) : -1;
+        }
+    float pv[3][DMAXE];
+    auto fetch = [&](int m, int tl) {
+        const float *src = E + m * N + (int64_t)refl_idx(tl, n0) * plane;
+#pragma unroll
+        for (int e = 0; e < DMAXE; ++e) pv[m][e] = gofs[m][e] >= 0 ? src[gofs[m][e]] : 0.f;
+    };
+    auto store = [&](int m, int tl) {
+        float *pl = lds + off[m] + (tl % depth[m]) * HW[m];
+#pragma unroll
+        for (int e = 0; e < DMAXE; ++e)
+            if (gofs[m][e] >= 0) pl[tid + 256 * e] = pv[m][e];
+    };
+    // planes t_begin - ht .. t_begin + ht - 1 (logical t >= -r; shift by a multiple of
+    // depth keeps the slot index non-negative)
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        for (int tl = t_begin - ht[m]; tl < t_begin + ht[m]; ++tl) {
+            fetch(m, tl);
+            store(m, tl + 2 * depth[m]);
+        }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fetch(m, t_begin + ht[m]);
+
+    float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    for (int t = t_begin; t < t_end; ++t) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) store(m, t + ht[m]);
+        if (t + 1 < t_end) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) fetch(m, t + 1 + ht[m]);
+        }
+        __syncthreads();
+        if (valid) {
+            const int64_t ov = ((int64_t)t * n1 + x) * n2 + y;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const uint32_t rm = a.rays[m];
+                const float *ring = lds + off[m];
+                const int idx = (lx + hx[m]) * W[m] + ly + hy[m];
+                const int s0 = t % depth[m];  // slot of plane t; plane t+d sits in s0+d (mod depth)
+                const float *cpl = ring + s0 * HW[m] + idx;
+                const float c = cpl[0];
+                float sum = 0.f;
+                if (rm & 1u) {
+#pragma unroll
+                    for (int s = 1; s <= (R > 0 ? R : 32); ++s) {
+                        if (R == 0 && s > r) break;
+                        const int sl = s0 + s - (s0 + s >= depth[m] ? depth[m] : 0);
+                        sum += fabsf(c - g[s - 1] * ring[sl * HW[m] + idx]);
+                    }
+                }
+                if (rm & 2u) {
+#pragma unroll
+                    for (int s = 1; s <= (R > 0 ? R : 32); ++s) {
+                        if (R == 0 && s > r) break;
+                        const int sl = s0 - s + (s0 - s < 0 ? depth[m] : 0);
+                        sum += fabsf(c - g[s - 1] * ring[sl * HW[m] + idx]);
+                    }
+                }
+#pragma unroll
+                for (int ax = 1; ax < 3; ++ax) {
+                    const int step = ax == 1 ? W[m] : 1;
+                    if (rm & (4u << (2 * (ax - 1)))) {
+#pragma unroll
+                        for (int s = 1; s <= (R > 0 ? R : 32); ++s) {
+                            if (R == 0 && s > r) break;
+                            sum += fabsf(c - g[s - 1] * cpl[s * step]);
+                        }
+                    }
+                    if (rm & (8u << (2 * (ax - 1)))) {
+#pragma unroll
+                        for (int s = 1; s <= (R > 0 ? R : 32); ++s) {
+                            if (R == 0 && s > r) break;
+                            sum += fabsf(c - g[s - 1] * cpl[-s * step]);
+                        }
+                    }
+                }
+                const float sv = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
+                S[m * N + ov] = sv;
+                mn[m] = fminf(mn[m], sv);
+                mx[m] = fmaxf(mx[m], sv);
+            }
+        }
+        __syncthreads();
+    }
+    if (mm_part == nullptr) return;
+    const int lane = tid & 63, wave = tid >> 6;
+    float *red = lds;  // reuse: the walk is over
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+        for (int q = 32; q >= 1; q >>= 1) {
+            mn[m] = fminf(mn[m], __shfl_xor(mn[m], q));
+            mx[m] = fmaxf(mx[m], __shfl_xor(mx[m], q));
+        }
+        if (lane == 0) {
+            red[wave * 6 + 2 * m] = mn[m];
+            red[wave * 6 + 2 * m + 1] = mx[m];
+        }
+    }
+    __syncthreads();
+    if (tid < 6) {
+        float v = red[tid];
+        for (int w = 1; w < 4; ++w) v = (tid & 1) ? fmaxf(v, red[w * 6 + tid]) : fminf(v, red[w * 6 + tid]);
+        mm_part[(int64_t)bid * 6 + tid] = v;
+    }
+}
+
+// LDS floats the tiled comparison needs for these rays and r, or a huge value when a
+// plane does not fit the per-thread element budget.
+static int64_t dcs_tiled_lds_floats(const uint32_t rays[3], int r)
+{
+    int64_t tot = 0;
+    for (int m = 0; m < 3; ++m) {
+        const int ht = (rays[m] & 3u) ? r : 0, hx = (rays[m] & 12u) ? r : 0, hy = (rays[m] & 48u) ? r : 0;
+        const int64_t hw = (int64_t)(DTX + 2 * hx) * (DTY + 2 * hy);
+        if (hw > 256 * DMAXE) return INT64_MAX / 2;
+        tot += (2 * ht + 1) * hw;
+    }
+    return tot;
+}
+static const int64_t DCS_LDS_MAX_FLOATS = 64 * 1024 / 4;
 
 // ------------------------------------------------------------------------------------
 // FP64 volume-wide statistics {lo_t, hi_t, lo_x, hi_x, lo_y, hi_y, max|V|} from partials.
@@ -400,6 +574,34 @@ __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ S_raw
         }
     }
     S[v] = (float)acc;
+}
+
+// Same, four consecutive voxels per thread (N divisible by 4, 16-byte aligned maps).
+__global__ __launch_bounds__(256) void k_combine4(const float4 *__restrict__ S_raw, int64_t N4,
+                                                  const double *__restrict__ stats, double wa,
+                                                  double wb, double wc, int normalize,
+                                                  double zero_range, float4 *__restrict__ S)
+{
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= N4) return;
+    const double w[3] = {wa, wb, wc};
+    double lo[3], sc[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        lo[m] = normalize ? stats[2 * m] : 0.0;
+        const double range = stats[2 * m + 1] - stats[2 * m];
+        sc[m] = normalize ? (range > zero_range * stats[6] ? 1.0 / range : 0.0) : 1.0;
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const float4 x = S_raw[m * N4 + v];
+        acc[0] += w[m] * (((double)x.x - lo[m]) * sc[m]);
+        acc[1] += w[m] * (((double)x.y - lo[m]) * sc[m]);
+        acc[2] += w[m] * (((double)x.z - lo[m]) * sc[m]);
+        acc[3] += w[m] * (((double)x.w - lo[m]) * sc[m]);
+    }
+    S[v] = make_float4((float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]);
 }
 
 // ------------------------------------------------------------------------------------
@@ -533,6 +735,8 @@ static hipError_t launch_energy_L(const sal_ctx *c, const float *V, int64_t n0, 
     int64_t nb;
     energy_grid<L>(n0, n1, n2, &nby, &nbx, &tt, &nb);
     if (nparts) *nparts = (int)nb;
+    if (c->p.precision != SAL_FP32)
+        return launch_energy16(c, V, n0, n1, n2, E, vmax_part, nby, nbx, tt, nb, s);
     hipLaunchKernelGGL(k_energy_f32<L>, dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s, V,
                        (int)n0, (int)n1, (int)n2, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_bin,
                        E, vmax_part);
@@ -546,7 +750,13 @@ hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n
     return launch_energy_L<16>(c, V, n0, n1, n2, E, vmax_part, nparts, s);
 }
 
-int64_t dcs_num_blocks(int64_t n0, int64_t n1, int64_t n2) { return (n0 * n1 * n2 + 255) / 256; }
+int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
+{
+    if (dcs_tiled_lds_floats(c->p.rays, c->r) <= DCS_LDS_MAX_FLOATS)
+        return ((n1 + DTX - 1) / DTX) * ((n2 + DTY - 1) / DTY) * ((n0 + DTT - 1) / DTT);
+    const int64_t nb = (n0 * n1 * n2 + 255) / 256;
+    return nb < 8192 ? nb : 8192;
+}
 
 hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
                       float *S_raw, float *minmax_part, hipStream_t s)
@@ -558,8 +768,24 @@ hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, 
         a.Q[m] = c->Q[m];
     }
     for (int i = 0; i < 32; ++i) a.g[i] = c->g[i];
-    hipLaunchKernelGGL(k_dcs, dim3((unsigned)dcs_num_blocks(n0, n1, n2)), dim3(256), 0, s, E,
-                       (int)n0, (int)n1, (int)n2, a, S_raw, minmax_part);
+    const int64_t nf = dcs_tiled_lds_floats(c->p.rays, c->r);
+    const unsigned nb = (unsigned)dcs_num_blocks(c, n0, n1, n2);
+    if (nf <= DCS_LDS_MAX_FLOATS) {
+        const size_t lds = (size_t)(nf > 24 ? nf : 24) * sizeof(float);
+        const int nbx = (int)((n1 + DTX - 1) / DTX), nby = (int)((n2 + DTY - 1) / DTY);
+        if (c->r == 4)
+            hipLaunchKernelGGL(k_dcs_tiled<4>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1,
+                               (int)n2, a, nbx, nby, S_raw, minmax_part);
+        else if (c->r == 8)
+            hipLaunchKernelGGL(k_dcs_tiled<8>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1,
+                               (int)n2, a, nbx, nby, S_raw, minmax_part);
+        else
+            hipLaunchKernelGGL(k_dcs_tiled<0>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1,
+                               (int)n2, a, nbx, nby, S_raw, minmax_part);
+    } else {
+        hipLaunchKernelGGL(k_dcs, dim3(nb), dim3(256), 0, s, E, (int)n0, (int)n1, (int)n2, a,
+                           S_raw, minmax_part);
+    }
     return hipGetLastError();
 }
 
@@ -574,6 +800,13 @@ hipError_t launch_combine(const float *S_raw, int64_t nvox, const double *stats,
                           double b, double c, int normalize, double zero_range, float *S,
                           hipStream_t s)
 {
+    if (nvox % 4 == 0) {
+        const int64_t n4 = nvox / 4;
+        hipLaunchKernelGGL(k_combine4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                           reinterpret_cast<const float4 *>(S_raw), n4, stats, a, b, c, normalize,
+                           zero_range, reinterpret_cast<float4 *>(S));
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_combine, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, s, S_raw,
                        nvox, stats, a, b, c, normalize, zero_range, S);
     return hipGetLastError();

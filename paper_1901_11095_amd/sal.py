@@ -15,7 +15,10 @@ import torch
 from .build import LIB as _LIB_PATH
 
 SAL_OK, SAL_E_INVAL, SAL_E_UNSUPPORTED, SAL_E_DEVICE, SAL_E_WORKSPACE = range(5)
-FP32, BF16, BF16_SPLIT, FP16, FP16_SPLIT = range(5)
+FP32, BF16, BF16_SPLIT, FP16, FP16_SPLIT, BF16_SPLITW, FP16_SPLITW = range(7)
+PRECISION_NAMES = {FP32: "fp32", BF16: "bf16", BF16_SPLIT: "bf16_split", FP16: "fp16",
+                   FP16_SPLIT: "fp16_split", BF16_SPLITW: "bf16_splitw",
+                   FP16_SPLITW: "fp16_splitw"}
 RAY_PT, RAY_MT, RAY_PX, RAY_MX, RAY_PY, RAY_MY = 1, 2, 4, 8, 16, 32
 RAYS_AXIS = (RAY_PT | RAY_MT, RAY_PX | RAY_MX, RAY_PY | RAY_MY)
 RAYS_ALL = (63, 63, 63)

@@ -1,0 +1,73 @@
+"""Precision forms of the DFT contractions (16-bit MFMA operands, FP32 accumulation)
+against the FP64 oracle.
+
+Error bound (max|gpu - oracle| / max|oracle| per map).  Every stage rounds its input to
+16 bits: unit roundoff u = 2^-8 (BF16) or 2^-11 (FP16) per sample.  The rounding errors of
+the large low-frequency values leak into every bin of the window's spectrum and, through
+the magnitude, add up with one sign over the hundreds of bins of an energy, so E keeps an
+error of order u/4 (a CPU emulation of the staged rounding gives 8.5e-4 for BF16 data and
+9e-5 for FP16 data on this volume).  Splitting the data as well (d = d_hi + d_lo) leaves
+about 2u^2, 1e-6 for BF16.  Eq. (5) and the normalisation can add a factor ~2.
+Bounds: split forms (matrix and data split) 1e-3 on every map, the target they are held
+to; matrix-only split 5e-3 (BF16) / 1e-3 (FP16); unsplit 8e-3 (BF16) / 2e-3 (FP16).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1901_11095_amd import sal, synth
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {sal.BF16_SPLIT: 1e-3, sal.FP16_SPLIT: 1e-3, sal.BF16_SPLITW: 5e-3,
+         sal.FP16_SPLITW: 1e-3, sal.BF16: 8e-3, sal.FP16: 2e-3}
+NAMES = sal.PRECISION_NAMES
+
+
+def relmax(got, ref):
+    return float(np.abs(np.asarray(got, np.float64) - ref).max() / np.abs(ref).max())
+
+
+@pytest.fixture(scope="module")
+def vol():
+    return synth.make_volume((28, 30, 45), seed=31, n_faults=1, n_chaotic=1, chaotic_size=12)
+
+
+@pytest.fixture(scope="module")
+def refs(vol):
+    return {L: O.saliency(vol, O.Params(L=L)) for L in (8, 16)}
+
+
+@pytest.mark.parametrize("L", [8, 16])
+@pytest.mark.parametrize("prec", [sal.BF16_SPLIT, sal.FP16_SPLIT, sal.BF16_SPLITW,
+                                  sal.FP16_SPLITW, sal.BF16, sal.FP16])
+def test_precision_form_error(vol, refs, L, prec):
+    ctx = sal.Saliency(L=L, precision=prec)
+    S, E, Sr, st = ctx.saliency_maps(torch.from_numpy(vol).cuda())
+    torch.cuda.synchronize()
+    ref = refs[L]
+    errs = {}
+    for m, name in enumerate("txy"):
+        errs["E_" + name] = relmax(E[m].cpu().numpy(), ref["E"][m])
+        errs["S_" + name] = relmax(Sr[m].cpu().numpy(), ref["S_raw"][m])
+    errs["S"] = relmax(S.cpu().numpy(), ref["S"])
+    print("L=%d %s errors: %s" % (L, NAMES[prec], {k: "%.2e" % v for k, v in errs.items()}))
+    assert max(errs.values()) <= BOUND[prec], errs
+
+
+@pytest.mark.parametrize("fam", ["bf16", "fp16"])
+def test_splitting_orders_the_errors(vol, refs, fam):
+    """Splitting the data removes the dominant rounding: the fully split form is far closer
+    than both the unsplit and the matrix-only forms (for BF16 the matrix rounding is small
+    next to the data rounding, so those two are close to each other)."""
+    V = torch.from_numpy(vol).cuda()
+    forms = ((sal.BF16, sal.BF16_SPLITW, sal.BF16_SPLIT) if fam == "bf16"
+             else (sal.FP16, sal.FP16_SPLITW, sal.FP16_SPLIT))
+    err = []
+    for prec in forms:
+        _, E, _, _ = sal.Saliency(L=8, precision=prec).saliency_maps(V)
+        err.append(max(relmax(E[m].cpu().numpy(), refs[8]["E"][m]) for m in range(3)))
+    assert err[2] < 0.05 * min(err[0], err[1]), err
+    if fam == "fp16":
+        assert err[0] > err[1], err
