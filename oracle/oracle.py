@@ -17,7 +17,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "sal_oracle.c")
+_SRCS = [os.path.join(_HERE, "sal_oracle.c"), os.path.join(_HERE, "net_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -33,11 +33,13 @@ RAYS_ALL = (63, 63, 63)
 
 
 def build(force: bool = False) -> str:
-    """Compile ``sal_oracle.c`` with gcc (FP64, OpenMP) into ``liboracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the C oracle (FP64, OpenMP) with gcc into ``liboracle.so``."""
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s)
+                                            for s in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -68,6 +70,14 @@ def lib() -> ctypes.CDLL:
         l.oracle_raw_box.argtypes = [_fp, _L, _L, _L, _L, _L, ctypes.c_double, _up, _lp, _lp,
                                      _dp, _dp]
         l.oracle_raw_box.restype = ctypes.c_int
+        l.oracle_gelu.argtypes = [ctypes.c_double]
+        l.oracle_gelu.restype = ctypes.c_double
+        l.oracle_gelu_grad.argtypes = [ctypes.c_double]
+        l.oracle_gelu_grad.restype = ctypes.c_double
+        l.oracle_conv3d.argtypes = [_dp, _L, _L, _L, _dp, _dp, _L, _dp]
+        l.oracle_conv3d_backward.argtypes = [_dp, _L, _L, _L, _dp, _L, _dp, _dp, _dp, _dp]
+        l.oracle_net_forward.argtypes = [_dp, _L, _L, _L, _lp, _dp, _dp, _dp]
+        l.oracle_net_backward.argtypes = [_dp, _L, _L, _L, _lp, _dp, _dp, _dp]
         _lib = l
     return _lib
 
@@ -209,3 +219,71 @@ def raw_box(V, p: Params, lo, bn):
                                _longs(lo), _longs(bn), _d(E), _d(S))
     assert bad == 0
     return E, S
+
+
+# ------------------------------------------------------------------ learned surrogate ----
+# Channel-last activations x[b][t][u][w][c] over crops of S^3; weights W[co][27][ci] with tap
+# k = (dt*3 + du)*3 + dw reading (t+dt-1, u+du-1, w+dw-1), reflected inside the crop.
+
+SURROGATE_CHANNELS = (1, 24, 24, 24, 24, 3)
+
+
+def gelu(z: float) -> float:
+    return lib().oracle_gelu(float(z))
+
+
+def gelu_grad(z: float) -> float:
+    return lib().oracle_gelu_grad(float(z))
+
+
+def conv3d(x, W, b=None):
+    """y = conv3d(x) + b with reflect padding inside each crop (FP64)."""
+    x = np.ascontiguousarray(x, np.float64)
+    W = np.ascontiguousarray(W, np.float64)
+    nb, S = x.shape[0], x.shape[1]
+    ci, co = x.shape[-1], W.shape[0]
+    y = np.zeros((nb, S, S, S, co), np.float64)
+    bb = None if b is None else np.ascontiguousarray(b, np.float64)
+    lib().oracle_conv3d(_d(x), nb, S, ci, _d(W), None if bb is None else _d(bb), co, _d(y))
+    return y
+
+
+def conv3d_backward(x, W, dy):
+    """(dx, dW, db) of sum(dy * conv3d(x)) -- the exact adjoint, reflect taps included."""
+    x = np.ascontiguousarray(x, np.float64)
+    W = np.ascontiguousarray(W, np.float64)
+    dy = np.ascontiguousarray(dy, np.float64)
+    nb, S, ci, co = x.shape[0], x.shape[1], x.shape[-1], W.shape[0]
+    dx = np.zeros_like(x)
+    dW = np.zeros_like(W)
+    db = np.zeros(co, np.float64)
+    lib().oracle_conv3d_backward(_d(x), nb, S, ci, _d(W), co, _d(dy), _d(dx), _d(dW), _d(db))
+    return dx, dW, db
+
+
+def net_num_params(ch=SURROGATE_CHANNELS) -> int:
+    return sum(ch[l + 1] * 27 * ch[l] + ch[l + 1] for l in range(len(ch) - 1))
+
+
+def net_forward(x, params, ch=SURROGATE_CHANNELS):
+    """Output of the conv/GELU stack for x[b][S][S][S][ch0]; params flat FP64 (per layer W
+    then bias)."""
+    x = np.ascontiguousarray(x, np.float64)
+    p = np.ascontiguousarray(params, np.float64)
+    nb, S = x.shape[0], x.shape[1]
+    y = np.zeros((nb, S, S, S, ch[-1]), np.float64)
+    cha = (ctypes.c_long * len(ch))(*ch)
+    lib().oracle_net_forward(_d(x), nb, S, len(ch) - 1, cha, _d(p), _d(y), None)
+    return y
+
+
+def net_backward(x, params, dy, ch=SURROGATE_CHANNELS):
+    """Gradient of sum(dy * net(x)) with respect to the flat parameter vector."""
+    x = np.ascontiguousarray(x, np.float64)
+    p = np.ascontiguousarray(params, np.float64)
+    dy = np.ascontiguousarray(dy, np.float64)
+    nb, S = x.shape[0], x.shape[1]
+    g = np.zeros_like(p)
+    cha = (ctypes.c_long * len(ch))(*ch)
+    lib().oracle_net_backward(_d(x), nb, S, len(ch) - 1, cha, _d(p), _d(dy), _d(g))
+    return g
