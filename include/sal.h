@@ -168,6 +168,76 @@ sal_status sal_saliency(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, in
 sal_status sal_profile_enable(sal_ctx *ctx, int on);
 sal_status sal_profile_read(sal_ctx *ctx, double ms[4], int64_t *calls, int reset);
 
+/*
+ * Steps 4b-5 on given raw maps S_raw float [3][n0][n1][n2]: the FP64 volume-wide statistics
+ * and the normalised combination of Eq. (6) (same arithmetic as sal_saliency).  V (optional,
+ * float [n0][n1][n2]) supplies max|V| for the zero-contrast rule; NULL uses 1.  stats_out:
+ * optional DEVICE double [SAL_STATS_LEN].  workspace: at least sal_workspace_size() bytes.
+ */
+sal_status sal_normalize_combine(sal_ctx *ctx, const float *V, const float *S_raw, int64_t n0,
+                                 int64_t n1, int64_t n2, float *S, double *stats_out,
+                                 void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Tile check of a predicted raw map against the plain method: over the tile
+ * [tile_lo, tile_lo + tile_dims) of S_raw (float [3][n0][n1][n2]) and the same voxels of
+ * `exact` (float [3][c0][c1][c2], the plain method's raw maps on the crop starting at
+ * crop_lo), err = max over voxels and components m of |pred - exact| / (hi_m - lo_m) with
+ * the range from `stats` (DEVICE double [SAL_STATS_LEN], e.g. of the predicted map).  Writes
+ * err to *err_out (DEVICE float) and, when err > bound, overwrites the tile of S_raw with
+ * the exact values.  The tile must lie inside both the volume and the crop.
+ */
+sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, int64_t n2,
+                          const float *exact, const int64_t crop_lo[3], const int64_t crop_dims[3],
+                          const int64_t tile_lo[3], const int64_t tile_dims[3],
+                          const double *stats, double bound, float *err_out, void *stream);
+
+/* ------------------------------------------------------------------------------------
+ * Learned surrogate (not part of the paper's method): five 3x3x3 convolutions, channels
+ * 1 -> 24 -> 24 -> 24 -> 24 -> 3 with GELU between them, predicting the raw maps
+ * S_t, S_x, S_y of Eq. (5) from the volume; BF16 weights/activations, FP32 accumulation,
+ * FP32 master weights trained with Adam.  The normalisation and Eq. (6) stay exact
+ * (sal_normalize_combine).  Activations are channel-last over nb blocks of n0 x n1 x n2
+ * voxels; convolution taps are reflected inside each block.  Parameters are one flat FP32
+ * vector: for each layer, W[co][27][ci] (tap k = (dt*3+du)*3+dw reads (t+dt-1, u+du-1,
+ * w+dw-1)) then the bias[co].  A sal_net owns its device buffers; not thread-safe.
+ */
+typedef struct sal_net sal_net;
+
+int64_t sal_net_num_params(void);
+const char *sal_net_last_error(const sal_net *net);
+/* Kaiming-uniform weights from `seed`, zero biases. */
+sal_status sal_net_create(int device, uint64_t seed, sal_net **out);
+void sal_net_destroy(sal_net *net);
+/* Copy the FP32 master parameters to (write = 0) or from (write = 1) host memory. */
+sal_status sal_net_params(sal_net *net, float *host, int64_t count, int write);
+/* Copy the accumulated FP32 gradient to host memory; zero it when zero != 0 (synchronises). */
+sal_status sal_net_grads(sal_net *net, float *host, int64_t count, int zero);
+/* Inference output = network output * scale[c] (the training targets are divided by it). */
+sal_status sal_net_set_output_scale(sal_net *net, const float scale[3]);
+/* Device workspace of sal_net_forward/backward/train_step (train != 0) or sal_net_infer. */
+sal_status sal_net_workspace_size(sal_net *net, int64_t nb, int64_t n0, int64_t n1, int64_t n2,
+                                  int train, size_t *bytes);
+/* Forward pass: X float [nb][n0][n1][n2] -> Y float [nb][n0][n1][n2][3]; keeps the
+ * activations in the workspace for sal_net_backward. */
+sal_status sal_net_forward(sal_net *net, const float *X, int64_t nb, int64_t n0, int64_t n1,
+                           int64_t n2, float *Y, void *workspace, size_t ws_bytes, void *stream);
+/* Backward pass after sal_net_forward on the same X and workspace: adds the gradient of
+ * sum(dY * Y) to the net's gradient.  Exact only when dY vanishes within 5 voxels of every
+ * block face (the input gradient uses zero padding). */
+sal_status sal_net_backward(sal_net *net, const float *X, const float *dY, int64_t nb, int64_t n0,
+                            int64_t n1, int64_t n2, void *workspace, size_t ws_bytes,
+                            void *stream);
+/* One Adam step (lr, betas 0.9/0.999, eps 1e-8) on the mean squared error between the
+ * network output and T float [nb][S][S][S][3] over the voxels at least `margin` (>= 5)
+ * from every face of their S^3 block.  loss_out: optional DEVICE float. */
+sal_status sal_net_train_step(sal_net *net, const float *X, const float *T, int64_t nb, int64_t S,
+                              int32_t margin, float lr, float *loss_out, void *workspace,
+                              size_t ws_bytes, void *stream);
+/* Whole-volume inference: V float [n0][n1][n2] -> S_raw float [3][n0][n1][n2]. */
+sal_status sal_net_infer(sal_net *net, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                         float *S_raw, void *workspace, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

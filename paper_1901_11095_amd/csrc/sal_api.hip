@@ -483,6 +483,61 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     return SAL_OK;
 }
 
+sal_status sal_normalize_combine(sal_ctx *c, const float *V, const float *S_raw, int64_t n0, int64_t n1,
+                                 int64_t n2, float *S, double *stats_out, void *workspace, size_t ws_bytes,
+                                 void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!S_raw || !S || !workspace) return fail(c, SAL_E_INVAL, "null pointer");
+    if (!aligned16(S_raw) || !aligned16(S) || !aligned16(workspace) || (V && !aligned16(V)) ||
+        (stats_out && !aligned16(stats_out)))
+        return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    const WsLayout w = ws_layout(c, n0, n1, n2);
+    if (ws_bytes < w.total) return fail(c, SAL_E_WORKSPACE, "workspace too small");
+    DevScope ds(c->device);
+    if ((st = sticky(c)) != SAL_OK) return st;
+    const int64_t N = n0 * n1 * n2, nb = merge_red_blocks(N);
+    char *ws = (char *)workspace;
+    float *mm = (float *)(ws + w.e);
+    float *vmax = (float *)(ws + w.e + align256((size_t)nb * 6 * sizeof(float)));
+    double *stats = stats_out ? stats_out : (double *)(ws + w.stats);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_minmax_absmax(V, S_raw, N, mm, vmax, s);
+    if (e == hipSuccess) e = launch_stats(vmax, nb, mm, nb, stats, s);
+    if (e == hipSuccess)
+        e = launch_combine(S_raw, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);
+    if (e != hipSuccess) return dev_fail(c, e, "normalize/combine launch");
+    return SAL_OK;
+}
+
+sal_status sal_tile_merge(sal_ctx *c, float *S_raw, int64_t n0, int64_t n1, int64_t n2, const float *exact,
+                          const int64_t crop_lo[3], const int64_t crop_dims[3], const int64_t tile_lo[3],
+                          const int64_t tile_dims[3], const double *stats, double bound, float *err_out,
+                          void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!S_raw || !exact || !crop_lo || !crop_dims || !tile_lo || !tile_dims || !stats || !err_out)
+        return fail(c, SAL_E_INVAL, "null pointer");
+    const int64_t n[3] = {n0, n1, n2};
+    for (int a = 0; a < 3; ++a) {
+        if (tile_dims[a] < 1 || tile_lo[a] < 0 || tile_lo[a] + tile_dims[a] > n[a])
+            return fail(c, SAL_E_INVAL, "tile outside the volume");
+        if (crop_dims[a] < 1 || crop_lo[a] < 0 || tile_lo[a] < crop_lo[a] ||
+            tile_lo[a] + tile_dims[a] > crop_lo[a] + crop_dims[a])
+            return fail(c, SAL_E_INVAL, "tile outside the crop");
+    }
+    if (!(bound >= 0.0)) return fail(c, SAL_E_INVAL, "bound must be >= 0");
+    DevScope ds(c->device);
+    sal_status st;
+    if ((st = sticky(c)) != SAL_OK) return st;
+    hipError_t e = launch_tile_merge(S_raw, n0, n1, n2, exact, crop_lo, crop_dims, tile_lo, tile_dims, stats,
+                                     bound, err_out, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(c, e, "tile merge launch");
+    return SAL_OK;
+}
+
 sal_status sal_profile_enable(sal_ctx *c, int on)
 {
     if (!c) return fail(c, SAL_E_INVAL, "null context");

@@ -68,6 +68,14 @@ hipError_t launch_combine(const float *S_raw, int64_t nvox, const double *stats,
                           double b, double c, int normalize, double zero_range, float *S,
                           hipStream_t s);
 
+int64_t merge_red_blocks(int64_t N);
+hipError_t launch_minmax_absmax(const float *V, const float *S_raw, int64_t N, float *mm_part,
+                                float *vmax_part, hipStream_t s);
+hipError_t launch_tile_merge(float *S_raw, int64_t n0, int64_t n1, int64_t n2, const float *exact,
+                             const int64_t crop_lo[3], const int64_t crop_dims[3],
+                             const int64_t tile_lo[3], const int64_t tile_dims[3],
+                             const double *stats, double bound, float *err, hipStream_t s);
+
 hipError_t launch_local_spectra(const sal_ctx *c, const float *V, int64_t n0, int64_t n1,
                                 int64_t n2, const int64_t lo[3], const int64_t bn[3],
                                 float *out, hipStream_t s);

@@ -26,7 +26,11 @@ STATS_LEN = 7
 
 EXPORTS = ("sal_default_params", "sal_create", "sal_destroy", "sal_last_error",
            "sal_workspace_size", "sal_local_spectra", "sal_project", "sal_directional_compare",
-           "sal_saliency", "sal_profile_enable", "sal_profile_read")
+           "sal_saliency", "sal_profile_enable", "sal_profile_read", "sal_normalize_combine",
+           "sal_tile_merge", "sal_net_num_params", "sal_net_last_error", "sal_net_create",
+           "sal_net_destroy", "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
+           "sal_net_workspace_size", "sal_net_forward", "sal_net_backward", "sal_net_train_step",
+           "sal_net_infer")
 KERNELS = ("energy", "dcs", "stats", "combine")
 
 
@@ -76,9 +80,33 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     l.sal_profile_enable.argtypes = [vp, ctypes.c_int]
     l.sal_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    i64, sz, fp = ctypes.c_int64, ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)
+    l.sal_normalize_combine.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, sz, vp]
+    l.sal_tile_merge.argtypes = [vp, vp, i64, i64, i64, vp, _i64p, _i64p, _i64p, _i64p, vp,
+                                 ctypes.c_double, vp, vp]
+    l.sal_net_num_params.argtypes = []
+    l.sal_net_num_params.restype = i64
+    l.sal_net_last_error.argtypes = [vp]
+    l.sal_net_last_error.restype = ctypes.c_char_p
+    l.sal_net_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(vp)]
+    l.sal_net_destroy.argtypes = [vp]
+    l.sal_net_destroy.restype = None
+    l.sal_net_params.argtypes = [vp, fp, i64, ctypes.c_int]
+    l.sal_net_grads.argtypes = [vp, fp, i64, ctypes.c_int]
+    l.sal_net_set_output_scale.argtypes = [vp, fp]
+    l.sal_net_workspace_size.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int,
+                                         ctypes.POINTER(sz)]
+    l.sal_net_forward.argtypes = [vp, vp, i64, i64, i64, i64, vp, vp, sz, vp]
+    l.sal_net_backward.argtypes = [vp, vp, vp, i64, i64, i64, i64, vp, sz, vp]
+    l.sal_net_train_step.argtypes = [vp, vp, vp, i64, i64, ctypes.c_int32, ctypes.c_float, vp,
+                                     vp, sz, vp]
+    l.sal_net_infer.argtypes = [vp, vp, i64, i64, i64, vp, vp, sz, vp]
     for f in ("sal_create", "sal_workspace_size", "sal_local_spectra", "sal_project",
               "sal_directional_compare", "sal_saliency", "sal_profile_enable",
-              "sal_profile_read"):
+              "sal_profile_read", "sal_normalize_combine", "sal_tile_merge", "sal_net_create",
+              "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
+              "sal_net_workspace_size", "sal_net_forward", "sal_net_backward",
+              "sal_net_train_step", "sal_net_infer"):
         getattr(l, f).restype = ctypes.c_int
     _lib = l
     return l
@@ -227,3 +255,132 @@ class Saliency:
         st = torch.empty(STATS_LEN + 1, dtype=torch.float64, device=V.device)
         S = self.saliency(V, E_out=E, S_raw_out=Sr, stats_out=st)
         return S, E, Sr, st[:STATS_LEN]
+
+
+def _i64x3(v):
+    return (ctypes.c_int64 * 3)(*[int(x) for x in v])
+
+
+def normalize_combine(ctx: "Saliency", S_raw: torch.Tensor, V: Optional[torch.Tensor] = None,
+                      S: Optional[torch.Tensor] = None, stats_out: Optional[torch.Tensor] = None):
+    """Exact FP64 statistics and Eq. (6) on given raw maps [3, n0, n1, n2] (CUDA float32)."""
+    if not (S_raw.is_cuda and S_raw.dtype == torch.float32 and S_raw.is_contiguous()):
+        raise ValueError("S_raw must be a contiguous float32 CUDA tensor")
+    shape = tuple(S_raw.shape[1:])
+    if S is None:
+        S = torch.empty(shape, dtype=torch.float32, device=S_raw.device)
+    ws = ctx.workspace(shape)
+    ctx._raise(ctx._lib.sal_normalize_combine(ctx._h, _ptr(V), _ptr(S_raw), *shape, _ptr(S),
+                                              _ptr(stats_out), _ptr(ws), ws.numel(),
+                                              _stream(S_raw.device)))
+    return S
+
+
+def tile_merge(ctx: "Saliency", S_raw: torch.Tensor, exact: torch.Tensor, crop_lo, tile_lo,
+               tile_dims, stats: torch.Tensor, bound: float, err_out: torch.Tensor):
+    """Check the tile of S_raw against `exact` (raw maps of the crop at crop_lo) and replace
+    it when max |pred - exact| / range > bound.  err_out: CUDA float32 [>=1]."""
+    shape = tuple(S_raw.shape[1:])
+    ctx._raise(ctx._lib.sal_tile_merge(ctx._h, _ptr(S_raw), *shape, _ptr(exact), _i64x3(crop_lo),
+                                       _i64x3(exact.shape[1:]), _i64x3(tile_lo), _i64x3(tile_dims),
+                                       _ptr(stats), float(bound), _ptr(err_out),
+                                       _stream(S_raw.device)))
+
+
+class Net:
+    """The learned surrogate (five 3x3x3 conv layers, 24 channels, GELU) in HIP kernels."""
+
+    def __init__(self, seed: int = 0, device: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        st = self._lib.sal_net_create(device, int(seed), ctypes.byref(h))
+        if st != SAL_OK:
+            raise SalError(st, self._lib.sal_net_last_error(None).decode())
+        self._h = h
+        self.device = torch.device("cuda", device)
+        self.num_params = int(self._lib.sal_net_num_params())
+        self._ws = None
+        self.out_scale = (1.0, 1.0, 1.0)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sal_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        if st != SAL_OK:
+            raise SalError(st, self._lib.sal_net_last_error(self._h).decode())
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.num_params, np.float32)
+        self._raise(self._lib.sal_net_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                             self.num_params, 0))
+        return a
+
+    def set_params(self, a):
+        import numpy as np
+        a = np.ascontiguousarray(a, np.float32)
+        self._raise(self._lib.sal_net_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                             self.num_params, 1))
+
+    def grads(self, zero: bool = True):
+        import numpy as np
+        a = np.zeros(self.num_params, np.float32)
+        self._raise(self._lib.sal_net_grads(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            self.num_params, int(zero)))
+        return a
+
+    def set_output_scale(self, scale):
+        self.out_scale = tuple(float(s) for s in scale)
+        arr = (ctypes.c_float * 3)(*self.out_scale)
+        self._raise(self._lib.sal_net_set_output_scale(self._h, arr))
+
+    def workspace(self, nb, shape, train: bool):
+        n = ctypes.c_size_t()
+        self._raise(self._lib.sal_net_workspace_size(self._h, int(nb), *[int(s) for s in shape],
+                                                     int(train), ctypes.byref(n)))
+        if self._ws is None or self._ws.numel() < n.value:
+            self._ws = None
+            self._ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        """X [nb, n0, n1, n2] float32 -> Y [nb, n0, n1, n2, 3] (activations kept)."""
+        nb, shape = X.shape[0], tuple(X.shape[1:])
+        Y = torch.empty(X.shape + (3,), dtype=torch.float32, device=X.device)
+        ws = self.workspace(nb, shape, True)
+        self._raise(self._lib.sal_net_forward(self._h, _ptr(X), nb, *shape, _ptr(Y), _ptr(ws),
+                                              ws.numel(), _stream(X.device)))
+        return Y
+
+    def backward(self, X: torch.Tensor, dY: torch.Tensor):
+        nb, shape = X.shape[0], tuple(X.shape[1:])
+        ws = self.workspace(nb, shape, True)
+        self._raise(self._lib.sal_net_backward(self._h, _ptr(X), _ptr(dY.contiguous()), nb, *shape,
+                                               _ptr(ws), ws.numel(), _stream(X.device)))
+
+    def train_step(self, X: torch.Tensor, T: torch.Tensor, margin: int, lr: float,
+                   loss_out: Optional[torch.Tensor] = None):
+        nb, S = X.shape[0], X.shape[1]
+        ws = self.workspace(nb, (S, S, S), True)
+        self._raise(self._lib.sal_net_train_step(self._h, _ptr(X), _ptr(T), nb, S, int(margin),
+                                                 float(lr), _ptr(loss_out), _ptr(ws), ws.numel(),
+                                                 _stream(X.device)))
+
+    def infer(self, V: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Predicted raw maps [3, n0, n1, n2] of a whole volume."""
+        _check_vol(V)
+        shape = tuple(V.shape)
+        if out is None:
+            out = torch.empty((3,) + shape, dtype=torch.float32, device=V.device)
+        ws = self.workspace(1, shape, False)
+        self._raise(self._lib.sal_net_infer(self._h, _ptr(V), *shape, _ptr(out), _ptr(ws),
+                                            ws.numel(), _stream(V.device)))
+        return out
