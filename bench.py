@@ -56,7 +56,7 @@ def traffic_from_profiles(kernel_tag: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(V, L: int, sample_shape=(96, 128, 128)):
+def cpu_baseline(V, L: int, sample_shape=(160, 192, 192)):
     """The FP64 oracle (unmodified) on a bounded sub-block of the same volume: energies on
     the block plus the comparison halo, Eq. (5) and the normalised combination."""
     import numpy as np
@@ -95,6 +95,112 @@ def parity_sample(V, S, E, Sr, stats, L: int, seed: int = 7, b: int = 24):
             "S": rel(S[sl].cpu().numpy(), Sref), "block": [list(lo), [b, b, b]]}
 
 
+def time_form(ctx, Vg, steps, warmup):
+    """Average ms per sal_saliency pass and per-kernel ms (HIP events) for one context."""
+    import torch
+    S = torch.empty_like(Vg)
+    ws = ctx.workspace(Vg.shape)
+    for _ in range(warmup):
+        ctx.saliency(Vg, S=S, workspace=ws)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.saliency(Vg, S=S, workspace=ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms, n = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    return 1e3 * elapsed / steps, {k: v / max(n, 1) for k, v in kms.items()}
+
+
+def sampled_error(ctx, V, Vg, L, seed=7, b=24):
+    import torch
+    dev = Vg.device
+    shp = (3,) + tuple(Vg.shape)
+    E = torch.empty(shp, dtype=torch.float32, device=dev)
+    Sr = torch.empty(shp, dtype=torch.float32, device=dev)
+    st = torch.empty(8, dtype=torch.float64, device=dev)
+    S = ctx.saliency(Vg, E_out=E, S_raw_out=Sr, stats_out=st)
+    torch.cuda.synchronize()
+    err = parity_sample(V, S, E, Sr, st, L, seed=seed, b=b)
+    del E, Sr
+    return err
+
+
+def surrogate_leg(args, dev):
+    """Learned surrogate on the held-out 512^3 volume (cube 16): inference, seeded 2% tile
+    check with split-BF16 fallback, exact normalisation; against the plain FP32 method."""
+    import numpy as np
+    import torch
+    from paper_1901_11095_amd import sal, surrogate, synth
+    print("# surrogate: generating held-out %d^3 volume" % args.sur_n, file=sys.stderr, flush=True)
+    V = torch.from_numpy(synth.make_volume(**surrogate.volume_kwargs(99, (args.sur_n,) * 3))).to(dev)
+    N = V.numel()
+    net = surrogate.load()
+    ctx_plain = sal.Saliency(L=16)
+    ctx_fb = sal.Saliency(L=16, precision=sal.BF16_SPLIT)
+    S_raw = torch.empty((3,) + tuple(V.shape), dtype=torch.float32, device=dev)
+    for _ in range(max(1, args.warmup // 2)):
+        res = surrogate.infer_with_fallback(net, ctx_fb, V, S_raw=S_raw)
+    torch.cuda.synchronize()
+    steps = max(2, args.steps // 4)
+    print("# surrogate: timing %d passes" % steps, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = surrogate.infer_with_fallback(net, ctx_fb, V, S_raw=S_raw)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / steps
+    # the plain method on the same volume, FP32 and split-BF16
+    print("# surrogate: plain method on the same volume", file=sys.stderr, flush=True)
+    ms_plain, _ = time_form(ctx_plain, V, 2, 1)
+    ms_fb, _ = time_form(ctx_fb, V, 2, 1)
+    st_ref = torch.zeros(8, dtype=torch.float64, device=dev)
+    Sr_ref = torch.empty_like(S_raw)
+    S_ref = ctx_plain.saliency(V, S_raw_out=Sr_ref, stats_out=st_ref)
+    pred = net.infer(V)
+    rng = (st_ref[1:6:2] - st_ref[0:6:2]).float().reshape(3, 1, 1, 1)
+    raw_err = ((pred - Sr_ref).abs() / rng).amax(0)
+    t = 32
+    n0, n1, n2 = V.shape
+    tmax = raw_err.reshape(n0 // t, t, n1 // t, t, n2 // t, t).amax(dim=(1, 3, 5))
+    S_pre = sal.normalize_combine(ctx_plain, pred.contiguous(), V)
+    dS_pre = (S_pre - S_ref).abs()
+    dS = (res["S"] - S_ref).abs()
+    # the exact map of the checked tiles is within the bound by construction; report it
+    checked_err = []
+    for lo, td in res["tiles"]:
+        sl = tuple(slice(a, a + d) for a, d in zip(lo, td))
+        checked_err.append(float(dS[sl].max()))
+    flops = 2 * 47952  # multiply-adds of the five convolutions per voxel
+    net.infer(V, out=pred)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        net.infer(V, out=pred)
+    torch.cuda.synchronize()
+    t_net = (time.perf_counter() - t0) / 3
+    net_tf = flops * N / t_net / 1e12
+    return {
+        "voxels_per_s": N / t_sur, "ms": 1e3 * t_sur, "L": 16, "volume": [args.sur_n] * 3,
+        "tile": 32, "checked_tiles": len(res["tiles"]), "n_tiles": res["n_tiles"],
+        "checked_over_bound": int((res["tile_err"] > 0.02).sum()), "bound": 0.02,
+        "speedup_vs_plain_fp32": ms_plain / (1e3 * t_sur), "plain_fp32_ms": ms_plain,
+        "speedup_vs_plain_bf16_split": ms_fb / (1e3 * t_sur), "plain_bf16_split_ms": ms_fb,
+        "tiles_within_bound_before_fallback": float((tmax <= 0.02).float().mean()),
+        "S_abs_err_vs_plain_fp32": {"max": float(dS.max()), "mean": float(dS.mean()),
+                                    "max_on_checked_tiles": max(checked_err),
+                                    "max_before_fallback": float(dS_pre.max()),
+                                    "mean_before_fallback": float(dS_pre.mean())},
+        "net_inference_ms": 1e3 * t_net,
+        "roofline": {"bound": "mfma", "achieved": net_tf, "peak": PEAK_TFLOPS["bf16"],
+                     "unit": "TFLOP/s", "frac": net_tf / PEAK_TFLOPS["bf16"],
+                     "kernel": "k_conv3 (five layers, network inference only)",
+                     "flops_per_voxel": flops},
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,7 +209,10 @@ def main(argv=None):
     ap.add_argument("--workload", default="survey256x512x512")
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle checks")
+    ap.add_argument("--no-forms", action="store_true", help="only the FP32 form")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned surrogate leg")
+    ap.add_argument("--sur-n", type=int, default=512, help="side of the surrogate's volume")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -113,7 +222,6 @@ def main(argv=None):
               "(use --gpus 1)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
     from paper_1901_11095_amd import build as B
     from paper_1901_11095_amd import sal, synth
@@ -135,47 +243,44 @@ def main(argv=None):
     N = V.size
     Vg = torch.from_numpy(V).to(dev)
     ctx = sal.Saliency(L=args.L)
-    S = torch.empty_like(Vg)
-    ws = ctx.workspace(Vg.shape)
-    print("# warmup %d" % args.warmup, file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        ctx.saliency(Vg, S=S, workspace=ws)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
-    print("# timing %d steps" % args.steps, file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.saliency(Vg, S=S, workspace=ws)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kms, ncalls = ctx.profile_read(reset=True)
-    ctx.profile(False)
-    elapsed = t1 - t0
-    value = N * args.steps / elapsed
-    ms_step = 1e3 * elapsed / args.steps
+    print("# fp32: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    ms_step, kms = time_form(ctx, Vg, args.steps, args.warmup)
+    value = N / (ms_step * 1e-3)
 
-    e_ms = kms["energy"] / max(ncalls, 1)
-    flops = dft_flops_per_voxel(args.L) * N
-    achieved = flops / (e_ms * 1e-3) / 1e12
+    fpv = dft_flops_per_voxel(args.L)
+    e_ms = kms["energy"]
+    achieved = fpv * N / (e_ms * 1e-3) / 1e12
     tag = "energy_f32_L%d_%s" % (args.L, args.workload)
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic_from_profiles(tag),
-            "kernel": "k_energy_f32<%d>" % args.L, "kernel_ms": e_ms,
-            "flops_per_voxel": dft_flops_per_voxel(args.L),
-            "kernels_ms": {k: v / max(ncalls, 1) for k, v in kms.items()}}
+            "kernel": "k_energy_f32<%d>" % args.L, "kernel_ms": e_ms, "flops_per_voxel": fpv,
+            "kernels_ms": kms}
 
     err = None
     if not args.no_check:
-        print("# sampled oracle check", file=sys.stderr, flush=True)
-        shp = (3,) + tuple(Vg.shape)
-        E = torch.empty(shp, dtype=torch.float32, device=dev)
-        Sr = torch.empty(shp, dtype=torch.float32, device=dev)
-        st = torch.empty(8, dtype=torch.float64, device=dev)
-        ctx.saliency(Vg, S=S, E_out=E, S_raw_out=Sr, stats_out=st, workspace=ws)
-        torch.cuda.synchronize()
-        err = parity_sample(V, S, E, Sr, st, args.L)
-        del E, Sr
+        print("# fp32: sampled oracle check", file=sys.stderr, flush=True)
+        err = sampled_error(ctx, V, Vg, args.L)
+
+    forms = {}
+    if not args.no_forms:
+        for prec in (sal.BF16_SPLIT, sal.FP16_SPLITW, sal.FP16_SPLIT, sal.BF16, sal.FP16):
+            name = sal.PRECISION_NAMES[prec]
+            print("# form %s" % name, file=sys.stderr, flush=True)
+            c = sal.Saliency(L=args.L, precision=prec)
+            ms_f, km = time_form(c, Vg, max(3, args.steps // 4), 2)
+            dt = "bf16" if "bf16" in name else "f16"
+            ach = fpv * N / (km["energy"] * 1e-3) / 1e12
+            forms[name] = {
+                "voxels_per_s": N / (ms_f * 1e-3), "ms_per_step": ms_f,
+                "speedup_vs_fp32": ms_step / ms_f, "kernels_ms": km,
+                "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[dt],
+                             "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[dt],
+                             "kernel": "k_energy_h<%d>" % args.L},
+                "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, args.L),
+            }
+            del c
+    if not args.no_surrogate:
+        forms["surrogate"] = surrogate_leg(args, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -192,6 +297,7 @@ def main(argv=None):
                    "parallelism": "none (1 GPU)"},
         "max_rel_err_vs_oracle": err,
         "roofline": roof,
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

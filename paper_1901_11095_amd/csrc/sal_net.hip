@@ -35,6 +35,7 @@ constexpr int TT = 4, TU = 4, TW = 16;                  // output tile of a work
 constexpr int PT = TT + 2, PU = TU + 2, PW = TW + 2;    // input tile with the 1-voxel halo
 constexpr int NPOS = PT * PU * PW;
 constexpr int WG_BLOCKS = 512;                          // workgroups of the weight-gradient pass
+constexpr unsigned CONV_BLOCKS = 2048;                  // persistent workgroups of a convolution
 
 enum { MODE_REFLECT = 0, MODE_ZERO = 1 };
 enum { EPI_GELU = 0, EPI_LINEAR = 1, EPI_DGELU = 2 };
@@ -108,16 +109,10 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, n = lane & 15;
     const int ntw = (n2 + TW - 1) / TW, ntu = (n1 + TU - 1) / TU, ntt = (n0 + TT - 1) / TT;
-    int bid = blockIdx.x;
-    const int tw_ = bid % ntw;
-    bid /= ntw;
-    const int tu_ = bid % ntu;
-    bid /= ntu;
-    const int tt_ = bid % ntt;
-    const int b = bid / ntt;
-    const int t0 = tt_ * TT, u0 = tu_ * TU, w0 = tw_ * TW;
+    const int ntiles = nb * ntt * ntu * ntw;
     const int64_t vol = (int64_t)n0 * n1 * n2;
 
+    // the weights stay in registers while the workgroup walks its tiles
     u32x4 A[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -125,21 +120,50 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
         for (int s = 0; s < KS; ++s)
             A[mt][s] = reinterpret_cast<const u32x4 *>(wtab)[((mt * 16 + n) * KS * 32 + s * 32 + 8 * g) / 8];
 
-    // input tile with halo
+#pragma unroll 1
+    for (int tile_id = blockIdx.x; tile_id < ntiles; tile_id += gridDim.x) {
+    int bid = tile_id;
+    const int tw_ = bid % ntw;
+    bid /= ntw;
+    const int tu_ = bid % ntu;
+    bid /= ntu;
+    const int tt_ = bid % ntt;
+    const int b = bid / ntt;
+    const int t0 = tt_ * TT, u0 = tu_ * TU, w0 = tw_ * TW;
+    __syncthreads();  // the previous tile is no longer read
+
+    // input tile with halo: one row of PW positions per (pt, pu)
     if (CI == 1) {
         const float *src = reinterpret_cast<const float *>(in) + b * vol;
         for (int p = threadIdx.x; p < NPOS; p += 256) {
-            const int pt = p / (PU * PW), pu = (p / PW) % PU, pw = p % PW;
+            const int row = p / PW, pw = p - row * PW;
+            const int pt = row / PU, pu = row - pt * PU;
             const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE),
                       gw = map_idx(w0 - 1 + pw, n2, MODE);
             const float v = (gt < 0 || gu < 0 || gw < 0) ? 0.f : src[((int64_t)gt * n1 + gu) * n2 + gw];
             tile[p] = f2bf(v);
         }
+    } else if (CI % 8 == 0) {
+        // 16-byte chunks of 8 channels
+        constexpr int CHK = CIP / 8, ROWLEN = PW * CHK;
+        const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
+        for (int i = threadIdx.x; i < PT * PU * ROWLEN; i += 256) {
+            const int row = i / ROWLEN, j = i - row * ROWLEN;
+            const int pw = j / CHK, ch = j - pw * CHK;
+            const int pt = row / PU, pu = row - pt * PU;
+            const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE),
+                      gw = map_idx(w0 - 1 + pw, n2, MODE);
+            u32x4 val = u32x4{0u, 0u, 0u, 0u};
+            if (gt >= 0 && gu >= 0 && gw >= 0)
+                val = *reinterpret_cast<const u32x4 *>(src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch);
+            *reinterpret_cast<u32x4 *>(&tile[(row * PW + pw) * CIP + 8 * ch]) = val;
+        }
     } else {
         const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
         for (int i = threadIdx.x; i < NPOS * CIP; i += 256) {
             const int p = i / CIP, c = i - p * CIP;
-            const int pt = p / (PU * PW), pu = (p / PW) % PU, pw = p % PW;
+            const int row = p / PW, pw = p - row * PW;
+            const int pt = row / PU, pu = row - pt * PU;
             const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE),
                       gw = map_idx(w0 - 1 + pw, n2, MODE);
             tile[i] = (c >= CI || gt < 0 || gu < 0 || gw < 0)
@@ -234,6 +258,7 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
             }
         }
     }
+    }  // tile loop
 }
 
 // ------------------------------------------------------------------------------------
@@ -529,7 +554,10 @@ void conv(const void *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, const 
           const float *bias, const uint16_t *zprev, void *o0, void *o1, int64_t vs, int64_t cs,
           hipStream_t s, float3 oscale = make_float3(1.f, 1.f, 1.f))
 {
-    hipLaunchKernelGGL((k_conv3<CI, CO, MODE, EPI>), dim3(conv_grid(nb, n0, n1, n2)), dim3(256), 0, s,
+    // persistent workgroups: a few per CU, each walking tiles with its weights in registers
+    const unsigned tiles = conv_grid(nb, n0, n1, n2);
+    const unsigned grid = tiles < CONV_BLOCKS ? tiles : CONV_BLOCKS;
+    hipLaunchKernelGGL((k_conv3<CI, CO, MODE, EPI>), dim3(grid), dim3(256), 0, s,
                        in, (int)nb, (int)n0, (int)n1, (int)n2, w, bias, zprev, o0, o1, vs, cs, oscale);
 }
 

@@ -1,0 +1,183 @@
+"""Learned surrogate of the saliency method: training driver, checkpoints, and inference
+with tile checks and exact fallback.  The arithmetic runs in libsal's HIP kernels
+(sal_net_*, sal_saliency, sal_tile_merge, sal_normalize_combine); this module only
+selects windows and tiles and moves tensors.
+
+Training pairs.  The plain method (cube L = 16, FP32) gives the raw directional maps
+S_t, S_x, S_y of seeded synthetic volumes.  A pair is a voxel v with its label S_m(v) and
+the 16^3 window around it.  The network is run on 16^3 windows; its output at a voxel
+depends on the 11^3 neighbourhood (five 3^3 layers), so the 6^3 centre of every window is
+labelled and each window carries 216 pairs.  Targets are divided by the per-component
+standard deviation over the training volumes; inference multiplies it back.
+
+Fallback.  After inference a seeded sample of tiles is recomputed by the plain method on a
+crop (tile plus L voxels of context, which holds every sample the tile's exact values
+depend on) and any tile whose error exceeds the bound (max |pred - exact| over the
+component's range) is replaced by the exact values before the exact FP64 normalisation
+and Eq. (6).  Tiles outside the sample are not verified.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from dataclasses import asdict, dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import sal, synth
+
+WINDOW = 16
+MARGIN = 5
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                       "surrogate_L16.safetensors")
+
+
+@dataclass
+class TrainConfig:
+    L: int = 16
+    n_volumes: int = 8
+    shape: tuple = (256, 256, 256)
+    seeds: tuple = (10, 11, 12, 13, 14, 15, 16, 17)
+    pairs_per_epoch: int = 2_000_000
+    epochs: int = 8
+    batch: int = 64
+    lr: float = 2e-3
+    lr_min: float = 1e-4
+    window_seed: int = 18
+    init_seed: int = 0
+    history: list = field(default_factory=list)
+
+
+def volume_kwargs(seed: int, shape) -> dict:
+    """Training/held-out volumes: faults, a chaotic body and noise, sized to the shape."""
+    side = min(shape)
+    return dict(shape=tuple(shape), seed=int(seed), n_faults=3, n_chaotic=1,
+                chaotic_size=max(8, side // 4), snr_db=10.0)
+
+
+def exact_raw_maps(ctx: sal.Saliency, V: torch.Tensor) -> torch.Tensor:
+    """Plain-method raw maps [3, n0, n1, n2] of a device volume."""
+    Sr = torch.empty((3,) + tuple(V.shape), dtype=torch.float32, device=V.device)
+    ctx.saliency(V, S_raw_out=Sr)
+    return Sr
+
+
+def make_training_set(cfg: TrainConfig, device="cuda"):
+    """Volumes and their exact raw maps, on the device."""
+    ctx = sal.Saliency(L=cfg.L)
+    vols, labels = [], []
+    for s in cfg.seeds[:cfg.n_volumes]:
+        V = torch.from_numpy(synth.make_volume(**volume_kwargs(s, cfg.shape))).to(device)
+        vols.append(V)
+        labels.append(exact_raw_maps(ctx, V))
+    torch.cuda.synchronize()
+    return vols, labels
+
+
+def _windows(vols, labels, pos, scale):
+    """Gather windows (X [B, W, W, W]) and channel-last targets (T [B, W, W, W, 3])."""
+    X, T = [], []
+    for (i, t, x, y) in pos:
+        X.append(vols[i][t:t + WINDOW, x:x + WINDOW, y:y + WINDOW])
+        T.append(labels[i][:, t:t + WINDOW, x:x + WINDOW, y:y + WINDOW])
+    X = torch.stack(X).contiguous()
+    T = (torch.stack(T).permute(0, 2, 3, 4, 1) / scale).contiguous()
+    return X, T
+
+
+def train(cfg: TrainConfig, net: Optional[sal.Net] = None, log=print):
+    """Train the network; returns (net, cfg with the loss history and scale)."""
+    vols, labels = make_training_set(cfg)
+    scale = torch.stack([torch.cat([lb[m].flatten() for lb in labels]).std() for m in range(3)])
+    scale = scale.reshape(1, 1, 1, 1, 3).float()
+    net = net or sal.Net(seed=cfg.init_seed)
+    net.set_output_scale(scale.flatten().tolist())
+    per_window = (WINDOW - 2 * MARGIN) ** 3
+    n_windows = math.ceil(cfg.pairs_per_epoch / per_window)
+    steps_per_epoch = math.ceil(n_windows / cfg.batch)
+    total = steps_per_epoch * cfg.epochs
+    rng = np.random.default_rng(cfg.window_seed)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    step = 0
+    t0 = time.time()
+    for ep in range(cfg.epochs):
+        acc = 0.0
+        for it in range(steps_per_epoch):
+            pos = [(int(rng.integers(0, len(vols))),) +
+                   tuple(int(rng.integers(0, n - WINDOW + 1)) for n in cfg.shape)
+                   for _ in range(cfg.batch)]
+            X, T = _windows(vols, labels, pos, scale)
+            lr = cfg.lr_min + 0.5 * (cfg.lr - cfg.lr_min) * (1 + math.cos(math.pi * step / total))
+            net.train_step(X, T, MARGIN, lr, loss_out=loss)
+            acc += float(loss.item()) if it % 16 == 0 else 0.0
+            step += 1
+        mean = acc / max(1, (steps_per_epoch + 15) // 16)
+        cfg.history.append(mean)
+        log("epoch %d/%d  loss %.4f  (%.1f s)" % (ep + 1, cfg.epochs, mean, time.time() - t0))
+    return net, cfg
+
+
+def save(net: sal.Net, cfg: TrainConfig, path: str = WEIGHTS):
+    from safetensors.numpy import save_file
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    meta = {"config": json.dumps({k: v for k, v in asdict(cfg).items()})}
+    save_file({"params": net.get_params(), "out_scale": np.asarray(net.out_scale, np.float32)},
+              path, metadata=meta)
+
+
+def load(path: str = WEIGHTS, device: int = 0) -> sal.Net:
+    from safetensors.numpy import load_file
+    d = load_file(path)
+    net = sal.Net(seed=0, device=device)
+    net.set_params(d["params"])
+    net.set_output_scale(d["out_scale"].tolist())
+    return net
+
+
+def tiles_of(shape, tile: int):
+    return [(t, x, y) for t in range(0, shape[0], tile) for x in range(0, shape[1], tile)
+            for y in range(0, shape[2], tile)]
+
+
+def infer_with_fallback(net: sal.Net, ctx_exact: sal.Saliency, V: torch.Tensor, tile: int = 32,
+                        frac: float = 0.02, bound: float = 0.02, seed: int = 0,
+                        S_raw: Optional[torch.Tensor] = None, check_extremes: bool = True):
+    """Surrogate maps, a seeded check of `frac` of the tiles (plus the tiles holding each
+    map's predicted extremes) against the plain method with exact replacement of the tiles
+    over `bound`, then the exact normalisation and Eq. (6).
+    Returns a dict with S, S_raw, stats, the checked tiles and their errors."""
+    shape = tuple(V.shape)
+    dev = V.device
+    S_raw = net.infer(V, out=S_raw)
+    stats = torch.zeros(8, dtype=torch.float64, device=dev)
+    S = sal.normalize_combine(ctx_exact, S_raw, V, stats_out=stats)
+    all_tiles = tiles_of(shape, tile)
+    k = max(1, int(round(frac * len(all_tiles))))
+    pick = set(np.random.default_rng(seed).choice(len(all_tiles), size=k, replace=False).tolist())
+    if check_extremes:
+        # the volume-wide minimum and maximum of every predicted map set the normalisation:
+        # their tiles are always checked
+        nt = [(n + tile - 1) // tile for n in shape]
+        for m in range(3):
+            for flat in (int(torch.argmax(S_raw[m])), int(torch.argmin(S_raw[m]))):
+                t, x, y = np.unravel_index(flat, shape)
+                pick.add(int((t // tile * nt[1] + x // tile) * nt[2] + y // tile))
+    halo = ctx_exact.L  # floor(L/2) window + floor(d/2) comparison reach, d = L
+    errs = torch.zeros(len(pick), dtype=torch.float32, device=dev)
+    checked = []
+    for j, ti in enumerate(sorted(pick)):
+        lo = all_tiles[ti]
+        td = tuple(min(tile, n - a) for a, n in zip(lo, shape))
+        clo = tuple(max(0, a - halo) for a in lo)
+        chi = tuple(min(n, a + d + halo) for a, d, n in zip(lo, td, shape))
+        crop = V[clo[0]:chi[0], clo[1]:chi[1], clo[2]:chi[2]].contiguous()
+        exact = exact_raw_maps(ctx_exact, crop)
+        sal.tile_merge(ctx_exact, S_raw, exact, clo, lo, td, stats, bound, errs[j:j + 1])
+        checked.append((lo, td))
+    S = sal.normalize_combine(ctx_exact, S_raw, V, S=S, stats_out=stats)
+    return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": checked, "tile_err": errs,
+            "n_tiles": len(all_tiles)}
