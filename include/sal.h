@@ -170,12 +170,13 @@ sal_status sal_profile_read(sal_ctx *ctx, double ms[4], int64_t *calls, int rese
 
 /*
  * Steps 4b-5 on given raw maps S_raw float [3][n0][n1][n2]: the FP64 volume-wide statistics
- * and the normalised combination of Eq. (6) (same arithmetic as sal_saliency).  V (optional,
- * float [n0][n1][n2]) supplies max|V| for the zero-contrast rule; NULL uses 1.  stats_out:
+ * and the normalised combination of Eq. (6) (same arithmetic as sal_saliency).  The scale of
+ * the zero-contrast rule is max|V| over V (float [n0][n1][n2]) when V is given, else the
+ * caller's vmax (> 0; e.g. reduced slab by slab when V is not resident).  stats_out:
  * optional DEVICE double [SAL_STATS_LEN].  workspace: at least sal_workspace_size() bytes.
  */
-sal_status sal_normalize_combine(sal_ctx *ctx, const float *V, const float *S_raw, int64_t n0,
-                                 int64_t n1, int64_t n2, float *S, double *stats_out,
+sal_status sal_normalize_combine(sal_ctx *ctx, const float *V, double vmax, const float *S_raw,
+                                 int64_t n0, int64_t n1, int64_t n2, float *S, double *stats_out,
                                  void *workspace, size_t ws_bytes, void *stream);
 
 /*

@@ -483,10 +483,11 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     return SAL_OK;
 }
 
-sal_status sal_normalize_combine(sal_ctx *c, const float *V, const float *S_raw, int64_t n0, int64_t n1,
-                                 int64_t n2, float *S, double *stats_out, void *workspace, size_t ws_bytes,
-                                 void *stream)
+sal_status sal_normalize_combine(sal_ctx *c, const float *V, double vmax_in, const float *S_raw, int64_t n0,
+                                 int64_t n1, int64_t n2, float *S, double *stats_out, void *workspace,
+                                 size_t ws_bytes, void *stream)
 {
+    if (!V && !(vmax_in > 0.0)) return fail(c, SAL_E_INVAL, "vmax must be > 0 when V is NULL");
     if (!c) return fail(c, SAL_E_INVAL, "null context");
     if (!S_raw || !S || !workspace) return fail(c, SAL_E_INVAL, "null pointer");
     if (!aligned16(S_raw) || !aligned16(S) || !aligned16(workspace) || (V && !aligned16(V)) ||
@@ -504,7 +505,7 @@ sal_status sal_normalize_combine(sal_ctx *c, const float *V, const float *S_raw,
     float *vmax = (float *)(ws + w.e + align256((size_t)nb * 6 * sizeof(float)));
     double *stats = stats_out ? stats_out : (double *)(ws + w.stats);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_minmax_absmax(V, S_raw, N, mm, vmax, s);
+    hipError_t e = launch_minmax_absmax(V, (float)vmax_in, S_raw, N, mm, vmax, s);
     if (e == hipSuccess) e = launch_stats(vmax, nb, mm, nb, stats, s);
     if (e == hipSuccess)
         e = launch_combine(S_raw, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);

@@ -69,8 +69,8 @@ hipError_t launch_combine(const float *S_raw, int64_t nvox, const double *stats,
                           hipStream_t s);
 
 int64_t merge_red_blocks(int64_t N);
-hipError_t launch_minmax_absmax(const float *V, const float *S_raw, int64_t N, float *mm_part,
-                                float *vmax_part, hipStream_t s);
+hipError_t launch_minmax_absmax(const float *V, float vmax, const float *S_raw, int64_t N,
+                                float *mm_part, float *vmax_part, hipStream_t s);
 hipError_t launch_tile_merge(float *S_raw, int64_t n0, int64_t n1, int64_t n2, const float *exact,
                              const int64_t crop_lo[3], const int64_t crop_dims[3],
                              const int64_t tile_lo[3], const int64_t tile_dims[3],

@@ -47,10 +47,11 @@ __global__ __launch_bounds__(256) void k_minmax3(const float *__restrict__ S, in
     }
 }
 
-// partial max|V| per workgroup (1 when V is absent)
-__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ V, int64_t N, float *__restrict__ part)
+// partial max|V| per workgroup (the given value when V is absent)
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ V, int64_t N, float vmax,
+                                                float *__restrict__ part)
 {
-    float m = V ? 0.f : 1.f;
+    float m = V ? 0.f : vmax;
     if (V)
         for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256)
             m = fmaxf(m, fabsf(V[v]));
@@ -119,12 +120,12 @@ int64_t merge_red_blocks(int64_t N)
     return nb < RED_BLOCKS ? nb : RED_BLOCKS;
 }
 
-hipError_t launch_minmax_absmax(const float *V, const float *S_raw, int64_t N, float *mm_part,
-                                float *vmax_part, hipStream_t s)
+hipError_t launch_minmax_absmax(const float *V, float vmax, const float *S_raw, int64_t N,
+                                float *mm_part, float *vmax_part, hipStream_t s)
 {
     const unsigned nb = (unsigned)merge_red_blocks(N);
     hipLaunchKernelGGL(k_minmax3, dim3(nb), dim3(256), 0, s, S_raw, N, mm_part);
-    hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(256), 0, s, V, N, vmax_part);
+    hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(256), 0, s, V, N, vmax, vmax_part);
     return hipGetLastError();
 }
 

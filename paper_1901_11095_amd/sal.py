@@ -81,7 +81,8 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     l.sal_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     i64, sz, fp = ctypes.c_int64, ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)
-    l.sal_normalize_combine.argtypes = [vp, vp, vp, i64, i64, i64, vp, vp, vp, sz, vp]
+    l.sal_normalize_combine.argtypes = [vp, vp, ctypes.c_double, vp, i64, i64, i64, vp, vp, vp, sz,
+                                        vp]
     l.sal_tile_merge.argtypes = [vp, vp, i64, i64, i64, vp, _i64p, _i64p, _i64p, _i64p, vp,
                                  ctypes.c_double, vp, vp]
     l.sal_net_num_params.argtypes = []
@@ -262,15 +263,17 @@ def _i64x3(v):
 
 
 def normalize_combine(ctx: "Saliency", S_raw: torch.Tensor, V: Optional[torch.Tensor] = None,
-                      S: Optional[torch.Tensor] = None, stats_out: Optional[torch.Tensor] = None):
-    """Exact FP64 statistics and Eq. (6) on given raw maps [3, n0, n1, n2] (CUDA float32)."""
+                      S: Optional[torch.Tensor] = None, stats_out: Optional[torch.Tensor] = None,
+                      vmax: float = 1.0):
+    """Exact FP64 statistics and Eq. (6) on given raw maps [3, n0, n1, n2] (CUDA float32);
+    max|V| from V when given, else `vmax`."""
     if not (S_raw.is_cuda and S_raw.dtype == torch.float32 and S_raw.is_contiguous()):
         raise ValueError("S_raw must be a contiguous float32 CUDA tensor")
     shape = tuple(S_raw.shape[1:])
     if S is None:
         S = torch.empty(shape, dtype=torch.float32, device=S_raw.device)
     ws = ctx.workspace(shape)
-    ctx._raise(ctx._lib.sal_normalize_combine(ctx._h, _ptr(V), _ptr(S_raw), *shape, _ptr(S),
+    ctx._raise(ctx._lib.sal_normalize_combine(ctx._h, _ptr(V), float(vmax), _ptr(S_raw), *shape, _ptr(S),
                                               _ptr(stats_out), _ptr(ws), ws.numel(),
                                               _stream(S_raw.device)))
     return S

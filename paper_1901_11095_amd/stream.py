@@ -1,0 +1,124 @@
+"""Volumes larger than one should keep resident: streamed through HBM in slabs along t.
+
+Every output voxel of the method depends on samples at most `halo` voxels away along each
+axis (floor(L/2) for the window plus floor(d/2) for the comparison of Eq. (5); 5 for the
+surrogate's five 3^3 layers), so a slab of rows [s0, s1) is computed exactly from the rows
+[s0 - halo, s1 + halo) clipped to the volume: reflection at a clipped face is the
+volume's own.  The raw maps of every slab are kept in HBM (3 floats per voxel) and the
+volume-wide FP64 statistics and Eq. (6) run once at the end.  Host-to-device copies of the
+next slab run on a second stream while the current slab computes (double-buffered pinned
+staging); max|V| for the zero-contrast rule is reduced slab by slab.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import sal, surrogate
+
+
+def pinned(V: np.ndarray) -> torch.Tensor:
+    """A page-locked host copy of the volume (allocated pinned, then filled)."""
+    t = torch.empty(V.shape, dtype=torch.float32, pin_memory=True)
+    t.numpy()[...] = V
+    return t
+
+
+def _slabs(n0: int, slab: int, halo: int):
+    for s0 in range(0, n0, slab):
+        s1 = min(n0, s0 + slab)
+        yield s0, s1, max(0, s0 - halo), min(n0, s1 + halo)
+
+
+def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
+                      S_raw: Optional[torch.Tensor] = None, device="cuda"):
+    """Raw maps [3, n0, n1, n2] (device) of a pinned host volume; `compute(Vslab)` returns
+    the raw maps [3, m, n1, n2] of a device slab [m, n1, n2].  Returns (S_raw, max|V|)."""
+    n0, n1, n2 = V_host.shape
+    dev = torch.device(device)
+    if S_raw is None:
+        S_raw = torch.empty((3, n0, n1, n2), dtype=torch.float32, device=dev)
+    rows = min(n0, slab + 2 * halo)
+    bufs = [torch.empty((rows, n1, n2), dtype=torch.float32, device=dev) for _ in range(2)]
+    comp = torch.cuda.current_stream(dev)
+    copy = torch.cuda.Stream(dev)
+    done = [torch.cuda.Event(), torch.cuda.Event()]     # buffer free again
+    ready = [torch.cuda.Event(), torch.cuda.Event()]    # buffer filled
+    slabs = list(_slabs(n0, slab, halo))
+    vmax = torch.zeros(len(slabs), dtype=torch.float32, device=dev)
+
+    def upload(i):
+        _, _, a, b = slabs[i]
+        k = i % 2
+        with torch.cuda.stream(copy):
+            if i >= 2:
+                copy.wait_event(done[k])
+            bufs[k][:b - a].copy_(V_host[a:b], non_blocking=True)
+            ready[k].record(copy)
+
+    upload(0)
+    for i, (s0, s1, a, b) in enumerate(slabs):
+        k = i % 2
+        if i + 1 < len(slabs):
+            upload(i + 1)
+        comp.wait_event(ready[k])
+        Vs = bufs[k][:b - a]
+        out = compute(Vs)
+        S_raw[:, s0:s1].copy_(out[:, s0 - a:s1 - a])
+        vmax[i] = Vs[s0 - a:s1 - a].abs().max()
+        done[k].record(comp)
+    return S_raw, float(vmax.max())
+
+
+def plain_streamed(ctx: sal.Saliency, V_host: torch.Tensor, slab: int = 64):
+    """The plain method on a host volume, slab by slab; returns (S, S_raw, stats)."""
+    halo = ctx.L // 2 + ctx.params.d // 2
+
+    def compute(Vs):
+        o = torch.empty((3,) + tuple(Vs.shape), dtype=torch.float32, device=Vs.device)
+        ctx.saliency(Vs, S_raw_out=o)
+        return o
+
+    S_raw, vmax = raw_maps_streamed(V_host, compute, halo, slab)
+    stats = torch.zeros(8, dtype=torch.float64, device=S_raw.device)
+    S = sal.normalize_combine(ctx, S_raw, None, stats_out=stats, vmax=vmax)
+    return S, S_raw, stats
+
+
+def surrogate_streamed(net: sal.Net, ctx_fallback: sal.Saliency, V_host: torch.Tensor,
+                       slab: int = 64, tile: int = 32, frac: float = 0.02, bound: float = 0.02,
+                       seed: int = 0):
+    """Surrogate first, slab by slab (halo 5), then the seeded tile check on crops copied
+    from the host volume with the plain method (ctx_fallback, e.g. split-BF16) and exact
+    replacement, then the FP64 normalisation and Eq. (6)."""
+
+    S_raw, vmax = raw_maps_streamed(V_host, net.infer, 5, slab)
+    dev = S_raw.device
+    shape = tuple(V_host.shape)
+    stats = torch.zeros(8, dtype=torch.float64, device=dev)
+    S = sal.normalize_combine(ctx_fallback, S_raw, None, stats_out=stats, vmax=vmax)
+    all_tiles = surrogate.tiles_of(shape, tile)
+    k = max(1, int(round(frac * len(all_tiles))))
+    pick = set(np.random.default_rng(seed).choice(len(all_tiles), size=k, replace=False).tolist())
+    nt = [(n + tile - 1) // tile for n in shape]
+    for m in range(3):
+        for flat in (int(torch.argmax(S_raw[m])), int(torch.argmin(S_raw[m]))):
+            t, x, y = np.unravel_index(flat, shape)
+            pick.add(int((t // tile * nt[1] + x // tile) * nt[2] + y // tile))
+    halo = ctx_fallback.L
+    errs = torch.zeros(len(pick), dtype=torch.float32, device=dev)
+    checked = []
+    for j, ti in enumerate(sorted(pick)):
+        lo = all_tiles[ti]
+        td = tuple(min(tile, n - a) for a, n in zip(lo, shape))
+        clo = tuple(max(0, a - halo) for a in lo)
+        chi = tuple(min(n, a + d + halo) for a, d, n in zip(lo, td, shape))
+        crop = V_host[clo[0]:chi[0], clo[1]:chi[1], clo[2]:chi[2]].contiguous().to(dev, non_blocking=True)
+        exact = surrogate.exact_raw_maps(ctx_fallback, crop)
+        sal.tile_merge(ctx_fallback, S_raw, exact, clo, lo, td, stats, bound, errs[j:j + 1])
+        checked.append((lo, td))
+    S = sal.normalize_combine(ctx_fallback, S_raw, None, S=S, stats_out=stats, vmax=vmax)
+    return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": checked, "tile_err": errs,
+            "n_tiles": len(all_tiles)}
