@@ -26,10 +26,16 @@ chunking.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 _SLAB = 32
+
+
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 def ricker(f_peak: float = 30.0, dt: float = 0.004) -> np.ndarray:
@@ -98,30 +104,42 @@ def make_volume(shape=(64, 64, 64), seed: int = 0, n_faults: int = 1, throw: int
     yy = np.arange(n2, dtype=np.float64)
 
     # --- per slab of axis-1 rows: reflectivity, faults, chaotic boxes, wavelet ---------
-    for s0 in range(0, n1, _SLAB):
+    # slabs are independent (their random fields come from per-slab generators), so they
+    # are filled by a thread pool; the result does not depend on the number of workers
+    def fill(s0):
         s1 = min(n1, s0 + _SLAB)
         xs = np.arange(s0, s1, dtype=np.float64)
-        refl = np.zeros((nt, s1 - s0, n2), np.float64)
         X = (xs[:, None] - n1 / 2.0)
         Y = (yy[None, :] - n2 / 2.0)
-        cols = np.arange((s1 - s0) * n2)
-        for b in range(len(depths)):
-            zb = depths[b] + gx[b] * X + gy[b] * Y - t_lo
-            i0 = np.floor(zb).astype(np.int64)
-            fr = zb - i0
-            for off, wgt in ((0, 1.0 - fr), (1, fr)):
-                it = (i0 + off).ravel()
-                ok = (it >= 0) & (it < nt)
-                flat = refl.reshape(nt, -1)
-                # one entry per column in each call, so plain fancy-index accumulation is exact
-                flat[it[ok], cols[ok]] += coeffs[b] * wgt.ravel()[ok]
-        tt = (np.arange(nt, dtype=np.float64) + t_lo)[:, None, None]
+        ncol = (s1 - s0) * n2
+        # every boundary adds to the two samples around its depth in each column; the adds
+        # are applied in boundary order (then upper sample first), as np.bincount sums its
+        # weights in the order of its index list
+        zb = (depths[:, None, None] + gx[:, None, None] * X[None] + gy[:, None, None] * Y[None]
+              - t_lo).reshape(len(depths), 1, ncol)
+        i0 = np.floor(zb).astype(np.int64)
+        fr = zb - i0
+        it = np.concatenate([i0, i0 + 1], axis=1)
+        val = coeffs[:, None, None] * np.concatenate([1.0 - fr, fr], axis=1)
+        lin = it * ncol + np.arange(ncol)
+        ok = (it >= 0) & (it < nt)
+        refl = np.bincount(lin[ok], weights=val[ok], minlength=nt * ncol).reshape(nt, s1 - s0, n2)
+        tt = np.arange(nt, dtype=np.float64) + t_lo
+        rows = np.arange(nt)[:, None, None]
         for nrm, p0 in faults:
-            side = (nrm[0] * (tt - p0[0]) + nrm[1] * (xs[None, :, None] - p0[1]) +
-                    nrm[2] * (yy[None, None, :] - p0[2])) > 0.0
-            shifted = np.zeros_like(refl)
-            shifted[throw:] = refl[:-throw] if throw > 0 else refl
-            refl = np.where(side, shifted, refl)
+            # hanging wall: nrm . (p - p0) > 0, summed in the order t, x, y.  With nrm[0] > 0
+            # the partial sum over t and x never decreases down a column, and a rounded sum
+            # of two doubles is positive exactly when the exact sum is, so the wall of each
+            # column is the rows from the first one whose t+x part exceeds minus the y part
+            tx = (nrm[0] * (tt - p0[0]))[:, None] + nrm[1] * (xs - p0[1])[None, :]
+            my = -(nrm[2] * (yy - p0[2]))
+            first = np.stack([np.searchsorted(tx[:, j], my, side="right")
+                              for j in range(s1 - s0)])
+            if throw > 0:
+                wall = rows >= first[None]
+                src = refl[:-throw].copy()
+                np.copyto(refl[throw:], src, where=wall[throw:])
+                refl[:throw][wall[:throw]] = 0.0
         for ib, (bt, bx, by, c) in enumerate(boxes):
             lo_x, hi_x = max(bx, s0), min(bx + c, s1)
             if lo_x >= hi_x:
@@ -129,19 +147,31 @@ def make_volume(shape=(64, 64, 64), seed: int = 0, n_faults: int = 1, throw: int
             r = _slab_rng(seed, 10 + ib, s0 // _SLAB)
             blk = r.standard_normal((c, hi_x - lo_x, c))
             refl[bt - t_lo:bt - t_lo + c, lo_x - s0:hi_x - s0, by:by + c] = blk
-        trace = np.zeros((n0, s1 - s0, n2), np.float64)
-        for k in range(-K, K + 1):
-            # trace[t] = sum_k wav[k] refl[t - k]
-            trace += wav[k + K] * refl[(0 - t_lo) - k:(n0 - t_lo) - k]
-        out[:, s0:s1, :] = trace.astype(np.float32)
+        # trace[t] = sum_k wav[k] refl[t - k], in blocks of rows that stay in cache
+        tb = max(1, (1 << 18) // ((s1 - s0) * n2))
+        tmp = np.empty((tb, s1 - s0, n2), np.float64)
+        for a in range(0, n0, tb):
+            b = min(n0, a + tb)
+            trace = np.zeros((b - a, s1 - s0, n2), np.float64)
+            for k in range(-K, K + 1):
+                np.multiply(refl[a - t_lo - k:b - t_lo - k], wav[k + K], out=tmp[:b - a])
+                trace += tmp[:b - a]
+            out[a:b, s0:s1, :] = trace
+
+    with ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(fill, range(0, n1, _SLAB)))
 
     # --- noise at the requested SNR, then unit variance ---------------------------------
     sig_var = float(np.var(out, dtype=np.float64))
     nstd = math.sqrt(sig_var / snr_lin) if sig_var > 0 else 0.0
-    for s0 in range(0, n1, _SLAB):
+
+    def noise(s0):
         s1 = min(n1, s0 + _SLAB)
         r = _slab_rng(seed, 2, s0 // _SLAB)
         out[:, s0:s1, :] += (nstd * r.standard_normal((n0, s1 - s0, n2))).astype(np.float32)
+
+    with ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(noise, range(0, n1, _SLAB)))
     mean = float(np.mean(out, dtype=np.float64))
     std = float(np.std(out, dtype=np.float64))
     out -= np.float32(mean)
