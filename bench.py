@@ -75,8 +75,9 @@ def cpu_baseline(V, L: int, sample_shape=(160, 192, 192)):
                       % (sample_shape + (lo, dt))}
 
 
-def parity_sample(V, S, E, Sr, stats, L: int, seed: int = 7, b: int = 24):
-    """Max relative error of the GPU maps against the oracle on a seeded b^3 sub-block."""
+def parity_sample(V, S, E, Sr, stats, L: int, seed: int = 7, b: int = 24, keep=None):
+    """Max relative error of the GPU maps against the oracle on a seeded b^3 sub-block
+    (the oracle's raw maps of the block are stored in `keep` when given)."""
     import numpy as np
     import oracle as O
     rng = np.random.default_rng(seed)
@@ -85,6 +86,8 @@ def parity_sample(V, S, E, Sr, stats, L: int, seed: int = 7, b: int = 24):
     Eo, So = O.raw_box(V, O.Params(L=L), lo, (b, b, b))
     st = stats.cpu().numpy()
     Sref = O.combine_with_stats(So, st[:6], vmax=st[6])
+    if keep is not None:
+        keep["S_raw"], keep["S"] = So, Sref
 
     def rel(g, r):
         return float(np.abs(g - r).max() / np.abs(r).max())
@@ -201,6 +204,95 @@ def surrogate_leg(args, dev):
     }
 
 
+def stream_leg(args, dev):
+    """The 512 x 1024 x 1024 survey (2 GiB, cube 16) from pinned host memory: the surrogate
+    streamed through HBM in t-slabs with split-BF16 fallback tiles, against the plain method
+    resident and streamed; errors against the plain FP32 GPU map and the oracle."""
+    import numpy as np
+    import torch
+    from paper_1901_11095_amd import sal, stream, surrogate, synth
+    name = "survey512x1024x1024"
+    print("# stream: generating %s" % name, file=sys.stderr, flush=True)
+    V = synth.workload(name)
+    N = V.size
+    Vh = stream.pinned(V)
+    net = surrogate.load()
+    ctx32 = sal.Saliency(L=16)
+    ctxb = sal.Saliency(L=16, precision=sal.BF16_SPLIT)
+    slab = args.slab
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, 1e3 * (time.perf_counter() - t0) / reps
+
+    print("# stream: host-to-device copy", file=sys.stderr, flush=True)
+    Vg = torch.empty(V.shape, dtype=torch.float32, device=dev)
+    Vg.copy_(Vh, non_blocking=True)
+    _, ms_h2d = timed(lambda: Vg.copy_(Vh, non_blocking=True), 2)
+
+    print("# stream: surrogate streamed (slab %d)" % slab, file=sys.stderr, flush=True)
+    sur = lambda: stream.surrogate_streamed(net, ctxb, Vh, slab=slab)  # noqa: E731
+    sur()
+    res, ms_sur = timed(sur, 2)
+    print("# stream: surrogate resident", file=sys.stderr, flush=True)
+    Sr_buf = torch.empty((3,) + V.shape, dtype=torch.float32, device=dev)
+    res_dev, ms_sur_dev = timed(
+        lambda: surrogate.infer_with_fallback(net, ctxb, Vg, S_raw=Sr_buf), 2)
+    del res_dev, Sr_buf
+    print("# stream: plain FP32 and split-BF16 resident, FP32 streamed", file=sys.stderr, flush=True)
+    ms_fp32, _ = time_form(ctx32, Vg, 1, 1)
+    ms_bf, _ = time_form(ctxb, Vg, 1, 1)
+    _, ms_fp32_st = timed(lambda: stream.plain_streamed(ctx32, Vh, slab=slab), 1)
+
+    # the plain FP32 GPU map with every intermediate (reference for the surrogate's errors)
+    S_ref, E_ref, Sr_ref, st_ref = ctx32.saliency_maps(Vg)
+    dS = (res["S"] - S_ref).abs()
+    rng = (st_ref[1:6:2] - st_ref[0:6:2]).float().reshape(3, 1, 1, 1)
+    t = 32
+    n0, n1, n2 = V.shape
+    raw_err = ((res["S_raw"] - Sr_ref).abs() / rng).amax(0)
+    tmax = raw_err.reshape(n0 // t, t, n1 // t, t, n2 // t, t).amax(dim=(1, 3, 5))
+    checked = [float(dS[tuple(slice(a, a + d) for a, d in zip(lo, td))].max())
+               for lo, td in res["tiles"]]
+
+    blocks = []
+    if not args.no_check:
+        print("# stream: oracle on a seeded 32^3 sub-block", file=sys.stderr, flush=True)
+        b = 32
+        ref = {}
+        plain = parity_sample(V, S_ref, E_ref, Sr_ref, st_ref, 16, seed=5, b=b, keep=ref)
+        So, Sref_o = ref["S_raw"], ref["S"]
+        sl = tuple(slice(a, a + b) for a in plain["block"][0])
+        st = st_ref.cpu().numpy()
+        rng_o = (st[1:6:2] - st[0:6:2]).reshape(3, 1, 1, 1)
+        Ssur = res["S_raw"][(slice(None),) + sl].cpu().numpy()
+        blocks.append({"block": plain["block"], "plain_fp32_max_rel_err": plain,
+                       "surrogate_raw_err_over_range": float((np.abs(Ssur - So) / rng_o).max()),
+                       "surrogate_S_abs_err": float(np.abs(res["S"][sl].cpu().numpy() - Sref_o).max())})
+    del E_ref
+    return {
+        "workload": name, "shape": list(V.shape), "L": 16, "slab": slab, "tile": 32,
+        "bound": 0.02, "data": "synthetic, pinned host memory",
+        "surrogate_streamed": {"voxels_per_s": N / (ms_sur * 1e-3), "ms": ms_sur,
+                               "checked_tiles": len(res["tiles"]), "n_tiles": res["n_tiles"],
+                               "checked_over_bound": int((res["tile_err"] > 0.02).sum())},
+        "surrogate_resident": {"voxels_per_s": N / (ms_sur_dev * 1e-3), "ms": ms_sur_dev},
+        "plain_fp32_resident": {"voxels_per_s": N / (ms_fp32 * 1e-3), "ms": ms_fp32},
+        "plain_fp32_streamed": {"voxels_per_s": N / (ms_fp32_st * 1e-3), "ms": ms_fp32_st},
+        "plain_bf16_split_resident": {"voxels_per_s": N / (ms_bf * 1e-3), "ms": ms_bf},
+        "host_to_device_GBps": V.nbytes / (ms_h2d * 1e-3) / 1e9,
+        "speedup_surrogate_streamed_vs_plain_fp32_resident": ms_fp32 / ms_sur,
+        "tiles_within_bound": {"before_fallback": float((tmax <= 0.02).float().mean())},
+        "S_abs_err_vs_plain_fp32": {"max": float(dS.max()), "mean": float(dS.mean()),
+                                    "max_on_checked_tiles": max(checked)},
+        "oracle_blocks": blocks,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +305,9 @@ def main(argv=None):
     ap.add_argument("--no-forms", action="store_true", help="only the FP32 form")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned surrogate leg")
     ap.add_argument("--sur-n", type=int, default=512, help="side of the surrogate's volume")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the 512x1024x1024 host-streamed leg")
+    ap.add_argument("--slab", type=int, default=128, help="t-rows per streamed slab")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -281,6 +376,11 @@ def main(argv=None):
             del c
     if not args.no_surrogate:
         forms["surrogate"] = surrogate_leg(args, dev)
+    streamed = None
+    if not args.no_stream:
+        del Vg
+        torch.cuda.empty_cache()
+        streamed = stream_leg(args, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -298,6 +398,7 @@ def main(argv=None):
         "max_rel_err_vs_oracle": err,
         "roofline": roof,
         "forms": forms,
+        "streamed": streamed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
