@@ -33,13 +33,16 @@ def dft_flops_per_voxel(L: int) -> int:
     return 4 * h * L + 8 * h * L * L + 8 * h * L ** 3
 
 
-def kernel_source_hash() -> str:
+# sources that define the FP32 fused kernel (its code, device helpers and launch set-up)
+ENERGY_F32_SOURCES = ("sal_kernels.hip", "sal_device.h", "sal_internal.h")
+
+
+def kernel_source_hash(files=ENERGY_F32_SOURCES) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1901_11095_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -204,6 +207,37 @@ def surrogate_leg(args, dev):
     }
 
 
+def precision_table(dev):
+    """Every precision form against the FP64 oracle on the whole 64^3 volume at cube 8 and
+    16: max and mean of |GPU - oracle| / max|oracle| for E_t, E_x, E_y, S_t, S_x, S_y (raw
+    maps of Eq. (5)) and the combined S of Eq. (6)."""
+    import numpy as np
+    import torch
+    import oracle as O
+    from paper_1901_11095_amd import sal, synth
+    V = synth.workload("vol64")
+    Vg = torch.from_numpy(V).to(dev)
+    names = ("E_t", "E_x", "E_y", "S_t", "S_x", "S_y")
+    table = {}
+    for L in (8, 16):
+        print("# precision table: oracle at cube %d" % L, file=sys.stderr, flush=True)
+        ref = O.saliency(V, O.Params(L=L))
+        maps_ref = [ref["E"][m] for m in range(3)] + [ref["S_raw"][m] for m in range(3)]
+        for prec in sorted(sal.PRECISION_NAMES):
+            c = sal.Saliency(L=L, precision=prec)
+            S, E, Sr, _ = c.saliency_maps(Vg)
+            got = [E[m] for m in range(3)] + [Sr[m] for m in range(3)]
+            row = {}
+            for n, g, r in zip(names + ("S",), got + [S], maps_ref + [ref["S"]]):
+                d = np.abs(g.double().cpu().numpy() - r)
+                den = float(np.abs(r).max())
+                row[n] = {"max": float(d.max()) / den, "mean": float(d.mean()) / den}
+            table["L%d_%s" % (L, sal.PRECISION_NAMES[prec])] = row
+            del c
+    return {"volume": "vol64 (64^3, seed 0)", "metric": "|GPU - FP64 oracle| / max|oracle|",
+            "maps": table}
+
+
 def stream_leg(args, dev):
     """The 512 x 1024 x 1024 survey (2 GiB, cube 16) from pinned host memory: the surrogate
     streamed through HBM in t-slabs with split-BF16 fallback tiles, against the plain method
@@ -308,6 +342,8 @@ def main(argv=None):
     ap.add_argument("--no-stream", action="store_true",
                     help="skip the 512x1024x1024 host-streamed leg")
     ap.add_argument("--slab", type=int, default=128, help="t-rows per streamed slab")
+    ap.add_argument("--no-table", action="store_true",
+                    help="skip the per-map error table of every form on the 64^3 volume")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -376,6 +412,9 @@ def main(argv=None):
             del c
     if not args.no_surrogate:
         forms["surrogate"] = surrogate_leg(args, dev)
+    table = None
+    if not args.no_table and not args.no_check:
+        table = precision_table(dev)
     streamed = None
     if not args.no_stream:
         del Vg
@@ -399,6 +438,7 @@ def main(argv=None):
         "roofline": roof,
         "forms": forms,
         "streamed": streamed,
+        "precision_table": table,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
