@@ -169,6 +169,20 @@ sal_status sal_profile_enable(sal_ctx *ctx, int on);
 sal_status sal_profile_read(sal_ctx *ctx, double ms[4], int64_t *calls, int reset);
 
 /*
+ * Steps 1-4 for one box of the volume (Sec. 2, Eqs. (1)-(5)): the raw maps S_t, S_x, S_y of
+ * the positions box_lo + [0, box_dims), written box-local to S_raw_box (DEVICE float
+ * [3][b0][b1][b2]), equal to the same positions of the whole-volume maps of sal_saliency.
+ * The energies are computed on the box grown by r = floor(d/2) (clipped to the volume) and
+ * windows reflect at the volume faces only, so V may be the whole volume or any crop whose
+ * faces inside the volume lie at least floor(L/2) + r from the box.  workspace: at least
+ * sal_raw_box_workspace_size(box_dims) bytes, DEVICE, 16-byte aligned.
+ */
+sal_status sal_raw_box_workspace_size(sal_ctx *ctx, const int64_t box_dims[3], size_t *bytes);
+sal_status sal_raw_box(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                       const int64_t box_lo[3], const int64_t box_dims[3], float *S_raw_box,
+                       void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * Steps 4b-5 on given raw maps S_raw float [3][n0][n1][n2]: the FP64 volume-wide statistics
  * and the normalised combination of Eq. (6) (same arithmetic as sal_saliency).  The scale of
  * the zero-contrast rule is max|V| over V (float [n0][n1][n2]) when V is given, else the
@@ -192,6 +206,16 @@ sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, in
                           const float *exact, const int64_t crop_lo[3], const int64_t crop_dims[3],
                           const int64_t tile_lo[3], const int64_t tile_dims[3],
                           const double *stats, double bound, float *err_out, void *stream);
+
+/*
+ * Per-tile extremes of raw maps S_raw (float [3][n0][n1][n2]) over the tiles of side `tile`
+ * (the last tile along an axis may be shorter), tiles numbered (t, x, y) with y fastest:
+ * out (DEVICE float [ntiles][6]) = {min_t, max_t, min_x, max_x, min_y, max_y} per tile,
+ * ntiles = ceil(n0/tile) ceil(n1/tile) ceil(n2/tile).  Used to find every tile whose
+ * predicted values could set the volume-wide statistics of Eq. (6).
+ */
+sal_status sal_tile_minmax(sal_ctx *ctx, const float *S_raw, int64_t n0, int64_t n1, int64_t n2,
+                           int32_t tile, float *out, void *stream);
 
 /* ------------------------------------------------------------------------------------
  * Learned surrogate (not part of the paper's method): five 3x3x3 convolutions, channels

@@ -468,7 +468,7 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     hipEvent_t *ev = take_events(c);
     int nv = 0;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipError_t e = launch_energy(c, V, n0, n1, n2, E, vmax, &nv, s);
+    hipError_t e = launch_energy(c, V, n0, n1, n2, nullptr, E, vmax, &nv, s);
     if (e != hipSuccess) return dev_fail(c, e, "energy launch");
     if (ev) (void)hipEventRecord(ev[1], s);
     e = launch_dcs(c, E, n0, n1, n2, Sr, mm, s);
@@ -480,6 +480,68 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     e = launch_combine(Sr, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);
     if (e != hipSuccess) return dev_fail(c, e, "combine launch");
     if (ev) (void)hipEventRecord(ev[4], s);
+    return SAL_OK;
+}
+
+// The box grown by r along every axis, clipped to the volume: E of these positions holds
+// every neighbour Eq. (5) reads for the box.
+static void grow_box(const sal_ctx *c, const int64_t n[3], const int64_t lo[3], const int64_t bd[3], int64_t eo[3],
+              int64_t ed[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        eo[a] = lo[a] - c->r > 0 ? lo[a] - c->r : 0;
+        const int64_t hi = lo[a] + bd[a] + c->r < n[a] ? lo[a] + bd[a] + c->r : n[a];
+        ed[a] = hi - eo[a];
+    }
+}
+
+static size_t raw_box_ws(const sal_ctx *c, const int64_t bd[3], const int64_t ed[3])
+{
+    (void)bd;
+    return align256((size_t)3 * ed[0] * ed[1] * ed[2] * sizeof(float)) +
+           align256((size_t)energy_num_blocks(c, ed[0], ed[1], ed[2]) * sizeof(float));
+}
+
+sal_status sal_raw_box_workspace_size(sal_ctx *c, const int64_t box_dims[3], size_t *bytes)
+{
+    if (!c || !box_dims || !bytes) return fail(c, SAL_E_INVAL, "null argument");
+    int64_t ed[3];
+    for (int a = 0; a < 3; ++a) {
+        if (box_dims[a] < 1 || box_dims[a] > (1 << 20)) return fail(c, SAL_E_INVAL, "bad box size");
+        ed[a] = box_dims[a] + 2 * c->r;
+    }
+    *bytes = raw_box_ws(c, box_dims, ed);
+    return SAL_OK;
+}
+
+sal_status sal_raw_box(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const int64_t box_lo[3],
+                       const int64_t box_dims[3], float *S_raw_box, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!V || !box_lo || !box_dims || !S_raw_box || !workspace) return fail(c, SAL_E_INVAL, "null pointer");
+    if (!aligned16(V) || !aligned16(S_raw_box) || !aligned16(workspace))
+        return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    const int64_t n[3] = {n0, n1, n2};
+    for (int a = 0; a < 3; ++a)
+        if (box_lo[a] < 0 || box_dims[a] < 1 || box_lo[a] + box_dims[a] > n[a])
+            return fail(c, SAL_E_INVAL, "box outside the volume");
+    int64_t eo[3], ed[3];
+    grow_box(c, n, box_lo, box_dims, eo, ed);
+    const size_t need = raw_box_ws(c, box_dims, ed);
+    if (ws_bytes < need) return fail(c, SAL_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    DevScope ds(c->device);
+    if ((st = sticky(c)) != SAL_OK) return st;
+    char *ws = (char *)workspace;
+    float *Eb = (float *)ws;
+    float *vmax = (float *)(ws + align256((size_t)3 * ed[0] * ed[1] * ed[2] * sizeof(float)));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t box[6] = {eo[0], eo[1], eo[2], ed[0], ed[1], ed[2]};
+    hipError_t e = launch_energy(c, V, n0, n1, n2, box, Eb, vmax, nullptr, s);
+    if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    e = launch_dcs_box(c, Eb, eo, ed, n, box_lo, box_dims, S_raw_box, s);
+    if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
     return SAL_OK;
 }
 
@@ -536,6 +598,24 @@ sal_status sal_tile_merge(sal_ctx *c, float *S_raw, int64_t n0, int64_t n1, int6
     hipError_t e = launch_tile_merge(S_raw, n0, n1, n2, exact, crop_lo, crop_dims, tile_lo, tile_dims, stats,
                                      bound, err_out, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(c, e, "tile merge launch");
+    return SAL_OK;
+}
+
+sal_status sal_tile_minmax(sal_ctx *c, const float *S_raw, int64_t n0, int64_t n1, int64_t n2, int32_t tile,
+                           float *out, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!S_raw || !out) return fail(c, SAL_E_INVAL, "null pointer");
+    if (n0 < 1 || n1 < 1 || n2 < 1 || n0 * n1 * n2 > ((int64_t)1 << 31) - 1)
+        return fail(c, SAL_E_INVAL, "volume dimensions out of range");
+    if (tile < 1 || tile > 1024) return fail(c, SAL_E_INVAL, "tile must be in [1, 1024]");
+    const int64_t nt = ((n0 + tile - 1) / tile) * ((n1 + tile - 1) / tile) * ((n2 + tile - 1) / tile);
+    if (nt > ((int64_t)1 << 31) - 1) return fail(c, SAL_E_INVAL, "too many tiles");
+    DevScope ds(c->device);
+    sal_status st;
+    if ((st = sticky(c)) != SAL_OK) return st;
+    if (hipError_t e = launch_tile_minmax(S_raw, n0, n1, n2, tile, out, (hipStream_t)stream); e != hipSuccess)
+        return dev_fail(c, e, "tile min/max launch");
     return SAL_OK;
 }
 

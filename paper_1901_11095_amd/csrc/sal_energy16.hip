@@ -84,7 +84,7 @@ __device__ __forceinline__ u32x4 lds4(const uint32_t *p) { return u32x4{p[0], p[
 
 template <int L, typename T, bool DS>
 __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
-    const float *__restrict__ V, int n0, int n1, int n2, int tt_len, int nby, int nbx,
+    const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
     const uint32_t *__restrict__ w_c16, const uint32_t *__restrict__ w_a16,
     const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
 {
@@ -111,9 +111,9 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     const int g = lane >> 4, n = lane & 15;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
-    const int y_base = ty * TY, x_base = tx * NW;
-    const int t_begin = tb * tt_len;
-    const int t_end = min(n0, t_begin + tt_len);
+    const int y_base = bx.o2 + ty * TY, x_base = bx.o1 + tx * NW;
+    const int t_begin = bx.o0 + tb * tt_len;
+    const int t_end = min(bx.o0 + bx.d0, t_begin + tt_len);
 
     u32x4 wc[MT][J], wa[MTA];
 #pragma unroll
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
         off_xy[jj] = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
     }
     const int64_t plane = (int64_t)n1 * n2;
-    const int64_t nvox = plane * n0;
+    const int64_t nbox = (int64_t)bx.d0 * bx.d1 * bx.d2;
     float vmax = 0.0f;
     uint32_t *Bw = B_s[wave][0];
     uint32_t *Bw_lo = B_s[wave][NP - 1];
@@ -311,11 +311,11 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
                 e[c][m] = s;
             }
             const int y = y_base + c * 16 + n;
-            if (g == 0 && x < n1 && y < n2) {
-                const int64_t o = ((int64_t)t0 * n1 + x) * n2 + y;
+            if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
+                const int64_t o = ((int64_t)(t0 - bx.o0) * bx.d1 + (x - bx.o1)) * bx.d2 + (y - bx.o2);
                 E[o] = e[c][0];
-                E[nvox + o] = e[c][1];
-                E[2 * nvox + o] = e[c][2];
+                E[nbox + o] = e[c][1];
+                E[2 * nbox + o] = e[c][2];
             }
         }
     }
@@ -332,23 +332,23 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
 
 template <int L, typename T, bool DS>
 static hipError_t launch_h(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
-                           float *E, float *vmax_part, int nby, int nbx, int tt, int64_t nb,
-                           hipStream_t s)
+                           const ebox &bx, float *E, float *vmax_part, int nby, int nbx, int tt,
+                           int64_t nb, hipStream_t s)
 {
     hipLaunchKernelGGL((k_energy_h<L, T, DS>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s,
-                       V, (int)n0, (int)n1, (int)n2, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
+                       V, (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
                        c->t.w_bin, E, vmax_part);
     return hipGetLastError();
 }
 
 hipError_t launch_energy16(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
-                           float *E, float *vmax_part, int nby, int nbx, int tt, int64_t nb,
-                           hipStream_t s)
+                           const ebox &bx, float *E, float *vmax_part, int nby, int nbx, int tt,
+                           int64_t nb, hipStream_t s)
 {
     const int p = c->p.precision;
     const bool bf = p == SAL_BF16 || p == SAL_BF16_SPLIT || p == SAL_BF16_SPLITW;
     const bool ds = p == SAL_BF16_SPLIT || p == SAL_FP16_SPLIT;
-#define SAL_LAUNCH_H(LL, TT, DD) launch_h<LL, TT, DD>(c, V, n0, n1, n2, E, vmax_part, nby, nbx, tt, nb, s)
+#define SAL_LAUNCH_H(LL, TT, DD) launch_h<LL, TT, DD>(c, V, n0, n1, n2, bx, E, vmax_part, nby, nbx, tt, nb, s)
     if (c->L == 8) {
         if (bf) return ds ? SAL_LAUNCH_H(8, __bf16, true) : SAL_LAUNCH_H(8, __bf16, false);
         return ds ? SAL_LAUNCH_H(8, _Float16, true) : SAL_LAUNCH_H(8, _Float16, false);

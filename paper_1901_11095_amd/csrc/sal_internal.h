@@ -48,18 +48,31 @@ struct dcs_args {
     float g[32];
 };
 
+// Output box of the fused kernels: E is computed for the volume positions o + [0, d) and
+// stored box-local as [3][d0][d1][d2]; windows still read the whole volume (reflected at
+// its faces).
+struct ebox {
+    int o0, o1, o2, d0, d1, d2;
+};
+
 // ------------------------------------------------------------------ launchers
 // All return hipSuccess or the launch error.
+// box: NULL for the whole volume, else {o0, o1, o2, d0, d1, d2}: E of the positions o + [0, d)
+// stored box-local as [3][d0][d1][d2]
 hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
-                         float *E, float *vmax_part, int *nparts, hipStream_t s);
+                         const int64_t *box, float *E, float *vmax_part, int *nparts,
+                         hipStream_t s);
 int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
 hipError_t launch_energy16(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
-                           float *E, float *vmax_part, int nby, int nbx, int tt, int64_t nb,
-                           hipStream_t s);
+                           const ebox &bx, float *E, float *vmax_part, int nby, int nbx, int tt,
+                           int64_t nb, hipStream_t s);
 
 hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
                       float *S_raw, float *minmax_part, hipStream_t s);
 int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
+hipError_t launch_dcs_box(const sal_ctx *c, const float *Eb, const int64_t eo[3], const int64_t ed[3],
+                          const int64_t n[3], const int64_t bo[3], const int64_t bd[3], float *S,
+                          hipStream_t s);
 
 hipError_t launch_stats(const float *vmax_part, int64_t nv, const float *minmax_part,
                         int64_t nm, double *stats, hipStream_t s);
@@ -75,6 +88,9 @@ hipError_t launch_tile_merge(float *S_raw, int64_t n0, int64_t n1, int64_t n2, c
                              const int64_t crop_lo[3], const int64_t crop_dims[3],
                              const int64_t tile_lo[3], const int64_t tile_dims[3],
                              const double *stats, double bound, float *err, hipStream_t s);
+
+hipError_t launch_tile_minmax(const float *S_raw, int64_t n0, int64_t n1, int64_t n2, int tile,
+                              float *out, hipStream_t s);
 
 hipError_t launch_local_spectra(const sal_ctx *c, const float *V, int64_t n0, int64_t n1,
                                 int64_t n2, const int64_t lo[3], const int64_t bn[3],

@@ -37,7 +37,7 @@
 // count (|F|^2, sqrt, three weighted sums) is kept minimal.
 template <int L>
 __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
-    const float *__restrict__ V, int n0, int n1, int n2, int tt_len, int nby, int nbx,
+    const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
     const float *__restrict__ w_c, const float *__restrict__ w_a,
     const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
 {
@@ -61,9 +61,9 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
-    const int y_base = ty * TY, x_base = tx * NW;
-    const int t_begin = tb * tt_len;
-    const int t_end = min(n0, t_begin + tt_len);
+    const int y_base = bx.o2 + ty * TY, x_base = bx.o1 + tx * NW;
+    const int t_begin = bx.o0 + tb * tt_len;
+    const int t_end = min(bx.o0 + bx.d0, t_begin + tt_len);
 
     // constant MFMA A-operands: lane (g, n) holds row n of each M tile at K = KS*g + kk
     float wc[MT][KS];
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
         off_xy[jj] = gx * n2 + gy;
     }
     const int64_t plane = (int64_t)n1 * n2;
-    const int64_t nvox = plane * n0;
+    const int64_t nbox = (int64_t)bx.d0 * bx.d1 * bx.d2;
     float vmax = 0.0f;
     float2 *Bw = B_s[wave];
 
@@ -256,11 +256,11 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
                 e[c][m] = s;
             }
             const int y = y_base + c * 16 + n;
-            if (g == 0 && x < n1 && y < n2) {
-                const int64_t o = ((int64_t)t0 * n1 + x) * n2 + y;
+            if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
+                const int64_t o = ((int64_t)(t0 - bx.o0) * bx.d1 + (x - bx.o1)) * bx.d2 + (y - bx.o2);
                 E[o] = e[c][0];
-                E[nvox + o] = e[c][1];
-                E[2 * nvox + o] = e[c][2];
+                E[nbox + o] = e[c][1];
+                E[2 * nbox + o] = e[c][2];
             }
         }
     }
@@ -335,6 +335,43 @@ __global__ __launch_bounds__(256) void k_dcs(const float *__restrict__ E, int n0
         float r = red[0][k];
         for (int w = 1; w < 4; ++w) r = (k & 1) ? fmaxf(r, red[w][k]) : fminf(r, red[w][k]);
         mm_part[(int64_t)blockIdx.x * 6 + k] = r;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Step 4, Eq. (5) on a box of the volume: E is given on the box grown by r (clipped to the
+// volume), Eb [3][ed0][ed1][ed2] at origin eo; S_raw of the box positions bo + [0, bd) is
+// written box-local [3][bd0][bd1][bd2].  Neighbours are reflected at the volume faces and
+// then read from the grown box, which holds every such position.  Same order of the sums as
+// k_dcs.
+__global__ __launch_bounds__(256) void k_dcs_box(const float *__restrict__ Eb, int3 eo, int3 ed, int3 nv,
+                                                 int3 bo, int3 bd, dcs_args a, float *__restrict__ S)
+{
+    const int nb = bd.x * bd.y * bd.z;
+    const int64_t NE = (int64_t)ed.x * ed.y * ed.z;
+    const int dims[3] = {nv.x, nv.y, nv.z};
+    const int org[3] = {eo.x, eo.y, eo.z};
+    const int64_t stride[3] = {(int64_t)ed.y * ed.z, ed.z, 1};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < nb; i += gridDim.x * 256) {
+        const int pos[3] = {bo.x + i / (bd.y * bd.z), bo.y + (i / bd.z) % bd.y, bo.z + i % bd.z};
+        const int64_t v = (pos[0] - eo.x) * stride[0] + (pos[1] - eo.y) * stride[1] + (pos[2] - eo.z);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const float *Em = Eb + m * NE;
+            const float c = Em[v];
+            float sum = 0.f;
+            for (int b = 0; b < 6; ++b) {
+                if (!((a.rays[m] >> b) & 1u)) continue;
+                const int ax = b >> 1;
+                const int dir = (b & 1) ? -1 : 1;
+                const int64_t base = v - (int64_t)(pos[ax] - org[ax]) * stride[ax];
+                for (int s = 1; s <= a.r; ++s) {
+                    const int u = refl_idx(pos[ax] + dir * s, dims[ax]) - org[ax];
+                    sum += fabsf(c - a.g[s - 1] * Em[base + (int64_t)u * stride[ax]]);
+                }
+            }
+            S[(int64_t)m * nb + i] = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
+        }
     }
 }
 
@@ -728,26 +765,29 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 
 template <int L>
 static hipError_t launch_energy_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1,
-                                  int64_t n2, float *E, float *vmax_part, int *nparts,
-                                  hipStream_t s)
+                                  int64_t n2, const ebox &bx, float *E, float *vmax_part,
+                                  int *nparts, hipStream_t s)
 {
     int nby, nbx, tt;
     int64_t nb;
-    energy_grid<L>(n0, n1, n2, &nby, &nbx, &tt, &nb);
+    energy_grid<L>(bx.d0, bx.d1, bx.d2, &nby, &nbx, &tt, &nb);
     if (nparts) *nparts = (int)nb;
     if (c->p.precision != SAL_FP32)
-        return launch_energy16(c, V, n0, n1, n2, E, vmax_part, nby, nbx, tt, nb, s);
+        return launch_energy16(c, V, n0, n1, n2, bx, E, vmax_part, nby, nbx, tt, nb, s);
     hipLaunchKernelGGL(k_energy_f32<L>, dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s, V,
-                       (int)n0, (int)n1, (int)n2, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_bin,
-                       E, vmax_part);
+                       (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a,
+                       c->t.w_bin, E, vmax_part);
     return hipGetLastError();
 }
 
 hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
-                         float *E, float *vmax_part, int *nparts, hipStream_t s)
+                         const int64_t *box, float *E, float *vmax_part, int *nparts,
+                         hipStream_t s)
 {
-    if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, E, vmax_part, nparts, s);
-    return launch_energy_L<16>(c, V, n0, n1, n2, E, vmax_part, nparts, s);
+    ebox bx{0, 0, 0, (int)n0, (int)n1, (int)n2};
+    if (box) bx = ebox{(int)box[0], (int)box[1], (int)box[2], (int)box[3], (int)box[4], (int)box[5]};
+    if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
 }
 
 int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
@@ -839,5 +879,24 @@ hipError_t launch_project(const sal_ctx *c, const float *spectra, int64_t nvox, 
         hipLaunchKernelGGL(k_project<8>, dim3((unsigned)nvox), dim3(64), 0, s, F, nvox, w, E);
     else
         hipLaunchKernelGGL(k_project<16>, dim3((unsigned)nvox), dim3(64), 0, s, F, nvox, w, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_dcs_box(const sal_ctx *c, const float *Eb, const int64_t eo[3], const int64_t ed[3],
+                          const int64_t n[3], const int64_t bo[3], const int64_t bd[3], float *S,
+                          hipStream_t s)
+{
+    dcs_args a;
+    a.r = c->r;
+    for (int m = 0; m < 3; ++m) {
+        a.rays[m] = c->p.rays[m];
+        a.Q[m] = c->Q[m];
+    }
+    for (int i = 0; i < 32; ++i) a.g[i] = c->g[i];
+    const int64_t nb = bd[0] * bd[1] * bd[2];
+    const unsigned blocks = (unsigned)((nb + 255) / 256 < 4096 ? (nb + 255) / 256 : 4096);
+    auto i3 = [](const int64_t *v) { return make_int3((int)v[0], (int)v[1], (int)v[2]); };
+    hipLaunchKernelGGL(k_dcs_box, dim3(blocks), dim3(256), 0, s, Eb, i3(eo), i3(ed), i3(n), i3(bo), i3(bd), a,
+                       S);
     return hipGetLastError();
 }

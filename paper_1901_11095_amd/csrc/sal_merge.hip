@@ -114,6 +114,51 @@ __global__ __launch_bounds__(256) void k_tile_copy(float *__restrict__ S, int n0
     }
 }
 
+// {min, max} of each raw map over one tile per workgroup; tiles numbered (t, x, y), y fastest
+__global__ __launch_bounds__(256) void k_tile_minmax(const float *__restrict__ S, int n0, int n1, int n2, int tile,
+                                                     int ntx, int nty, float *__restrict__ out)
+{
+    const int ti = blockIdx.x;
+    const int c = ti % nty, b = (ti / nty) % ntx, a = ti / (nty * ntx);
+    const int t0 = a * tile, x0 = b * tile, y0 = c * tile;
+    const int dt = min(tile, n0 - t0), dx = min(tile, n1 - x0), dy = min(tile, n2 - y0);
+    const int cnt = dt * dx * dy;
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+        const int y = i % dy, r = i / dy;
+        const int x = r % dx, t = r / dx;
+        const int64_t v = ((int64_t)(t0 + t) * n1 + (x0 + x)) * n2 + (y0 + y);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const float s = S[m * N + v];
+            mn[m] = fminf(mn[m], s);
+            mx[m] = fmaxf(mx[m], s);
+        }
+    }
+    __shared__ float red[4][6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            mn[m] = fminf(mn[m], __shfl_xor(mn[m], o));
+            mx[m] = fmaxf(mx[m], __shfl_xor(mx[m], o));
+        }
+        if (lane == 0) {
+            red[wave][2 * m] = mn[m];
+            red[wave][2 * m + 1] = mx[m];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float r = red[0][k];
+        for (int w = 1; w < 4; ++w) r = (k & 1) ? fmaxf(r, red[w][k]) : fminf(r, red[w][k]);
+        out[(int64_t)ti * 6 + k] = r;
+    }
+}
+
 int64_t merge_red_blocks(int64_t N)
 {
     const int64_t nb = (N + 255) / 256;
@@ -148,5 +193,15 @@ hipError_t launch_tile_merge(float *S_raw, int64_t n0, int64_t n1, int64_t n2, c
                        stats, err);
     hipLaunchKernelGGL(k_tile_copy, dim3(nb), dim3(256), 0, s, S_raw, (int)n0, (int)n1, (int)n2, exact, c, t,
                        err, (float)bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_minmax(const float *S_raw, int64_t n0, int64_t n1, int64_t n2, int tile, float *out,
+                              hipStream_t s)
+{
+    const int nt0 = (int)((n0 + tile - 1) / tile), nt1 = (int)((n1 + tile - 1) / tile),
+              nt2 = (int)((n2 + tile - 1) / tile);
+    hipLaunchKernelGGL(k_tile_minmax, dim3((unsigned)nt0 * nt1 * nt2), dim3(256), 0, s, S_raw, (int)n0, (int)n1,
+                       (int)n2, tile, nt1, nt2, out);
     return hipGetLastError();
 }

@@ -27,7 +27,8 @@ STATS_LEN = 7
 EXPORTS = ("sal_default_params", "sal_create", "sal_destroy", "sal_last_error",
            "sal_workspace_size", "sal_local_spectra", "sal_project", "sal_directional_compare",
            "sal_saliency", "sal_profile_enable", "sal_profile_read", "sal_normalize_combine",
-           "sal_tile_merge", "sal_net_num_params", "sal_net_last_error", "sal_net_create",
+           "sal_tile_merge", "sal_tile_minmax", "sal_raw_box_workspace_size", "sal_raw_box",
+           "sal_net_num_params", "sal_net_last_error", "sal_net_create",
            "sal_net_destroy", "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
            "sal_net_workspace_size", "sal_net_forward", "sal_net_backward", "sal_net_train_step",
            "sal_net_infer")
@@ -85,6 +86,9 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
                                         vp]
     l.sal_tile_merge.argtypes = [vp, vp, i64, i64, i64, vp, _i64p, _i64p, _i64p, _i64p, vp,
                                  ctypes.c_double, vp, vp]
+    l.sal_tile_minmax.argtypes = [vp, vp, i64, i64, i64, ctypes.c_int32, vp, vp]
+    l.sal_raw_box_workspace_size.argtypes = [vp, _i64p, ctypes.POINTER(sz)]
+    l.sal_raw_box.argtypes = [vp, vp, i64, i64, i64, _i64p, _i64p, vp, vp, sz, vp]
     l.sal_net_num_params.argtypes = []
     l.sal_net_num_params.restype = i64
     l.sal_net_last_error.argtypes = [vp]
@@ -104,7 +108,8 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     l.sal_net_infer.argtypes = [vp, vp, i64, i64, i64, vp, vp, sz, vp]
     for f in ("sal_create", "sal_workspace_size", "sal_local_spectra", "sal_project",
               "sal_directional_compare", "sal_saliency", "sal_profile_enable",
-              "sal_profile_read", "sal_normalize_combine", "sal_tile_merge", "sal_net_create",
+              "sal_profile_read", "sal_normalize_combine", "sal_tile_merge", "sal_tile_minmax",
+              "sal_raw_box_workspace_size", "sal_raw_box", "sal_net_create",
               "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
               "sal_net_workspace_size", "sal_net_forward", "sal_net_backward",
               "sal_net_train_step", "sal_net_infer"):
@@ -237,6 +242,25 @@ class Saliency:
                                            ws.numel() * ws.element_size(), _stream(V.device)))
         return S
 
+    def raw_box(self, V: torch.Tensor, box_lo, box_dims, out: Optional[torch.Tensor] = None,
+                workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Raw maps [3, *box_dims] of the positions box_lo + [0, box_dims) of V."""
+        _check_vol(V)
+        dims = tuple(int(d) for d in box_dims)
+        if out is None:
+            out = torch.empty((3,) + dims, dtype=torch.float32, device=V.device)
+        if workspace is None:
+            n = ctypes.c_size_t()
+            self._raise(self._lib.sal_raw_box_workspace_size(self._h, _i64x3(dims), ctypes.byref(n)))
+            wsb = getattr(self, "_wsb", None)
+            if wsb is None or wsb.numel() < n.value:
+                wsb = self._wsb = torch.empty(max(1, n.value), dtype=torch.uint8, device=V.device)
+            workspace = wsb
+        self._raise(self._lib.sal_raw_box(self._h, _ptr(V), *V.shape, _i64x3(box_lo), _i64x3(dims),
+                                          _ptr(out), _ptr(workspace), workspace.numel(),
+                                          _stream(V.device)))
+        return out
+
     def profile(self, on: bool = True):
         """Enable/disable per-kernel HIP-event timing of saliency()."""
         self._raise(self._lib.sal_profile_enable(self._h, int(bool(on))))
@@ -288,6 +312,22 @@ def tile_merge(ctx: "Saliency", S_raw: torch.Tensor, exact: torch.Tensor, crop_l
                                        _i64x3(exact.shape[1:]), _i64x3(tile_lo), _i64x3(tile_dims),
                                        _ptr(stats), float(bound), _ptr(err_out),
                                        _stream(S_raw.device)))
+
+
+def tile_minmax(ctx: "Saliency", S_raw: torch.Tensor, tile: int,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-tile {min, max} of each raw map: float32 [ntiles, 6] on the device."""
+    if not (S_raw.is_cuda and S_raw.dtype == torch.float32 and S_raw.is_contiguous()):
+        raise ValueError("S_raw must be a contiguous float32 CUDA tensor")
+    shape = tuple(S_raw.shape[1:])
+    nt = 1
+    for n in shape:
+        nt *= (n + tile - 1) // tile
+    if out is None:
+        out = torch.empty((nt, 6), dtype=torch.float32, device=S_raw.device)
+    ctx._raise(ctx._lib.sal_tile_minmax(ctx._h, _ptr(S_raw), *shape, int(tile), _ptr(out),
+                                        _stream(S_raw.device)))
+    return out
 
 
 class Net:

@@ -89,36 +89,25 @@ def plain_streamed(ctx: sal.Saliency, V_host: torch.Tensor, slab: int = 64):
 
 def surrogate_streamed(net: sal.Net, ctx_fallback: sal.Saliency, V_host: torch.Tensor,
                        slab: int = 64, tile: int = 32, frac: float = 0.02, bound: float = 0.02,
-                       seed: int = 0):
-    """Surrogate first, slab by slab (halo 5), then the seeded tile check on crops copied
-    from the host volume with the plain method (ctx_fallback, e.g. split-BF16) and exact
-    replacement, then the FP64 normalisation and Eq. (6)."""
-
+                       seed: int = 0, max_rounds: int = 8, per_round: int = 32):
+    """Surrogate first, slab by slab (halo 5), then the seeded tile check and the check of
+    the tiles holding each map's extremes, on crops copied from the host volume, with the
+    plain method (ctx_fallback, e.g. split-BF16) and exact replacement; then the FP64
+    normalisation and Eq. (6)."""
     S_raw, vmax = raw_maps_streamed(V_host, net.infer, 5, slab)
     dev = S_raw.device
-    shape = tuple(V_host.shape)
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
     S = sal.normalize_combine(ctx_fallback, S_raw, None, stats_out=stats, vmax=vmax)
-    all_tiles = surrogate.tiles_of(shape, tile)
-    k = max(1, int(round(frac * len(all_tiles))))
-    pick = set(np.random.default_rng(seed).choice(len(all_tiles), size=k, replace=False).tolist())
-    nt = [(n + tile - 1) // tile for n in shape]
-    for m in range(3):
-        for flat in (int(torch.argmax(S_raw[m])), int(torch.argmin(S_raw[m]))):
-            t, x, y = np.unravel_index(flat, shape)
-            pick.add(int((t // tile * nt[1] + x // tile) * nt[2] + y // tile))
-    halo = ctx_fallback.L
-    errs = torch.zeros(len(pick), dtype=torch.float32, device=dev)
-    checked = []
-    for j, ti in enumerate(sorted(pick)):
-        lo = all_tiles[ti]
-        td = tuple(min(tile, n - a) for a, n in zip(lo, shape))
-        clo = tuple(max(0, a - halo) for a in lo)
-        chi = tuple(min(n, a + d + halo) for a, d, n in zip(lo, td, shape))
-        crop = V_host[clo[0]:chi[0], clo[1]:chi[1], clo[2]:chi[2]].contiguous().to(dev, non_blocking=True)
-        exact = surrogate.exact_raw_maps(ctx_fallback, crop)
-        sal.tile_merge(ctx_fallback, S_raw, exact, clo, lo, td, stats, bound, errs[j:j + 1])
-        checked.append((lo, td))
+    sample = surrogate.seeded_tiles(len(surrogate.tiles_of(tuple(V_host.shape), tile)), frac, seed)
+
+    def crop(lo, hi):
+        return V_host[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].contiguous().to(dev), lo
+
+    chk = surrogate.TileCheck(ctx_fallback, S_raw, stats, crop, tile, bound,
+                              len(sample) + 6 * per_round * max_rounds)
+    for ti in sample:
+        chk.check(ti)
+    rounds = chk.verify_extremes(max_rounds, per_round)
     S = sal.normalize_combine(ctx_fallback, S_raw, None, S=S, stats_out=stats, vmax=vmax)
-    return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": checked, "tile_err": errs,
-            "n_tiles": len(all_tiles)}
+    return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": chk.tiles, "tile_err": chk.errors(),
+            "n_tiles": chk.n_tiles(), "extreme_rounds": rounds}

@@ -49,14 +49,24 @@ class TrainConfig:
     lr_min: float = 1e-4
     window_seed: int = 18
     init_seed: int = 0
+    mix: bool = False          # draw each training volume's structure and SNR from its seed
     history: list = field(default_factory=list)
 
 
-def volume_kwargs(seed: int, shape) -> dict:
-    """Training/held-out volumes: faults, a chaotic body and noise, sized to the shape."""
+def volume_kwargs(seed: int, shape, mix: bool = False) -> dict:
+    """Training/held-out volumes: faults, a chaotic body and noise, sized to the shape.
+    With `mix` the structure is drawn from the seed as well (1-6 faults, 0-2 chaotic bodies
+    of side/8 to side/4, SNR 3-12 dB), so a training set spans the noise levels and
+    structure counts of the survey-scale volumes."""
     side = min(shape)
-    return dict(shape=tuple(shape), seed=int(seed), n_faults=3, n_chaotic=1,
-                chaotic_size=max(8, side // 4), snr_db=10.0)
+    if not mix:
+        return dict(shape=tuple(shape), seed=int(seed), n_faults=3, n_chaotic=1,
+                    chaotic_size=max(8, side // 4), snr_db=10.0)
+    r = np.random.default_rng([int(seed), 77])
+    return dict(shape=tuple(shape), seed=int(seed), n_faults=int(r.integers(1, 7)),
+                n_chaotic=int(r.integers(0, 3)),
+                chaotic_size=max(8, int(r.integers(side // 8, side // 4 + 1))),
+                snr_db=float(r.uniform(3.0, 12.0)))
 
 
 def exact_raw_maps(ctx: sal.Saliency, V: torch.Tensor) -> torch.Tensor:
@@ -71,7 +81,7 @@ def make_training_set(cfg: TrainConfig, device="cuda"):
     ctx = sal.Saliency(L=cfg.L)
     vols, labels = [], []
     for s in cfg.seeds[:cfg.n_volumes]:
-        V = torch.from_numpy(synth.make_volume(**volume_kwargs(s, cfg.shape))).to(device)
+        V = torch.from_numpy(synth.make_volume(**volume_kwargs(s, cfg.shape, cfg.mix))).to(device)
         vols.append(V)
         labels.append(exact_raw_maps(ctx, V))
     torch.cuda.synchronize()
@@ -143,41 +153,111 @@ def tiles_of(shape, tile: int):
             for y in range(0, shape[2], tile)]
 
 
+class TileCheck:
+    """Checks tiles of predicted raw maps against the plain method and replaces those over
+    the bound.  `source(lo, hi)` returns (volume, origin): a device volume holding at least
+    the samples of the box [lo, hi) of the full volume, and the full-volume position of its
+    first sample (the resident volume itself with origin 0, or a crop copied from host
+    memory).  A tile is checked at most once."""
+
+    def __init__(self, ctx: sal.Saliency, S_raw: torch.Tensor, stats: torch.Tensor, source,
+                 tile: int, bound: float, capacity: int):
+        self.ctx, self.S_raw, self.stats, self.source = ctx, S_raw, stats, source
+        self.shape = tuple(S_raw.shape[1:])
+        self.tile, self.bound = tile, bound
+        self.nt = [(n + tile - 1) // tile for n in self.shape]
+        self.errs = torch.zeros(capacity, dtype=torch.float32, device=S_raw.device)
+        self.done = {}      # tile index -> slot in errs
+        self.tiles = []     # (lo, dims) in check order
+        self.exact = torch.empty((3, tile, tile, tile), dtype=torch.float32, device=S_raw.device)
+
+    def n_tiles(self) -> int:
+        return self.nt[0] * self.nt[1] * self.nt[2]
+
+    def tile_lo(self, ti: int):
+        a, rest = divmod(ti, self.nt[1] * self.nt[2])
+        b, c = divmod(rest, self.nt[2])
+        return (a * self.tile, b * self.tile, c * self.tile)
+
+    def tile_of_voxel(self, flat: int) -> int:
+        t, x, y = np.unravel_index(flat, self.shape)
+        return int((t // self.tile * self.nt[1] + x // self.tile) * self.nt[2] + y // self.tile)
+
+    def check(self, ti: int) -> bool:
+        if ti in self.done or len(self.done) >= len(self.errs):
+            return False
+        j = len(self.done)
+        self.done[ti] = j
+        lo = self.tile_lo(ti)
+        td = tuple(min(self.tile, n - a) for a, n in zip(lo, self.shape))
+        halo = self.ctx.L  # floor(L/2) window + floor(d/2) comparison reach, d = L
+        clo = tuple(max(0, a - halo) for a in lo)
+        chi = tuple(min(n, a + d + halo) for a, d, n in zip(lo, td, self.shape))
+        V, org = self.source(clo, chi)
+        exact = self.exact[:, :td[0], :td[1], :td[2]]
+        if td != (self.tile,) * 3:
+            exact = torch.empty((3,) + td, dtype=torch.float32, device=self.S_raw.device)
+        self.ctx.raw_box(V, tuple(a - o for a, o in zip(lo, org)), td, out=exact)
+        sal.tile_merge(self.ctx, self.S_raw, exact, lo, lo, td, self.stats, self.bound,
+                       self.errs[j:j + 1])
+        self.tiles.append((lo, td))
+        return True
+
+    def verify_extremes(self, max_rounds: int = 8, per_round: int = 32) -> int:
+        """The volume-wide minimum and maximum of each map set the normalisation of Eq. (6).
+        Check every unchecked tile whose values pass the extremes of the checked tiles by
+        more than the bound (as a fraction of the checked range; a smaller excess moves the
+        normalised map by less than the bound), up to `per_round` per extreme and round,
+        most extreme first, until no unchecked tile does.  Returns the rounds used."""
+        for r in range(max_rounds):
+            mm = sal.tile_minmax(self.ctx, self.S_raw, self.tile).cpu().numpy()
+            done = np.zeros(len(mm), dtype=bool)
+            done[list(self.done)] = True
+            new = []
+            for m in range(3):
+                lo, hi = mm[done, 2 * m].min(), mm[done, 2 * m + 1].max()
+                tol = self.bound * (hi - lo)
+                col = mm[:, 2 * m + 1]
+                cand = np.nonzero(~done & (col > hi + tol))[0]
+                new.extend(int(t) for t in cand[np.argsort(-col[cand], kind="stable")][:per_round])
+                col = mm[:, 2 * m]
+                cand = np.nonzero(~done & (col < lo - tol))[0]
+                new.extend(int(t) for t in cand[np.argsort(col[cand], kind="stable")][:per_round])
+            new = list(dict.fromkeys(new))
+            if not new:
+                return r
+            for ti in new:
+                self.check(ti)
+        return max_rounds
+
+    def errors(self) -> torch.Tensor:
+        return self.errs[:len(self.done)]
+
+
+def seeded_tiles(n_tiles: int, frac: float, seed: int):
+    k = max(1, int(round(frac * n_tiles)))
+    return sorted(np.random.default_rng(seed).choice(n_tiles, size=k, replace=False).tolist())
+
+
 def infer_with_fallback(net: sal.Net, ctx_exact: sal.Saliency, V: torch.Tensor, tile: int = 32,
                         frac: float = 0.02, bound: float = 0.02, seed: int = 0,
-                        S_raw: Optional[torch.Tensor] = None, check_extremes: bool = True):
-    """Surrogate maps, a seeded check of `frac` of the tiles (plus the tiles holding each
-    map's predicted extremes) against the plain method with exact replacement of the tiles
-    over `bound`, then the exact normalisation and Eq. (6).
+                        S_raw: Optional[torch.Tensor] = None, check_extremes: bool = True,
+                        max_rounds: int = 8, per_round: int = 32):
+    """Surrogate maps, a seeded check of `frac` of the tiles against the plain method with
+    exact replacement of the tiles over `bound`, then (with `check_extremes`) the tiles that
+    hold each map's extremes until all of them are checked, then the exact FP64
+    normalisation and Eq. (6).
     Returns a dict with S, S_raw, stats, the checked tiles and their errors."""
-    shape = tuple(V.shape)
     dev = V.device
     S_raw = net.infer(V, out=S_raw)
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
     S = sal.normalize_combine(ctx_exact, S_raw, V, stats_out=stats)
-    all_tiles = tiles_of(shape, tile)
-    k = max(1, int(round(frac * len(all_tiles))))
-    pick = set(np.random.default_rng(seed).choice(len(all_tiles), size=k, replace=False).tolist())
-    if check_extremes:
-        # the volume-wide minimum and maximum of every predicted map set the normalisation:
-        # their tiles are always checked
-        nt = [(n + tile - 1) // tile for n in shape]
-        for m in range(3):
-            for flat in (int(torch.argmax(S_raw[m])), int(torch.argmin(S_raw[m]))):
-                t, x, y = np.unravel_index(flat, shape)
-                pick.add(int((t // tile * nt[1] + x // tile) * nt[2] + y // tile))
-    halo = ctx_exact.L  # floor(L/2) window + floor(d/2) comparison reach, d = L
-    errs = torch.zeros(len(pick), dtype=torch.float32, device=dev)
-    checked = []
-    for j, ti in enumerate(sorted(pick)):
-        lo = all_tiles[ti]
-        td = tuple(min(tile, n - a) for a, n in zip(lo, shape))
-        clo = tuple(max(0, a - halo) for a in lo)
-        chi = tuple(min(n, a + d + halo) for a, d, n in zip(lo, td, shape))
-        crop = V[clo[0]:chi[0], clo[1]:chi[1], clo[2]:chi[2]].contiguous()
-        exact = exact_raw_maps(ctx_exact, crop)
-        sal.tile_merge(ctx_exact, S_raw, exact, clo, lo, td, stats, bound, errs[j:j + 1])
-        checked.append((lo, td))
+    sample = seeded_tiles(len(tiles_of(tuple(V.shape), tile)), frac, seed)
+    chk = TileCheck(ctx_exact, S_raw, stats, lambda lo, hi: (V, (0, 0, 0)),
+                    tile, bound, len(sample) + (6 * per_round * max_rounds if check_extremes else 0))
+    for ti in sample:
+        chk.check(ti)
+    rounds = chk.verify_extremes(max_rounds, per_round) if check_extremes else 0
     S = sal.normalize_combine(ctx_exact, S_raw, V, S=S, stats_out=stats)
-    return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": checked, "tile_err": errs,
-            "n_tiles": len(all_tiles)}
+    return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": chk.tiles, "tile_err": chk.errors(),
+            "n_tiles": chk.n_tiles(), "extreme_rounds": rounds}

@@ -19,9 +19,10 @@ import torch
 from . import sal, surrogate, synth
 
 
-def evaluate(net, shape=(256, 256, 256), seed=99, L=16, bound=0.02, frac=0.02):
+def evaluate(net, V: torch.Tensor, L=16, bound=0.02, frac=0.02):
+    """Errors of the surrogate against the plain FP32 method on one device volume, before
+    and after the tile check with exact fallback."""
     ctx = sal.Saliency(L=L)
-    V = torch.from_numpy(synth.make_volume(**surrogate.volume_kwargs(seed, shape))).cuda()
     st_ref = torch.zeros(8, dtype=torch.float64, device="cuda")
     Sr_ref = torch.empty((3,) + tuple(V.shape), dtype=torch.float32, device="cuda")
     S_ref = ctx.saliency(V, S_raw_out=Sr_ref, stats_out=st_ref)
@@ -32,9 +33,11 @@ def evaluate(net, shape=(256, 256, 256), seed=99, L=16, bound=0.02, frac=0.02):
     out = {"raw_rel_max": float(raw_err.max()), "raw_rel_mean": float(raw_err.mean()),
            "S_abs_max_before": float((S_pred - S_ref).abs().max()),
            "S_abs_mean_before": float((S_pred - S_ref).abs().mean())}
+    del S_pred
     # tiles within the bound before any fallback
     t = 32
     te = raw_err.amax(0)
+    del raw_err
     n0, n1, n2 = V.shape
     tiles = te[:n0 // t * t, :n1 // t * t, :n2 // t * t].reshape(n0 // t, t, n1 // t, t, n2 // t, t)
     tmax = tiles.amax(dim=(1, 3, 5))
@@ -56,17 +59,28 @@ def main(argv=None):
     ap.add_argument("--out", default=surrogate.WEIGHTS)
     ap.add_argument("--eval-shape", type=int, default=256)
     ap.add_argument("--volumes", type=int, default=8)
+    ap.add_argument("--mix", action="store_true",
+                    help="draw faults, chaotic bodies and SNR of each training volume from its seed")
+    ap.add_argument("--eval-survey", action="store_true",
+                    help="also evaluate on the 512 x 1024 x 1024 survey volume")
     args = ap.parse_args(argv)
     cfg = surrogate.TrainConfig(epochs=args.epochs, batch=args.batch, lr=args.lr,
                                 shape=(args.shape,) * 3, n_volumes=args.volumes,
-                                seeds=tuple(range(10, 10 + args.volumes)))
+                                seeds=tuple(range(10, 10 + args.volumes)), mix=args.mix)
     t0 = time.time()
     net, cfg = surrogate.train(cfg, log=lambda s: print(s, flush=True))
     torch.cuda.synchronize()
     print("trained in %.1f s" % (time.time() - t0), flush=True)
     surrogate.save(net, cfg, args.out)
     print("wrote", args.out, flush=True)
-    ev = evaluate(net, shape=(args.eval_shape,) * 3)
+    shape = (args.eval_shape,) * 3
+    V = torch.from_numpy(synth.make_volume(**surrogate.volume_kwargs(99, shape))).cuda()
+    ev = {"held_out_%d" % args.eval_shape: evaluate(net, V)}
+    del V
+    if args.eval_survey:
+        V = torch.from_numpy(synth.workload("survey512x1024x1024")).cuda()
+        ev["survey512x1024x1024"] = evaluate(net, V)
+        del V
     print(json.dumps({"eval": ev, "loss_history": cfg.history}), flush=True)
     return 0
 

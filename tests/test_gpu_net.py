@@ -132,3 +132,19 @@ def test_tile_merge():
     assert abs(err.item() - 0.05) <= 1e-7
     assert abs(S_raw[1, 6, 7, 8].item() - 0.05) <= 1e-7  # over the bound: replaced
     assert S_raw[1, 5, 6, 7].item() == 0.0 and S_raw[0, 0, 0, 0].item() == 1.0
+
+
+@pytest.mark.parametrize("shape,tile", [((37, 20, 45), 16), ((32, 32, 32), 32), ((5, 7, 3), 4)])
+def test_tile_minmax(shape, tile):
+    """Per-tile extremes equal a direct reduction over every (ragged) tile, bit for bit."""
+    ctx = sal.Saliency(L=8)
+    g = torch.Generator().manual_seed(3)
+    S_raw = torch.randn((3,) + shape, generator=g).cuda()
+    out = sal.tile_minmax(ctx, S_raw, tile).cpu()
+    ref = []
+    for t in range(0, shape[0], tile):
+        for x in range(0, shape[1], tile):
+            for y in range(0, shape[2], tile):
+                blk = S_raw[:, t:t + tile, x:x + tile, y:y + tile].reshape(3, -1).cpu()
+                ref.append(torch.stack([blk.amin(1), blk.amax(1)], 1).reshape(6))
+    assert torch.equal(out, torch.stack(ref))
