@@ -170,7 +170,24 @@ hipError_t build_tables(sal_ctx *c)
         twiddle(k, L, &cs, &sn);
         tw[2 * k] = (float)cs;
         tw[2 * k + 1] = (float)sn;
+        c->tw_host[2 * k] = (float)cs;
+        c->tw_host[2 * k + 1] = (float)sn;
     }
+    // vector-ALU kernel (L < 8): weights of every bin (mu <= L/2, nu, om) with the
+    // multiplicity of the conjugate bin (-mu, -nu, -om) the half spectrum leaves out, and
+    // 1/L^3 of the DFT and 1/(L^3 - 1) of the mean
+    std::vector<float> wg;
+    if (L < 8)
+        for (long mu = 0; mu < h; ++mu) {
+            const double mult = (mu == 0 || 2 * mu == L) ? 1.0 : 2.0;
+            for (long nu = 0; nu < L; ++nu)
+                for (long om = 0; om < L; ++om) {
+                    double w[3];
+                    proj_w(sfreq(mu, L), sfreq(nu, L), sfreq(om, L), w);
+                    for (int m = 0; m < 3; ++m)
+                        wg.push_back((float)(w[m] * mult / ((double)L3 * (double)(L3 - 1))));
+                }
+        }
     std::vector<float> wp((size_t)4 * L3, 0.f);
     for (long mu = 0; mu < L; ++mu)
         for (long nu = 0; nu < L; ++nu)
@@ -227,12 +244,13 @@ hipError_t build_tables(sal_ctx *c)
     if ((e = upload(&c->t.w_proj, wp)) != hipSuccess) return e;
     if ((e = upload(&c->t.w_c16, c16)) != hipSuccess) return e;
     if ((e = upload(&c->t.w_a16, a16)) != hipSuccess) return e;
+    if (!wg.empty() && (e = upload(&c->t.w_gen, wg)) != hipSuccess) return e;
     return hipSuccess;
 }
 
 void free_tables(sal_tables *t)
 {
-    float **fp[] = {&t->w_c, &t->w_a, &t->w_bin, &t->twiddle, &t->w_proj};
+    float **fp[] = {&t->w_c, &t->w_a, &t->w_bin, &t->twiddle, &t->w_proj, &t->w_gen};
     for (float **p : fp)
         if (*p) {
             (void)hipFree(*p);
@@ -335,8 +353,10 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
     if (p->precision < SAL_FP32 || p->precision > SAL_FP16_SPLITW)
         return fail(nullptr, SAL_E_INVAL, "unknown precision");
     if (!(p->zero_range >= 0.0)) return fail(nullptr, SAL_E_INVAL, "zero_range must be >= 0");
-    if (p->L != 8 && p->L != 16)
-        return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements L = 8 and L = 16");
+    if (p->L > 8 && p->L != 16)
+        return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements L = 2..8 and L = 16");
+    if (p->L < 8 && p->precision != SAL_FP32)
+        return fail(nullptr, SAL_E_UNSUPPORTED, "L < 8 runs in FP32 only");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(nullptr, SAL_E_DEVICE, "no such HIP device");

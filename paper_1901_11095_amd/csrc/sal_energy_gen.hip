@@ -1,0 +1,234 @@
+// Steps 1-3 of the saliency method (Shafiq et al., ICIP 2017, Sec. 2) for cube sides that
+// do not fill 16-wide matrix tiles: L = 2..7, among them the paper's own 5 x 5 x 5 cube.
+// The contractions have 2L <= 14 real rows and columns, so a 16 x 16 matrix-core tile would
+// be mostly padding; at these sizes the work per voxel is a few thousand flops and the
+// vector ALUs carry it in FP32.
+//
+// The decomposition is the one of the matrix-core kernels: the window DFT (with 1/L^3
+// folded into the weights) as three separable contractions that share the first two axes
+// between overlapping windows, t real -> half spectrum mu <= L/2, then x, then y per
+// voxel, followed by the plane projections of Eqs. (1)-(4) with DC excluded and the mean
+// magnitudes E_m.  A workgroup owns NX x-rows by NY y-columns and walks t:
+//   ring    the L t-planes of the (NX + L - 1) x (NY + L - 1) patch the windows cover, one
+//           new plane per t (reflected at the volume faces when loaded);
+//   stage A A[pos][mu] = sum_p W[mu, p] V[t0 - H + p, pos] for every patch position;
+//   stage B per mu: B[x0][y'][nu] = sum_q W[nu, q] A[x0 + q, y'][mu];
+//   stage C per mu and nu, one thread per voxel (x0, y0): F[om] = sum_r W[om, r]
+//           B[x0][y0 + r][nu], |F| weighted by the projections into E_t, E_x, E_y.
+// Bins with mu and L - mu have equal magnitudes and weights (conjugates); the weight table
+// carries that multiplicity, so only mu <= L/2 is computed.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sal_device.h"
+#include "sal_internal.h"
+
+namespace {
+
+template <int L>
+struct GenCfg {
+    static constexpr int NX = L <= 5 ? 16 : 8;  // x-rows per workgroup
+    static constexpr int NY = 256 / NX;         // y-columns per workgroup
+};
+
+template <int L>
+struct GenTw {
+    float2 w[L];  // e^{-2 pi i k / L}, k = 0..L-1
+};
+
+__device__ __forceinline__ float2 cmad(float2 a, float2 w, float2 acc)
+{
+    acc.x = fmaf(a.x, w.x, fmaf(-a.y, w.y, acc.x));
+    acc.y = fmaf(a.x, w.y, fmaf(a.y, w.x, acc.y));
+    return acc;
+}
+
+}  // namespace
+
+template <int L>
+__global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V, int n0, int n1, int n2, ebox bx,
+                                                    int tt_len, int nby, int nbx, GenTw<L> tw,
+                                                    const float *__restrict__ wgen, float *__restrict__ E,
+                                                    float *__restrict__ vmax_part)
+{
+    constexpr int H = L / 2, h = L / 2 + 1;
+    constexpr int NX = GenCfg<L>::NX, NY = GenCfg<L>::NY;
+    constexpr int PX = NX + L - 1, PY = NY + L - 1, NP = PX * PY;
+    constexpr int NW3 = h * L * L * 3;
+    __shared__ float ring[L][NP];
+    __shared__ float2 A_s[NP * h];
+    __shared__ float2 B_s[NX * PY * L];
+    __shared__ float wg_s[NW3];
+    __shared__ float2 tw_s[L];
+    __shared__ float red_s[4];
+
+    const int tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
+    const int y_base = bx.o2 + ty * NY, x_base = bx.o1 + tx * NX;
+    const int t_begin = bx.o0 + tb * tt_len;
+    const int t_end = min(bx.o0 + bx.d0, t_begin + tt_len);
+    const int64_t plane = (int64_t)n1 * n2;
+    const int64_t nbox = (int64_t)bx.d0 * bx.d1 * bx.d2;
+
+    for (int i = tid; i < NW3; i += 256) wg_s[i] = wgen[i];
+    if (tid == 0)
+#pragma unroll
+        for (int k = 0; k < L; ++k) tw_s[k] = tw.w[k];
+
+    float vmax = 0.f;
+    auto load_plane = [&](int tv) {
+        const int slot = ((tv % L) + L) % L;
+        const int64_t gt = refl_idx(tv, n0);
+        for (int p = tid; p < NP; p += 256) {
+            const int xp = p / PY, yp = p - xp * PY;
+            const int gx = refl_idx(x_base - H + xp, n1), gy = refl_idx(y_base - H + yp, n2);
+            const float v = V[gt * plane + (int64_t)gx * n2 + gy];
+            vmax = fmaxf(vmax, fabsf(v));
+            ring[slot][p] = v;
+        }
+    };
+    for (int k = 0; k < L - 1; ++k) load_plane(t_begin - H + k);
+
+    const int x0 = tid / NY, y0 = tid - (tid / NY) * NY;
+    for (int t0 = t_begin; t0 < t_end; ++t0) {
+        load_plane(t0 - H + L - 1);
+        __syncthreads();
+        // ---------------- stage A: real DFT along t, mu <= L/2 ---------------------------
+        for (int p = tid; p < NP; p += 256) {
+            float v[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) v[k] = ring[(((t0 - H + k) % L) + L) % L][p];
+#pragma unroll
+            for (int mu = 0; mu < h; ++mu) {
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    re = fmaf(v[k], tw.w[(mu * k) % L].x, re);
+                    im = fmaf(v[k], tw.w[(mu * k) % L].y, im);
+                }
+                A_s[p * h + mu] = make_float2(re, im);
+            }
+        }
+        __syncthreads();
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+#pragma unroll 1
+        for (int mu = 0; mu < h; ++mu) {
+            // ---------------- stage B: DFT along x for this mu ---------------------------
+            for (int i = tid; i < NX * PY * L; i += 256) {
+                const int nu = i % L, rest = i / L;
+                const int yp = rest % PY, xr = rest / PY;
+                float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int q = 0; q < L; ++q) {
+                    // the twiddle index depends on nu, a run-time value here: read it from LDS
+                    acc = cmad(A_s[((xr + q) * PY + yp) * h + mu], tw_s[(nu * q) % L], acc);
+                }
+                B_s[i] = acc;
+            }
+            __syncthreads();
+            // ---------------- stage C: DFT along y per voxel, projections, energies ------
+#pragma unroll 1
+            for (int nu = 0; nu < L; ++nu) {
+                float2 b[L];
+#pragma unroll
+                for (int r = 0; r < L; ++r) b[r] = B_s[(x0 * PY + y0 + r) * L + nu];
+                const float *w = &wg_s[(mu * L + nu) * L * 3];
+#pragma unroll
+                for (int om = 0; om < L; ++om) {
+                    float2 f = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int r = 0; r < L; ++r) f = cmad(b[r], tw.w[(om * r) % L], f);
+                    const float m = __builtin_amdgcn_sqrtf(fmaf(f.x, f.x, f.y * f.y));
+                    e0 = fmaf(w[3 * om], m, e0);
+                    e1 = fmaf(w[3 * om + 1], m, e1);
+                    e2 = fmaf(w[3 * om + 2], m, e2);
+                }
+            }
+            __syncthreads();
+        }
+        const int x = x_base + x0, y = y_base + y0;
+        if (x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
+            const int64_t o = ((int64_t)(t0 - bx.o0) * bx.d1 + (x - bx.o1)) * bx.d2 + (y - bx.o2);
+            E[o] = e0;
+            E[nbox + o] = e1;
+            E[2 * nbox + o] = e2;
+        }
+    }
+    // max |V| of everything this workgroup read (all of it lies in the volume)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    if ((tid & 63) == 0) red_s[tid >> 6] = vmax;
+    __syncthreads();
+    if (tid == 0) vmax_part[blockIdx.x] = fmaxf(fmaxf(red_s[0], red_s[1]), fmaxf(red_s[2], red_s[3]));
+}
+
+// ====================================================================== launchers
+
+namespace {
+
+int gen_tt_len(int64_t n0, int64_t tiles_xy)
+{
+    // enough workgroups to fill 256 CUs several times over; long t walks otherwise
+    int64_t tt = 32;
+    while (tt > 2 && tiles_xy * ((n0 + tt - 1) / tt) < 2048) tt >>= 1;
+    return (int)tt;
+}
+
+template <int L>
+void gen_grid(int64_t d0, int64_t d1, int64_t d2, int *nby, int *nbx, int *tt, int64_t *nb)
+{
+    *nby = (int)((d2 + GenCfg<L>::NY - 1) / GenCfg<L>::NY);
+    *nbx = (int)((d1 + GenCfg<L>::NX - 1) / GenCfg<L>::NX);
+    *tt = gen_tt_len(d0, (int64_t)(*nby) * (*nbx));
+    *nb = (int64_t)(*nby) * (*nbx) * ((d0 + *tt - 1) / *tt);
+}
+
+template <int L>
+hipError_t launch_gen_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
+                        float *E, float *vmax_part, int *nparts, hipStream_t s)
+{
+    int nby, nbx, tt;
+    int64_t nb;
+    gen_grid<L>(bx.d0, bx.d1, bx.d2, &nby, &nbx, &tt, &nb);
+    if (nparts) *nparts = (int)nb;
+    if (nb == 0) return hipSuccess;
+    GenTw<L> tw;
+    for (int k = 0; k < L; ++k) tw.w[k] = make_float2(c->tw_host[2 * k], c->tw_host[2 * k + 1]);
+    hipLaunchKernelGGL(k_energy_gen<L>, dim3((unsigned)nb), dim3(256), 0, s, V, (int)n0, (int)n1, (int)n2, bx, tt,
+                       nby, nbx, tw, c->t.w_gen, E, vmax_part);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t energy_gen_num_blocks(int L, int64_t d0, int64_t d1, int64_t d2)
+{
+    int nby, nbx, tt;
+    int64_t nb = 0;
+    switch (L) {
+    case 2: gen_grid<2>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
+    case 3: gen_grid<3>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
+    case 4: gen_grid<4>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
+    case 5: gen_grid<5>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
+    case 6: gen_grid<6>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
+    case 7: gen_grid<7>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
+    default: break;
+    }
+    return nb;
+}
+
+hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
+                             float *E, float *vmax_part, int *nparts, hipStream_t s)
+{
+    switch (c->L) {
+    case 2: return launch_gen_L<2>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    case 3: return launch_gen_L<3>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    case 4: return launch_gen_L<4>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    case 5: return launch_gen_L<5>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    case 6: return launch_gen_L<6>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    case 7: return launch_gen_L<7>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    default: return hipErrorInvalidValue;
+    }
+}

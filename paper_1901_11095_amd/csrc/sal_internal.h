@@ -23,6 +23,8 @@ struct sal_tables {
     uint32_t *w_c16;  // 16-bit forms: per M tile, MFMA and lane, the eight 16-bit A-operand
                       // values (W_hi | W_lo halves) of the x and y contractions
     uint32_t *w_a16;  // likewise for the t contraction
+    float *w_gen;     // vector-ALU kernel (L < 8): [mu <= L/2][nu][om][3] projection weights
+                      // times the conjugate multiplicity of mu, / (L^3 (L^3 - 1)), DC = 0
 };
 
 struct sal_ctx {
@@ -32,6 +34,7 @@ struct sal_ctx {
     float g[32];       // Gaussian neighbour weights w(s), s = 1..r (index s-1)
     float q_inv[3];    // unused by the kernels (kept for diagnostics)
     float Q[3];        // number of terms of Eq. (5) per component
+    float tw_host[32]; // e^{-2 pi i k / L} (re, im), k < L
     sal_tables t;
     std::string err;
     // per-kernel timing of sal_saliency (sal_profile_enable / sal_profile_read)
@@ -66,6 +69,10 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
 hipError_t launch_energy16(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
                            const ebox &bx, float *E, float *vmax_part, int nby, int nbx, int tt,
                            int64_t nb, hipStream_t s);
+
+int64_t energy_gen_num_blocks(int L, int64_t d0, int64_t d1, int64_t d2);
+hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
+                             float *E, float *vmax_part, int *nparts, hipStream_t s);
 
 hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
                       float *S_raw, float *minmax_part, hipStream_t s);

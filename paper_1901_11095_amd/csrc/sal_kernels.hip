@@ -758,8 +758,10 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
     int64_t nb;
     if (c->L == 8)
         energy_grid<8>(n0, n1, n2, &nby, &nbx, &tt, &nb);
-    else
+    else if (c->L == 16)
         energy_grid<16>(n0, n1, n2, &nby, &nbx, &tt, &nb);
+    else
+        nb = energy_gen_num_blocks(c->L, n0, n1, n2);
     return nb;
 }
 
@@ -787,7 +789,8 @@ hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n
     ebox bx{0, 0, 0, (int)n0, (int)n1, (int)n2};
     if (box) bx = ebox{(int)box[0], (int)box[1], (int)box[2], (int)box[3], (int)box[4], (int)box[5]};
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
-    return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
 }
 
 int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
@@ -860,12 +863,20 @@ hipError_t launch_local_spectra(const sal_ctx *c, const float *V, int64_t n0, in
     if (nb == 0) return hipSuccess;
     const float2 *tw = reinterpret_cast<const float2 *>(c->t.twiddle);
     float2 *o = reinterpret_cast<float2 *>(out);
-    if (c->L == 8)
-        hipLaunchKernelGGL(k_local_spectra<8>, dim3(nb), dim3(256), 0, s, V, (int)n0, (int)n1,
-                           (int)n2, (int)lo[0], (int)lo[1], (int)lo[2], (int)bn[1], (int)bn[2], tw, o);
-    else
-        hipLaunchKernelGGL(k_local_spectra<16>, dim3(nb), dim3(256), 0, s, V, (int)n0, (int)n1,
-                           (int)n2, (int)lo[0], (int)lo[1], (int)lo[2], (int)bn[1], (int)bn[2], tw, o);
+#define SAL_SPECTRA(LL)                                                                                        \
+    hipLaunchKernelGGL(k_local_spectra<LL>, dim3(nb), dim3(256), 0, s, V, (int)n0, (int)n1, (int)n2, (int)lo[0], \
+                       (int)lo[1], (int)lo[2], (int)bn[1], (int)bn[2], tw, o)
+    switch (c->L) {
+    case 2: SAL_SPECTRA(2); break;
+    case 3: SAL_SPECTRA(3); break;
+    case 4: SAL_SPECTRA(4); break;
+    case 5: SAL_SPECTRA(5); break;
+    case 6: SAL_SPECTRA(6); break;
+    case 7: SAL_SPECTRA(7); break;
+    case 8: SAL_SPECTRA(8); break;
+    default: SAL_SPECTRA(16); break;
+    }
+#undef SAL_SPECTRA
     return hipGetLastError();
 }
 
@@ -875,10 +886,18 @@ hipError_t launch_project(const sal_ctx *c, const float *spectra, int64_t nvox, 
     if (nvox == 0) return hipSuccess;
     const float2 *F = reinterpret_cast<const float2 *>(spectra);
     const float4 *w = reinterpret_cast<const float4 *>(c->t.w_proj);
-    if (c->L == 8)
-        hipLaunchKernelGGL(k_project<8>, dim3((unsigned)nvox), dim3(64), 0, s, F, nvox, w, E);
-    else
-        hipLaunchKernelGGL(k_project<16>, dim3((unsigned)nvox), dim3(64), 0, s, F, nvox, w, E);
+#define SAL_PROJECT(LL) hipLaunchKernelGGL(k_project<LL>, dim3((unsigned)nvox), dim3(64), 0, s, F, nvox, w, E)
+    switch (c->L) {
+    case 2: SAL_PROJECT(2); break;
+    case 3: SAL_PROJECT(3); break;
+    case 4: SAL_PROJECT(4); break;
+    case 5: SAL_PROJECT(5); break;
+    case 6: SAL_PROJECT(6); break;
+    case 7: SAL_PROJECT(7); break;
+    case 8: SAL_PROJECT(8); break;
+    default: SAL_PROJECT(16); break;
+    }
+#undef SAL_PROJECT
     return hipGetLastError();
 }
 

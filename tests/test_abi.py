@@ -41,13 +41,17 @@ def test_default_params(lib):
     assert p.a == p.b == p.c == 1.0 / 3.0 and p.normalize == 1 and p.precision == sal.FP32
 
 
-@pytest.mark.parametrize("field,value,status", [
-    ("L", 1, 1), ("d", 1, 1), ("sigma", 0.0, 1), ("precision", 9, 1), ("L", 5, 2), ("L", 4, 2),
+@pytest.mark.parametrize("fields,status", [
+    ({"L": 1}, 1), ({"d": 1}, 1), ({"sigma": 0.0}, 1), ({"precision": 9}, 1), ({"L": 9}, 2),
+    ({"L": 12}, 2), ({"L": 32}, 2), ({"L": 5, "precision": 2}, 2), ({"L": 4, "precision": 1}, 2),
 ])
-def test_create_rejects(lib, field, value, status):
+def test_create_rejects(lib, fields, status):
+    """Invalid parameters are rejected before any device call; cube sides without a GPU
+    kernel (9..15, > 16) and 16-bit forms below L = 8 are unsupported."""
     from paper_1901_11095_amd import sal
     p = sal.default_params(8)
-    setattr(p, field, value)
+    for k, v in fields.items():
+        setattr(p, k, v)
     h = ctypes.c_void_p()
     st = lib.sal_create(ctypes.byref(p), 0, ctypes.byref(h))
     assert st == status
