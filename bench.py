@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "saliency voxels/sec (plain FP32 vs BF16-split vs surrogate) at stated max error"
-PEAK_TFLOPS = {"f32": 157.3, "bf16": 2516.6, "f16": 2516.6}
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "f32_vector": 78.6}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -205,6 +205,22 @@ def surrogate_leg(args, dev):
                      "kernel": "k_conv3 (five layers, network inference only)",
                      "flops_per_voxel": flops},
     }
+
+
+def small_cube_leg(args, V, Vg, L=5):
+    """The paper's own cube (5 x 5 x 5, Sec. 2) on the same volume: FP32 on the vector ALUs
+    (2L = 10 rows would fill 10/16 of a matrix-core tile).  Roofline against the FP32 vector
+    peak without packed instructions (78.6 TFLOP/s: 256 CUs x 128 lanes x 2 flops x 2.4 GHz)."""
+    from paper_1901_11095_amd import sal
+    ctx = sal.Saliency(L=L)
+    ms, km = time_form(ctx, Vg, max(3, args.steps // 2), 2)
+    fpv = dft_flops_per_voxel(L)
+    ach = fpv * V.size / (km["energy"] * 1e-3) / 1e12
+    return {"L": L, "voxels_per_s": V.size / (ms * 1e-3), "ms_per_step": ms, "kernels_ms": km,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS["f32_vector"],
+                         "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["f32_vector"],
+                         "kernel": "k_energy_gen<%d>" % L, "flops_per_voxel": fpv},
+            "max_rel_err_vs_oracle": None if args.no_check else sampled_error(ctx, V, Vg, L)}
 
 
 def precision_table(dev):
@@ -410,6 +426,9 @@ def main(argv=None):
                 "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, args.L),
             }
             del c
+    if not args.no_forms:
+        print("# paper cube 5^3", file=sys.stderr, flush=True)
+        forms["fp32_paper_cube_L5"] = small_cube_leg(args, V, Vg, 5)
     if not args.no_surrogate:
         forms["surrogate"] = surrogate_leg(args, dev)
     table = None

@@ -816,15 +816,19 @@ hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, 
     if (nf <= DCS_LDS_MAX_FLOATS) {
         const size_t lds = (size_t)(nf > 24 ? nf : 24) * sizeof(float);
         const int nbx = (int)((n1 + DTX - 1) / DTX), nby = (int)((n2 + DTY - 1) / DTY);
-        if (c->r == 4)
-            hipLaunchKernelGGL(k_dcs_tiled<4>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1,
-                               (int)n2, a, nbx, nby, S_raw, minmax_part);
-        else if (c->r == 8)
-            hipLaunchKernelGGL(k_dcs_tiled<8>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1,
-                               (int)n2, a, nbx, nby, S_raw, minmax_part);
-        else
-            hipLaunchKernelGGL(k_dcs_tiled<0>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1,
-                               (int)n2, a, nbx, nby, S_raw, minmax_part);
+#define SAL_DCS_T(RR)                                                                                          \
+    hipLaunchKernelGGL(k_dcs_tiled<RR>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1, (int)n2, a, nbx, nby, \
+                       S_raw, minmax_part)
+        // r known at compile time for the default d = L of every supported cube side
+        switch (c->r) {
+        case 1: SAL_DCS_T(1); break;
+        case 2: SAL_DCS_T(2); break;
+        case 3: SAL_DCS_T(3); break;
+        case 4: SAL_DCS_T(4); break;
+        case 8: SAL_DCS_T(8); break;
+        default: SAL_DCS_T(0); break;
+        }
+#undef SAL_DCS_T
     } else {
         hipLaunchKernelGGL(k_dcs, dim3(nb), dim3(256), 0, s, E, (int)n0, (int)n1, (int)n2, a,
                            S_raw, minmax_part);
