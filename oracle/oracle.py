@@ -30,6 +30,10 @@ _L = ctypes.c_long
 RAY_PT, RAY_MT, RAY_PX, RAY_MX, RAY_PY, RAY_MY = 1, 2, 4, 8, 16, 32
 RAYS_AXIS = (RAY_PT | RAY_MT, RAY_PX | RAY_MX, RAY_PY | RAY_MY)  # S_t: +-t, S_x: +-x, S_y: +-y
 RAYS_ALL = (63, 63, 63)
+# oriented rays (Fig. 3): bits 6-9 the t-x diagonals (+t+x, -t-x, +t-x, -t+x), 10-13 the
+# t-y diagonals, 14-17 the x-y diagonals, 18-25 the body diagonals
+RAY_DIAG_TX, RAY_DIAG_TY, RAY_DIAG_XY, RAY_BODY = 0xF << 6, 0xF << 10, 0xF << 14, 0xFF << 18
+RAYS_26 = ((1 << 26) - 1,) * 3
 
 
 def build(force: bool = False) -> str:

@@ -212,15 +212,40 @@ void oracle_energy(const float *V, long n0, long n1, long n2, long L, double *E)
     oracle_energy_box(V, n0, n1, n2, L, lo, bn, E);
 }
 
+/* Step vector (t, x, y) of ray bit b of the comparison masks. */
+static void ray_step(int b, long e[3])
+{
+    e[0] = e[1] = e[2] = 0;
+    if (b < 6) {
+        e[b / 2] = (b % 2 == 0) ? 1 : -1;
+    } else if (b < 18) {
+        /* planes (t,x), (t,y), (x,y); signs (+,+), (-,-), (+,-), (-,+) */
+        static const int ax[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        static const int sg[4][2] = {{1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+        int pl = (b - 6) / 4, k = (b - 6) % 4;
+        e[ax[pl][0]] = sg[k][0];
+        e[ax[pl][1]] = sg[k][1];
+    } else {
+        int k = b - 18;
+        e[0] = (k & 1) ? -1 : 1;
+        e[1] = (k & 2) ? -1 : 1;
+        e[2] = (k & 4) ? -1 : 1;
+    }
+}
+
 /*
- * Directional center-surround comparison -- Eq. (5) and the paragraph after Fig. 3:
+ * Directional center-surround comparison -- Eq. (5), the paragraph after it and Fig. 3
+ * (comparisons along t, along x and along the t-x diagonal; the orientation is a tunable
+ * choice of the method):
  *     S_m[v] = (1/Q) sum_{neighbours u} | E_m[v] - w(u) E_m[u] |.
- * reading: the d x 1 window centred on v is taken as rays of r = floor(d/2) steps; bit
- * 2a (2a+1) of rays[m] enables the ray along +axis a (-axis a); w(s) = exp(-s^2/(2 sigma^2))
- * weights the neighbour s steps from the centre; Q = (number of enabled rays) * r;
- * neighbours beyond the volume are reflected.  E is given on the box
- * [elo, elo+ebn) of a volume of dims n; S_raw is produced for the box [lo, lo+bn), which
- * must lie inside the E box together with every neighbour it reads.
+ * reading: the d x 1 window centred on v is taken as rays of r = floor(d/2) steps from v;
+ * a ray has a step vector e of the 26-neighbourhood and its s-th sample is v + s e;
+ * w = exp(-|s e|^2 / (2 sigma^2)) (Gaussian in the Euclidean distance from the centre);
+ * Q = (number of enabled rays) * r; each coordinate of a neighbour beyond the volume is
+ * reflected.  Bits of rays[m] (see ray_step): 0-5 the axis rays +t, -t, +x, -x, +y, -y;
+ * 6-17 the face diagonals of the t-x, t-y and x-y planes; 18-25 the body diagonals.
+ * E is given on the box [elo, elo+ebn) of a volume of dims n; S_raw is produced for the box
+ * [lo, lo+bn), which must lie inside the E box together with every neighbour it reads.
  */
 int oracle_dcs_box(const double *E, const long elo[3], const long ebn[3],
                    long n0, long n1, long n2, long r, double sigma,
@@ -232,27 +257,27 @@ int oracle_dcs_box(const double *E, const long elo[3], const long ebn[3],
     int bad = 0;
     for (int m = 0; m < 3; ++m) {
         long nrays = 0;
-        for (int b = 0; b < 6; ++b) nrays += (rays[m] >> b) & 1u;
+        for (int b = 0; b < 26; ++b) nrays += (rays[m] >> b) & 1u;
         double Q = (double)(nrays * r);
         for (long v = 0; v < nb; ++v) {
             long pos[3] = {lo[0] + v / (bn[1] * bn[2]), lo[1] + (v / bn[2]) % bn[1], lo[2] + v % bn[2]};
             long ec = ((pos[0] - elo[0]) * ebn[1] + (pos[1] - elo[1])) * ebn[2] + (pos[2] - elo[2]);
             double centre = E[m * ne + ec];
             double sum = 0.0;
-            for (int b = 0; b < 6; ++b) {
+            for (int b = 0; b < 26; ++b) {
                 if (!((rays[m] >> b) & 1u)) continue;
-                int axis = b / 2;
-                long dir = (b % 2 == 0) ? 1 : -1;
+                long e[3];
+                ray_step(b, e);
+                long len2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
                 for (long s = 1; s <= r; ++s) {
-                    long q[3] = {pos[0], pos[1], pos[2]};
-                    q[axis] = refl_index(q[axis] + dir * s, n[axis]);
-                    long rel[3] = {q[0] - elo[0], q[1] - elo[1], q[2] - elo[2]};
+                    long rel[3];
+                    for (int a = 0; a < 3; ++a) rel[a] = refl_index(pos[a] + e[a] * s, n[a]) - elo[a];
                     if (rel[0] < 0 || rel[0] >= ebn[0] || rel[1] < 0 || rel[1] >= ebn[1] ||
                         rel[2] < 0 || rel[2] >= ebn[2]) {
                         bad = 1;
                         continue;
                     }
-                    double w = exp(-(double)(s * s) / (2.0 * sigma * sigma));
+                    double w = exp(-(double)(s * s * len2) / (2.0 * sigma * sigma));
                     double nbv = E[m * ne + (rel[0] * ebn[1] + rel[1]) * ebn[2] + rel[2]];
                     sum += fabs(centre - w * nbv);
                 }

@@ -237,6 +237,74 @@ def test_dcs_delta_golden(oracle_mod):
             assert abs(got - want) <= 1e-15, (case["name"], item, got, want)
 
 
+def _ray_steps(mask):
+    """Step vectors of the enabled rays: bits 0-5 axis (+t, -t, +x, -x, +y, -y), 6-17 face
+    diagonals of the t-x, t-y, x-y planes with signs (+,+), (-,-), (+,-), (-,+), 18-25 body
+    diagonals with the sign of t, x, y negative where bit 0, 1, 2 of (bit - 18) is set."""
+    out = []
+    for b in range(26):
+        if not (mask >> b) & 1:
+            continue
+        e = [0, 0, 0]
+        if b < 6:
+            e[b // 2] = 1 if b % 2 == 0 else -1
+        elif b < 18:
+            (a0, a1), (s0, s1) = [(0, 1), (0, 2), (1, 2)][(b - 6) // 4], [(1, 1), (-1, -1), (1, -1), (-1, 1)][(b - 6) % 4]
+            e[a0], e[a1] = s0, s1
+        else:
+            k = b - 18
+            e = [-1 if k & 1 else 1, -1 if k & 2 else 1, -1 if k & 4 else 1]
+        out.append(tuple(e))
+    return out
+
+
+@pytest.mark.parametrize("mask", ["tx", "body", "all26"])
+def test_dcs_constant_energy_oriented(oracle_mod, mask):
+    """Oriented rays (Fig. 3) on E = e: a ray with step e_ray sees e (1 - g(s |e_ray|)) at
+    step s, so S = e / Q * sum over rays and steps of (1 - g(s |e_ray|))."""
+    m = {"tx": oracle_mod.RAY_DIAG_TX, "body": oracle_mod.RAY_BODY, "all26": (1 << 26) - 1}[mask]
+    r, sigma, e = 3, 1.5, 0.61
+    E = np.full((3, 9, 10, 11), e)
+    S = oracle_mod.dcs(E, r, sigma, (m, m, m))
+    steps = _ray_steps(m)
+    expect = e * sum(1.0 - _g(s * math.sqrt(sum(c * c for c in st)), sigma)
+                     for st in steps for s in range(1, r + 1)) / (len(steps) * r)
+    assert np.abs(S - expect).max() <= 1e-14
+
+
+@pytest.mark.parametrize("mask", ["tx", "xy_body", "all26"])
+def test_dcs_spike_oriented(oracle_mod, mask):
+    """A unit spike of E at c, far from the faces: the spike sees S = 1; a voxel v sees one
+    term g(s |e|) for every ray e and step s with v + s e = c, so S(v) is the sum of those
+    terms over Q (each voxel's value is built here from the spike's side)."""
+    m = {"tx": oracle_mod.RAY_DIAG_TX, "xy_body": oracle_mod.RAY_DIAG_XY | oracle_mod.RAY_BODY,
+         "all26": (1 << 26) - 1}[mask]
+    r, sigma = 3, 1.7
+    shape, c = (13, 14, 15), (6, 7, 7)
+    E = np.zeros((3,) + shape)
+    E[1][c] = 1.0
+    S = oracle_mod.dcs(E, r, sigma, (0, m, 0))[1]
+    steps = _ray_steps(m)
+    Q = len(steps) * r
+    want = np.zeros(shape)
+    for st in steps:
+        for s in range(1, r + 1):
+            v = tuple(ci - s * ei for ci, ei in zip(c, st))
+            want[v] += _g(s * math.sqrt(sum(x * x for x in st)), sigma) / Q
+    want[c] = 1.0
+    assert np.abs(S - want).max() <= 1e-15
+
+
+def test_dcs_tx_diagonal_transpose(oracle_mod):
+    """The four t-x diagonals are symmetric under swapping t and x: transposed E gives the
+    transposed map."""
+    E = np.random.default_rng(5).random((3, 11, 12, 9))
+    m = oracle_mod.RAY_DIAG_TX
+    S = oracle_mod.dcs(E, 2, 1.3, (m, m, m))
+    St = oracle_mod.dcs(np.ascontiguousarray(E.transpose(0, 2, 1, 3)), 2, 1.3, (m, m, m))
+    assert np.abs(St.transpose(0, 2, 1, 3) - S).max() <= 1e-14
+
+
 # ------------------------------------------------------- Eq. (6) and normalisation -------
 
 def test_combine_closed_form(oracle_mod):
