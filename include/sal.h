@@ -63,10 +63,18 @@ typedef enum {
 /* In every 16-bit form each contraction stage rounds its input to the 16-bit type and
  * scales its FP32 output by 1/L (exact), so FP16 forms need |V| < 65504. */
 
-/* Rays of the directional comparison of Eq. (5): +t, -t, +x, -x, +y, -y. */
+/* Rays of the directional comparison of Eq. (5), one bit each.  Bits 0-5: the axis rays
+ * +t, -t, +x, -x, +y, -y.  Oriented rays (Fig. 3 shows a t-x diagonal comparison): bits
+ * 6-9 the t-x diagonals with step (t, x) = (+1,+1), (-1,-1), (+1,-1), (-1,+1); bits 10-13
+ * the t-y and bits 14-17 the x-y diagonals in the same sign order; bits 18-25 the body
+ * diagonals, bit 18 + k stepping -1 along t, x, y where bit 0, 1, 2 of k is set, else +1.
+ * The s-th sample of a ray with step e is v + s e, weighted by
+ * exp(-|s e|^2 / (2 sigma^2)). */
 enum {
     SAL_RAY_PT = 1, SAL_RAY_MT = 2, SAL_RAY_PX = 4,
-    SAL_RAY_MX = 8, SAL_RAY_PY = 16, SAL_RAY_MY = 32
+    SAL_RAY_MX = 8, SAL_RAY_PY = 16, SAL_RAY_MY = 32,
+    SAL_RAY_DIAG_TX = 0xF << 6, SAL_RAY_DIAG_TY = 0xF << 10, SAL_RAY_DIAG_XY = 0xF << 14,
+    SAL_RAY_BODY = 0xFF << 18, SAL_RAY_ALL = (1 << 26) - 1
 };
 
 /* Length of the statistics vector written by sal_saliency:
@@ -80,9 +88,9 @@ typedef struct {
                            the line is r = floor(d/2) neighbours on each enabled ray. */
     double sigma;       /* width of the Gaussian neighbour weight w(s) = exp(-s^2/(2 sigma^2))
                            of Eq. (5); the paper gives none, default d/4. */
-    uint32_t rays[3];   /* SAL_RAY_* masks used by S_t, S_x, S_y; default {+-t, +-x, +-y}
-                           ("along t, x and y respectively", after Fig. 3). */
-    double a, b, c;     /* weights of Eq. (6); default 1/3 each ("equal weights"). */
+    uint32_t rays[3];   /* SAL_RAY_* masks used by S_t, S_x, S_y; default {+-t, +-x, +-y}:
+                           each map compares along its own axis (Sec. 2, after Fig. 3). */
+    double a, b, c;     /* weights of Eq. (6); default 1/3 each (equal shares, Sec. 2). */
     int32_t normalize;  /* 1: map each S_m to [0,1] by its volume-wide min and max before
                            Eq. (6) (default); 0: combine the raw maps. */
     double zero_range;  /* a component whose range is <= zero_range * max|V| has no

@@ -348,8 +348,8 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
     if (p->d < 2 || p->d > 64) return fail(nullptr, SAL_E_INVAL, "d must be in [2, 64]");
     if (!(p->sigma > 0.0)) return fail(nullptr, SAL_E_INVAL, "sigma must be > 0 (may be inf)");
     for (int m = 0; m < 3; ++m)
-        if (p->rays[m] == 0 || p->rays[m] > 63u)
-            return fail(nullptr, SAL_E_INVAL, "each ray mask must be a nonempty subset of 6 rays");
+        if (p->rays[m] == 0 || p->rays[m] > (uint32_t)SAL_RAY_ALL)
+            return fail(nullptr, SAL_E_INVAL, "each ray mask must be a nonempty subset of the 26 rays");
     if (p->precision < SAL_FP32 || p->precision > SAL_FP16_SPLITW)
         return fail(nullptr, SAL_E_INVAL, "unknown precision");
     if (!(p->zero_range >= 0.0)) return fail(nullptr, SAL_E_INVAL, "zero_range must be >= 0");
@@ -371,11 +371,15 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
     c->h = p->L / 2 + 1;
     c->r = p->d / 2;
     c->nrows = (c->h - 2) * c->L + 2 * (c->L / 2 + 1);
-    for (int s = 0; s < 32; ++s)
-        c->g[s] = (s < c->r) ? (float)std::exp(-(double)((s + 1) * (s + 1)) / (2.0 * p->sigma * p->sigma)) : 0.f;
+    // neighbour weights at distance s |e| for the three step lengths |e|^2 = 1, 2, 3
+    for (int k = 1; k <= 3; ++k)
+        for (int s = 0; s < 32; ++s)
+            c->g[32 * (k - 1) + s] = (s < c->r) ? (float)std::exp(-(double)((s + 1) * (s + 1) * k) /
+                                                                  (2.0 * p->sigma * p->sigma))
+                                                : 0.f;
     for (int m = 0; m < 3; ++m) {
         int nr = 0;
-        for (int b = 0; b < 6; ++b) nr += (p->rays[m] >> b) & 1;
+        for (int b = 0; b < 26; ++b) nr += (p->rays[m] >> b) & 1;
         c->Q[m] = (float)(nr * c->r);
         c->q_inv[m] = 1.0f / c->Q[m];
     }

@@ -31,7 +31,7 @@ struct sal_ctx {
     sal_params p;
     int device;
     int L, H, h, r, nrows;
-    float g[32];       // Gaussian neighbour weights w(s), s = 1..r (index s-1)
+    float g[96];       // Gaussian neighbour weights w(s |e|), s = 1..r (index 32 (|e|^2 - 1) + s - 1)
     float q_inv[3];    // unused by the kernels (kept for diagnostics)
     float Q[3];        // number of terms of Eq. (5) per component
     float tw_host[32]; // e^{-2 pi i k / L} (re, im), k < L
@@ -48,8 +48,32 @@ struct dcs_args {
     int r;
     uint32_t rays[3];
     float Q[3];
-    float g[32];
+    float g[96];  // w(s |e|) at index 32 (|e|^2 - 1) + s - 1
 };
+
+// Step (t, x, y) of ray bit b of a comparison mask (axis rays, face and body diagonals;
+// the bit layout of SAL_RAY_*).
+__host__ __device__ inline void ray_step(int b, int &dt, int &dx, int &dy)
+{
+    dt = dx = dy = 0;
+    if (b < 6) {
+        const int d = (b & 1) ? -1 : 1;
+        if (b < 2) dt = d;
+        else if (b < 4) dx = d;
+        else dy = d;
+    } else if (b < 18) {
+        const int pl = (b - 6) >> 2, k = (b - 6) & 3;
+        const int s0 = (k == 0 || k == 2) ? 1 : -1, s1 = (k == 0 || k == 3) ? 1 : -1;
+        if (pl == 0) { dt = s0; dx = s1; }
+        else if (pl == 1) { dt = s0; dy = s1; }
+        else { dx = s0; dy = s1; }
+    } else {
+        const int k = b - 18;
+        dt = (k & 1) ? -1 : 1;
+        dx = (k & 2) ? -1 : 1;
+        dy = (k & 4) ? -1 : 1;
+    }
+}
 
 // Output box of the fused kernels: E is computed for the volume positions o + [0, d) and
 // stored box-local as [3][d0][d1][d2]; windows still read the whole volume (reflected at

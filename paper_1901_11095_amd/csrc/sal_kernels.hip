@@ -278,34 +278,35 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
 
 // ------------------------------------------------------------------------------------
 // Step 4, Eq. (5): grid-stride over voxels, one voxel per thread and trip; neighbours are
-// read through the caches.  The bounded grid keeps the min/max partials few.
+// read through the caches.  The bounded grid keeps the min/max partials few.  Handles every
+// ray of the 26-neighbourhood (the oriented comparisons of Fig. 3): each coordinate of a
+// neighbour is reflected at the volume faces, and the weight is the Gaussian of its
+// Euclidean distance s |e|.  Sums run over the ray bits in order, then the steps.
 __global__ __launch_bounds__(256) void k_dcs(const float *__restrict__ E, int n0, int n1, int n2,
                                              dcs_args a, float *__restrict__ S,
                                              float *__restrict__ mm_part)
 {
     const int64_t N = (int64_t)n0 * n1 * n2;
     float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-    const int dims[3] = {n0, n1, n2};
-    const int64_t stride[3] = {(int64_t)n1 * n2, n2, 1};
     for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256) {
         const int y = (int)(v % n2);
         const int64_t rest = v / n2;
         const int x = (int)(rest % n1);
         const int t = (int)(rest / n1);
-        const int pos[3] = {t, x, y};
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const float *Em = E + m * N;
             const float c = Em[v];
             float sum = 0.f;
-            for (int b = 0; b < 6; ++b) {
+            for (int b = 0; b < 26; ++b) {
                 if (!((a.rays[m] >> b) & 1u)) continue;
-                const int ax = b >> 1;
-                const int dir = (b & 1) ? -1 : 1;
-                const int64_t base = v - (int64_t)pos[ax] * stride[ax];
+                int dt, dx, dy;
+                ray_step(b, dt, dx, dy);
+                const float *gw = a.g + 32 * (dt * dt + dx * dx + dy * dy - 1);
                 for (int s = 1; s <= a.r; ++s) {
-                    const int u = refl_idx(pos[ax] + dir * s, dims[ax]);
-                    sum += fabsf(c - a.g[s - 1] * Em[base + (int64_t)u * stride[ax]]);
+                    const int ut = refl_idx(t + dt * s, n0), ux = refl_idx(x + dx * s, n1),
+                              uy = refl_idx(y + dy * s, n2);
+                    sum += fabsf(c - gw[s - 1] * Em[((int64_t)ut * n1 + ux) * n2 + uy]);
                 }
             }
             const float sv = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
@@ -360,14 +361,16 @@ __global__ __launch_bounds__(256) void k_dcs_box(const float *__restrict__ Eb, i
             const float *Em = Eb + m * NE;
             const float c = Em[v];
             float sum = 0.f;
-            for (int b = 0; b < 6; ++b) {
+            for (int b = 0; b < 26; ++b) {
                 if (!((a.rays[m] >> b) & 1u)) continue;
-                const int ax = b >> 1;
-                const int dir = (b & 1) ? -1 : 1;
-                const int64_t base = v - (int64_t)(pos[ax] - org[ax]) * stride[ax];
+                int st[3];
+                ray_step(b, st[0], st[1], st[2]);
+                const float *gw = a.g + 32 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2] - 1);
                 for (int s = 1; s <= a.r; ++s) {
-                    const int u = refl_idx(pos[ax] + dir * s, dims[ax]) - org[ax];
-                    sum += fabsf(c - a.g[s - 1] * Em[base + (int64_t)u * stride[ax]]);
+                    int u[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) u[k] = refl_idx(pos[k] + st[k] * s, dims[k]) - org[k];
+                    sum += fabsf(c - gw[s - 1] * Em[u[0] * stride[0] + u[1] * stride[1] + u[2]]);
                 }
             }
             S[(int64_t)m * nb + i] = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
@@ -542,6 +545,7 @@ static int64_t dcs_tiled_lds_floats(const uint32_t rays[3], int r)
 {
     int64_t tot = 0;
     for (int m = 0; m < 3; ++m) {
+        if (rays[m] & ~63u) return INT64_MAX / 2;  // oriented rays: the grid-stride kernel
         const int ht = (rays[m] & 3u) ? r : 0, hx = (rays[m] & 12u) ? r : 0, hy = (rays[m] & 48u) ? r : 0;
         const int64_t hw = (int64_t)(DTX + 2 * hx) * (DTY + 2 * hy);
         if (hw > 256 * DMAXE) return INT64_MAX / 2;
@@ -810,7 +814,7 @@ hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, 
         a.rays[m] = c->p.rays[m];
         a.Q[m] = c->Q[m];
     }
-    for (int i = 0; i < 32; ++i) a.g[i] = c->g[i];
+    for (int i = 0; i < 96; ++i) a.g[i] = c->g[i];
     const int64_t nf = dcs_tiled_lds_floats(c->p.rays, c->r);
     const unsigned nb = (unsigned)dcs_num_blocks(c, n0, n1, n2);
     if (nf <= DCS_LDS_MAX_FLOATS) {
@@ -915,7 +919,7 @@ hipError_t launch_dcs_box(const sal_ctx *c, const float *Eb, const int64_t eo[3]
         a.rays[m] = c->p.rays[m];
         a.Q[m] = c->Q[m];
     }
-    for (int i = 0; i < 32; ++i) a.g[i] = c->g[i];
+    for (int i = 0; i < 96; ++i) a.g[i] = c->g[i];
     const int64_t nb = bd[0] * bd[1] * bd[2];
     const unsigned blocks = (unsigned)((nb + 255) / 256 < 4096 ? (nb + 255) / 256 : 4096);
     auto i3 = [](const int64_t *v) { return make_int3((int)v[0], (int)v[1], (int)v[2]); };

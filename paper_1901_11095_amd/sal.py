@@ -20,6 +20,9 @@ PRECISION_NAMES = {FP32: "fp32", BF16: "bf16", BF16_SPLIT: "bf16_split", FP16: "
                    FP16_SPLIT: "fp16_split", BF16_SPLITW: "bf16_splitw",
                    FP16_SPLITW: "fp16_splitw"}
 RAY_PT, RAY_MT, RAY_PX, RAY_MX, RAY_PY, RAY_MY = 1, 2, 4, 8, 16, 32
+# oriented rays (bit layout of SAL_RAY_* in sal.h): t-x, t-y, x-y diagonals, body diagonals
+RAY_DIAG_TX, RAY_DIAG_TY, RAY_DIAG_XY, RAY_BODY = 0xF << 6, 0xF << 10, 0xF << 14, 0xFF << 18
+RAY_ALL = (1 << 26) - 1
 RAYS_AXIS = (RAY_PT | RAY_MT, RAY_PX | RAY_MX, RAY_PY | RAY_MY)
 RAYS_ALL = (63, 63, 63)
 STATS_LEN = 7
