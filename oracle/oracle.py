@@ -74,6 +74,10 @@ def lib() -> ctypes.CDLL:
         l.oracle_raw_box.argtypes = [_fp, _L, _L, _L, _L, _L, ctypes.c_double, _up, _lp, _lp,
                                      _dp, _dp]
         l.oracle_raw_box.restype = ctypes.c_int
+        l.oracle_energy_lattice.argtypes = [_fp, _L, _L, _L, _L, _L, _dp]
+        l.oracle_upsample.argtypes = [_dp, _L, _L, _L, _L, _dp]
+        l.oracle_saliency_strided.argtypes = [_fp, _L, _L, _L, _L, _L, _L, ctypes.c_double, _up, _dp,
+                                              ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
         l.oracle_gelu.argtypes = [ctypes.c_double]
         l.oracle_gelu.restype = ctypes.c_double
         l.oracle_gelu_grad.argtypes = [ctypes.c_double]
@@ -96,6 +100,7 @@ class Params:
     abc: tuple = (1.0 / 3, 1.0 / 3, 1.0 / 3)  # Eq. (6) weights, equal (Sec. 2, last para.)
     normalize: int = 1
     zero_range: float = 1e-6
+    stride: int = 1                 # window lattice stride (Sec. 2 first step: overlap > 50%)
 
     @property
     def r(self) -> int:
@@ -209,9 +214,36 @@ def saliency(V, p: Params = Params()):
     Sr = np.zeros((3,) + V.shape, np.float64)
     stats = np.zeros(6, np.float64)
     w = np.asarray(p.abc, np.float64)
-    lib().oracle_saliency(pV, *V.shape, p.L, p.r, float(p.sig), _rays(p.rays), _d(w),
-                          int(p.normalize), float(p.zero_range), _d(S), _d(E), _d(Sr), _d(stats))
+    if p.stride == 1:
+        lib().oracle_saliency(pV, *V.shape, p.L, p.r, float(p.sig), _rays(p.rays), _d(w),
+                              int(p.normalize), float(p.zero_range), _d(S), _d(E), _d(Sr), _d(stats))
+    else:
+        lib().oracle_saliency_strided(pV, *V.shape, p.L, p.stride, p.r, float(p.sig), _rays(p.rays),
+                                      _d(w), int(p.normalize), float(p.zero_range), _d(S), _d(E),
+                                      _d(Sr), _d(stats))
     return {"S": S, "E": E, "S_raw": Sr, "stats": stats}
+
+
+def lattice_shape(shape, s: int):
+    return tuple((n + s - 1) // s for n in shape)
+
+
+def energy_lattice(V, L: int, s: int) -> np.ndarray:
+    """Energies E_t, E_x, E_y of the windows at the lattice positions k s (Sec. 2, first and
+    third steps, strided windows): double [3][K0][K1][K2]."""
+    V, pV = _f32(V)
+    E = np.zeros((3,) + lattice_shape(V.shape, s), np.float64)
+    lib().oracle_energy_lattice(pV, *V.shape, L, s, _d(E))
+    return E
+
+
+def upsample(E_lat, s: int, shape) -> np.ndarray:
+    """Trilinear interpolation of lattice values [3][K...] onto the full grid [3][shape]."""
+    E_lat = np.ascontiguousarray(E_lat, np.float64)
+    assert E_lat.shape[1:] == lattice_shape(shape, s)
+    E = np.zeros((3,) + tuple(shape), np.float64)
+    lib().oracle_upsample(_d(E_lat), s, *shape, _d(E))
+    return E
 
 
 def raw_box(V, p: Params, lo, bn):

@@ -392,6 +392,85 @@ void oracle_saliency(const float *V, long n0, long n1, long n2, long L, long r, 
 }
 
 /*
+ * Strided windows -- Sec. 2, first step: the sliding cube only has to overlap its
+ * neighbours by more than half, so windows may sit on a lattice of stride s < L/2 while
+ * the map keeps the size of V.
+ * reading: the lattice holds the positions k s, k = 0 .. ceil(n/s) - 1, along every axis;
+ * the energies of Sec. 2 (third step) are computed there, and every voxel takes the
+ * trilinear interpolation of the lattice points around it (beyond the last lattice point
+ * of an axis the last value is held).  Eq. (5) and Eq. (6) then run on the full grid.
+ * E_lat: double [3][K0][K1][K2] with K_a = ceil(n_a / s).
+ */
+void oracle_energy_lattice(const float *V, long n0, long n1, long n2, long L, long s, double *E_lat)
+{
+    const long K0 = (n0 + s - 1) / s, K1 = (n1 + s - 1) / s, K2 = (n2 + s - 1) / s;
+    const long nk = K0 * K1 * K2;
+#pragma omp parallel
+    {
+        double *F = (double *)malloc(sizeof(double) * 2 * L * L * L);
+#pragma omp for schedule(dynamic, 16)
+        for (long v = 0; v < nk; ++v) {
+            long a = v / (K1 * K2), b = (v / K2) % K1, c = v % K2;
+            double e[3];
+            oracle_window_spectrum(V, n0, n1, n2, a * s, b * s, c * s, L, F);
+            oracle_project(F, L, e);
+            for (int m = 0; m < 3; ++m) E_lat[m * nk + v] = e[m];
+        }
+        free(F);
+    }
+}
+
+/* Trilinear interpolation of lattice values (stride s) onto the full grid n0 x n1 x n2. */
+void oracle_upsample(const double *E_lat, long s, long n0, long n1, long n2, double *E)
+{
+    const long K[3] = {(n0 + s - 1) / s, (n1 + s - 1) / s, (n2 + s - 1) / s};
+    const long nk = K[0] * K[1] * K[2], nv = n0 * n1 * n2;
+    for (long v = 0; v < nv; ++v) {
+        const long pos[3] = {v / (n1 * n2), (v / n2) % n1, v % n2};
+        long k0[3], k1[3];
+        double f[3];
+        for (int a = 0; a < 3; ++a) {
+            k0[a] = pos[a] / s;
+            k1[a] = k0[a] + 1 < K[a] ? k0[a] + 1 : k0[a];
+            f[a] = k1[a] == k0[a] ? 0.0 : (double)(pos[a] - k0[a] * s) / (double)s;
+        }
+        for (int m = 0; m < 3; ++m) {
+            double acc = 0.0;
+            for (int corner = 0; corner < 8; ++corner) {
+                long idx[3];
+                double w = 1.0;
+                for (int a = 0; a < 3; ++a) {
+                    int hi = (corner >> (2 - a)) & 1;
+                    idx[a] = hi ? k1[a] : k0[a];
+                    w *= hi ? f[a] : 1.0 - f[a];
+                }
+                acc += w * E_lat[m * nk + (idx[0] * K[1] + idx[1]) * K[2] + idx[2]];
+            }
+            E[m * nv + v] = acc;
+        }
+    }
+}
+
+/* The whole method with windows on the stride-s lattice (s = 1 is oracle_saliency). */
+void oracle_saliency_strided(const float *V, long n0, long n1, long n2, long L, long s, long r,
+                             double sigma, const uint32_t rays[3], const double abc[3], int normalize,
+                             double zero_range, double *S, double *E_out, double *S_raw_out, double *stats)
+{
+    const long nvox = n0 * n1 * n2;
+    const long nk = ((n0 + s - 1) / s) * ((n1 + s - 1) / s) * ((n2 + s - 1) / s);
+    double *E_lat = (double *)malloc(sizeof(double) * 3 * nk);
+    double *E = E_out ? E_out : (double *)malloc(sizeof(double) * 3 * nvox);
+    double *Sr = S_raw_out ? S_raw_out : (double *)malloc(sizeof(double) * 3 * nvox);
+    oracle_energy_lattice(V, n0, n1, n2, L, s, E_lat);
+    oracle_upsample(E_lat, s, n0, n1, n2, E);
+    oracle_dcs(E, n0, n1, n2, r, sigma, rays, Sr);
+    oracle_combine(Sr, nvox, abc, normalize, zero_range, oracle_absmax(V, nvox), S, stats);
+    free(E_lat);
+    if (!E_out) free(E);
+    if (!S_raw_out) free(Sr);
+}
+
+/*
  * Raw maps (E and S_raw) of the box [lo, lo+bn) of a large volume, without computing the
  * whole volume: energies are evaluated on the box grown by r on every side (clipped to
  * the volume), which holds every neighbour Eq. (5) reads, reflected ones included.

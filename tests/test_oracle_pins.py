@@ -305,6 +305,62 @@ def test_dcs_tx_diagonal_transpose(oracle_mod):
     assert np.abs(St.transpose(0, 2, 1, 3) - S).max() <= 1e-14
 
 
+# ----------------------------------------------------------- strided windows ------------
+
+def test_stride_one_is_the_plain_method(oracle_mod):
+    """A lattice of stride 1 holds every voxel: the strided path is the plain one exactly."""
+    V = synth.make_volume((11, 12, 13), seed=4)
+    a = oracle_mod.saliency(V, oracle_mod.Params(L=4))
+    lat = oracle_mod.energy_lattice(V, 4, 1)
+    E1 = oracle_mod.upsample(lat, 1, V.shape)
+    assert np.array_equal(E1, a["E"])
+
+
+@pytest.mark.parametrize("s,shape", [(2, (9, 10, 11)), (3, (13, 7, 8))])
+def test_upsample_reproduces_trilinear_functions(oracle_mod, s, shape):
+    """Trilinear interpolation is exact for functions linear in each coordinate: lattice
+    samples of f = a + b t + c x + d y + e t x y give f at every voxel inside the last lattice
+    point, and beyond it the value at the last lattice point along that axis."""
+    K = oracle_mod.lattice_shape(shape, s)
+    f = lambda t, x, y, m: (1.5 + m) + 0.25 * t - 0.5 * x + 0.125 * y + 0.01 * t * x * y  # noqa: E731
+    lat = np.zeros((3,) + K)
+    for idx in np.ndindex(*K):
+        for m in range(3):
+            lat[(m,) + idx] = f(*(s * k for k in idx), m)
+    E = oracle_mod.upsample(lat, s, shape)
+    last = [s * (k - 1) for k in K]
+    for pos in np.ndindex(*shape):
+        q = [min(p_, l_) for p_, l_ in zip(pos, last)]
+        for m in range(3):
+            assert abs(E[(m,) + pos] - f(*q, m)) <= 1e-12
+
+
+def test_lattice_energies_are_window_energies(oracle_mod):
+    """Every lattice energy is the energy of the window at k s (brute-force window DFT)."""
+    V = synth.random_volume((9, 8, 10), seed=2)
+    L, s = 4, 2
+    lat = oracle_mod.energy_lattice(V, L, s)
+    for idx in [(0, 0, 0), (4, 3, 4), (2, 1, 3)]:
+        t, x, y = (s * k for k in idx)
+        f = _window(V, t, x, y, L)
+        F = _dft_bruteforce(f)
+        e = oracle_mod.project(F)
+        assert np.abs(lat[(slice(None),) + idx] - e).max() <= 1e-12
+
+
+def test_strided_plane_wave(oracle_mod):
+    """An interior plane wave has the same energy in every window, so the interpolated
+    energies equal the plain ones away from the faces."""
+    L, s = 4, 2
+    n = 16
+    t, x, y = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    V = np.cos(2 * np.pi * (1 * t + 1 * x + 2 * y) / L).astype(np.float32)
+    a = oracle_mod.saliency(V, oracle_mod.Params(L=L))
+    b = oracle_mod.saliency(V, oracle_mod.Params(L=L, stride=s))
+    sl = (slice(None), slice(L, n - L), slice(L, n - L), slice(L, n - L))
+    assert np.abs(a["E"][sl] - b["E"][sl]).max() <= 1e-12
+
+
 # ------------------------------------------------------- Eq. (6) and normalisation -------
 
 def test_combine_closed_form(oracle_mod):
