@@ -96,6 +96,11 @@ typedef struct {
     double zero_range;  /* a component whose range is <= zero_range * max|V| has no
                            contrast and contributes 0 (default 1e-6). */
     int32_t precision;  /* sal_precision, default SAL_FP32 */
+    int32_t stride;     /* window stride s (Sec. 2 step 1 needs more than 50% overlap, s < L/2):
+                           1 (default) = one window per voxel; 2 = windows on the lattice of
+                           even positions (L >= 5), energies interpolated trilinearly to every
+                           voxel, the last lattice value held at the far faces; Eq. (5) and
+                           Eq. (6) on the full grid.  Other values: SAL_E_UNSUPPORTED. */
 } sal_params;
 
 /* Fill *p with the defaults above for cube side L. */

@@ -264,19 +264,31 @@ void free_tables(sal_tables *t)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t e, s_raw, vmax, mm, stats, total;
+    size_t e, s_raw, vmax, mm, stats, e_lat, total;
 };
+
+// lattice sizes K = ceil(n / stride) of the window positions
+void lattice_dims(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2, int64_t K[3])
+{
+    const int S = c->p.stride;
+    K[0] = (n0 + S - 1) / S;
+    K[1] = (n1 + S - 1) / S;
+    K[2] = (n2 + S - 1) / S;
+}
 
 WsLayout ws_layout(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 {
     const size_t N = (size_t)n0 * n1 * n2;
+    int64_t K[3];
+    lattice_dims(c, n0, n1, n2, K);
     WsLayout w;
     w.e = 0;
     w.s_raw = w.e + align256(3 * N * sizeof(float));
     w.vmax = w.s_raw + align256(3 * N * sizeof(float));
     w.mm = w.vmax + align256((size_t)energy_num_blocks(c, n0, n1, n2) * sizeof(float));
     w.stats = w.mm + align256((size_t)dcs_num_blocks(c, n0, n1, n2) * 6 * sizeof(float));
-    w.total = w.stats + align256(8 * sizeof(double));
+    w.e_lat = w.stats + align256(8 * sizeof(double));
+    w.total = w.e_lat + (c->p.stride > 1 ? align256((size_t)3 * K[0] * K[1] * K[2] * sizeof(float)) : 0);
     return w;
 }
 
@@ -338,6 +350,7 @@ void sal_default_params(sal_params *p, int32_t L)
     p->normalize = 1;
     p->zero_range = 1e-6;
     p->precision = SAL_FP32;
+    p->stride = 1;
 }
 
 sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
@@ -357,6 +370,10 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
         return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements L = 2..8 and L = 16");
     if (p->L < 8 && p->precision != SAL_FP32)
         return fail(nullptr, SAL_E_UNSUPPORTED, "L < 8 runs in FP32 only");
+    if (p->stride < 1) return fail(nullptr, SAL_E_INVAL, "stride must be >= 1");
+    if (p->stride > 2) return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements stride 1 and 2");
+    if (p->stride == 2 && 2 * p->stride >= p->L)
+        return fail(nullptr, SAL_E_INVAL, "stride must be below L/2 (windows overlap by more than half)");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(nullptr, SAL_E_DEVICE, "no such HIP device");
@@ -492,7 +509,18 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     hipEvent_t *ev = take_events(c);
     int nv = 0;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipError_t e = launch_energy(c, V, n0, n1, n2, nullptr, E, vmax, &nv, s);
+    hipError_t e;
+    if (c->p.stride > 1) {
+        // windows on the lattice, energies interpolated onto every voxel
+        int64_t K[3];
+        lattice_dims(c, n0, n1, n2, K);
+        float *El = (float *)(ws + w.e_lat);
+        e = launch_energy(c, V, n0, n1, n2, nullptr, El, vmax, &nv, s);
+        if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+        e = launch_upsample(El, K[0], K[1], K[2], c->p.stride, n0, n1, n2, E, s);
+    } else {
+        e = launch_energy(c, V, n0, n1, n2, nullptr, E, vmax, &nv, s);
+    }
     if (e != hipSuccess) return dev_fail(c, e, "energy launch");
     if (ev) (void)hipEventRecord(ev[1], s);
     e = launch_dcs(c, E, n0, n1, n2, Sr, mm, s);
@@ -545,6 +573,7 @@ sal_status sal_raw_box(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64
     if (!V || !box_lo || !box_dims || !S_raw_box || !workspace) return fail(c, SAL_E_INVAL, "null pointer");
     if (!aligned16(V) || !aligned16(S_raw_box) || !aligned16(workspace))
         return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    if (c->p.stride != 1) return fail(c, SAL_E_UNSUPPORTED, "box maps are computed with stride 1 only");
     sal_status st = check_dims(c, n0, n1, n2);
     if (st != SAL_OK) return st;
     const int64_t n[3] = {n0, n1, n2};

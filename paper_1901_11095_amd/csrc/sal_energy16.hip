@@ -82,7 +82,7 @@ __device__ __forceinline__ u32x4 lds4(const uint32_t *p) { return u32x4{p[0], p[
 
 }  // namespace
 
-template <int L, typename T, bool DS>
+template <int L, typename T, bool DS, int S>
 __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
     const uint32_t *__restrict__ w_c16, const uint32_t *__restrict__ w_a16,
@@ -94,7 +94,8 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     constexpr int H = G::H, h = G::h, MT = G::MT, MTA = G::MTA;
     constexpr int J = L / 8;  // 16x16x32 MFMAs per split complex contraction (K = 4L)
     constexpr int NW = C::NW, TY = C::TY;
-    constexpr int PX = NW + L - 1, PY = TY + L - 1;
+    // windows of x-rows and y-columns S apart (S = 2: the half-resolution lattice)
+    constexpr int PX = S * (NW - 1) + L, PY = S * (TY - 1) + L;
     constexpr int NTB = (PY + 15) / 16, PYB = NTB * 16, NTC = TY / 16;
     constexpr int NPOS = PX * PY, NTA = (NPOS + 15) / 16, NJ = (NTA + NW - 1) / NW;
     constexpr int NGK = L / 2 + 1;
@@ -111,9 +112,10 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     const int g = lane >> 4, n = lane & 15;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
-    const int y_base = bx.o2 + ty * TY, x_base = bx.o1 + tx * NW;
-    const int t_begin = bx.o0 + tb * tt_len;
-    const int t_end = min(bx.o0 + bx.d0, t_begin + tt_len);
+    const int y_base = bx.o2 + S * ty * TY, x_base = bx.o1 + S * tx * NW;
+    const int t_begin = bx.o0 + S * tb * tt_len;
+    const int t_end = min(bx.o0 + bx.d0, t_begin + S * tt_len);
+    const int K1 = (bx.d1 + S - 1) / S, K2 = (bx.d2 + S - 1) / S;
 
     u32x4 wc[MT][J], wa[MTA];
 #pragma unroll
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
         off_xy[jj] = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
     }
     const int64_t plane = (int64_t)n1 * n2;
-    const int64_t nbox = (int64_t)bx.d0 * bx.d1 * bx.d2;
+    const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
     float vmax = 0.0f;
     uint32_t *Bw = B_s[wave][0];
     uint32_t *Bw_lo = B_s[wave][NP - 1];
@@ -152,14 +154,14 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     };
     load_a(t_begin);
 
-    for (int t0 = t_begin; t0 < t_end; ++t0) {
+    for (int t0 = t_begin; t0 < t_end; t0 += S) {
         __syncthreads();
         float vcur[NJ][4];
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj)
 #pragma unroll
             for (int e = 0; e < 4; ++e) vcur[jj][e] = vnext[jj][e];
-        if (t0 + 1 < t_end) load_a(t0 + 1);
+        if (t0 + S < t_end) load_a(t0 + S);
         // ---------------- stage A: real DFT along t -------------------------------------
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
                 for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
-                    const int ao = (mu * PY + yp) * PX + wave + 8 * j + qoff;
+                    const int ao = (mu * PY + yp) * PX + S * wave + 8 * j + qoff;
                     const u32x4 b = lds4(&A_s[0][ao]);
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
                 }
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
-                    const int y0 = c * 16 + n;
+                    const int y0 = S * (c * 16 + n);
                     f4 acc[MT];
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        const int x = x_base + wave;
+        const int x = x_base + S * wave;
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
 #pragma unroll
@@ -310,9 +312,9 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
                 s += __shfl_xor(s, 32);
                 e[c][m] = s;
             }
-            const int y = y_base + c * 16 + n;
+            const int y = y_base + S * (c * 16 + n);
             if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
-                const int64_t o = ((int64_t)(t0 - bx.o0) * bx.d1 + (x - bx.o1)) * bx.d2 + (y - bx.o2);
+                const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
                 E[o] = e[c][0];
                 E[nbox + o] = e[c][1];
                 E[2 * nbox + o] = e[c][2];
@@ -335,9 +337,14 @@ static hipError_t launch_h(const sal_ctx *c, const float *V, int64_t n0, int64_t
                            const ebox &bx, float *E, float *vmax_part, int nby, int nbx, int tt,
                            int64_t nb, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_energy_h<L, T, DS>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s,
-                       V, (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
-                       c->t.w_bin, E, vmax_part);
+    if (c->p.stride == 2)
+        hipLaunchKernelGGL((k_energy_h<L, T, DS, 2>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s,
+                           V, (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
+                           c->t.w_bin, E, vmax_part);
+    else
+        hipLaunchKernelGGL((k_energy_h<L, T, DS, 1>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s,
+                           V, (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
+                           c->t.w_bin, E, vmax_part);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ __device__ __forceinline__ float2 cmad(float2 a, float2 w, float2 acc)
 
 }  // namespace
 
-template <int L>
+template <int L, int S>
 __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V, int n0, int n1, int n2, ebox bx,
                                                     int tt_len, int nby, int nbx, GenTw<L> tw,
                                                     const float *__restrict__ wgen, float *__restrict__ E,
@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
 {
     constexpr int H = L / 2, h = L / 2 + 1;
     constexpr int NX = GenCfg<L>::NX, NY = GenCfg<L>::NY;
-    constexpr int PX = NX + L - 1, PY = NY + L - 1, NP = PX * PY;
+    // windows of x-rows and y-columns S apart (S = 2: the half-resolution lattice)
+    constexpr int PX = S * (NX - 1) + L, PY = S * (NY - 1) + L, NP = PX * PY;
     constexpr int NW3 = h * L * L * 3;
     __shared__ float ring[L][NP];
     __shared__ float2 A_s[NP * h];
@@ -66,11 +67,12 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
     const int tid = threadIdx.x;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
-    const int y_base = bx.o2 + ty * NY, x_base = bx.o1 + tx * NX;
-    const int t_begin = bx.o0 + tb * tt_len;
-    const int t_end = min(bx.o0 + bx.d0, t_begin + tt_len);
+    const int y_base = bx.o2 + S * ty * NY, x_base = bx.o1 + S * tx * NX;
+    const int t_begin = bx.o0 + S * tb * tt_len;
+    const int t_end = min(bx.o0 + bx.d0, t_begin + S * tt_len);
     const int64_t plane = (int64_t)n1 * n2;
-    const int64_t nbox = (int64_t)bx.d0 * bx.d1 * bx.d2;
+    const int K1 = (bx.d1 + S - 1) / S, K2 = (bx.d2 + S - 1) / S;
+    const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
 
     for (int i = tid; i < NW3; i += 256) wg_s[i] = wgen[i];
     if (tid == 0)
@@ -89,11 +91,12 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
             ring[slot][p] = v;
         }
     };
-    for (int k = 0; k < L - 1; ++k) load_plane(t_begin - H + k);
+    for (int k = 0; k < L - S; ++k) load_plane(t_begin - H + k);
 
     const int x0 = tid / NY, y0 = tid - (tid / NY) * NY;
-    for (int t0 = t_begin; t0 < t_end; ++t0) {
-        load_plane(t0 - H + L - 1);
+    for (int t0 = t_begin; t0 < t_end; t0 += S) {
+        // the S planes that enter the windows of t0 (the ring slots of the S that left)
+        for (int k = L - S; k < L; ++k) load_plane(t0 - H + k);
         __syncthreads();
         // ---------------- stage A: real DFT along t, mu <= L/2 ---------------------------
         for (int p = tid; p < NP; p += 256) {
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
 #pragma unroll
                 for (int q = 0; q < L; ++q) {
                     // the twiddle index depends on nu, a run-time value here: read it from LDS
-                    acc = cmad(A_s[((xr + q) * PY + yp) * h + mu], tw_s[(nu * q) % L], acc);
+                    acc = cmad(A_s[((S * xr + q) * PY + yp) * h + mu], tw_s[(nu * q) % L], acc);
                 }
                 B_s[i] = acc;
             }
@@ -133,7 +136,7 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
             for (int nu = 0; nu < L; ++nu) {
                 float2 b[L];
 #pragma unroll
-                for (int r = 0; r < L; ++r) b[r] = B_s[(x0 * PY + y0 + r) * L + nu];
+                for (int r = 0; r < L; ++r) b[r] = B_s[(x0 * PY + S * y0 + r) * L + nu];
                 const float *w = &wg_s[(mu * L + nu) * L * 3];
 #pragma unroll
                 for (int om = 0; om < L; ++om) {
@@ -148,9 +151,9 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
             }
             __syncthreads();
         }
-        const int x = x_base + x0, y = y_base + y0;
+        const int x = x_base + S * x0, y = y_base + S * y0;
         if (x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
-            const int64_t o = ((int64_t)(t0 - bx.o0) * bx.d1 + (x - bx.o1)) * bx.d2 + (y - bx.o2);
+            const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
             E[o] = e0;
             E[nbox + o] = e1;
             E[2 * nbox + o] = e2;
@@ -189,15 +192,20 @@ template <int L>
 hipError_t launch_gen_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
                         float *E, float *vmax_part, int *nparts, hipStream_t s)
 {
+    const int S = c->p.stride;
     int nby, nbx, tt;
     int64_t nb;
-    gen_grid<L>(bx.d0, bx.d1, bx.d2, &nby, &nbx, &tt, &nb);
+    gen_grid<L>((bx.d0 + S - 1) / S, (bx.d1 + S - 1) / S, (bx.d2 + S - 1) / S, &nby, &nbx, &tt, &nb);
     if (nparts) *nparts = (int)nb;
     if (nb == 0) return hipSuccess;
     GenTw<L> tw;
     for (int k = 0; k < L; ++k) tw.w[k] = make_float2(c->tw_host[2 * k], c->tw_host[2 * k + 1]);
-    hipLaunchKernelGGL(k_energy_gen<L>, dim3((unsigned)nb), dim3(256), 0, s, V, (int)n0, (int)n1, (int)n2, bx, tt,
-                       nby, nbx, tw, c->t.w_gen, E, vmax_part);
+    if (S == 2 && L > 2)
+        hipLaunchKernelGGL((k_energy_gen<L, (L > 2 ? 2 : 1)>), dim3((unsigned)nb), dim3(256), 0, s, V, (int)n0,
+                           (int)n1, (int)n2, bx, tt, nby, nbx, tw, c->t.w_gen, E, vmax_part);
+    else
+        hipLaunchKernelGGL((k_energy_gen<L, 1>), dim3((unsigned)nb), dim3(256), 0, s, V, (int)n0, (int)n1,
+                           (int)n2, bx, tt, nby, nbx, tw, c->t.w_gen, E, vmax_part);
     return hipGetLastError();
 }
 

@@ -101,6 +101,8 @@ hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64
 hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
                       float *S_raw, float *minmax_part, hipStream_t s);
 int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
+hipError_t launch_upsample(const float *El, int64_t K0, int64_t K1, int64_t K2, int S, int64_t n0, int64_t n1,
+                           int64_t n2, float *E, hipStream_t s);
 hipError_t launch_dcs_box(const sal_ctx *c, const float *Eb, const int64_t eo[3], const int64_t ed[3],
                           const int64_t n[3], const int64_t bo[3], const int64_t bd[3], float *S,
                           hipStream_t s);

@@ -35,7 +35,7 @@
 // magnitudes are summed before weighting: one "group" per (mu, k), k = 0..L/2.
 // Floating-point MFMA and VALU work serialise on a SIMD on this chip, so the per-bin VALU
 // count (|F|^2, sqrt, three weighted sums) is kept minimal.
-template <int L>
+template <int L, int S>
 __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
     const float *__restrict__ w_c, const float *__restrict__ w_a,
@@ -45,7 +45,9 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     using C = TileCfg<L>;
     constexpr int H = G::H, h = G::h, KS = G::KS, MT = G::MT, KSA = G::KSA, MTA = G::MTA;
     constexpr int NW = C::NW, TY = C::TY;
-    constexpr int PX = NW + L - 1, PY = TY + L - 1;
+    // windows of the x-rows and y-columns S apart (S = 1: every voxel, S = 2: the
+    // half-resolution lattice) cover this patch
+    constexpr int PX = S * (NW - 1) + L, PY = S * (TY - 1) + L;
     constexpr int NTB = (PY + 15) / 16, PYB = NTB * 16, NTC = TY / 16;
     constexpr int NPOS = PX * PY, NTA = (NPOS + 15) / 16, NJ = (NTA + NW - 1) / NW;
     constexpr int NGK = L / 2 + 1;  // groups per mu
@@ -61,9 +63,11 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
-    const int y_base = bx.o2 + ty * TY, x_base = bx.o1 + tx * NW;
-    const int t_begin = bx.o0 + tb * tt_len;
-    const int t_end = min(bx.o0 + bx.d0, t_begin + tt_len);
+    const int y_base = bx.o2 + S * ty * TY, x_base = bx.o1 + S * tx * NW;
+    const int t_begin = bx.o0 + S * tb * tt_len;
+    const int t_end = min(bx.o0 + bx.d0, t_begin + S * tt_len);
+    // output grid: the positions o + S k of the box, K = ceil(d / S) along each axis
+    const int K1 = (bx.d1 + S - 1) / S, K2 = (bx.d2 + S - 1) / S;
 
     // constant MFMA A-operands: lane (g, n) holds row n of each M tile at K = KS*g + kk
     float wc[MT][KS];
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
         off_xy[jj] = gx * n2 + gy;
     }
     const int64_t plane = (int64_t)n1 * n2;
-    const int64_t nbox = (int64_t)bx.d0 * bx.d1 * bx.d2;
+    const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
     float vmax = 0.0f;
     float2 *Bw = B_s[wave];
 
@@ -105,14 +109,14 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     };
     load_a(t_begin);
 
-    for (int t0 = t_begin; t0 < t_end; ++t0) {
+    for (int t0 = t_begin; t0 < t_end; t0 += S) {
         __syncthreads();  // previous t0 is done with A_s
         float vcur[NJ][KSA];
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj)
 #pragma unroll
             for (int kk = 0; kk < KSA; ++kk) vcur[jj][kk] = vnext[jj][kk];
-        if (t0 + 1 < t_end) load_a(t0 + 1);
+        if (t0 + S < t_end) load_a(t0 + S);
         // ---------------- stage A: real DFT along t -------------------------------------
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
@@ -158,14 +162,14 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
                 if (self) {
 #pragma unroll
                     for (int kk = 0; kk < KS; kk += 2) {
-                        const float a = A_s[((wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu].x;
+                        const float a = A_s[((S * wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu].x;
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma4(wc[mt][kk], a, acc[mt]);
                     }
                 } else {
 #pragma unroll
                     for (int kk = 0; kk < KS; kk += 2) {
-                        const float2 a = A_s[((wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu];
+                        const float2 a = A_s[((S * wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu];
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
                             acc[mt] = mfma4(wc[mt][kk], a.x, acc[mt]);
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
                 }
 #pragma unroll
                 for (int c = 0; c < NTC; ++c) {
-                    const int y0 = c * 16 + n;
+                    const int y0 = S * (c * 16 + n);
                     f4 acc[MT];
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         // reduce the four lane groups (lanes n, n+16, n+32, n+48 hold the same voxel)
-        const int x = x_base + wave;
+        const int x = x_base + S * wave;
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
 #pragma unroll
@@ -255,9 +259,9 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
                 s += __shfl_xor(s, 32);
                 e[c][m] = s;
             }
-            const int y = y_base + c * 16 + n;
+            const int y = y_base + S * (c * 16 + n);
             if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
-                const int64_t o = ((int64_t)(t0 - bx.o0) * bx.d1 + (x - bx.o1)) * bx.d2 + (y - bx.o2);
+                const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
                 E[o] = e[c][0];
                 E[nbox + o] = e[c][1];
                 E[2 * nbox + o] = e[c][2];
@@ -336,6 +340,39 @@ __global__ __launch_bounds__(256) void k_dcs(const float *__restrict__ E, int n0
         float r = red[0][k];
         for (int w = 1; w < 4; ++w) r = (k & 1) ? fmaxf(r, red[w][k]) : fminf(r, red[w][k]);
         mm_part[(int64_t)blockIdx.x * 6 + k] = r;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Strided windows: energies on the lattice of stride S (El [3][K0][K1][K2], positions k S)
+// interpolated trilinearly onto every voxel; beyond the last lattice point of an axis the
+// last value is held.  Corners are summed in the order (t, x, y) = 000, 001, ..., 111.
+__global__ __launch_bounds__(256) void k_upsample(const float *__restrict__ El, int K0, int K1, int K2, int S,
+                                                  int n0, int n1, int n2, float *__restrict__ E)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2, NK = (int64_t)K0 * K1 * K2;
+    const float inv = 1.0f / (float)S;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256) {
+        const int y = (int)(v % n2);
+        const int64_t rest = v / n2;
+        const int x = (int)(rest % n1), t = (int)(rest / n1);
+        const int kt = t / S, kx = x / S, ky = y / S;
+        const int kt1 = min(kt + 1, K0 - 1), kx1 = min(kx + 1, K1 - 1), ky1 = min(ky + 1, K2 - 1);
+        const float ft = kt1 == kt ? 0.f : (float)(t - kt * S) * inv;
+        const float fx = kx1 == kx ? 0.f : (float)(x - kx * S) * inv;
+        const float fy = ky1 == ky ? 0.f : (float)(y - ky * S) * inv;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const float *P = El + m * NK;
+            float acc = 0.f;
+#pragma unroll
+            for (int corner = 0; corner < 8; ++corner) {
+                const int ht = (corner >> 2) & 1, hx = (corner >> 1) & 1, hy = corner & 1;
+                const float w = (ht ? ft : 1.f - ft) * (hx ? fx : 1.f - fx) * (hy ? fy : 1.f - fy);
+                acc = fmaf(w, P[((int64_t)(ht ? kt1 : kt) * K1 + (hx ? kx1 : kx)) * K2 + (hy ? ky1 : ky)], acc);
+            }
+            E[m * N + v] = acc;
+        }
     }
 }
 
@@ -758,14 +795,17 @@ static void energy_grid(int64_t n0, int64_t n1, int64_t n2, int *nby, int *nbx, 
 
 int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 {
+    // the grid covers the window positions: every voxel, or the stride-S lattice
+    const int S = c->p.stride;
+    const int64_t k0 = (n0 + S - 1) / S, k1 = (n1 + S - 1) / S, k2 = (n2 + S - 1) / S;
     int nby, nbx, tt;
     int64_t nb;
     if (c->L == 8)
-        energy_grid<8>(n0, n1, n2, &nby, &nbx, &tt, &nb);
+        energy_grid<8>(k0, k1, k2, &nby, &nbx, &tt, &nb);
     else if (c->L == 16)
-        energy_grid<16>(n0, n1, n2, &nby, &nbx, &tt, &nb);
+        energy_grid<16>(k0, k1, k2, &nby, &nbx, &tt, &nb);
     else
-        nb = energy_gen_num_blocks(c->L, n0, n1, n2);
+        nb = energy_gen_num_blocks(c->L, k0, k1, k2);
     return nb;
 }
 
@@ -774,15 +814,21 @@ static hipError_t launch_energy_L(const sal_ctx *c, const float *V, int64_t n0, 
                                   int64_t n2, const ebox &bx, float *E, float *vmax_part,
                                   int *nparts, hipStream_t s)
 {
+    const int S = c->p.stride;
     int nby, nbx, tt;
     int64_t nb;
-    energy_grid<L>(bx.d0, bx.d1, bx.d2, &nby, &nbx, &tt, &nb);
+    energy_grid<L>((bx.d0 + S - 1) / S, (bx.d1 + S - 1) / S, (bx.d2 + S - 1) / S, &nby, &nbx, &tt, &nb);
     if (nparts) *nparts = (int)nb;
     if (c->p.precision != SAL_FP32)
         return launch_energy16(c, V, n0, n1, n2, bx, E, vmax_part, nby, nbx, tt, nb, s);
-    hipLaunchKernelGGL(k_energy_f32<L>, dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s, V,
-                       (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a,
-                       c->t.w_bin, E, vmax_part);
+    if (S == 2)
+        hipLaunchKernelGGL((k_energy_f32<L, 2>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s, V,
+                           (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_bin, E,
+                           vmax_part);
+    else
+        hipLaunchKernelGGL((k_energy_f32<L, 1>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s, V,
+                           (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_bin, E,
+                           vmax_part);
     return hipGetLastError();
 }
 
@@ -925,5 +971,15 @@ hipError_t launch_dcs_box(const sal_ctx *c, const float *Eb, const int64_t eo[3]
     auto i3 = [](const int64_t *v) { return make_int3((int)v[0], (int)v[1], (int)v[2]); };
     hipLaunchKernelGGL(k_dcs_box, dim3(blocks), dim3(256), 0, s, Eb, i3(eo), i3(ed), i3(n), i3(bo), i3(bd), a,
                        S);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample(const float *El, int64_t K0, int64_t K1, int64_t K2, int S, int64_t n0, int64_t n1,
+                           int64_t n2, float *E, hipStream_t s)
+{
+    const int64_t N = n0 * n1 * n2;
+    const unsigned nb = (unsigned)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
+    hipLaunchKernelGGL(k_upsample, dim3(nb), dim3(256), 0, s, El, (int)K0, (int)K1, (int)K2, S, (int)n0, (int)n1,
+                       (int)n2, E);
     return hipGetLastError();
 }

@@ -48,7 +48,8 @@ class Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("d", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("rays", ctypes.c_uint32 * 3), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("c", ctypes.c_double), ("normalize", ctypes.c_int32),
-                ("zero_range", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("zero_range", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("stride", ctypes.c_int32)]
 
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -146,7 +147,7 @@ class Saliency:
     def __init__(self, L: int = 8, d: Optional[int] = None, sigma: Optional[float] = None,
                  rays: Sequence[int] = RAYS_AXIS, abc=(1 / 3, 1 / 3, 1 / 3),
                  normalize: bool = True, zero_range: float = 1e-6, precision: int = FP32,
-                 device: int = 0):
+                 stride: int = 1, device: int = 0):
         self._lib = load()
         p = default_params(L)
         if d is not None:
@@ -160,6 +161,7 @@ class Saliency:
         p.normalize = int(bool(normalize))
         p.zero_range = float(zero_range)
         p.precision = int(precision)
+        p.stride = int(stride)
         self.params = p
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()

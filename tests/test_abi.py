@@ -44,6 +44,7 @@ def test_default_params(lib):
 @pytest.mark.parametrize("fields,status", [
     ({"L": 1}, 1), ({"d": 1}, 1), ({"sigma": 0.0}, 1), ({"precision": 9}, 1), ({"L": 9}, 2),
     ({"L": 12}, 2), ({"L": 32}, 2), ({"L": 5, "precision": 2}, 2), ({"L": 4, "precision": 1}, 2),
+    ({"stride": 0}, 1), ({"stride": 3}, 2), ({"L": 4, "stride": 2}, 1), ({"rays": 1 << 26}, 1),
 ])
 def test_create_rejects(lib, fields, status):
     """Invalid parameters are rejected before any device call; cube sides without a GPU
@@ -51,7 +52,10 @@ def test_create_rejects(lib, fields, status):
     from paper_1901_11095_amd import sal
     p = sal.default_params(8)
     for k, v in fields.items():
-        setattr(p, k, v)
+        if k == "rays":
+            p.rays[0] = v
+        else:
+            setattr(p, k, v)
     h = ctypes.c_void_p()
     st = lib.sal_create(ctypes.byref(p), 0, ctypes.byref(h))
     assert st == status

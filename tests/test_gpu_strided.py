@@ -1,0 +1,67 @@
+"""Strided windows (stride 2, the half-resolution lattice) on the GPU against the FP64
+oracle: energies on the lattice, trilinear interpolation to every voxel, Eq. (5) and
+Eq. (6) on the full grid.  Ragged volumes put lattice points and held values at every
+face."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1901_11095_amd import sal, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def relmax(got, ref):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def check(L, shape, prec=sal.FP32, tol=1e-5, seed=3):
+    print("strided L=%d shape %s precision %d" % (L, shape, prec), flush=True)
+    V = synth.make_volume(shape, seed=seed + L, n_faults=1, throw=2, n_chaotic=1, chaotic_size=8)
+    ctx = sal.Saliency(L=L, stride=2, precision=prec)
+    ref = O.saliency(V, O.Params(L=L, stride=2))
+    S, E, Sr, st = ctx.saliency_maps(torch.from_numpy(V).cuda())
+    E, Sr, S = E.cpu().numpy(), Sr.cpu().numpy(), S.cpu().numpy()
+    for m in range(3):
+        assert relmax(E[m], ref["E"][m]) <= tol, ("E", m, relmax(E[m], ref["E"][m]))
+        assert relmax(Sr[m], ref["S_raw"][m]) <= tol, ("S_raw", m, relmax(Sr[m], ref["S_raw"][m]))
+    assert relmax(S, ref["S"]) <= tol, ("S", relmax(S, ref["S"]))
+
+
+@pytest.mark.parametrize("L", [5, 6, 7, 8])
+@pytest.mark.parametrize("shape", [(21, 19, 35), (34, 40, 17)])
+def test_strided_fp32(L, shape):
+    check(L, shape)
+
+
+@pytest.mark.parametrize("shape", [(20, 18, 33), (33, 40, 24)])
+def test_strided_fp32_L16(shape):
+    check(16, shape)
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_strided_bf16_split(L):
+    check(L, (24, 36, 40), prec=sal.BF16_SPLIT, tol=1e-3)
+
+
+def test_strided_vol64_paper_cube():
+    V = synth.workload("vol64")
+    ctx = sal.Saliency(L=5, stride=2)
+    ref = O.saliency(V, O.Params(L=5, stride=2))
+    S = ctx.saliency(torch.from_numpy(V).cuda()).cpu().numpy()
+    assert relmax(S, ref["S"]) <= 1e-5
+
+
+def test_strided_rejects():
+    with pytest.raises(sal.SalError) as ei:
+        sal.Saliency(L=8, stride=3)
+    assert ei.value.status == sal.SAL_E_UNSUPPORTED
+    with pytest.raises(sal.SalError) as ei:
+        sal.Saliency(L=4, stride=2)
+    assert ei.value.status == sal.SAL_E_INVAL
+    ctx = sal.Saliency(L=8, stride=2)
+    with pytest.raises(sal.SalError) as ei:
+        ctx.raw_box(torch.zeros((20, 20, 20), device="cuda"), (0, 0, 0), (4, 4, 4))
+    assert ei.value.status == sal.SAL_E_UNSUPPORTED
