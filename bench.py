@@ -223,6 +223,30 @@ def small_cube_leg(args, V, Vg, L=5):
             "max_rel_err_vs_oracle": None if args.no_check else sampled_error(ctx, V, Vg, L)}
 
 
+def strided_leg(args, V, Vg):
+    """Windows on the stride-2 lattice (Sec. 2 first step allows any overlap above one half)
+    with the energies interpolated back to every voxel: speed against stride 1 and the
+    difference of the final map from the stride-1 map (what the lattice gives up)."""
+    import torch
+    from paper_1901_11095_amd import sal
+    out = {}
+    for L, prec in ((args.L, sal.FP32), (args.L, sal.BF16_SPLIT)):
+        c1 = sal.Saliency(L=L, precision=prec)
+        c2 = sal.Saliency(L=L, precision=prec, stride=2)
+        ms1, _ = time_form(c1, Vg, max(3, args.steps // 4), 2)
+        ms2, km2 = time_form(c2, Vg, max(3, args.steps // 4), 2)
+        S1 = c1.saliency(Vg)
+        S2 = c2.saliency(Vg)
+        d = (S2 - S1).abs()
+        out["L%d_%s" % (L, sal.PRECISION_NAMES[prec])] = {
+            "voxels_per_s": V.size / (ms2 * 1e-3), "ms_per_step": ms2, "kernels_ms": km2,
+            "speedup_vs_stride1": ms1 / ms2,
+            "S_abs_diff_vs_stride1": {"max": float(d.max()), "mean": float(d.mean())}}
+        del c1, c2, S1, S2, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def precision_table(dev):
     """Every precision form against the FP64 oracle on the whole 64^3 volume at cube 8 and
     16: max and mean of |GPU - oracle| / max|oracle| for E_t, E_x, E_y, S_t, S_x, S_y (raw
@@ -429,6 +453,8 @@ def main(argv=None):
     if not args.no_forms:
         print("# paper cube 5^3", file=sys.stderr, flush=True)
         forms["fp32_paper_cube_L5"] = small_cube_leg(args, V, Vg, 5)
+        print("# stride-2 windows", file=sys.stderr, flush=True)
+        forms["stride2"] = strided_leg(args, V, Vg)
     if not args.no_surrogate:
         forms["surrogate"] = surrogate_leg(args, dev)
     table = None
