@@ -136,9 +136,9 @@ void oracle_window_spectrum(const float *V, long n0, long n1, long n2,
  *     F_t = F * sqrt(j^2+k^2)/sqrt(i^2+j^2+k^2)   (projection along f_t)
  *     F_x = F * sqrt(i^2+k^2)/sqrt(i^2+j^2+k^2)
  *     F_y = F * sqrt(i^2+j^2)/sqrt(i^2+j^2+k^2)
- *     E_m = "absolute mean" of F_m over the cube, DC bin excluded.
+ *     E_m = mean of |F_m| over the cube, DC bin excluded.
  * reading: (i, j, k) are the signed frequencies of (mu, nu, om) on axes (t, x, y); the
- * absolute mean is the mean of |F_m| over the L^3 - 1 bins that remain once DC is dropped.
+ * mean runs over the L^3 - 1 bins that remain once DC is dropped.
  */
 void oracle_project(const double *F, long L, double E[3])
 {
