@@ -132,31 +132,45 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
     const int t0 = tt_ * TT, u0 = tu_ * TU, w0 = tw_ * TW;
     __syncthreads();  // the previous tile is no longer read
 
-    // input tile with halo: one row of PW positions per (pt, pu)
+    // input tile with halo: one row of PW positions per (pt, pu).  Each wave loads whole
+    // rows, so the row's (t, u) source index is wave-uniform and a lane's position along
+    // w is fixed for the tile.
     if (CI == 1) {
+        // three rows of PW floats per wave and step
         const float *src = reinterpret_cast<const float *>(in) + b * vol;
-        for (int p = threadIdx.x; p < NPOS; p += 256) {
-            const int row = p / PW, pw = p - row * PW;
-            const int pt = row / PU, pu = row - pt * PU;
-            const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE),
-                      gw = map_idx(w0 - 1 + pw, n2, MODE);
-            const float v = (gt < 0 || gu < 0 || gw < 0) ? 0.f : src[((int64_t)gt * n1 + gu) * n2 + gw];
-            tile[p] = f2bf(v);
+        const int r3 = lane / PW, pw = lane - r3 * PW;
+        const bool act = r3 < 3;
+        const int gw = map_idx(w0 - 1 + pw, n2, MODE);
+#pragma unroll
+        for (int it = 0; it < (PT * PU + 11) / 12; ++it) {
+            const int row = 12 * it + 3 * wave + r3;
+            if (act && row < PT * PU) {
+                const int pt = row / PU, pu = row - pt * PU;
+                const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE);
+                const float v = (gt < 0 || gu < 0 || gw < 0) ? 0.f : src[((int64_t)gt * n1 + gu) * n2 + gw];
+                tile[row * PW + pw] = f2bf(v);
+            }
         }
     } else if (CI % 8 == 0) {
-        // 16-byte chunks of 8 channels
+        // 16-byte chunks of 8 channels; a row of PW positions is ROWLEN <= 64 chunks
         constexpr int CHK = CIP / 8, ROWLEN = PW * CHK;
+        static_assert(ROWLEN <= 64, "one wave loads a whole row");
         const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
-        for (int i = threadIdx.x; i < PT * PU * ROWLEN; i += 256) {
-            const int row = i / ROWLEN, j = i - row * ROWLEN;
-            const int pw = j / CHK, ch = j - pw * CHK;
-            const int pt = row / PU, pu = row - pt * PU;
-            const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE),
-                      gw = map_idx(w0 - 1 + pw, n2, MODE);
-            u32x4 val = u32x4{0u, 0u, 0u, 0u};
-            if (gt >= 0 && gu >= 0 && gw >= 0)
-                val = *reinterpret_cast<const u32x4 *>(src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch);
-            *reinterpret_cast<u32x4 *>(&tile[(row * PW + pw) * CIP + 8 * ch]) = val;
+        const bool act = lane < ROWLEN;
+        const int pw = lane / CHK, ch = lane - (lane / CHK) * CHK;
+        const int gw = map_idx(w0 - 1 + pw, n2, MODE);
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+#pragma unroll
+        for (int it = 0; it < (PT * PU + 3) / 4; ++it) {
+            const int row = 4 * it + wv;
+            if (row < PT * PU) {
+                const int pt = row / PU, pu = row - pt * PU;
+                const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE);
+                u32x4 val = u32x4{0u, 0u, 0u, 0u};
+                if (act && gt >= 0 && gu >= 0 && gw >= 0)
+                    val = *reinterpret_cast<const u32x4 *>(src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch);
+                if (act) *reinterpret_cast<u32x4 *>(&tile[(row * PW + pw) * CIP + 8 * ch]) = val;
+            }
         }
     } else {
         const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
