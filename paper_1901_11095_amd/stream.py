@@ -11,6 +11,7 @@ staging); max|V| for the zero-contrast rule is reduced slab by slab.
 """
 from __future__ import annotations
 
+import math
 from typing import Optional
 
 import numpy as np
@@ -89,7 +90,7 @@ def plain_streamed(ctx: sal.Saliency, V_host: torch.Tensor, slab: int = 64):
 
 def surrogate_streamed(net: sal.Net, ctx_fallback: sal.Saliency, V_host: torch.Tensor,
                        slab: int = 64, tile: int = 32, frac: float = 0.02, bound: float = 0.02,
-                       seed: int = 0, max_rounds: int = 8, per_round: int = 32):
+                       seed: int = 0, max_rounds: int = 8, per_round: int = 32, top_frac: float = 0.05):
     """Surrogate first, slab by slab (halo 5), then the seeded tile check and the check of
     the tiles holding each map's extremes, on crops copied from the host volume, with the
     plain method (ctx_fallback, e.g. split-BF16) and exact replacement; then the FP64
@@ -98,15 +99,17 @@ def surrogate_streamed(net: sal.Net, ctx_fallback: sal.Saliency, V_host: torch.T
     dev = S_raw.device
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
     S = sal.normalize_combine(ctx_fallback, S_raw, None, stats_out=stats, vmax=vmax)
-    sample = surrogate.seeded_tiles(len(surrogate.tiles_of(tuple(V_host.shape), tile)), frac, seed)
+    n_all = len(surrogate.tiles_of(tuple(V_host.shape), tile))
+    sample = surrogate.seeded_tiles(n_all, frac, seed)
 
     def crop(lo, hi):
         return V_host[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].contiguous().to(dev), lo
 
     chk = surrogate.TileCheck(ctx_fallback, S_raw, stats, crop, tile, bound,
-                              len(sample) + 6 * per_round * max_rounds)
+                              len(sample) + int(math.ceil(top_frac * n_all)) + 6 * per_round * max_rounds)
     for ti in sample:
         chk.check(ti)
+    chk.check_top(top_frac)
     rounds = chk.verify_extremes(max_rounds, per_round)
     S = sal.normalize_combine(ctx_fallback, S_raw, None, S=S, stats_out=stats, vmax=vmax)
     return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": chk.tiles, "tile_err": chk.errors(),

@@ -230,6 +230,26 @@ class TileCheck:
                 self.check(ti)
         return max_rounds
 
+    def check_top(self, frac: float, abc=(1 / 3, 1 / 3, 1 / 3)) -> int:
+        """Check the `frac` of the tiles with the highest predicted saliency: the upper bound
+        sum_m a_m (max_m - lo_m) / (hi_m - lo_m) of Eq. (6) over the tile, with the predicted
+        volume-wide ranges.  The surrogate's largest errors sit in such tiles (edges of
+        chaotic bodies).  Returns the number of tiles checked."""
+        k = int(math.ceil(frac * self.n_tiles()))
+        if k <= 0:
+            return 0
+        mm = sal.tile_minmax(self.ctx, self.S_raw, self.tile).cpu().numpy().astype(np.float64)
+        st = self.stats.cpu().numpy()
+        score = np.zeros(len(mm))
+        for m in range(3):
+            rng = st[2 * m + 1] - st[2 * m]
+            if rng > 0:
+                score += abc[m] * (mm[:, 2 * m + 1] - st[2 * m]) / rng
+        n = 0
+        for ti in np.argsort(-score, kind="stable")[:k]:
+            n += int(self.check(int(ti)))
+        return n
+
     def errors(self) -> torch.Tensor:
         return self.errs[:len(self.done)]
 
@@ -242,21 +262,24 @@ def seeded_tiles(n_tiles: int, frac: float, seed: int):
 def infer_with_fallback(net: sal.Net, ctx_exact: sal.Saliency, V: torch.Tensor, tile: int = 32,
                         frac: float = 0.02, bound: float = 0.02, seed: int = 0,
                         S_raw: Optional[torch.Tensor] = None, check_extremes: bool = True,
-                        max_rounds: int = 8, per_round: int = 32):
+                        max_rounds: int = 8, per_round: int = 32, top_frac: float = 0.05):
     """Surrogate maps, a seeded check of `frac` of the tiles against the plain method with
-    exact replacement of the tiles over `bound`, then (with `check_extremes`) the tiles that
-    hold each map's extremes until all of them are checked, then the exact FP64
-    normalisation and Eq. (6).
+    exact replacement of the tiles over `bound`, optionally the `top_frac` of the tiles with
+    the highest predicted saliency, then (with `check_extremes`) the tiles that hold each
+    map's extremes until all of them are checked, then the exact FP64 normalisation and
+    Eq. (6).
     Returns a dict with S, S_raw, stats, the checked tiles and their errors."""
     dev = V.device
     S_raw = net.infer(V, out=S_raw)
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
     S = sal.normalize_combine(ctx_exact, S_raw, V, stats_out=stats)
-    sample = seeded_tiles(len(tiles_of(tuple(V.shape), tile)), frac, seed)
-    chk = TileCheck(ctx_exact, S_raw, stats, lambda lo, hi: (V, (0, 0, 0)),
-                    tile, bound, len(sample) + (6 * per_round * max_rounds if check_extremes else 0))
+    n_all = len(tiles_of(tuple(V.shape), tile))
+    sample = seeded_tiles(n_all, frac, seed)
+    cap = len(sample) + int(math.ceil(top_frac * n_all)) + (6 * per_round * max_rounds if check_extremes else 0)
+    chk = TileCheck(ctx_exact, S_raw, stats, lambda lo, hi: (V, (0, 0, 0)), tile, bound, cap)
     for ti in sample:
         chk.check(ti)
+    chk.check_top(top_frac)
     rounds = chk.verify_extremes(max_rounds, per_round) if check_extremes else 0
     S = sal.normalize_combine(ctx_exact, S_raw, V, S=S, stats_out=stats)
     return {"S": S, "S_raw": S_raw, "stats": stats, "tiles": chk.tiles, "tile_err": chk.errors(),

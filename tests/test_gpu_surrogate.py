@@ -117,3 +117,22 @@ def test_survey_like_volume(net):
         a, b = res["S_raw"][m][inside], res["S_raw"][m][~inside]
         tol = 0.02 * float(a.max() - a.min())
         assert float(b.max()) <= float(a.max()) + tol and float(b.min()) >= float(a.min()) - tol
+
+
+def test_top_saliency_tiles_checked(net, ctx):
+    """The default pipeline also checks the 5% of tiles with the highest predicted Eq. (6)
+    upper bound (where the network's largest errors sit on survey-sized volumes)."""
+    V = held_out(128)
+    S_ref = ctx.saliency(V)
+    P = net.infer(V)
+    st = torch.zeros(8, dtype=torch.float64, device="cuda")
+    sal.normalize_combine(ctx, P, V, stats_out=st)
+    mm = sal.tile_minmax(ctx, P, 32).cpu().numpy().astype(np.float64)
+    s = st.cpu().numpy()
+    score = sum((mm[:, 2 * m + 1] - s[2 * m]) / (s[2 * m + 1] - s[2 * m]) / 3 for m in range(3))
+    k = int(np.ceil(0.05 * len(score)))
+    top = set(np.argsort(-score, kind="stable")[:k].tolist())
+    res = surrogate.infer_with_fallback(net, ctx, V)
+    checked = {(lo[0] // 32 * 16 + lo[1] // 32 * 4 + lo[2] // 32) for lo, _ in res["tiles"]}
+    assert top <= checked
+    assert float((res["S"] - S_ref).abs().mean()) <= 0.01
