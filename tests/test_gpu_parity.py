@@ -237,3 +237,42 @@ def test_error_paths(dev, ctx8):
     with pytest.raises(sal.SalError) as ei:
         sal.Saliency(L=5, precision=sal.BF16_SPLIT)
     assert ei.value.status == sal.SAL_E_UNSUPPORTED
+
+
+def test_saliency_full_survey_subblocks(dev):
+    """The 512 x 1024 x 1024 survey (2 GiB, six faults, two chaotic bodies, 5 dB) at cube
+    16, in the launch configuration of the benchmark: the oracle on 16^3 sub-blocks at a
+    corner, at the far corner and inside (energies on the block plus the comparison halo)."""
+    ctx = sal.Saliency(L=16)
+    V = synth.workload("survey512x1024x1024")
+    Vg = gpu(V, dev)
+    S, E, Sr, st = ctx.saliency_maps(Vg)
+    torch.cuda.synchronize()
+    stats = st.cpu().numpy()
+    b = 16
+    los = [(0, 0, 0), (V.shape[0] - b, V.shape[1] - b, V.shape[2] - b), (250, 600, 301)]
+    p = O.Params(L=16)
+    for lo in los:
+        print("survey sub-block", lo, flush=True)
+        sl = tuple(slice(a, a + b) for a in lo)
+        Eo, So = O.raw_box(V, p, lo, (b, b, b))
+        for m in range(3):
+            assert relmax(E[(m,) + sl].cpu().numpy(), Eo[m]) <= TOL
+            assert relmax(Sr[(m,) + sl].cpu().numpy(), So[m]) <= TOL
+        Sref = O.combine_with_stats(So, stats[:6], vmax=stats[6])
+        assert relmax(S[sl].cpu().numpy(), Sref) <= TOL
+    for m in range(3):
+        assert stats[2 * m] == float(Sr[m].min()) and stats[2 * m + 1] == float(Sr[m].max())
+
+
+def test_size_limits(dev, ctx8):
+    """Smallest accepted volume (every side max(floor(L/2), r) + 1) against the oracle; a
+    volume of 2^31 voxels or more is rejected before any launch."""
+    V = synth.random_volume((5, 5, 5), seed=1)
+    _check_full(ctx8, V, 8, dev)
+    with pytest.raises(sal.SalError) as ei:
+        ctx8.workspace_size((2048, 1024, 1024))
+    assert ei.value.status == sal.SAL_E_INVAL
+    with pytest.raises(sal.SalError) as ei:
+        ctx8.workspace_size((4, 100, 100))
+    assert ei.value.status == sal.SAL_E_INVAL
