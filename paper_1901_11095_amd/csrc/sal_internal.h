@@ -51,6 +51,12 @@ struct dcs_args {
     float g[96];  // w(s |e|) at index 32 (|e|^2 - 1) + s - 1
 };
 
+// Ray bits with a step along t, x, y (axis rays, the diagonals of the planes holding the
+// axis, the body diagonals)
+constexpr uint32_t RAYS_T = 0x3u | (0xFu << 6) | (0xFu << 10) | (0xFFu << 18);
+constexpr uint32_t RAYS_X = 0xCu | (0xFu << 6) | (0xFu << 14) | (0xFFu << 18);
+constexpr uint32_t RAYS_Y = 0x30u | (0xFu << 10) | (0xFu << 14) | (0xFFu << 18);
+
 // Step (t, x, y) of ray bit b of a comparison mask (axis rays, face and body diagonals;
 // the bit layout of SAL_RAY_*).
 __host__ __device__ inline void ray_step(int b, int &dt, int &dx, int &dy)

@@ -444,14 +444,15 @@ __global__ __launch_bounds__(256) void k_dcs_tiled(const float *__restrict__ E, 
     float g[R > 0 ? R : 32];
 #pragma unroll
     for (int s = 0; s < (R > 0 ? R : 32); ++s) g[s] = a.g[s];
+    const bool diag = ((a.rays[0] | a.rays[1] | a.rays[2]) & ~63u) != 0;
 
     int ht[3], hx[3], hy[3], W[3], HW[3], depth[3], off[3];
     int o = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        ht[m] = (a.rays[m] & 3u) ? r : 0;
-        hx[m] = (a.rays[m] & 12u) ? r : 0;
-        hy[m] = (a.rays[m] & 48u) ? r : 0;
+        ht[m] = (a.rays[m] & RAYS_T) ? r : 0;
+        hx[m] = (a.rays[m] & RAYS_X) ? r : 0;
+        hy[m] = (a.rays[m] & RAYS_Y) ? r : 0;
         W[m] = DTY + 2 * hy[m];
         HW[m] = (DTX + 2 * hx[m]) * W[m];
         depth[m] = 2 * ht[m] + 1;
@@ -545,6 +546,23 @@ __global__ __launch_bounds__(256) void k_dcs_tiled(const float *__restrict__ E, 
                         }
                     }
                 }
+                // oriented rays (face and body diagonals): plane t + s dt of the ring,
+                // offset s (dx W + dy) inside it
+                if (diag && (rm & ~63u)) {
+#pragma unroll 1
+                    for (int b = 6; b < 26; ++b) {
+                        if (!((rm >> b) & 1u)) continue;
+                        int dt, dx, dy;
+                        ray_step(b, dt, dx, dy);
+                        const float *gw = a.g + 32 * (dt * dt + dx * dx + dy * dy - 1);
+                        const int dxy = dx * W[m] + dy;
+                        for (int s = 1; s <= r; ++s) {
+                            int sl = s0 + dt * s;
+                            sl += sl < 0 ? depth[m] : (sl >= depth[m] ? -depth[m] : 0);
+                            sum += fabsf(c - gw[s - 1] * ring[sl * HW[m] + idx + s * dxy]);
+                        }
+                    }
+                }
                 const float sv = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
                 S[m * N + ov] = sv;
                 mn[m] = fminf(mn[m], sv);
@@ -582,15 +600,15 @@ static int64_t dcs_tiled_lds_floats(const uint32_t rays[3], int r)
 {
     int64_t tot = 0;
     for (int m = 0; m < 3; ++m) {
-        if (rays[m] & ~63u) return INT64_MAX / 2;  // oriented rays: the grid-stride kernel
-        const int ht = (rays[m] & 3u) ? r : 0, hx = (rays[m] & 12u) ? r : 0, hy = (rays[m] & 48u) ? r : 0;
+        const int ht = (rays[m] & RAYS_T) ? r : 0, hx = (rays[m] & RAYS_X) ? r : 0, hy = (rays[m] & RAYS_Y) ? r : 0;
         const int64_t hw = (int64_t)(DTX + 2 * hx) * (DTY + 2 * hy);
         if (hw > 256 * DMAXE) return INT64_MAX / 2;
         tot += (2 * ht + 1) * hw;
     }
     return tot;
 }
-static const int64_t DCS_LDS_MAX_FLOATS = 64 * 1024 / 4;
+// up to 144 KiB of the 160 KiB a gfx950 workgroup may use
+static const int64_t DCS_LDS_MAX_FLOATS = 144 * 1024 / 4;
 
 // ------------------------------------------------------------------------------------
 // FP64 volume-wide statistics {lo_t, hi_t, lo_x, hi_x, lo_y, hi_y, max|V|} from partials.
@@ -866,9 +884,14 @@ hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, 
     if (nf <= DCS_LDS_MAX_FLOATS) {
         const size_t lds = (size_t)(nf > 24 ? nf : 24) * sizeof(float);
         const int nbx = (int)((n1 + DTX - 1) / DTX), nby = (int)((n2 + DTY - 1) / DTY);
-#define SAL_DCS_T(RR)                                                                                          \
-    hipLaunchKernelGGL(k_dcs_tiled<RR>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1, (int)n2, a, nbx, nby, \
-                       S_raw, minmax_part)
+#define SAL_DCS_T(RR)                                                                                            \
+    do {                                                                                                          \
+        if (lds > 65536)                                                                                          \
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dcs_tiled<RR>),                           \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                      \
+        hipLaunchKernelGGL(k_dcs_tiled<RR>, dim3(nb), dim3(256), lds, s, E, (int)n0, (int)n1, (int)n2, a, nbx, nby, \
+                           S_raw, minmax_part);                                                                   \
+    } while (0)
         // r known at compile time for the default d = L of every supported cube side
         switch (c->r) {
         case 1: SAL_DCS_T(1); break;
