@@ -194,6 +194,14 @@ def surrogate_leg(args, dev):
             "checked_tiles": len(res_t["tiles"]),
             "S_abs_err_vs_plain_fp32": {"max": float(dS_t.max()), "mean": float(dS_t.mean())}}
     del res_t, dS_t
+    # the plain method on the stride-2 window lattice (split-BF16): the other fast
+    # approximation of the same map
+    ctx_s2 = sal.Saliency(L=16, precision=sal.BF16_SPLIT, stride=2)
+    ms_s2, _ = time_form(ctx_s2, V, 3, 1)
+    dS_s2 = (ctx_s2.saliency(V) - S_ref).abs()
+    stride2 = {"ms": ms_s2, "speedup_vs_plain_fp32": ms_plain / ms_s2,
+               "S_abs_err_vs_plain_fp32": {"max": float(dS_s2.max()), "mean": float(dS_s2.mean())}}
+    del ctx_s2, dS_s2
     flops = 2 * 47952  # multiply-adds of the five convolutions per voxel
     net.infer(V, out=pred)
     torch.cuda.synchronize()
@@ -217,6 +225,7 @@ def surrogate_leg(args, dev):
         "net_inference_ms": 1e3 * t_net,
         "top_saliency_check_frac": 0.05,
         "without_top_saliency_check": top5,
+        "plain_bf16_split_stride2": stride2,
         "roofline": {"bound": "mfma", "achieved": net_tf, "peak": PEAK_TFLOPS["bf16"],
                      "unit": "TFLOP/s", "frac": net_tf / PEAK_TFLOPS["bf16"],
                      "kernel": "k_conv3 (five layers, network inference only)",
