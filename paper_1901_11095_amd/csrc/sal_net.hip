@@ -104,13 +104,56 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
 {
     constexpr int CIP = CI == 1 ? 1 : pad8(CI);
     constexpr int KS = ksteps(CI), MT = (CO + 15) / 16;
-    __shared__ uint16_t tile[NPOS * CIP];
+    // multi-channel layers with reflected borders (the forward pass) stream the next tile
+    // into a second LDS buffer by direct global-to-LDS loads while the current one computes
+    constexpr bool ASYNC = CI > 1 && CI % 8 == 0 && MODE == MODE_REFLECT;
+    // two separate LDS objects, so the compiler can tell reads of one from the loads landing
+    // in the other (a read of the same object would wait for them)
+    __shared__ uint16_t tileA[NPOS * CIP];
+    __shared__ uint16_t tileB[ASYNC ? NPOS * CIP : 8];
+    // biases in LDS: a global load in the epilogue would wait for the tile in flight
+    __shared__ float bias_s[MT * 16];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, n = lane & 15;
     const int ntw = (n2 + TW - 1) / TW, ntu = (n1 + TU - 1) / TU, ntt = (n0 + TT - 1) / TT;
     const int ntiles = nb * ntt * ntu * ntw;
     const int64_t vol = (int64_t)n0 * n1 * n2;
+
+    // asynchronous load of tile `id` into buffer `bf`: each wave takes whole rows of PW
+    // positions; lane j < PW * CIP / 8 brings 16 bytes (8 channels) and the hardware puts
+    // them at row base + 16 j, which is the row's layout in LDS
+    auto issue = [&](int id, uint16_t *dst) {
+        if constexpr (ASYNC) {
+            constexpr int CHK = CIP / 8, ROWLEN = PW * CHK;
+            int bi = id;
+            const int tw2 = bi % ntw;
+            bi /= ntw;
+            const int tu2 = bi % ntu;
+            bi /= ntu;
+            const int tt2 = bi % ntt;
+            const int b2 = bi / ntt;
+            const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b2 * vol * CI;
+            const int pw = lane / CHK, ch = lane - (lane / CHK) * CHK;
+            const int gw = refl_idx(tw2 * TW - 1 + pw, n2);
+            const int wv = __builtin_amdgcn_readfirstlane(wave);
+#pragma unroll
+            for (int it = 0; it < (PT * PU + 3) / 4; ++it) {
+                const int row = 4 * it + wv;
+                if (row < PT * PU) {
+                    const int pt = row / PU, pu = row - pt * PU;
+                    const int gt = refl_idx(tt2 * TT - 1 + pt, n0), gu = refl_idx(tu2 * TU - 1 + pu, n1);
+                    if (lane < ROWLEN)
+                        __builtin_amdgcn_global_load_lds(
+                            src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch,
+                            (__attribute__((address_space(3))) void *)&dst[row * PW * CIP], 16, 0, 0);
+                }
+            }
+        }
+    };
+    for (int i = threadIdx.x; i < MT * 16; i += 256) bias_s[i] = (bias && i < CO) ? bias[i] : 0.f;
+    __syncthreads();
+    if (ASYNC && (int)blockIdx.x < ntiles) issue(blockIdx.x, tileA);
 
     // the weights stay in registers while the workgroup walks its tiles
     u32x4 A[MT][KS];
@@ -120,8 +163,9 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
         for (int s = 0; s < KS; ++s)
             A[mt][s] = reinterpret_cast<const u32x4 *>(wtab)[((mt * 16 + n) * KS * 32 + s * 32 + 8 * g) / 8];
 
-#pragma unroll 1
-    for (int tile_id = blockIdx.x; tile_id < ntiles; tile_id += gridDim.x) {
+    // one tile: wait for its input, start the next tile's loads into the other buffer,
+    // convolve, write the epilogue
+    auto process = [&](int tile_id, uint16_t *tile, uint16_t *other) __attribute__((always_inline)) {
     int bid = tile_id;
     const int tw_ = bid % ntw;
     bid /= ntw;
@@ -130,7 +174,15 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
     const int tt_ = bid % ntt;
     const int b = bid / ntt;
     const int t0 = tt_ * TT, u0 = tu_ * TU, w0 = tw_ * TW;
-    __syncthreads();  // the previous tile is no longer read
+    if (ASYNC) {
+        // this tile's loads have landed (every wave waits for its own, then the barrier);
+        // the other buffer is free again, so the next tile's loads can start
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tile_id + (int)gridDim.x < ntiles) issue(tile_id + gridDim.x, other);
+    } else {
+        __syncthreads();  // the previous tile is no longer read
+    }
 
     // input tile with halo: one row of PW positions per (pt, pu).  Each wave loads whole
     // rows, so the row's (t, u) source index is wave-uniform and a lane's position along
@@ -151,6 +203,8 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
                 tile[row * PW + pw] = f2bf(v);
             }
         }
+    } else if (ASYNC) {
+        // loaded by issue()
     } else if (CI % 8 == 0) {
         // 16-byte chunks of 8 channels; a row of PW positions is ROWLEN <= 64 chunks
         constexpr int CHK = CIP / 8, ROWLEN = PW * CHK;
@@ -185,7 +239,9 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
                           : src[(((int64_t)gt * n1 + gu) * n2 + gw) * CI + c];
         }
     }
-    __syncthreads();
+    // (asynchronous tiles were complete at the barrier above; a barrier here would wait for
+    // the next tile's loads)
+    if (!ASYNC) __syncthreads();
 
 #pragma unroll 1
     for (int row = 0; row < 4; ++row) {
@@ -242,7 +298,7 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
                     for (int j = 0; j < 4; ++j)
                         if (cb + j < CO) {
                             const float sc = cb + j == 0 ? oscale.x : (cb + j == 1 ? oscale.y : oscale.z);
-                            o[v * vstride + (cb + j) * cstride] = (acc[mt][j] + bias[cb + j]) * sc;
+                            o[v * vstride + (cb + j) * cstride] = (acc[mt][j] + bias_s[cb + j]) * sc;
                         }
                 } else if (cb < CO) {  // CO is a multiple of 4 here
                     uint16_t r[4];
@@ -250,7 +306,7 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
                         uint16_t zz[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            const float z = acc[mt][j] + bias[cb + j];
+                            const float z = acc[mt][j] + bias_s[cb + j];
                             zz[j] = f2bf(z);
                             r[j] = f2bf(gelu_f(bf2f(zz[j])));
                         }
@@ -272,7 +328,22 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
             }
         }
     }
-    }  // tile loop
+    };
+
+    if constexpr (ASYNC) {
+        // even steps read tileA and fill tileB, odd steps the other way round
+        for (int tile_id = blockIdx.x; tile_id < ntiles;) {
+            process(tile_id, tileA, tileB);
+            tile_id += gridDim.x;
+            if (tile_id >= ntiles) break;
+            process(tile_id, tileB, tileA);
+            tile_id += gridDim.x;
+        }
+    } else {
+#pragma unroll 1
+        for (int tile_id = blockIdx.x; tile_id < ntiles; tile_id += gridDim.x) process(tile_id, tileA, tileB);
+    }
+
 }
 
 // ------------------------------------------------------------------------------------
