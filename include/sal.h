@@ -8,7 +8,7 @@
  *           after Eq. (2), including the 1/L^3 factor);
  *   step 2  projection of each local spectrum along f_t, f_x, f_y (Eqs. (1)-(4)), with
  *           the DC bin excluded (paragraph after Fig. 2);
- *   step 3  spectral energies E_t, E_x, E_y: absolute mean of each projected spectrum;
+ *   step 3  spectral energies E_t, E_x, E_y: mean magnitude of each projected spectrum;
  *   step 4  directional center-surround comparison (Eq. (5)) with Gaussian weights;
  *   step 5  weighted combination S = a S_t + b S_x + c S_y (Eq. (6)).
  *
