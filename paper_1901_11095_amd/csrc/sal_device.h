@@ -58,16 +58,26 @@ struct Geo {
 #ifndef SAL_TY16
 #define SAL_TY16 16
 #endif
+// WPE: waves per SIMD the register allocation must allow.  At L = 8 the LDS of a workgroup
+// admits three per CU, i.e. six waves per SIMD; the registers are capped to match (a few
+// per-t0 address values then live in scratch, outside the inner loops).  At L = 16 the LDS
+// admits one workgroup per CU.
+#ifndef SAL_WPE8
+#define SAL_WPE8 6
+#endif
+#ifndef SAL_WPE16
+#define SAL_WPE16 2
+#endif
 template <int L>
 struct TileCfg;
 template <>
 struct TileCfg<8> {
-    static constexpr int NW = SAL_NW8, TY = SAL_TY8;
+    static constexpr int NW = SAL_NW8, TY = SAL_TY8, WPE = SAL_WPE8;
     static constexpr bool W_LDS = true;
 };
 template <>
 struct TileCfg<16> {
-    static constexpr int NW = SAL_NW16, TY = SAL_TY16;
+    static constexpr int NW = SAL_NW16, TY = SAL_TY16, WPE = SAL_WPE16;
     static constexpr bool W_LDS = false;
 };
 

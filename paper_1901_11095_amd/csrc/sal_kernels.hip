@@ -36,7 +36,7 @@
 // Floating-point MFMA and VALU work serialise on a SIMD on this chip, so the per-bin VALU
 // count (|F|^2, sqrt, three weighted sums) is kept minimal.
 template <int L, int S>
-__global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
+__global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
     const float *__restrict__ w_c, const float *__restrict__ w_a,
     const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
@@ -83,29 +83,27 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
-    // stage-A positions of this wave (fixed for the whole t walk)
-    int off_xy[NJ];
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-        int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
-        int xp = pos / PY, yp = pos - xp * PY;
-        int gx = refl_idx(x_base - H + xp, n1), gy = refl_idx(y_base - H + yp, n2);
-        off_xy[jj] = gx * n2 + gy;
-    }
     const int64_t plane = (int64_t)n1 * n2;
     const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
     float vmax = 0.0f;
     float2 *Bw = B_s[wave];
 
+    // Volume samples of the stage-A positions of this wave for one t0.  The loads for the
+    // next t0 are issued after stage C, so they hold no registers through stages B and C;
+    // the position offsets are recomputed for the same reason.
     float vnext[NJ][KSA];
     auto load_a = [&](int t0) {
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj)
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
+            const int xp = pos / PY, yp = pos - xp * PY;
+            const int off = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
 #pragma unroll
             for (int kk = 0; kk < KSA; ++kk) {
                 const int tr = refl_idx(t0 - H + KSA * g + kk, n0);
-                vnext[jj][kk] = (wave + NW * jj < NTA) ? V[tr * plane + off_xy[jj]] : 0.f;
+                vnext[jj][kk] = (wave + NW * jj < NTA) ? V[tr * plane + off] : 0.f;
             }
+        }
     };
     load_a(t_begin);
 
@@ -116,7 +114,6 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
         for (int jj = 0; jj < NJ; ++jj)
 #pragma unroll
             for (int kk = 0; kk < KSA; ++kk) vcur[jj][kk] = vnext[jj][kk];
-        if (t0 + S < t_end) load_a(t0 + S);
         // ---------------- stage A: real DFT along t -------------------------------------
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
@@ -188,9 +185,14 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // ---------------- stage C: complex DFT along y, projections, energies -------
+            // The NTC voxel tiles of a row run as independent MFMA chains, interleaved, so
+            // each tile's dependent steps and result latency overlap the other tiles'.
 #pragma unroll 1
             for (int k = 0; k < NGK; ++k, ++grp) {
                 const bool pair = !self && k > 0 && k < L / 2;
+                // for mu, nu in {0, L/2} the stage-B row is real (the quarter-turn twiddles
+                // are exact, so its imaginary part is an exact zero): skip those K steps
+                const bool real_row = self && (k == 0 || k == L / 2);
                 float wv[MT][6];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
@@ -198,56 +200,74 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
 #pragma unroll
                     for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
                 }
+                f4 acc[NTC][MT];
+                auto row_dft = [&](int nu, bool real) {
 #pragma unroll
-                for (int c = 0; c < NTC; ++c) {
-                    const int y0 = S * (c * 16 + n);
-                    f4 acc[MT];
+                    for (int c = 0; c < NTC; ++c)
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+                        for (int mt = 0; mt < MT; ++mt) acc[c][mt] = f4{0.f, 0.f, 0.f, 0.f};
+                    const float2 *Brow = Bw + nu * PYB + S * n + ((KS * g) >> 1);
+                    if (real) {
 #pragma unroll
-                    for (int kk = 0; kk < KS; kk += 2) {
-                        const float2 b = Bw[k * PYB + y0 + ((KS * g + kk) >> 1)];
+                        for (int kk = 0; kk < KS; kk += 2)
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) {
-                            acc[mt] = mfma4(wc[mt][kk], b.x, acc[mt]);
-                            acc[mt] = mfma4(wc[mt][kk + 1], b.y, acc[mt]);
-                        }
-                    }
-                    float m0[MT], m1[MT];
+                            for (int c = 0; c < NTC; ++c) {
+                                const float b = Brow[S * c * 16 + (kk >> 1)].x;
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) {
-                        m0[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
-                        m1[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
-                    }
-                    if (pair) {
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+                                for (int mt = 0; mt < MT; ++mt) acc[c][mt] = mfma4(wc[mt][kk], b, acc[c][mt]);
+                            }
+                    } else {
 #pragma unroll
                         for (int kk = 0; kk < KS; kk += 2) {
-                            const float2 b = Bw[(L - k) * PYB + y0 + ((KS * g + kk) >> 1)];
+                            float2 b[NTC];
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) {
-                                acc[mt] = mfma4(wc[mt][kk], b.x, acc[mt]);
-                                acc[mt] = mfma4(wc[mt][kk + 1], b.y, acc[mt]);
-                            }
-                        }
+                            for (int c = 0; c < NTC; ++c) b[c] = Brow[S * c * 16 + (kk >> 1)];
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) {
-                            m0[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
-                            m1[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                            for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                                for (int mt = 0; mt < MT; ++mt) acc[c][mt] = mfma4(wc[mt][kk], b[c].x, acc[c][mt]);
+#pragma unroll
+                            for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                                for (int mt = 0; mt < MT; ++mt)
+                                    acc[c][mt] = mfma4(wc[mt][kk + 1], b[c].y, acc[c][mt]);
                         }
                     }
+                };
+                float m0[NTC][MT], m1[NTC][MT];
+                row_dft(k, real_row);
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const f4 a = acc[c][mt];
+                        m0[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                        m1[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
+                    }
+                if (pair) {
+                    row_dft(L - k, false);
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const f4 a = acc[c][mt];
+                            m0[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                            m1[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
+                        }
+                }
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                         for (int m = 0; m < 3; ++m)
-                            e[c][m] = fmaf(wv[mt][3 + m], m1[mt], fmaf(wv[mt][m], m0[mt], e[c][m]));
-                }
+                            e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        if (t0 + S < t_end) load_a(t0 + S);
         // reduce the four lane groups (lanes n, n+16, n+32, n+48 hold the same voxel)
         const int x = x_base + S * wave;
 #pragma unroll
