@@ -82,8 +82,28 @@ __device__ __forceinline__ u32x4 lds4(const uint32_t *p) { return u32x4{p[0], p[
 
 }  // namespace
 
+// Waves per SIMD the register allocation must allow, as measured best: four at cube 8 (more
+// would force spills into the inner loops), four at cube 16 without the data split; with it
+// the LDS of a cube-16 workgroup admits one per CU, so two.  Strided tiles are LDS-bound.
+#ifndef SAL_HWPE8D
+#define SAL_HWPE8D 4
+#endif
+#ifndef SAL_HWPE8
+#define SAL_HWPE8 4
+#endif
+#ifndef SAL_HWPE16D
+#define SAL_HWPE16D 2
+#endif
+#ifndef SAL_HWPE16
+#define SAL_HWPE16 4
+#endif
+template <int L, bool DS, int S>
+struct HWpe {
+    static constexpr int v = S != 1 ? 2 : L == 8 ? (DS ? SAL_HWPE8D : SAL_HWPE8) : (DS ? SAL_HWPE16D : SAL_HWPE16);
+};
+
 template <int L, typename T, bool DS, int S>
-__global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
+__global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
     const uint32_t *__restrict__ w_c16, const uint32_t *__restrict__ w_a16,
     const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
@@ -127,13 +147,6 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
-    int off_xy[NJ];
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-        const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
-        const int xp = pos / PY, yp = pos - xp * PY;
-        off_xy[jj] = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
-    }
     const int64_t plane = (int64_t)n1 * n2;
     const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
     float vmax = 0.0f;
@@ -141,16 +154,22 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     uint32_t *Bw_lo = B_s[wave][NP - 1];
     const int qoff = 4 * (g & 1);
 
+    // samples of this wave's stage-A positions for one t0; the next t0's loads are issued
+    // after stage C and the offsets recomputed, so neither holds registers through B and C
     float vnext[NJ][4];
     auto load_a = [&](int t0) {
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj)
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
+            const int xp = pos / PY, yp = pos - xp * PY;
+            const int off = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int p = 4 * g + e;
                 const int tr = refl_idx(t0 - H + p, n0);
-                vnext[jj][e] = (wave + NW * jj < NTA && p < L) ? V[tr * plane + off_xy[jj]] : 0.f;
+                vnext[jj][e] = (wave + NW * jj < NTA && p < L) ? V[tr * plane + off] : 0.f;
             }
+        }
     };
     load_a(t_begin);
 
@@ -161,7 +180,6 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
         for (int jj = 0; jj < NJ; ++jj)
 #pragma unroll
             for (int e = 0; e < 4; ++e) vcur[jj][e] = vnext[jj][e];
-        if (t0 + S < t_end) load_a(t0 + S);
         // ---------------- stage A: real DFT along t -------------------------------------
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
@@ -236,6 +254,7 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // ---------------- stage C: complex DFT along y, projections, energies -------
+            // the NTC voxel tiles of a row run as independent, interleaved MFMA chains
 #pragma unroll 1
             for (int k = 0; k < NGK; ++k, ++grp) {
                 const bool pair = !self && k > 0 && k < L / 2;
@@ -246,62 +265,67 @@ __global__ __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
 #pragma unroll
                     for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
                 }
+                f4 acc[NTC][MT];
+                auto row_dft = [&](int nu) {
 #pragma unroll
-                for (int c = 0; c < NTC; ++c) {
-                    const int y0 = S * (c * 16 + n);
-                    f4 acc[MT];
+                    for (int c = 0; c < NTC; ++c)
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+                        for (int mt = 0; mt < MT; ++mt) acc[c][mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int j = 0; j < J; ++j) {
-                        const int bo = k * PYB + y0 + 8 * j + qoff;
-                        const u32x4 b = lds4(&Bw[bo]);
+                        u32x4 b[NTC], bl[NTC];
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
+                        for (int c = 0; c < NTC; ++c) {
+                            const int bo = nu * PYB + S * (c * 16 + n) + 8 * j + qoff;
+                            b[c] = lds4(&Bw[bo]);
+                            if (DS) bl[c] = lds4(&Bw_lo[bo]);
+                        }
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) acc[c][mt] = HT::mma(wc[mt][j], b[c], acc[c][mt]);
                         if (DS) {
-                            const u32x4 bl = lds4(&Bw_lo[bo]);
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], bl, acc[mt]);
+                            for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                                for (int mt = 0; mt < MT; ++mt) acc[c][mt] = HT::mma(wc[mt][j], bl[c], acc[c][mt]);
                         }
                     }
-                    float m0[MT], m1[MT];
+                };
+                float m0[NTC][MT], m1[NTC][MT];
+                row_dft(k);
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) {
-                        m0[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
-                        m1[mt] = __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                        const f4 a = acc[c][mt];
+                        m0[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                        m1[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
                     }
-                    if (pair) {
+                if (pair) {
+                    row_dft(L - k);
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int j = 0; j < J; ++j) {
-                            const int bo = (L - k) * PYB + y0 + 8 * j + qoff;
-                            const u32x4 b = lds4(&Bw[bo]);
-#pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
-                            if (DS) {
-                                const u32x4 bl = lds4(&Bw_lo[bo]);
-#pragma unroll
-                                for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], bl, acc[mt]);
-                            }
-                        }
+                    for (int c = 0; c < NTC; ++c)
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
-                            m0[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][0], acc[mt][0], acc[mt][1] * acc[mt][1]));
-                            m1[mt] += __builtin_amdgcn_sqrtf(fmaf(acc[mt][2], acc[mt][2], acc[mt][3] * acc[mt][3]));
+                            const f4 a = acc[c][mt];
+                            m0[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                            m1[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
                         }
-                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NTC; ++c)
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                         for (int m = 0; m < 3; ++m)
-                            e[c][m] = fmaf(wv[mt][3 + m], m1[mt], fmaf(wv[mt][m], m0[mt], e[c][m]));
-                }
+                            e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        if (t0 + S < t_end) load_a(t0 + S);
         const int x = x_base + S * wave;
 #pragma unroll
         for (int c = 0; c < NTC; ++c) {
