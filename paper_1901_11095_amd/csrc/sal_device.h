@@ -27,6 +27,14 @@ __device__ __forceinline__ int refl_idx(int u, int n)
 // Workgroup -> tile order that keeps neighbouring tiles on one XCD: workgroups are
 // dispatched round-robin over the 8 XCDs, so workgroup b runs on XCD b % 8; giving each XCD
 // a contiguous range of tiles lets halo re-reads hit that XCD's L2.
+// The value unchanged, but opaque to the optimiser: an index derived from it inside a loop
+// is recomputed there instead of being hoisted and held in registers across the loop.
+__device__ __forceinline__ int opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 __device__ __forceinline__ int xcd_tile(int bid, int nblk)
 {
     const int q = nblk >> 3;

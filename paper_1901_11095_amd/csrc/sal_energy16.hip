@@ -82,14 +82,14 @@ __device__ __forceinline__ u32x4 lds4(const uint32_t *p) { return u32x4{p[0], p[
 
 }  // namespace
 
-// Waves per SIMD the register allocation must allow, as measured best: four at cube 8 (more
-// would force spills into the inner loops), four at cube 16 without the data split; with it
+// Waves per SIMD the register allocation must allow, as measured best: six at cube 8 (the
+// LDS of a workgroup admits three per CU), four at cube 16 without the data split; with it
 // the LDS of a cube-16 workgroup admits one per CU, so two.  Strided tiles are LDS-bound.
 #ifndef SAL_HWPE8D
-#define SAL_HWPE8D 4
+#define SAL_HWPE8D 6
 #endif
 #ifndef SAL_HWPE8
-#define SAL_HWPE8 4
+#define SAL_HWPE8 6
 #endif
 #ifndef SAL_HWPE16D
 #define SAL_HWPE16D 2
@@ -126,6 +126,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     __shared__ uint32_t A_s[NP][h * PY * PX];
     __shared__ uint32_t B_s[NW][NP][L * PYB];
     __shared__ float wb_s[NWB];
+    __shared__ u32x4 wa_s[MTA * 64];
     __shared__ float red_s[NW];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -137,13 +138,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     const int t_end = min(bx.o0 + bx.d0, t_begin + S * tt_len);
     const int K1 = (bx.d1 + S - 1) / S, K2 = (bx.d2 + S - 1) / S;
 
-    u32x4 wc[MT][J], wa[MTA];
+    u32x4 wc[MT][J];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < J; ++j) wc[mt][j] = reinterpret_cast<const u32x4 *>(w_c16)[(mt * J + j) * 64 + lane];
-#pragma unroll
-    for (int mt = 0; mt < MTA; ++mt) wa[mt] = reinterpret_cast<const u32x4 *>(w_a16)[mt * 64 + lane];
+    for (int i = threadIdx.x; i < MTA * 64; i += 64 * NW) wa_s[i] = reinterpret_cast<const u32x4 *>(w_a16)[i];
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
@@ -155,14 +155,20 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     const int qoff = 4 * (g & 1);
 
     // samples of this wave's stage-A positions for one t0; the next t0's loads are issued
-    // after stage C and the offsets recomputed, so neither holds registers through B and C
+    // after stage C so they hold no registers through B and C, and the 64-bit addresses are
+    // formed at each load from the kept 32-bit offsets
+    int off_xy[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
+        const int xp = pos / PY, yp = pos - xp * PY;
+        off_xy[jj] = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
+    }
     float vnext[NJ][4];
     auto load_a = [&](int t0) {
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
-            const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
-            const int xp = pos / PY, yp = pos - xp * PY;
-            const int off = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
+            const int off = opaque(off_xy[jj]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int p = 4 * g + e;
@@ -198,10 +204,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
                 f4 acc[MTA];
 #pragma unroll
                 for (int mt = 0; mt < MTA; ++mt) {
-                    acc[mt] = HT::mma(wa[mt], b, f4{0.f, 0.f, 0.f, 0.f});
-                    if (DS) acc[mt] = HT::mma(wa[mt], bl, acc[mt]);
+                    const u32x4 wa = wa_s[mt * 64 + lane];  // stage-A matrix, read when used
+                    acc[mt] = HT::mma(wa, b, f4{0.f, 0.f, 0.f, 0.f});
+                    if (DS) acc[mt] = HT::mma(wa, bl, acc[mt]);
                 }
-                const int pos = tl * 16 + n;
+                const int pos = tl * 16 + opaque(n);
                 if (pos < NPOS) {
                     const int xp = pos / PY, yp = pos - xp * PY;
 #pragma unroll
@@ -336,7 +343,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
                 s += __shfl_xor(s, 32);
                 e[c][m] = s;
             }
-            const int y = y_base + S * (c * 16 + n);
+            const int y = y_base + S * (c * 16 + opaque(n));
             if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
                 const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
                 E[o] = e[c][0];

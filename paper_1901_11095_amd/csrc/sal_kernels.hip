@@ -56,6 +56,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
     __shared__ float2 A_s[NPOS * h];
     __shared__ float2 B_s[NW][L * PYB];
     __shared__ float wb_s[NWB];
+    __shared__ float wa_s[16 * MTA * L];
     __shared__ float red_s[NW];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -75,11 +76,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) wc[mt][kk] = w_c[(16 * mt + n) * (2 * L) + KS * g + kk];
-    float wa[MTA][KSA];
-#pragma unroll
-    for (int mt = 0; mt < MTA; ++mt)
-#pragma unroll
-        for (int kk = 0; kk < KSA; ++kk) wa[mt][kk] = w_a[(16 * mt + n) * L + KSA * g + kk];
+    // the stage-A matrix is read from LDS when used (it is needed once per t0 only)
+    for (int i = threadIdx.x; i < 16 * MTA * L; i += 64 * NW) wa_s[i] = w_a[i];
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
@@ -89,15 +87,20 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
     float2 *Bw = B_s[wave];
 
     // Volume samples of the stage-A positions of this wave for one t0.  The loads for the
-    // next t0 are issued after stage C, so they hold no registers through stages B and C;
-    // the position offsets are recomputed for the same reason.
+    // next t0 are issued after stage C, so they hold no registers through stages B and C.
+    // The 32-bit position offsets are kept; the 64-bit addresses are formed at each load.
+    int off_xy[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
+        const int xp = pos / PY, yp = pos - xp * PY;
+        off_xy[jj] = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
+    }
     float vnext[NJ][KSA];
     auto load_a = [&](int t0) {
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
-            const int pos = min((wave + NW * jj) * 16 + n, NPOS - 1);
-            const int xp = pos / PY, yp = pos - xp * PY;
-            const int off = refl_idx(x_base - H + xp, n1) * n2 + refl_idx(y_base - H + yp, n2);
+            const int off = opaque(off_xy[jj]);
 #pragma unroll
             for (int kk = 0; kk < KSA; ++kk) {
                 const int tr = refl_idx(t0 - H + KSA * g + kk, n0);
@@ -127,9 +130,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
                     const float v = vcur[jj][kk];
                     vmax = fmaxf(vmax, fabsf(v));
 #pragma unroll
-                    for (int mt = 0; mt < MTA; ++mt) acc[mt] = mfma4(wa[mt][kk], v, acc[mt]);
+                    for (int mt = 0; mt < MTA; ++mt)
+                        acc[mt] = mfma4(wa_s[(16 * mt + n) * L + KSA * g + kk], v, acc[mt]);
                 }
-                const int pos = tl * 16 + n;
+                const int pos = tl * 16 + opaque(n);
                 if (pos < NPOS) {
 #pragma unroll
                     for (int mt = 0; mt < MTA; ++mt) {
@@ -279,7 +283,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
                 s += __shfl_xor(s, 32);
                 e[c][m] = s;
             }
-            const int y = y_base + S * (c * 16 + n);
+            const int y = y_base + S * (c * 16 + opaque(n));
             if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
                 const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
                 E[o] = e[c][0];
