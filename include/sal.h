@@ -221,6 +221,38 @@ sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, in
                           const double *stats, double bound, float *err_out, void *stream);
 
 /*
+ * Batched tile check (the surrogate's fallback): for nbox tiles of equal size tile_dims,
+ * steps 1-4 (Sec. 2, Eqs. (1)-(5)) on each tile as sal_raw_box computes them, then the check
+ * and replacement of sal_tile_merge, in one pass over all tiles.
+ *   V, n0..n2   DEVICE float volumes, each n0 x n1 x n2; volume b starts at V + b * vol_stride
+ *               (vol_stride = 0: every tile lies in the same volume, else a multiple of 4 of
+ *               at least n0 n1 n2 floats).  A volume may be a crop of a larger one: windows
+ *               reflect at its faces, so a face inside the larger volume must lie at least
+ *               floor(L/2) + r from the tile.
+ *   box_lo      HOST int64 [nbox][3]: origin of tile b in volume b
+ *   S_raw, m0..m2  DEVICE float [3][m0][m1][m2]: the predicted raw maps
+ *   tile_lo     HOST int64 [nbox][3]: origin of tile b in S_raw
+ *   stats       DEVICE double [SAL_STATS_LEN] giving the ranges hi_m - lo_m of the error
+ *   err_out     DEVICE float [nbox]: err of each tile as in sal_tile_merge; tiles with
+ *               err > bound are overwritten in S_raw with the exact maps
+ *   exact_out   optional DEVICE float [nbox][3][d0][d1][d2]: the exact maps (NULL: kept in
+ *               the workspace)
+ *   workspace   DEVICE, at least sal_check_tiles_workspace_size() bytes for the same
+ *               n0..n2, nbox and tile_dims
+ * Tiles must not overlap (the replacement of one would otherwise race with the check of
+ * another).  Requires stride 1.  Errors: SAL_E_INVAL (a tile outside its volume or the map,
+ * nbox outside [1, 2^20], tile sides outside [1, 1024]), SAL_E_UNSUPPORTED (stride 2),
+ * SAL_E_WORKSPACE, SAL_E_DEVICE.
+ */
+sal_status sal_check_tiles_workspace_size(sal_ctx *ctx, int64_t n0, int64_t n1, int64_t n2, int64_t nbox,
+                                          const int64_t tile_dims[3], size_t *bytes);
+sal_status sal_check_tiles(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                           int64_t vol_stride, const int64_t *box_lo, float *S_raw, int64_t m0, int64_t m1,
+                           int64_t m2, const int64_t *tile_lo, int64_t nbox, const int64_t tile_dims[3],
+                           const double *stats, double bound, float *err_out, float *exact_out,
+                           void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * Per-tile extremes of raw maps S_raw (float [3][n0][n1][n2]) over the tiles of side `tile`
  * (the last tile along an axis may be shorter), tiles numbered (t, x, y) with y fastest:
  * out (DEVICE float [ntiles][6]) = {min_t, max_t, min_x, max_x, min_y, max_y} per tile,

@@ -598,6 +598,109 @@ sal_status sal_raw_box(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64
     return SAL_OK;
 }
 
+// workspace of sal_check_tiles: E of every grown box, the exact tile maps, the box table and
+// the max|V| partials of the energy launch
+struct CheckWs {
+    size_t e, exact, table, vmax, total;
+    int64_t maxg[3], estride;
+};
+static CheckWs check_ws(const sal_ctx *c, const int64_t n[3], int64_t nbox, const int64_t td[3])
+{
+    CheckWs w;
+    for (int a = 0; a < 3; ++a) w.maxg[a] = td[a] + 2 * c->r < n[a] ? td[a] + 2 * c->r : n[a];
+    w.estride = 3 * w.maxg[0] * w.maxg[1] * w.maxg[2];
+    w.e = 0;
+    w.exact = w.e + align256((size_t)nbox * w.estride * sizeof(float));
+    w.table = w.exact + align256((size_t)nbox * 3 * td[0] * td[1] * td[2] * sizeof(float));
+    w.vmax = w.table + align256((size_t)nbox * BOX_TABLE * sizeof(int));
+    w.total = w.vmax + align256((size_t)energy_boxes_num_blocks(c, (int)nbox, w.maxg) * sizeof(float));
+    return w;
+}
+
+static sal_status check_tile_args(sal_ctx *c, int64_t n0, int64_t n1, int64_t n2, int64_t nbox,
+                                  const int64_t td[3])
+{
+    if (c->p.stride != 1) return fail(c, SAL_E_UNSUPPORTED, "tile checks are computed with stride 1 only");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    if (nbox < 1 || nbox > (1 << 20)) return fail(c, SAL_E_INVAL, "nbox must be in [1, 2^20]");
+    for (int a = 0; a < 3; ++a)
+        if (td[a] < 1 || td[a] > 1024) return fail(c, SAL_E_INVAL, "tile sides must be in [1, 1024]");
+    return SAL_OK;
+}
+
+sal_status sal_check_tiles_workspace_size(sal_ctx *c, int64_t n0, int64_t n1, int64_t n2, int64_t nbox,
+                                          const int64_t tile_dims[3], size_t *bytes)
+{
+    if (!c || !tile_dims || !bytes) return fail(c, SAL_E_INVAL, "null argument");
+    sal_status st = check_tile_args(c, n0, n1, n2, nbox, tile_dims);
+    if (st != SAL_OK) return st;
+    const int64_t n[3] = {n0, n1, n2};
+    *bytes = check_ws(c, n, nbox, tile_dims).total;
+    return SAL_OK;
+}
+
+sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, int64_t vol_stride,
+                           const int64_t *box_lo, float *S_raw, int64_t m0, int64_t m1, int64_t m2,
+                           const int64_t *tile_lo, int64_t nbox, const int64_t tile_dims[3], const double *stats,
+                           double bound, float *err_out, float *exact_out, void *workspace, size_t ws_bytes,
+                           void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!V || !box_lo || !S_raw || !tile_lo || !tile_dims || !stats || !err_out || !workspace)
+        return fail(c, SAL_E_INVAL, "null pointer");
+    if (!aligned16(V) || !aligned16(S_raw) || !aligned16(workspace) || (exact_out && !aligned16(exact_out)))
+        return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    sal_status st = check_tile_args(c, n0, n1, n2, nbox, tile_dims);
+    if (st != SAL_OK) return st;
+    if (m0 < 1 || m1 < 1 || m2 < 1 || m0 * m1 * m2 > ((int64_t)1 << 31) - 1)
+        return fail(c, SAL_E_INVAL, "map dimensions out of range");
+    const int64_t N = n0 * n1 * n2;
+    if (vol_stride != 0 && (vol_stride < N || (vol_stride & 3) != 0))
+        return fail(c, SAL_E_INVAL, "vol_stride must be 0 or a multiple of 4 of at least n0 n1 n2");
+    if (!(bound >= 0.0)) return fail(c, SAL_E_INVAL, "bound must be >= 0");
+    const int64_t n[3] = {n0, n1, n2}, m[3] = {m0, m1, m2};
+    std::vector<int> table((size_t)nbox * BOX_TABLE, 0);
+    for (int64_t b = 0; b < nbox; ++b) {
+        const int64_t *lo = box_lo + 3 * b, *to = tile_lo + 3 * b;
+        for (int a = 0; a < 3; ++a) {
+            if (lo[a] < 0 || lo[a] + tile_dims[a] > n[a])
+                return fail(c, SAL_E_INVAL, "box " + std::to_string(b) + " outside its volume");
+            if (to[a] < 0 || to[a] + tile_dims[a] > m[a])
+                return fail(c, SAL_E_INVAL, "tile " + std::to_string(b) + " outside the map");
+        }
+        int64_t eo[3], ed[3];
+        grow_box(c, n, lo, tile_dims, eo, ed);
+        int *q = &table[(size_t)b * BOX_TABLE];
+        for (int a = 0; a < 3; ++a) {
+            q[a] = (int)eo[a];
+            q[3 + a] = (int)ed[a];
+            q[6 + a] = (int)lo[a];
+            q[9 + a] = (int)to[a];
+        }
+    }
+    const CheckWs w = check_ws(c, n, nbox, tile_dims);
+    if (ws_bytes < w.total) return fail(c, SAL_E_WORKSPACE, "workspace too small: need " + std::to_string(w.total) + " bytes");
+    DevScope ds(c->device);
+    if ((st = sticky(c)) != SAL_OK) return st;
+    char *ws = (char *)workspace;
+    float *Eb = (float *)(ws + w.e);
+    float *X = exact_out ? exact_out : (float *)(ws + w.exact);
+    int *tab = (int *)(ws + w.table);
+    hipStream_t s = (hipStream_t)stream;
+    // the table is staged from pageable memory before the call returns
+    hipError_t e = hipMemcpyAsync(tab, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return dev_fail(c, e, "box table upload");
+    e = launch_energy_boxes(c, V, n0, n1, n2, vol_stride, tab, (int)nbox, w.maxg, Eb, w.estride,
+                            (float *)(ws + w.vmax), nullptr, s);
+    if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    e = launch_dcs_boxes(c, Eb, w.estride, tab, (int)nbox, n, tile_dims, X, s);
+    if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
+    e = launch_tile_merge_boxes(S_raw, m0, m1, m2, X, tab, (int)nbox, tile_dims, stats, bound, err_out, s);
+    if (e != hipSuccess) return dev_fail(c, e, "tile merge launch");
+    return SAL_OK;
+}
+
 sal_status sal_normalize_combine(sal_ctx *c, const float *V, double vmax_in, const float *S_raw, int64_t n0,
                                  int64_t n1, int64_t n2, float *S, double *stats_out, void *workspace,
                                  size_t ws_bytes, void *stream)

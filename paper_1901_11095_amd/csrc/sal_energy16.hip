@@ -131,7 +131,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, n = lane & 15;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int box;
+    const int tile = box_tile(bx, &box);
+    V += box * bx.vstride;
+    E += box * bx.estride;
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
     const int y_base = bx.o2 + S * ty * TY, x_base = bx.o1 + S * tx * NW;
     const int t_begin = bx.o0 + S * tb * tt_len;

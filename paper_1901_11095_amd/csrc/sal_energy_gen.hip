@@ -65,7 +65,10 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
     __shared__ float red_s[4];
 
     const int tid = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int box;
+    const int tile = box_tile(bx, &box);
+    V += box * bx.vstride;
+    E += box * bx.estride;
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
     const int y_base = bx.o2 + S * ty * NY, x_base = bx.o1 + S * tx * NX;
     const int t_begin = bx.o0 + S * tb * tt_len;
@@ -179,23 +182,28 @@ int gen_tt_len(int64_t n0, int64_t tiles_xy)
     return (int)tt;
 }
 
+// grid of one box (nbox > 1: the t walk is sized for that many boxes in one launch)
 template <int L>
-void gen_grid(int64_t d0, int64_t d1, int64_t d2, int *nby, int *nbx, int *tt, int64_t *nb)
+void gen_grid(int64_t d0, int64_t d1, int64_t d2, int *nby, int *nbx, int *tt, int64_t *nb, int64_t nbox = 1)
 {
     *nby = (int)((d2 + GenCfg<L>::NY - 1) / GenCfg<L>::NY);
     *nbx = (int)((d1 + GenCfg<L>::NX - 1) / GenCfg<L>::NX);
-    *tt = gen_tt_len(d0, (int64_t)(*nby) * (*nbx));
+    *tt = gen_tt_len(d0, (int64_t)(*nby) * (*nbx) * nbox);
     *nb = (int64_t)(*nby) * (*nbx) * ((d0 + *tt - 1) / *tt);
 }
 
 template <int L>
-hipError_t launch_gen_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
-                        float *E, float *vmax_part, int *nparts, hipStream_t s)
+hipError_t launch_gen_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
+                        float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
 {
     const int S = c->p.stride;
     int nby, nbx, tt;
     int64_t nb;
-    gen_grid<L>((bx.d0 + S - 1) / S, (bx.d1 + S - 1) / S, (bx.d2 + S - 1) / S, &nby, &nbx, &tt, &nb);
+    gen_grid<L>((bx.d0 + S - 1) / S, (bx.d1 + S - 1) / S, (bx.d2 + S - 1) / S, &nby, &nbx, &tt, &nb, nbox);
+    if (bx.table) {
+        bx.per_box = (int)nb;
+        nb *= nbox;
+    }
     if (nparts) *nparts = (int)nb;
     if (nb == 0) return hipSuccess;
     GenTw<L> tw;
@@ -211,32 +219,32 @@ hipError_t launch_gen_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1
 
 }  // namespace
 
-int64_t energy_gen_num_blocks(int L, int64_t d0, int64_t d1, int64_t d2)
+int64_t energy_gen_num_blocks(int L, int64_t d0, int64_t d1, int64_t d2, int64_t nbox)
 {
     int nby, nbx, tt;
     int64_t nb = 0;
     switch (L) {
-    case 2: gen_grid<2>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
-    case 3: gen_grid<3>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
-    case 4: gen_grid<4>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
-    case 5: gen_grid<5>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
-    case 6: gen_grid<6>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
-    case 7: gen_grid<7>(d0, d1, d2, &nby, &nbx, &tt, &nb); break;
+    case 2: gen_grid<2>(d0, d1, d2, &nby, &nbx, &tt, &nb, nbox); break;
+    case 3: gen_grid<3>(d0, d1, d2, &nby, &nbx, &tt, &nb, nbox); break;
+    case 4: gen_grid<4>(d0, d1, d2, &nby, &nbx, &tt, &nb, nbox); break;
+    case 5: gen_grid<5>(d0, d1, d2, &nby, &nbx, &tt, &nb, nbox); break;
+    case 6: gen_grid<6>(d0, d1, d2, &nby, &nbx, &tt, &nb, nbox); break;
+    case 7: gen_grid<7>(d0, d1, d2, &nby, &nbx, &tt, &nb, nbox); break;
     default: break;
     }
     return nb;
 }
 
 hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
-                             float *E, float *vmax_part, int *nparts, hipStream_t s)
+                             float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
 {
     switch (c->L) {
-    case 2: return launch_gen_L<2>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
-    case 3: return launch_gen_L<3>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
-    case 4: return launch_gen_L<4>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
-    case 5: return launch_gen_L<5>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
-    case 6: return launch_gen_L<6>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
-    case 7: return launch_gen_L<7>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    case 2: return launch_gen_L<2>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    case 3: return launch_gen_L<3>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    case 4: return launch_gen_L<4>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    case 5: return launch_gen_L<5>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    case 6: return launch_gen_L<6>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    case 7: return launch_gen_L<7>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     default: return hipErrorInvalidValue;
     }
 }

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "sal.h"
+#include "sal_device.h"
 
 // Device tables built once per context from FP64 values rounded to the kernel's type.
 struct sal_tables {
@@ -84,9 +85,37 @@ __host__ __device__ inline void ray_step(int b, int &dt, int &dx, int &dy)
 // Output box of the fused kernels: E is computed for the volume positions o + [0, d) and
 // stored box-local as [3][d0][d1][d2]; windows still read the whole volume (reflected at
 // its faces).
+// Batched boxes (tile checks): when `table` is set, workgroup w serves box b = w / per_box
+// (after the XCD-aware renumbering), whose o and d are the first six of its BOX_TABLE ints;
+// box b reads the volume starting vstride floats after that of box b - 1 and writes its E
+// estride floats after that of box b - 1.  The grid of one box is sized for the largest.
 struct ebox {
     int o0, o1, o2, d0, d1, d2;
+    const int *table = nullptr;
+    int per_box = 0;
+    int64_t vstride = 0, estride = 0;
 };
+// ints per box in a batch table: grown box {o0, o1, o2, d0, d1, d2} in volume b, the tile
+// origin in volume b, the tile origin in the predicted map, padding
+constexpr int BOX_TABLE = 12;
+
+// Workgroup -> tile of its box; for a batch it also loads the geometry of box *b (the
+// caller moves its volume and E pointers by b strides).
+__device__ __forceinline__ int box_tile(ebox &bx, int *b)
+{
+    const int t = sal_dev::xcd_tile(blockIdx.x, gridDim.x);
+    *b = 0;
+    if (!bx.table) return t;
+    *b = t / bx.per_box;
+    const int *q = bx.table + BOX_TABLE * *b;
+    bx.o0 = q[0];
+    bx.o1 = q[1];
+    bx.o2 = q[2];
+    bx.d0 = q[3];
+    bx.d1 = q[4];
+    bx.d2 = q[5];
+    return t - *b * bx.per_box;
+}
 
 // ------------------------------------------------------------------ launchers
 // All return hipSuccess or the launch error.
@@ -99,10 +128,25 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
 hipError_t launch_energy16(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
                            const ebox &bx, float *E, float *vmax_part, int nby, int nbx, int tt,
                            int64_t nb, hipStream_t s);
+// nbox boxes of at most maxd voxels per axis, geometry in the device table (BOX_TABLE ints
+// per box); returns the number of vmax partials written in *nparts
+hipError_t launch_energy_boxes(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                               int64_t vstride, const int *table, int nbox, const int64_t maxd[3], float *E,
+                               int64_t estride, float *vmax_part, int *nparts, hipStream_t s);
+int64_t energy_boxes_num_blocks(const sal_ctx *c, int nbox, const int64_t maxd[3]);
+// Eq. (5) on the tiles of a batch (tile origin in volume b from the table), each from the E
+// of its grown box; S_box[b][3][d0][d1][d2] written sstride floats apart
+hipError_t launch_dcs_boxes(const sal_ctx *c, const float *Eb, int64_t estride, const int *table, int nbox,
+                            const int64_t n[3], const int64_t bd[3], float *S_box, hipStream_t s);
+// error and replacement of the tiles of a batch in the predicted map (origin from the table)
+hipError_t launch_tile_merge_boxes(float *S_raw, int64_t n0, int64_t n1, int64_t n2, const float *exact,
+                                   const int *table, int nbox, const int64_t td[3], const double *stats,
+                                   double bound, float *err, hipStream_t s);
 
-int64_t energy_gen_num_blocks(int L, int64_t d0, int64_t d1, int64_t d2);
+int64_t energy_gen_num_blocks(int L, int64_t d0, int64_t d1, int64_t d2, int64_t nbox = 1);
+// bx.table set: nbox boxes of at most bx.d voxels per axis (the grid is nbox times that of one)
 hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
-                             float *E, float *vmax_part, int *nparts, hipStream_t s);
+                             float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox = 1);
 
 hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, int64_t n2,
                       float *S_raw, float *minmax_part, hipStream_t s);

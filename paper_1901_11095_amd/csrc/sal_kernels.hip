@@ -62,7 +62,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, n = lane & 15;
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int box;
+    const int tile = box_tile(bx, &box);
+    V += box * bx.vstride;
+    E += box * bx.estride;
     const int ty = tile % nby, tx = (tile / nby) % nbx, tb = tile / (nby * nbx);
     const int y_base = bx.o2 + S * ty * TY, x_base = bx.o1 + S * tx * NW;
     const int t_begin = bx.o0 + S * tb * tt_len;
@@ -406,36 +409,64 @@ __global__ __launch_bounds__(256) void k_upsample(const float *__restrict__ El, 
 // written box-local [3][bd0][bd1][bd2].  Neighbours are reflected at the volume faces and
 // then read from the grown box, which holds every such position.  Same order of the sums as
 // k_dcs.
+// Eq. (5) at position pos of a box: energies Eb of the grown box (origin org, size ed),
+// output element i of the box-local maps S[3][nb]
+__device__ __forceinline__ void dcs_box_at(const float *__restrict__ Eb, const int org[3], const int ed[3],
+                                           const int dims[3], const int pos[3], const dcs_args &a,
+                                           float *__restrict__ S, int nb, int i)
+{
+    const int64_t NE = (int64_t)ed[0] * ed[1] * ed[2];
+    const int64_t stride[3] = {(int64_t)ed[1] * ed[2], ed[2], 1};
+    const int64_t v = (pos[0] - org[0]) * stride[0] + (pos[1] - org[1]) * stride[1] + (pos[2] - org[2]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const float *Em = Eb + m * NE;
+        const float c = Em[v];
+        float sum = 0.f;
+        for (int b = 0; b < 26; ++b) {
+            if (!((a.rays[m] >> b) & 1u)) continue;
+            int st[3];
+            ray_step(b, st[0], st[1], st[2]);
+            const float *gw = a.g + 32 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2] - 1);
+            for (int s = 1; s <= a.r; ++s) {
+                int u[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) u[k] = refl_idx(pos[k] + st[k] * s, dims[k]) - org[k];
+                sum += fabsf(c - gw[s - 1] * Em[u[0] * stride[0] + u[1] * stride[1] + u[2]]);
+            }
+        }
+        S[(int64_t)m * nb + i] = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_dcs_box(const float *__restrict__ Eb, int3 eo, int3 ed, int3 nv,
                                                  int3 bo, int3 bd, dcs_args a, float *__restrict__ S)
 {
     const int nb = bd.x * bd.y * bd.z;
-    const int64_t NE = (int64_t)ed.x * ed.y * ed.z;
-    const int dims[3] = {nv.x, nv.y, nv.z};
-    const int org[3] = {eo.x, eo.y, eo.z};
-    const int64_t stride[3] = {(int64_t)ed.y * ed.z, ed.z, 1};
+    const int dims[3] = {nv.x, nv.y, nv.z}, org[3] = {eo.x, eo.y, eo.z}, edim[3] = {ed.x, ed.y, ed.z};
     for (int i = blockIdx.x * 256 + threadIdx.x; i < nb; i += gridDim.x * 256) {
         const int pos[3] = {bo.x + i / (bd.y * bd.z), bo.y + (i / bd.z) % bd.y, bo.z + i % bd.z};
-        const int64_t v = (pos[0] - eo.x) * stride[0] + (pos[1] - eo.y) * stride[1] + (pos[2] - eo.z);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const float *Em = Eb + m * NE;
-            const float c = Em[v];
-            float sum = 0.f;
-            for (int b = 0; b < 26; ++b) {
-                if (!((a.rays[m] >> b) & 1u)) continue;
-                int st[3];
-                ray_step(b, st[0], st[1], st[2]);
-                const float *gw = a.g + 32 * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2] - 1);
-                for (int s = 1; s <= a.r; ++s) {
-                    int u[3];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) u[k] = refl_idx(pos[k] + st[k] * s, dims[k]) - org[k];
-                    sum += fabsf(c - gw[s - 1] * Em[u[0] * stride[0] + u[1] * stride[1] + u[2]]);
-                }
-            }
-            S[(int64_t)m * nb + i] = a.Q[m] > 0.f ? sum / a.Q[m] : 0.f;
-        }
+        dcs_box_at(Eb, org, edim, dims, pos, a, S, nb, i);
+    }
+}
+
+// The same for the tiles of a batch: workgroups [b * per_box, (b + 1) * per_box) serve box
+// b, whose grown box and tile origin come from its table entry; E of box b starts estride
+// floats after that of box b - 1, its maps 3 * |bd| floats after.
+__global__ __launch_bounds__(256) void k_dcs_boxes(const float *__restrict__ Eb, int64_t estride,
+                                                   const int *__restrict__ table, int per_box, int3 nv,
+                                                   int3 bd, dcs_args a, float *__restrict__ S)
+{
+    const int b = blockIdx.x / per_box, blk = blockIdx.x - b * per_box;
+    const int *q = table + BOX_TABLE * b;
+    const int org[3] = {q[0], q[1], q[2]}, edim[3] = {q[3], q[4], q[5]}, bo[3] = {q[6], q[7], q[8]};
+    const int dims[3] = {nv.x, nv.y, nv.z};
+    const int nb = bd.x * bd.y * bd.z;
+    Eb += b * estride;
+    S += (int64_t)b * 3 * nb;
+    for (int i = blk * 256 + threadIdx.x; i < nb; i += per_box * 256) {
+        const int pos[3] = {bo[0] + i / (bd.y * bd.z), bo[1] + (i / bd.z) % bd.y, bo[2] + i % bd.z};
+        dcs_box_at(Eb, org, edim, dims, pos, a, S, nb, i);
     }
 }
 
@@ -825,13 +856,15 @@ static int tt_len_for(int64_t n0, int64_t tiles_xy)
     return (int)tt;
 }
 
+// grid of one box (nbox > 1: the t walk is sized for that many boxes in one launch)
 template <int L>
-static void energy_grid(int64_t n0, int64_t n1, int64_t n2, int *nby, int *nbx, int *tt, int64_t *nblk)
+static void energy_grid(int64_t n0, int64_t n1, int64_t n2, int *nby, int *nbx, int *tt, int64_t *nblk,
+                        int64_t nbox = 1)
 {
     using C = TileCfg<L>;
     *nby = (int)((n2 + C::TY - 1) / C::TY);
     *nbx = (int)((n1 + C::NW - 1) / C::NW);
-    *tt = tt_len_for(n0, (int64_t)(*nby) * (*nbx));
+    *tt = tt_len_for(n0, (int64_t)(*nby) * (*nbx) * nbox);
     *nblk = (int64_t)(*nby) * (*nbx) * ((n0 + *tt - 1) / *tt);
 }
 
@@ -853,13 +886,17 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 
 template <int L>
 static hipError_t launch_energy_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1,
-                                  int64_t n2, const ebox &bx, float *E, float *vmax_part,
-                                  int *nparts, hipStream_t s)
+                                  int64_t n2, ebox bx, float *E, float *vmax_part,
+                                  int *nparts, hipStream_t s, int nbox = 1)
 {
     const int S = c->p.stride;
     int nby, nbx, tt;
     int64_t nb;
-    energy_grid<L>((bx.d0 + S - 1) / S, (bx.d1 + S - 1) / S, (bx.d2 + S - 1) / S, &nby, &nbx, &tt, &nb);
+    energy_grid<L>((bx.d0 + S - 1) / S, (bx.d1 + S - 1) / S, (bx.d2 + S - 1) / S, &nby, &nbx, &tt, &nb, nbox);
+    if (bx.table) {
+        bx.per_box = (int)nb;
+        nb *= nbox;
+    }
     if (nparts) *nparts = (int)nb;
     if (c->p.precision != SAL_FP32)
         return launch_energy16(c, V, n0, n1, n2, bx, E, vmax_part, nby, nbx, tt, nb, s);
@@ -883,6 +920,32 @@ hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+}
+
+hipError_t launch_energy_boxes(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                               int64_t vstride, const int *table, int nbox, const int64_t maxd[3], float *E,
+                               int64_t estride, float *vmax_part, int *nparts, hipStream_t s)
+{
+    ebox bx{0, 0, 0, (int)maxd[0], (int)maxd[1], (int)maxd[2]};
+    bx.table = table;
+    bx.vstride = vstride;
+    bx.estride = estride;
+    if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+}
+
+int64_t energy_boxes_num_blocks(const sal_ctx *c, int nbox, const int64_t maxd[3])
+{
+    int nby, nbx, tt;
+    int64_t nb;
+    if (c->L == 8)
+        energy_grid<8>(maxd[0], maxd[1], maxd[2], &nby, &nbx, &tt, &nb, nbox);
+    else if (c->L == 16)
+        energy_grid<16>(maxd[0], maxd[1], maxd[2], &nby, &nbx, &tt, &nb, nbox);
+    else
+        nb = energy_gen_num_blocks(c->L, maxd[0], maxd[1], maxd[2], nbox);
+    return nb * nbox;
 }
 
 int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
@@ -1018,6 +1081,24 @@ hipError_t launch_dcs_box(const sal_ctx *c, const float *Eb, const int64_t eo[3]
     auto i3 = [](const int64_t *v) { return make_int3((int)v[0], (int)v[1], (int)v[2]); };
     hipLaunchKernelGGL(k_dcs_box, dim3(blocks), dim3(256), 0, s, Eb, i3(eo), i3(ed), i3(n), i3(bo), i3(bd), a,
                        S);
+    return hipGetLastError();
+}
+
+hipError_t launch_dcs_boxes(const sal_ctx *c, const float *Eb, int64_t estride, const int *table, int nbox,
+                            const int64_t n[3], const int64_t bd[3], float *S_box, hipStream_t s)
+{
+    dcs_args a;
+    a.r = c->r;
+    for (int m = 0; m < 3; ++m) {
+        a.rays[m] = c->p.rays[m];
+        a.Q[m] = c->Q[m];
+    }
+    for (int i = 0; i < 96; ++i) a.g[i] = c->g[i];
+    const int64_t nb = bd[0] * bd[1] * bd[2];
+    const int per_box = (int)((nb + 255) / 256 < 64 ? (nb + 255) / 256 : 64);
+    hipLaunchKernelGGL(k_dcs_boxes, dim3((unsigned)(per_box * nbox)), dim3(256), 0, s, Eb, estride, table,
+                       per_box, make_int3((int)n[0], (int)n[1], (int)n[2]),
+                       make_int3((int)bd[0], (int)bd[1], (int)bd[2]), a, S_box);
     return hipGetLastError();
 }
 

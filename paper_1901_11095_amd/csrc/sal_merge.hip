@@ -114,6 +114,62 @@ __global__ __launch_bounds__(256) void k_tile_copy(float *__restrict__ S, int n0
     }
 }
 
+__global__ __launch_bounds__(256) void k_fill_n(float *__restrict__ p, int n, float v)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// The tile check of k_tile_err / k_tile_copy for the tiles of a batch: workgroups
+// [b * per_box, (b + 1) * per_box) serve tile b, at the origin in the predicted map given by
+// its table entry; its exact maps are X[b][3][td].
+__global__ __launch_bounds__(256) void k_tile_err_boxes(const float *__restrict__ S, int n0, int n1, int n2,
+                                                        const float *__restrict__ X, const int *__restrict__ table,
+                                                        int per_box, int3 td, const double *__restrict__ stats,
+                                                        float *__restrict__ err)
+{
+    const int b = blockIdx.x / per_box, blk = blockIdx.x - b * per_box;
+    const int *q = table + BOX_TABLE * b;
+    const int nt = td.x * td.y * td.z;
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    X += (int64_t)b * 3 * nt;
+    float inv[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const double r = stats[2 * m + 1] - stats[2 * m];
+        inv[m] = r > 0.0 ? (float)(1.0 / r) : 0.f;
+    }
+    float e = 0.f;
+    for (int i = blk * 256 + threadIdx.x; i < nt; i += per_box * 256) {
+        const int t = q[9] + i / (td.y * td.z), x = q[10] + (i / td.z) % td.y, y = q[11] + i % td.z;
+        const int64_t vo = ((int64_t)t * n1 + x) * n2 + y;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) e = fmaxf(e, fabsf(S[m * N + vo] - X[m * nt + i]) * inv[m]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) e = fmaxf(e, __shfl_xor(e, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int *>(err + b), __float_as_uint(e));
+}
+
+__global__ __launch_bounds__(256) void k_tile_copy_boxes(float *__restrict__ S, int n0, int n1, int n2,
+                                                         const float *__restrict__ X, const int *__restrict__ table,
+                                                         int per_box, int3 td, const float *__restrict__ err,
+                                                         float bound)
+{
+    const int b = blockIdx.x / per_box, blk = blockIdx.x - b * per_box;
+    if (!(err[b] > bound)) return;
+    const int *q = table + BOX_TABLE * b;
+    const int nt = td.x * td.y * td.z;
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    X += (int64_t)b * 3 * nt;
+    for (int i = blk * 256 + threadIdx.x; i < nt; i += per_box * 256) {
+        const int t = q[9] + i / (td.y * td.z), x = q[10] + (i / td.z) % td.y, y = q[11] + i % td.z;
+        const int64_t vo = ((int64_t)t * n1 + x) * n2 + y;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) S[m * N + vo] = X[m * nt + i];
+    }
+}
+
 // {min, max} of each raw map over one tile per workgroup; tiles numbered (t, x, y), y fastest
 __global__ __launch_bounds__(256) void k_tile_minmax(const float *__restrict__ S, int n0, int n1, int n2, int tile,
                                                      int ntx, int nty, float *__restrict__ out)
@@ -193,6 +249,21 @@ hipError_t launch_tile_merge(float *S_raw, int64_t n0, int64_t n1, int64_t n2, c
                        stats, err);
     hipLaunchKernelGGL(k_tile_copy, dim3(nb), dim3(256), 0, s, S_raw, (int)n0, (int)n1, (int)n2, exact, c, t,
                        err, (float)bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_merge_boxes(float *S_raw, int64_t n0, int64_t n1, int64_t n2, const float *exact,
+                                   const int *table, int nbox, const int64_t td[3], const double *stats,
+                                   double bound, float *err, hipStream_t s)
+{
+    const int64_t nt = td[0] * td[1] * td[2];
+    const int per_box = (int)((nt + 255) / 256 < 32 ? (nt + 255) / 256 : 32);
+    const int3 t3 = make_int3((int)td[0], (int)td[1], (int)td[2]);
+    hipLaunchKernelGGL(k_fill_n, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, s, err, nbox, 0.f);
+    hipLaunchKernelGGL(k_tile_err_boxes, dim3((unsigned)(per_box * nbox)), dim3(256), 0, s, S_raw, (int)n0, (int)n1,
+                       (int)n2, exact, table, per_box, t3, stats, err);
+    hipLaunchKernelGGL(k_tile_copy_boxes, dim3((unsigned)(per_box * nbox)), dim3(256), 0, s, S_raw, (int)n0,
+                       (int)n1, (int)n2, exact, table, per_box, t3, err, (float)bound);
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@ import ctypes
 import os
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from .build import LIB as _LIB_PATH
@@ -31,6 +32,7 @@ EXPORTS = ("sal_default_params", "sal_create", "sal_destroy", "sal_last_error",
            "sal_workspace_size", "sal_local_spectra", "sal_project", "sal_directional_compare",
            "sal_saliency", "sal_profile_enable", "sal_profile_read", "sal_normalize_combine",
            "sal_tile_merge", "sal_tile_minmax", "sal_raw_box_workspace_size", "sal_raw_box",
+           "sal_check_tiles_workspace_size", "sal_check_tiles",
            "sal_net_num_params", "sal_net_last_error", "sal_net_create",
            "sal_net_destroy", "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
            "sal_net_workspace_size", "sal_net_forward", "sal_net_backward", "sal_net_train_step",
@@ -93,6 +95,9 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     l.sal_tile_minmax.argtypes = [vp, vp, i64, i64, i64, ctypes.c_int32, vp, vp]
     l.sal_raw_box_workspace_size.argtypes = [vp, _i64p, ctypes.POINTER(sz)]
     l.sal_raw_box.argtypes = [vp, vp, i64, i64, i64, _i64p, _i64p, vp, vp, sz, vp]
+    l.sal_check_tiles_workspace_size.argtypes = [vp, i64, i64, i64, i64, _i64p, ctypes.POINTER(sz)]
+    l.sal_check_tiles.argtypes = [vp, vp, i64, i64, i64, i64, _i64p, vp, i64, i64, i64, _i64p, i64,
+                                  _i64p, vp, ctypes.c_double, vp, vp, vp, sz, vp]
     l.sal_net_num_params.argtypes = []
     l.sal_net_num_params.restype = i64
     l.sal_net_last_error.argtypes = [vp]
@@ -113,7 +118,8 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     for f in ("sal_create", "sal_workspace_size", "sal_local_spectra", "sal_project",
               "sal_directional_compare", "sal_saliency", "sal_profile_enable",
               "sal_profile_read", "sal_normalize_combine", "sal_tile_merge", "sal_tile_minmax",
-              "sal_raw_box_workspace_size", "sal_raw_box", "sal_net_create",
+              "sal_raw_box_workspace_size", "sal_raw_box", "sal_check_tiles_workspace_size",
+              "sal_check_tiles", "sal_net_create",
               "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
               "sal_net_workspace_size", "sal_net_forward", "sal_net_backward",
               "sal_net_train_step", "sal_net_infer"):
@@ -317,6 +323,43 @@ def tile_merge(ctx: "Saliency", S_raw: torch.Tensor, exact: torch.Tensor, crop_l
                                        _i64x3(exact.shape[1:]), _i64x3(tile_lo), _i64x3(tile_dims),
                                        _ptr(stats), float(bound), _ptr(err_out),
                                        _stream(S_raw.device)))
+
+
+def check_tiles_workspace_size(ctx: "Saliency", vshape, nbox: int, tile_dims) -> int:
+    """Workspace bytes of check_tiles for volumes of shape vshape and nbox tiles."""
+    n = ctypes.c_size_t()
+    ctx._raise(ctx._lib.sal_check_tiles_workspace_size(ctx._h, *[int(v) for v in vshape], int(nbox),
+                                                       _i64x3(tile_dims), ctypes.byref(n)))
+    return n.value
+
+
+def check_tiles(ctx: "Saliency", V: torch.Tensor, box_lo, S_raw: torch.Tensor, tile_lo, tile_dims,
+                stats: torch.Tensor, bound: float, err_out: torch.Tensor,
+                exact_out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
+    """Batched tile check: V is one volume [n0, n1, n2] holding every tile, or a stack
+    [nbox, n0, n1, n2] with tile b in volume b; box_lo / tile_lo: nbox origins (in V, in
+    S_raw); tiles over `bound` are replaced in S_raw.  err_out: CUDA float32 [nbox]."""
+    if not (V.is_cuda and V.dtype == torch.float32 and V.is_contiguous() and V.dim() in (3, 4)):
+        raise ValueError("V must be a contiguous float32 CUDA tensor [n0, n1, n2] or [nbox, n0, n1, n2]")
+    box = np.ascontiguousarray(np.asarray(box_lo, dtype=np.int64).reshape(-1, 3))
+    til = np.ascontiguousarray(np.asarray(tile_lo, dtype=np.int64).reshape(-1, 3))
+    nbox = len(box)
+    if len(til) != nbox:
+        raise ValueError("box_lo and tile_lo must hold the same number of origins")
+    vshape = tuple(V.shape[-3:])
+    vstride = 0
+    if V.dim() == 4:
+        if V.shape[0] != nbox:
+            raise ValueError("a stacked V must hold one volume per tile")
+        vstride = vshape[0] * vshape[1] * vshape[2]
+    dims = _i64x3(tile_dims)
+    if workspace is None:
+        workspace = torch.empty(max(1, check_tiles_workspace_size(ctx, vshape, nbox, tile_dims)),
+                                dtype=torch.uint8, device=V.device)
+    ctx._raise(ctx._lib.sal_check_tiles(
+        ctx._h, _ptr(V), *vshape, vstride, box.ctypes.data_as(_i64p), _ptr(S_raw), *S_raw.shape[1:],
+        til.ctypes.data_as(_i64p), nbox, dims, _ptr(stats), float(bound), _ptr(err_out), _ptr(exact_out),
+        _ptr(workspace), workspace.numel(), _stream(V.device)))
 
 
 def tile_minmax(ctx: "Saliency", S_raw: torch.Tensor, tile: int,

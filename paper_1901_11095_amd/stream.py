@@ -34,9 +34,12 @@ def _slabs(n0: int, slab: int, halo: int):
 
 
 def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
-                      S_raw: Optional[torch.Tensor] = None, device="cuda"):
+                      S_raw: Optional[torch.Tensor] = None, device="cuda",
+                      keep: Optional[torch.Tensor] = None):
     """Raw maps [3, n0, n1, n2] (device) of a pinned host volume; `compute(Vslab)` returns
-    the raw maps [3, m, n1, n2] of a device slab [m, n1, n2].  Returns (S_raw, max|V|)."""
+    the raw maps [3, m, n1, n2] of a device slab [m, n1, n2].  With `keep` (device
+    [n0, n1, n2]) the rows of every slab are also kept there as they pass.  Returns
+    (S_raw, max|V|)."""
     n0, n1, n2 = V_host.shape
     dev = torch.device(device)
     if S_raw is None:
@@ -68,6 +71,8 @@ def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
         Vs = bufs[k][:b - a]
         out = compute(Vs)
         S_raw[:, s0:s1].copy_(out[:, s0 - a:s1 - a])
+        if keep is not None:
+            keep[s0:s1].copy_(Vs[s0 - a:s1 - a])
         vmax[i] = Vs[s0 - a:s1 - a].abs().max()
         done[k].record(comp)
     return S_raw, float(vmax.max())
@@ -88,27 +93,56 @@ def plain_streamed(ctx: sal.Saliency, V_host: torch.Tensor, slab: int = 64):
     return S, S_raw, stats
 
 
+def slab_volumes(V_host: torch.Tensor, tile: int, halo: int, slab_rows: int = 4, device="cuda"):
+    """For TileCheck.check_many without a resident volume: groups the tiles by runs of
+    `slab_rows` tile rows along t and uploads, per group, the rows it covers plus `halo`
+    (clipped to the volume), on the current stream."""
+    n0, n1, n2 = V_host.shape
+    nt12 = ((n1 + tile - 1) // tile) * ((n2 + tile - 1) // tile)
+
+    def volumes(tis):
+        rows = {}
+        for ti in tis:
+            rows.setdefault(ti // nt12 // slab_rows, []).append(ti)
+        for g in sorted(rows):
+            s0 = g * slab_rows * tile
+            s1 = min(n0, s0 + slab_rows * tile)
+            a, b = max(0, s0 - halo), min(n0, s1 + halo)
+            Vs = V_host[a:b].to(device, non_blocking=True)
+            yield Vs, (a, 0, 0), rows[g]
+    return volumes
+
+
 def surrogate_streamed(net: sal.Net, ctx_fallback: sal.Saliency, V_host: torch.Tensor,
                        slab: int = 64, tile: int = 32, frac: float = 0.02, bound: float = 0.02,
-                       seed: int = 0, max_rounds: int = 8, per_round: int = 32, top_frac: float = 0.05):
-    """Surrogate first, slab by slab (halo 5), then the seeded tile check and the check of
-    the tiles holding each map's extremes, on crops copied from the host volume, with the
-    plain method (ctx_fallback, e.g. split-BF16) and exact replacement; then the FP64
-    normalisation and Eq. (6)."""
-    S_raw, vmax = raw_maps_streamed(V_host, net.infer, 5, slab)
-    dev = S_raw.device
+                       seed: int = 0, max_rounds: int = 8, per_round: int = 32, top_frac: float = 0.05,
+                       keep_volume: bool = True):
+    """Surrogate first, slab by slab (halo 5), then the seeded tile check, the check of the
+    tiles with the highest predicted saliency and of the tiles holding each map's extremes,
+    with the plain method (ctx_fallback, e.g. split-BF16) and exact replacement, in batched
+    passes; then the FP64 normalisation and Eq. (6).  With keep_volume the slabs stay in HBM
+    as they stream (one more float per voxel) and the checks read them there; otherwise
+    the rows holding checked tiles are streamed again (halo floor(L/2) + r)."""
+    dev = torch.device("cuda")
+    keep = torch.empty(tuple(V_host.shape), dtype=torch.float32, device=dev) if keep_volume else None
+    S_raw, vmax = raw_maps_streamed(V_host, net.infer, 5, slab, keep=keep)
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
     S = sal.normalize_combine(ctx_fallback, S_raw, None, stats_out=stats, vmax=vmax)
     n_all = len(surrogate.tiles_of(tuple(V_host.shape), tile))
     sample = surrogate.seeded_tiles(n_all, frac, seed)
+    halo = ctx_fallback.L // 2 + ctx_fallback.params.d // 2
 
     def crop(lo, hi):
         return V_host[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].contiguous().to(dev), lo
 
+    if keep is not None:
+        volumes = lambda tis: [(keep, (0, 0, 0), tis)]
+    else:
+        volumes = slab_volumes(V_host, tile, halo, device=dev)
     chk = surrogate.TileCheck(ctx_fallback, S_raw, stats, crop, tile, bound,
-                              len(sample) + int(math.ceil(top_frac * n_all)) + 6 * per_round * max_rounds)
-    for ti in sample:
-        chk.check(ti)
+                              len(sample) + int(math.ceil(top_frac * n_all)) + 6 * per_round * max_rounds,
+                              volumes=volumes)
+    chk.check_many(sample)
     chk.check_top(top_frac)
     rounds = chk.verify_extremes(max_rounds, per_round)
     S = sal.normalize_combine(ctx_fallback, S_raw, None, S=S, stats_out=stats, vmax=vmax)

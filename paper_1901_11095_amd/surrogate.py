@@ -158,11 +158,15 @@ class TileCheck:
     the bound.  `source(lo, hi)` returns (volume, origin): a device volume holding at least
     the samples of the box [lo, hi) of the full volume, and the full-volume position of its
     first sample (the resident volume itself with origin 0, or a crop copied from host
-    memory).  A tile is checked at most once."""
+    memory); it serves `check`, one tile at a time.  `volumes(tiles)` yields
+    (volume, origin, subset) groups covering the given tile indices, each subset with its
+    halos inside its device volume; it serves `check_many`, which checks a group's tiles in
+    batched passes (sal_check_tiles).  A tile is checked at most once."""
 
     def __init__(self, ctx: sal.Saliency, S_raw: torch.Tensor, stats: torch.Tensor, source,
-                 tile: int, bound: float, capacity: int):
+                 tile: int, bound: float, capacity: int, volumes=None, chunk: int = 256):
         self.ctx, self.S_raw, self.stats, self.source = ctx, S_raw, stats, source
+        self.volumes, self.chunk = volumes, chunk
         self.shape = tuple(S_raw.shape[1:])
         self.tile, self.bound = tile, bound
         self.nt = [(n + tile - 1) // tile for n in self.shape]
@@ -170,6 +174,7 @@ class TileCheck:
         self.done = {}      # tile index -> slot in errs
         self.tiles = []     # (lo, dims) in check order
         self.exact = torch.empty((3, tile, tile, tile), dtype=torch.float32, device=S_raw.device)
+        self._ws = None
 
     def n_tiles(self) -> int:
         return self.nt[0] * self.nt[1] * self.nt[2]
@@ -203,6 +208,40 @@ class TileCheck:
         self.tiles.append((lo, td))
         return True
 
+    def tile_dims(self, ti: int):
+        return tuple(min(self.tile, n - a) for a, n in zip(self.tile_lo(ti), self.shape))
+
+    def check_many(self, tis) -> int:
+        """Check the given tiles not checked yet (up to the capacity) in batched passes;
+        returns how many were checked."""
+        new = [t for t in dict.fromkeys(int(t) for t in tis) if t not in self.done]
+        new = new[:max(0, len(self.errs) - len(self.done))]
+        if not new:
+            return 0
+        if self.volumes is None:
+            for ti in new:
+                self.check(ti)
+            return len(new)
+        for V, org, sub in self.volumes(new):
+            by_dims = {}
+            for ti in sub:
+                by_dims.setdefault(self.tile_dims(ti), []).append(ti)
+            for td, group in by_dims.items():
+                for c0 in range(0, len(group), self.chunk):
+                    part = group[c0:c0 + self.chunk]
+                    j0 = len(self.done)
+                    los = [self.tile_lo(ti) for ti in part]
+                    for k, ti in enumerate(part):
+                        self.done[ti] = j0 + k
+                        self.tiles.append((los[k], td))
+                    need = sal.check_tiles_workspace_size(self.ctx, V.shape, len(part), td)
+                    if self._ws is None or self._ws.numel() < need:
+                        self._ws = torch.empty(need, dtype=torch.uint8, device=V.device)
+                    box = [tuple(a - o for a, o in zip(lo, org)) for lo in los]
+                    sal.check_tiles(self.ctx, V, box, self.S_raw, los, td, self.stats, self.bound,
+                                    self.errs[j0:j0 + len(part)], workspace=self._ws)
+        return len(new)
+
     def verify_extremes(self, max_rounds: int = 8, per_round: int = 32) -> int:
         """The volume-wide minimum and maximum of each map set the normalisation of Eq. (6).
         Check every unchecked tile whose values pass the extremes of the checked tiles by
@@ -226,8 +265,7 @@ class TileCheck:
             new = list(dict.fromkeys(new))
             if not new:
                 return r
-            for ti in new:
-                self.check(ti)
+            self.check_many(new)
         return max_rounds
 
     def check_top(self, frac: float, abc=(1 / 3, 1 / 3, 1 / 3)) -> int:
@@ -245,10 +283,7 @@ class TileCheck:
             rng = st[2 * m + 1] - st[2 * m]
             if rng > 0:
                 score += abc[m] * (mm[:, 2 * m + 1] - st[2 * m]) / rng
-        n = 0
-        for ti in np.argsort(-score, kind="stable")[:k]:
-            n += int(self.check(int(ti)))
-        return n
+        return self.check_many(np.argsort(-score, kind="stable")[:k])
 
     def errors(self) -> torch.Tensor:
         return self.errs[:len(self.done)]
@@ -276,9 +311,9 @@ def infer_with_fallback(net: sal.Net, ctx_exact: sal.Saliency, V: torch.Tensor, 
     n_all = len(tiles_of(tuple(V.shape), tile))
     sample = seeded_tiles(n_all, frac, seed)
     cap = len(sample) + int(math.ceil(top_frac * n_all)) + (6 * per_round * max_rounds if check_extremes else 0)
-    chk = TileCheck(ctx_exact, S_raw, stats, lambda lo, hi: (V, (0, 0, 0)), tile, bound, cap)
-    for ti in sample:
-        chk.check(ti)
+    chk = TileCheck(ctx_exact, S_raw, stats, lambda lo, hi: (V, (0, 0, 0)), tile, bound, cap,
+                    volumes=lambda tis: [(V, (0, 0, 0), tis)])
+    chk.check_many(sample)
     chk.check_top(top_frac)
     rounds = chk.verify_extremes(max_rounds, per_round) if check_extremes else 0
     S = sal.normalize_combine(ctx_exact, S_raw, V, S=S, stats_out=stats)
