@@ -598,10 +598,53 @@ sal_status sal_raw_box(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64
     return SAL_OK;
 }
 
-// workspace of sal_check_tiles: E of every grown box, the exact tile maps, the box table and
-// the max|V| partials of the energy launch
+// Energy boxes one tile's check needs, inside the tile's grown box (eo, ed).  Eq. (5) reads
+// E_m only along the rays of map m: with axis rays only, that is the tile grown by r along y
+// (when some ray runs along y) plus slabs of r beyond its faces along t and along x (when
+// some ray runs along them); reflected neighbours stay inside the same ranges.  With a
+// diagonal ray, the whole grown box.  Returns the boxes as {o[3], d[3]}.
+static int check_boxes(const sal_ctx *c, const int64_t lo[3], const int64_t td[3], const int64_t eo[3],
+                       const int64_t ed[3], int64_t out[5][6])
+{
+    uint32_t any = 0;
+    for (int m = 0; m < 3; ++m) any |= c->p.rays[m];
+    auto put = [&](int k, const int64_t o[3], const int64_t d[3]) {
+        for (int a = 0; a < 3; ++a) {
+            out[k][a] = o[a];
+            out[k][3 + a] = d[a];
+        }
+    };
+    if (any >> 6) {
+        put(0, eo, ed);
+        return 1;
+    }
+    const bool along[3] = {(any & 3u) != 0, (any & 12u) != 0, (any & 48u) != 0};
+    int k = 0;
+    {
+        int64_t o[3] = {lo[0], lo[1], lo[2]}, d[3] = {td[0], td[1], td[2]};
+        if (along[2]) {
+            o[2] = eo[2];
+            d[2] = ed[2];
+        }
+        put(k++, o, d);
+    }
+    for (int a = 0; a < 2; ++a) {
+        if (!along[a]) continue;
+        int64_t o[3] = {lo[0], lo[1], lo[2]}, d[3] = {td[0], td[1], td[2]};
+        o[a] = eo[a];
+        d[a] = lo[a] - eo[a];
+        if (d[a] > 0) put(k++, o, d);
+        o[a] = lo[a] + td[a];
+        d[a] = eo[a] + ed[a] - o[a];
+        if (d[a] > 0) put(k++, o, d);
+    }
+    return k;
+}
+
+// workspace of sal_check_tiles: E of every grown box, the exact tile maps, and the tables
+// (at most five energy boxes per tile)
 struct CheckWs {
-    size_t e, exact, table, vmax, total;
+    size_t e, exact, table, total;
     int64_t maxg[3], estride;
 };
 static CheckWs check_ws(const sal_ctx *c, const int64_t n[3], int64_t nbox, const int64_t td[3])
@@ -612,8 +655,7 @@ static CheckWs check_ws(const sal_ctx *c, const int64_t n[3], int64_t nbox, cons
     w.e = 0;
     w.exact = w.e + align256((size_t)nbox * w.estride * sizeof(float));
     w.table = w.exact + align256((size_t)nbox * 3 * td[0] * td[1] * td[2] * sizeof(float));
-    w.vmax = w.table + align256((size_t)nbox * BOX_TABLE * sizeof(int));
-    w.total = w.vmax + align256((size_t)energy_boxes_num_blocks(c, (int)nbox, w.maxg) * sizeof(float));
+    w.total = w.table + align256((size_t)nbox * (5 * ENERGY_TABLE + BOX_TABLE) * sizeof(int));
     return w;
 }
 
@@ -660,7 +702,10 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
         return fail(c, SAL_E_INVAL, "vol_stride must be 0 or a multiple of 4 of at least n0 n1 n2");
     if (!(bound >= 0.0)) return fail(c, SAL_E_INVAL, "bound must be >= 0");
     const int64_t n[3] = {n0, n1, n2}, m[3] = {m0, m1, m2};
-    std::vector<int> table((size_t)nbox * BOX_TABLE, 0);
+    // energy boxes (ENERGY_TABLE ints each) first, then one BOX_TABLE entry per tile
+    std::vector<int> etab, ttab((size_t)nbox * BOX_TABLE, 0);
+    etab.reserve((size_t)nbox * 5 * ENERGY_TABLE);
+    int64_t maxd[3] = {1, 1, 1};
     for (int64_t b = 0; b < nbox; ++b) {
         const int64_t *lo = box_lo + 3 * b, *to = tile_lo + 3 * b;
         for (int a = 0; a < 3; ++a) {
@@ -669,16 +714,25 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
             if (to[a] < 0 || to[a] + tile_dims[a] > m[a])
                 return fail(c, SAL_E_INVAL, "tile " + std::to_string(b) + " outside the map");
         }
-        int64_t eo[3], ed[3];
+        int64_t eo[3], ed[3], sub[5][6];
         grow_box(c, n, lo, tile_dims, eo, ed);
-        int *q = &table[(size_t)b * BOX_TABLE];
+        int *q = &ttab[(size_t)b * BOX_TABLE];
         for (int a = 0; a < 3; ++a) {
             q[a] = (int)eo[a];
             q[3 + a] = (int)ed[a];
             q[6 + a] = (int)lo[a];
             q[9 + a] = (int)to[a];
         }
+        const int k = check_boxes(c, lo, tile_dims, eo, ed, sub);
+        for (int i = 0; i < k; ++i) {
+            const int e[ENERGY_TABLE] = {(int)sub[i][0], (int)sub[i][1], (int)sub[i][2], (int)sub[i][3],
+                                         (int)sub[i][4], (int)sub[i][5], (int)eo[0], (int)eo[1], (int)eo[2],
+                                         (int)ed[0], (int)ed[1], (int)ed[2], (int)b, 0, 0, 0};
+            etab.insert(etab.end(), e, e + ENERGY_TABLE);
+            for (int a = 0; a < 3; ++a) maxd[a] = sub[i][3 + a] > maxd[a] ? sub[i][3 + a] : maxd[a];
+        }
     }
+    const int nent = (int)(etab.size() / ENERGY_TABLE);
     const CheckWs w = check_ws(c, n, nbox, tile_dims);
     if (ws_bytes < w.total) return fail(c, SAL_E_WORKSPACE, "workspace too small: need " + std::to_string(w.total) + " bytes");
     DevScope ds(c->device);
@@ -686,17 +740,17 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
     char *ws = (char *)workspace;
     float *Eb = (float *)(ws + w.e);
     float *X = exact_out ? exact_out : (float *)(ws + w.exact);
-    int *tab = (int *)(ws + w.table);
+    int *etab_d = (int *)(ws + w.table), *ttab_d = etab_d + etab.size();
+    etab.insert(etab.end(), ttab.begin(), ttab.end());
     hipStream_t s = (hipStream_t)stream;
-    // the table is staged from pageable memory before the call returns
-    hipError_t e = hipMemcpyAsync(tab, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    // the tables are staged from pageable memory before the call returns
+    hipError_t e = hipMemcpyAsync(etab_d, etab.data(), etab.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return dev_fail(c, e, "box table upload");
-    e = launch_energy_boxes(c, V, n0, n1, n2, vol_stride, tab, (int)nbox, w.maxg, Eb, w.estride,
-                            (float *)(ws + w.vmax), nullptr, s);
+    e = launch_energy_boxes(c, V, n0, n1, n2, vol_stride, etab_d, nent, maxd, Eb, w.estride, nullptr, nullptr, s);
     if (e != hipSuccess) return dev_fail(c, e, "energy launch");
-    e = launch_dcs_boxes(c, Eb, w.estride, tab, (int)nbox, n, tile_dims, X, s);
+    e = launch_dcs_boxes(c, Eb, w.estride, ttab_d, (int)nbox, n, tile_dims, X, s);
     if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
-    e = launch_tile_merge_boxes(S_raw, m0, m1, m2, X, tab, (int)nbox, tile_dims, stats, bound, err_out, s);
+    e = launch_tile_merge_boxes(S_raw, m0, m1, m2, X, ttab_d, (int)nbox, tile_dims, stats, bound, err_out, s);
     if (e != hipSuccess) return dev_fail(c, e, "tile merge launch");
     return SAL_OK;
 }

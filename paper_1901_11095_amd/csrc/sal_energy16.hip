@@ -139,7 +139,13 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     const int y_base = bx.o2 + S * ty * TY, x_base = bx.o1 + S * tx * NW;
     const int t_begin = bx.o0 + S * tb * tt_len;
     const int t_end = min(bx.o0 + bx.d0, t_begin + S * tt_len);
-    const int K1 = (bx.d1 + S - 1) / S, K2 = (bx.d2 + S - 1) / S;
+    if (t_begin >= t_end || x_base >= bx.o1 + bx.d1 || y_base >= bx.o2 + bx.d2) {
+        // past a box smaller than the grid's (batched boxes): nothing to compute
+        if (threadIdx.x == 0 && vmax_part) vmax_part[blockIdx.x] = 0.f;
+        return;
+    }
+    // E frame (the box itself unless a batch entry says otherwise)
+    const int K1 = bx.fk1, K2 = bx.fk2;
 
     u32x4 wc[MT][J];
 #pragma unroll
@@ -151,7 +157,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
     const int64_t plane = (int64_t)n1 * n2;
-    const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
+    const int64_t nbox = (int64_t)bx.fk0 * K1 * K2;
     float vmax = 0.0f;
     uint32_t *Bw = B_s[wave][0];
     uint32_t *Bw_lo = B_s[wave][NP - 1];
@@ -348,7 +354,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
             }
             const int y = y_base + S * (c * 16 + opaque(n));
             if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
-                const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
+                const int64_t o = ((int64_t)((t0 - bx.fo0) / S) * K1 + (x - bx.fo1) / S) * K2 + (y - bx.fo2) / S;
                 E[o] = e[c][0];
                 E[nbox + o] = e[c][1];
                 E[2 * nbox + o] = e[c][2];
@@ -359,7 +365,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
     if (lane == 0) red_s[wave] = vmax;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && vmax_part) {
         float m = red_s[0];
         for (int w = 1; w < NW; ++w) m = fmaxf(m, red_s[w]);
         vmax_part[blockIdx.x] = m;

@@ -73,9 +73,15 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
     const int y_base = bx.o2 + S * ty * NY, x_base = bx.o1 + S * tx * NX;
     const int t_begin = bx.o0 + S * tb * tt_len;
     const int t_end = min(bx.o0 + bx.d0, t_begin + S * tt_len);
+    if (t_begin >= t_end || x_base >= bx.o1 + bx.d1 || y_base >= bx.o2 + bx.d2) {
+        // past a box smaller than the grid's (batched boxes): nothing to compute
+        if (tid == 0 && vmax_part) vmax_part[blockIdx.x] = 0.f;
+        return;
+    }
     const int64_t plane = (int64_t)n1 * n2;
-    const int K1 = (bx.d1 + S - 1) / S, K2 = (bx.d2 + S - 1) / S;
-    const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
+    // E frame (the box itself unless a batch entry says otherwise)
+    const int K1 = bx.fk1, K2 = bx.fk2;
+    const int64_t nbox = (int64_t)bx.fk0 * K1 * K2;
 
     for (int i = tid; i < NW3; i += 256) wg_s[i] = wgen[i];
     if (tid == 0)
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
         }
         const int x = x_base + S * x0, y = y_base + S * y0;
         if (x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
-            const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
+            const int64_t o = ((int64_t)((t0 - bx.fo0) / S) * K1 + (x - bx.fo1) / S) * K2 + (y - bx.fo2) / S;
             E[o] = e0;
             E[nbox + o] = e1;
             E[2 * nbox + o] = e2;
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
     for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
     if ((tid & 63) == 0) red_s[tid >> 6] = vmax;
     __syncthreads();
-    if (tid == 0) vmax_part[blockIdx.x] = fmaxf(fmaxf(red_s[0], red_s[1]), fmaxf(red_s[2], red_s[3]));
+    if (tid == 0 && vmax_part) vmax_part[blockIdx.x] = fmaxf(fmaxf(red_s[0], red_s[1]), fmaxf(red_s[2], red_s[3]));
 }
 
 // ====================================================================== launchers

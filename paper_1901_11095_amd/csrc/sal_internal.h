@@ -82,39 +82,64 @@ __host__ __device__ inline void ray_step(int b, int &dt, int &dx, int &dy)
     }
 }
 
-// Output box of the fused kernels: E is computed for the volume positions o + [0, d) and
-// stored box-local as [3][d0][d1][d2]; windows still read the whole volume (reflected at
-// its faces).
-// Batched boxes (tile checks): when `table` is set, workgroup w serves box b = w / per_box
-// (after the XCD-aware renumbering), whose o and d are the first six of its BOX_TABLE ints;
-// box b reads the volume starting vstride floats after that of box b - 1 and writes its E
-// estride floats after that of box b - 1.  The grid of one box is sized for the largest.
+// Output box of the fused kernels: E is computed for the volume positions o + [0, d) (the
+// positions o + S k, k < ceil(d / S), with stride S) and stored in a frame: as
+// [3][fk0][fk1][fk2] with position p at index (p - fo) / S.  For one box the frame is the
+// box itself; windows still read the whole volume (reflected at its faces).
+// Batched boxes (tile checks): when `table` is set, workgroup w serves table entry
+// e = w / per_box (after the XCD-aware renumbering), whose ENERGY_TABLE ints hold
+// {o, d, fo, fk, v}: the box, its frame, and the index v of its volume (which starts
+// v * vstride floats into V) and of its E (v * estride floats into E).  The grid of one
+// entry is sized for the largest box; workgroups past a smaller box exit at once.
 struct ebox {
     int o0, o1, o2, d0, d1, d2;
+    int fo0 = 0, fo1 = 0, fo2 = 0, fk0 = 0, fk1 = 0, fk2 = 0;
     const int *table = nullptr;
     int per_box = 0;
     int64_t vstride = 0, estride = 0;
 };
-// ints per box in a batch table: grown box {o0, o1, o2, d0, d1, d2} in volume b, the tile
-// origin in volume b, the tile origin in the predicted map, padding
+constexpr int ENERGY_TABLE = 16;
+// ints per tile in the table of the comparison and merge kernels of a batch: grown box
+// {o0, o1, o2, d0, d1, d2} in volume b, the tile origin in volume b, the tile origin in the
+// predicted map
 constexpr int BOX_TABLE = 12;
 
-// Workgroup -> tile of its box; for a batch it also loads the geometry of box *b (the
-// caller moves its volume and E pointers by b strides).
-__device__ __forceinline__ int box_tile(ebox &bx, int *b)
+// A box that is its own frame.
+inline ebox framed_box(int o0, int o1, int o2, int d0, int d1, int d2, int S)
+{
+    ebox b{o0, o1, o2, d0, d1, d2};
+    b.fo0 = o0;
+    b.fo1 = o1;
+    b.fo2 = o2;
+    b.fk0 = (d0 + S - 1) / S;
+    b.fk1 = (d1 + S - 1) / S;
+    b.fk2 = (d2 + S - 1) / S;
+    return b;
+}
+
+// Workgroup -> tile of its box; for a batch it also loads the geometry of its table entry
+// and returns in *v the index of the entry's volume and E (the caller moves its pointers).
+__device__ __forceinline__ int box_tile(ebox &bx, int *v)
 {
     const int t = sal_dev::xcd_tile(blockIdx.x, gridDim.x);
-    *b = 0;
+    *v = 0;
     if (!bx.table) return t;
-    *b = t / bx.per_box;
-    const int *q = bx.table + BOX_TABLE * *b;
+    const int e = t / bx.per_box;
+    const int *q = bx.table + ENERGY_TABLE * e;
     bx.o0 = q[0];
     bx.o1 = q[1];
     bx.o2 = q[2];
     bx.d0 = q[3];
     bx.d1 = q[4];
     bx.d2 = q[5];
-    return t - *b * bx.per_box;
+    bx.fo0 = q[6];
+    bx.fo1 = q[7];
+    bx.fo2 = q[8];
+    bx.fk0 = q[9];
+    bx.fk1 = q[10];
+    bx.fk2 = q[11];
+    *v = q[12];
+    return t - e * bx.per_box;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -128,12 +153,11 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
 hipError_t launch_energy16(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
                            const ebox &bx, float *E, float *vmax_part, int nby, int nbx, int tt,
                            int64_t nb, hipStream_t s);
-// nbox boxes of at most maxd voxels per axis, geometry in the device table (BOX_TABLE ints
-// per box); returns the number of vmax partials written in *nparts
+// nbox table entries (ENERGY_TABLE ints each, device) of boxes of at most maxd voxels per
+// axis; returns the number of vmax partials written in *nparts
 hipError_t launch_energy_boxes(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2,
                                int64_t vstride, const int *table, int nbox, const int64_t maxd[3], float *E,
                                int64_t estride, float *vmax_part, int *nparts, hipStream_t s);
-int64_t energy_boxes_num_blocks(const sal_ctx *c, int nbox, const int64_t maxd[3]);
 // Eq. (5) on the tiles of a batch (tile origin in volume b from the table), each from the E
 // of its grown box; S_box[b][3][d0][d1][d2] written sstride floats apart
 hipError_t launch_dcs_boxes(const sal_ctx *c, const float *Eb, int64_t estride, const int *table, int nbox,

@@ -70,8 +70,13 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
     const int y_base = bx.o2 + S * ty * TY, x_base = bx.o1 + S * tx * NW;
     const int t_begin = bx.o0 + S * tb * tt_len;
     const int t_end = min(bx.o0 + bx.d0, t_begin + S * tt_len);
-    // output grid: the positions o + S k of the box, K = ceil(d / S) along each axis
-    const int K1 = (bx.d1 + S - 1) / S, K2 = (bx.d2 + S - 1) / S;
+    if (t_begin >= t_end || x_base >= bx.o1 + bx.d1 || y_base >= bx.o2 + bx.d2) {
+        // past a box smaller than the grid's (batched boxes): nothing to compute
+        if (threadIdx.x == 0 && vmax_part) vmax_part[blockIdx.x] = 0.f;
+        return;
+    }
+    // E frame (the box itself unless a batch entry says otherwise)
+    const int K1 = bx.fk1, K2 = bx.fk2;
 
     // constant MFMA A-operands: lane (g, n) holds row n of each M tile at K = KS*g + kk
     float wc[MT][KS];
@@ -85,7 +90,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
     const int64_t plane = (int64_t)n1 * n2;
-    const int64_t nbox = (int64_t)((bx.d0 + S - 1) / S) * K1 * K2;
+    const int64_t nbox = (int64_t)bx.fk0 * K1 * K2;
     float vmax = 0.0f;
     float2 *Bw = B_s[wave];
 
@@ -288,7 +293,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
             }
             const int y = y_base + S * (c * 16 + opaque(n));
             if (g == 0 && x < bx.o1 + bx.d1 && y < bx.o2 + bx.d2) {
-                const int64_t o = ((int64_t)((t0 - bx.o0) / S) * K1 + (x - bx.o1) / S) * K2 + (y - bx.o2) / S;
+                const int64_t o = ((int64_t)((t0 - bx.fo0) / S) * K1 + (x - bx.fo1) / S) * K2 + (y - bx.fo2) / S;
                 E[o] = e[c][0];
                 E[nbox + o] = e[c][1];
                 E[2 * nbox + o] = e[c][2];
@@ -300,7 +305,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
     for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
     if (lane == 0) red_s[wave] = vmax;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && vmax_part) {
         float m = red_s[0];
         for (int w = 1; w < NW; ++w) m = fmaxf(m, red_s[w]);
         vmax_part[blockIdx.x] = m;
@@ -915,8 +920,9 @@ hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n
                          const int64_t *box, float *E, float *vmax_part, int *nparts,
                          hipStream_t s)
 {
-    ebox bx{0, 0, 0, (int)n0, (int)n1, (int)n2};
-    if (box) bx = ebox{(int)box[0], (int)box[1], (int)box[2], (int)box[3], (int)box[4], (int)box[5]};
+    const int S = c->p.stride;
+    ebox bx = box ? framed_box((int)box[0], (int)box[1], (int)box[2], (int)box[3], (int)box[4], (int)box[5], S)
+                  : framed_box(0, 0, 0, (int)n0, (int)n1, (int)n2, S);
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
@@ -933,19 +939,6 @@ hipError_t launch_energy_boxes(const sal_ctx *c, const float *V, int64_t n0, int
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
-}
-
-int64_t energy_boxes_num_blocks(const sal_ctx *c, int nbox, const int64_t maxd[3])
-{
-    int nby, nbx, tt;
-    int64_t nb;
-    if (c->L == 8)
-        energy_grid<8>(maxd[0], maxd[1], maxd[2], &nby, &nbx, &tt, &nb, nbox);
-    else if (c->L == 16)
-        energy_grid<16>(maxd[0], maxd[1], maxd[2], &nby, &nbx, &tt, &nb, nbox);
-    else
-        nb = energy_gen_num_blocks(c->L, maxd[0], maxd[1], maxd[2], nbox);
-    return nb * nbox;
 }
 
 int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
