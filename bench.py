@@ -46,9 +46,10 @@ def kernel_source_hash(files=ENERGY_F32_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_tag: str):
-    """HBM bytes per launch measured by rocprofv3 counters (scaled by a copy-kernel
-    calibration), if the committed summary was taken on the current kernel sources."""
+def counters_from_profiles(kernel_tag: str):
+    """The committed rocprofv3 counter summary of the kernel (HBM bytes per launch scaled by
+    a copy-kernel calibration, MFMA busy fraction), if it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(PROFILES, "traffic_%s.json" % kernel_tag)
     if not os.path.exists(path):
         return None
@@ -56,7 +57,7 @@ def traffic_from_profiles(kernel_tag: str):
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
 def cpu_baseline(V, L: int, sample_shape=(160, 192, 192)):
@@ -454,10 +455,11 @@ def main(argv=None):
     e_ms = kms["energy"]
     achieved = fpv * N / (e_ms * 1e-3) / 1e12
     tag = "energy_f32_L%d_%s" % (args.L, args.workload)
+    prof = counters_from_profiles(tag) or {}
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic_from_profiles(tag),
+            "frac": achieved / PEAK_TFLOPS["f32"], "traffic": prof.get("bytes_per_launch"),
             "kernel": "k_energy_f32<%d>" % args.L, "kernel_ms": e_ms, "flops_per_voxel": fpv,
-            "kernels_ms": kms}
+            "mfma_busy": prof.get("mfma_busy"), "kernels_ms": kms}
 
     err = None
     if not args.no_check:
