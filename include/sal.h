@@ -241,7 +241,8 @@ sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, in
  *               n0..n2, nbox and tile_dims
  * Tiles must not overlap (the replacement of one would otherwise race with the check of
  * another).  Requires stride 1.  Errors: SAL_E_INVAL (a tile outside its volume or the map,
- * nbox outside [1, 2^20], tile sides outside [1, 1024]), SAL_E_UNSUPPORTED (stride 2),
+ * nbox outside [1, 2^20], tile sides outside [1, 1024], or a batch whose energy boxes hold
+ * more than 2^31 - 1 voxels: split it over several calls), SAL_E_UNSUPPORTED (stride 2),
  * SAL_E_WORKSPACE, SAL_E_DEVICE.
  */
 sal_status sal_check_tiles_workspace_size(sal_ctx *ctx, int64_t n0, int64_t n1, int64_t n2, int64_t nbox,

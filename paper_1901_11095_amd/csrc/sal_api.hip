@@ -734,6 +734,9 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
     }
     const int nent = (int)(etab.size() / ENERGY_TABLE);
     const CheckWs w = check_ws(c, n, nbox, tile_dims);
+    // every workgroup of the energy grid covers at least one voxel of an entry's largest box
+    if ((double)nent * maxd[0] * maxd[1] * maxd[2] > 2147483647.0)
+        return fail(c, SAL_E_INVAL, "batch too large: split the tiles over several calls");
     if (ws_bytes < w.total) return fail(c, SAL_E_WORKSPACE, "workspace too small: need " + std::to_string(w.total) + " bytes");
     DevScope ds(c->device);
     if ((st = sticky(c)) != SAL_OK) return st;

@@ -123,8 +123,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     constexpr float invL = 1.0f / (float)L;
 
     constexpr int NP = DS ? 2 : 1;  // 16-bit parts stored per value
-    __shared__ uint32_t A_s[NP][h * PY * PX];
-    __shared__ uint32_t B_s[NW][NP][L * PYB];
+    // the hi and lo parts of a row lie next to each other (lo PX, resp. PYB, words after
+    // hi), so one base address and the instruction offsets reach both
+    __shared__ uint32_t A_s[h * PY * NP * PX];    // [mu][y'][part][x']
+    __shared__ uint32_t B_s[NW][L * NP * PYB];    // per wave [nu][part][y']
     __shared__ float wb_s[NWB];
     __shared__ u32x4 wa_s[MTA * 64];
     __shared__ float red_s[NW];
@@ -159,8 +161,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     const int64_t plane = (int64_t)n1 * n2;
     const int64_t nbox = (int64_t)bx.fk0 * K1 * K2;
     float vmax = 0.0f;
-    uint32_t *Bw = B_s[wave][0];
-    uint32_t *Bw_lo = B_s[wave][NP - 1];
+    uint32_t *Bw = B_s[wave];
     const int qoff = 4 * (g & 1);
 
     // samples of this wave's stage-A positions for one t0; the next t0's loads are issued
@@ -224,9 +225,9 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
                     for (int mt = 0; mt < MTA; ++mt) {
                         const int mu0 = 8 * mt + 2 * g;
                         if (mu0 < h)
-                            store_c<DS, T>(A_s[0], A_s[NP - 1], (mu0 * PY + yp) * PX + xp, acc[mt][0] * invL, acc[mt][1] * invL);
+                            store_c<DS, T>(A_s, A_s + PX, (mu0 * PY + yp) * NP * PX + xp, acc[mt][0] * invL, acc[mt][1] * invL);
                         if (mu0 + 1 < h)
-                            store_c<DS, T>(A_s[0], A_s[NP - 1], ((mu0 + 1) * PY + yp) * PX + xp, acc[mt][2] * invL, acc[mt][3] * invL);
+                            store_c<DS, T>(A_s, A_s + PX, ((mu0 + 1) * PY + yp) * NP * PX + xp, acc[mt][2] * invL, acc[mt][3] * invL);
                     }
                 }
             }
@@ -249,12 +250,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
                 for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
-                    const int ao = (mu * PY + yp) * PX + S * wave + 8 * j + qoff;
-                    const u32x4 b = lds4(&A_s[0][ao]);
+                    const int ao = (mu * PY + yp) * NP * PX + S * wave + 8 * j + qoff;
+                    const u32x4 b = lds4(&A_s[ao]);
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
                     if (DS) {
-                        const u32x4 bl = lds4(&A_s[NP - 1][ao]);
+                        const u32x4 bl = lds4(&A_s[ao + PX]);
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], bl, acc[mt]);
                     }
@@ -262,8 +263,9 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const int nu0 = 8 * mt + 2 * g;
-                    store_c<DS, T>(Bw, Bw_lo, nu0 * PYB + nb * 16 + n, acc[mt][0] * invL, acc[mt][1] * invL);
-                    store_c<DS, T>(Bw, Bw_lo, (nu0 + 1) * PYB + nb * 16 + n, acc[mt][2] * invL, acc[mt][3] * invL);
+                    store_c<DS, T>(Bw, Bw + PYB, nu0 * NP * PYB + nb * 16 + n, acc[mt][0] * invL, acc[mt][1] * invL);
+                    store_c<DS, T>(Bw, Bw + PYB, (nu0 + 1) * NP * PYB + nb * 16 + n, acc[mt][2] * invL,
+                                   acc[mt][3] * invL);
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -292,9 +294,9 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
                         u32x4 b[NTC], bl[NTC];
 #pragma unroll
                         for (int c = 0; c < NTC; ++c) {
-                            const int bo = nu * PYB + S * (c * 16 + n) + 8 * j + qoff;
+                            const int bo = nu * NP * PYB + S * (c * 16 + n) + 8 * j + qoff;
                             b[c] = lds4(&Bw[bo]);
-                            if (DS) bl[c] = lds4(&Bw_lo[bo]);
+                            if (DS) bl[c] = lds4(&Bw[bo + PYB]);
                         }
 #pragma unroll
                         for (int c = 0; c < NTC; ++c)
