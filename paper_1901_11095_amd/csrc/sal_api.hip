@@ -214,6 +214,10 @@ hipError_t build_tables(sal_ctx *c)
     };
     const long J = L / 8;
     std::vector<uint32_t> c16((size_t)MT * J * 64 * 4, 0u), a16((size_t)MTA * 64 * 4, 0u);
+    // cube 16, stage B in two halves of eight rows: half p holds the frequencies nu below,
+    // so that the rows nu = k and 16 - k of every weight group lie in the same half
+    static const long half_nu[2][8] = {{0, 1, 15, 2, 14, 3, 13, 8}, {4, 12, 5, 11, 6, 10, 7, 9}};
+    std::vector<uint32_t> c16b(L == 16 ? c16.size() : 4, 0u);
     if (prec != SAL_FP32) {
         for (long mt = 0; mt < MT; ++mt)
             for (long j = 0; j < J; ++j)
@@ -223,6 +227,11 @@ hipError_t build_tables(sal_ctx *c)
                         const long q = 8 * j + 4 * (g & 1) + e / 2, ci = e & 1;
                         const uint16_t v = part(wc[(16 * mt + i) * 2 * L + 2 * q + ci], (int)(g >> 1));
                         c16[((mt * J + j) * 64 + lane) * 4 + e / 2] |= (uint32_t)v << (16 * (e & 1));
+                        if (L == 16) {
+                            const long row = 2 * half_nu[mt][i / 2] + (i & 1);
+                            const uint16_t vb = part(wc[row * 2 * L + 2 * q + ci], (int)(g >> 1));
+                            c16b[((mt * J + j) * 64 + lane) * 4 + e / 2] |= (uint32_t)vb << (16 * (e & 1));
+                        }
                     }
                 }
         for (long mt = 0; mt < MTA; ++mt)
@@ -244,6 +253,7 @@ hipError_t build_tables(sal_ctx *c)
     if ((e = upload(&c->t.w_proj, wp)) != hipSuccess) return e;
     if ((e = upload(&c->t.w_c16, c16)) != hipSuccess) return e;
     if ((e = upload(&c->t.w_a16, a16)) != hipSuccess) return e;
+    if ((e = upload(&c->t.w_c16b, c16b)) != hipSuccess) return e;
     if (!wg.empty() && (e = upload(&c->t.w_gen, wg)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -258,7 +268,8 @@ void free_tables(sal_tables *t)
         }
     if (t->w_c16) (void)hipFree(t->w_c16);
     if (t->w_a16) (void)hipFree(t->w_a16);
-    t->w_c16 = t->w_a16 = nullptr;
+    if (t->w_c16b) (void)hipFree(t->w_c16b);
+    t->w_c16 = t->w_a16 = t->w_c16b = nullptr;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -92,7 +92,7 @@ __device__ __forceinline__ u32x4 lds4(const uint32_t *p) { return u32x4{p[0], p[
 #define SAL_HWPE8 6
 #endif
 #ifndef SAL_HWPE16D
-#define SAL_HWPE16D 2
+#define SAL_HWPE16D 4
 #endif
 #ifndef SAL_HWPE16
 #define SAL_HWPE16 4
@@ -106,7 +106,8 @@ template <int L, typename T, bool DS, int S>
 __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_h(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
     const uint32_t *__restrict__ w_c16, const uint32_t *__restrict__ w_a16,
-    const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
+    const uint32_t *__restrict__ w_c16b, const float *__restrict__ w_grp, float *__restrict__ E,
+    float *__restrict__ vmax_part)
 {
     using G = Geo<L>;
     using C = TileCfg<L>;
@@ -126,7 +127,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     // the hi and lo parts of a row lie next to each other (lo PX, resp. PYB, words after
     // hi), so one base address and the instruction offsets reach both
     __shared__ uint32_t A_s[h * PY * NP * PX];    // [mu][y'][part][x']
-    __shared__ uint32_t B_s[NW][L * NP * PYB];    // per wave [nu][part][y']
+    // With the data split at cube 16, stage B runs in two halves of eight frequency rows,
+    // each followed by the stage C of the weight groups whose rows it holds, so B_s keeps
+    // eight rows at a time and two workgroups fit a CU.  Otherwise one pass over all rows.
+    constexpr int NH = (L == 16 && DS) ? 2 : 1, NROW = NH > 1 ? 8 : L;
+    __shared__ uint32_t B_s[NW][NROW * NP * PYB];  // per wave [row][part][y']
+    __shared__ u32x4 wcb_s[NH > 1 ? NH * J * 64 : 1];  // stage-B matrix with the halves' row order
     __shared__ float wb_s[NWB];
     __shared__ u32x4 wa_s[MTA * 64];
     __shared__ float red_s[NW];
@@ -155,6 +161,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
 #pragma unroll
         for (int j = 0; j < J; ++j) wc[mt][j] = reinterpret_cast<const u32x4 *>(w_c16)[(mt * J + j) * 64 + lane];
     for (int i = threadIdx.x; i < MTA * 64; i += 64 * NW) wa_s[i] = reinterpret_cast<const u32x4 *>(w_a16)[i];
+    if (NH > 1)
+        for (int i = threadIdx.x; i < NH * J * 64; i += 64 * NW) wcb_s[i] = reinterpret_cast<const u32x4 *>(w_c16b)[i];
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
@@ -237,111 +245,138 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
         float e[NTC][3];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) e[c][0] = e[c][1] = e[c][2] = 0.f;
-        int grp = 0;
 #pragma unroll 1
         for (int mu = 0; mu < h; ++mu) {
             const bool self = (mu == 0 || mu == L / 2);
-            // ---------------- stage B: complex DFT along x for this mu ------------------
-#pragma unroll
-            for (int nb = 0; nb < NTB; ++nb) {
-                const int yp = min(nb * 16 + n, PY - 1);
-                f4 acc[MT];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const int ao = (mu * PY + yp) * NP * PX + S * wave + 8 * j + qoff;
-                    const u32x4 b = lds4(&A_s[ao]);
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], b, acc[mt]);
-                    if (DS) {
-                        const u32x4 bl = lds4(&A_s[ao + PX]);
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[mt] = HT::mma(wc[mt][j], bl, acc[mt]);
-                    }
-                }
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const int nu0 = 8 * mt + 2 * g;
-                    store_c<DS, T>(Bw, Bw + PYB, nu0 * NP * PYB + nb * 16 + n, acc[mt][0] * invL, acc[mt][1] * invL);
-                    store_c<DS, T>(Bw, Bw + PYB, (nu0 + 1) * NP * PYB + nb * 16 + n, acc[mt][2] * invL,
-                                   acc[mt][3] * invL);
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // ---------------- stage C: complex DFT along y, projections, energies -------
-            // the NTC voxel tiles of a row run as independent, interleaved MFMA chains
 #pragma unroll 1
-            for (int k = 0; k < NGK; ++k, ++grp) {
-                const bool pair = !self && k > 0 && k < L / 2;
-                float wv[MT][6];
+            for (int hp = 0; hp < NH; ++hp) {
+                // ---------- stage B: complex DFT along x for this mu (rows of half hp) ----------
+                // one pass: row nu at position nu; halves: position i holds the i-th frequency
+                // of the half's list (the matrix rows of w_c16b are ordered the same way)
+                constexpr int BT = NH > 1 ? 1 : MT;  // M tiles per pass
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const int wo = ((grp * MT + mt) * 4 + g) * 8;
+                for (int nb = 0; nb < NTB; ++nb) {
+                    const int yp = min(nb * 16 + n, PY - 1);
+                    f4 acc[BT];
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
-                }
-                f4 acc[NTC][MT];
-                auto row_dft = [&](int nu) {
-#pragma unroll
-                    for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[c][mt] = f4{0.f, 0.f, 0.f, 0.f};
+                    for (int mt = 0; mt < BT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int j = 0; j < J; ++j) {
-                        u32x4 b[NTC], bl[NTC];
+                        const int ao = (mu * PY + yp) * NP * PX + S * wave + 8 * j + qoff;
+                        const u32x4 b = lds4(&A_s[ao]);
+                        u32x4 bl;
+                        if (DS) bl = lds4(&A_s[ao + PX]);
 #pragma unroll
-                        for (int c = 0; c < NTC; ++c) {
-                            const int bo = nu * NP * PYB + S * (c * 16 + n) + 8 * j + qoff;
-                            b[c] = lds4(&Bw[bo]);
-                            if (DS) bl[c] = lds4(&Bw[bo + PYB]);
+                        for (int mt = 0; mt < BT; ++mt) {
+                            const u32x4 w = NH > 1 ? wcb_s[(hp * J + j) * 64 + lane] : wc[mt][j];
+                            acc[mt] = HT::mma(w, b, acc[mt]);
+                            if (DS) acc[mt] = HT::mma(w, bl, acc[mt]);
                         }
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < BT; ++mt) {
+                        const int i0 = 8 * mt + 2 * g;
+                        store_c<DS, T>(Bw, Bw + PYB, i0 * NP * PYB + nb * 16 + n, acc[mt][0] * invL,
+                                       acc[mt][1] * invL);
+                        store_c<DS, T>(Bw, Bw + PYB, (i0 + 1) * NP * PYB + nb * 16 + n, acc[mt][2] * invL,
+                                       acc[mt][3] * invL);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // ---------- stage C: complex DFT along y, projections, energies ----------------
+                // weight group (mu, k) of entry ei of the half: rows nu = k at position pa and,
+                // unless mu is 0 or L/2 or k is 0 or L/2, nu = L - k at position pb; the NTC
+                // voxel tiles of a row run as independent, interleaved MFMA chains
+                const int nent = NH == 1 ? NGK : (hp == 0 ? 5 : 4);
+#pragma unroll 1
+                for (int ei = 0; ei < nent; ++ei) {
+                    int k, pa, pb;
+                    if (NH == 1) {
+                        k = ei;
+                        pa = ei;
+                        pb = L - ei;
+                    } else if (hp == 0) {
+                        k = ei < 4 ? ei : 8;
+                        pa = ei == 0 ? 0 : (ei < 4 ? 2 * ei - 1 : 7);
+                        pb = 2 * ei;
+                    } else {
+                        k = 4 + ei;
+                        pa = 2 * ei;
+                        pb = 2 * ei + 1;
+                    }
+                    const bool pair = !self && k > 0 && k < L / 2;
+                    const int grp = mu * NGK + k;
+                    float wv[MT][6];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const int wo = ((grp * MT + mt) * 4 + g) * 8;
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
+                    }
+                    f4 acc[NTC][MT];
+                    auto row_dft = [&](int pos) {
 #pragma unroll
                         for (int c = 0; c < NTC; ++c)
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) acc[c][mt] = HT::mma(wc[mt][j], b[c], acc[c][mt]);
-                        if (DS) {
+                            for (int mt = 0; mt < MT; ++mt) acc[c][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int j = 0; j < J; ++j) {
+                            u32x4 b[NTC], bl[NTC];
+#pragma unroll
+                            for (int c = 0; c < NTC; ++c) {
+                                const int bo = pos * NP * PYB + S * (c * 16 + n) + 8 * j + qoff;
+                                b[c] = lds4(&Bw[bo]);
+                                if (DS) bl[c] = lds4(&Bw[bo + PYB]);
+                            }
 #pragma unroll
                             for (int c = 0; c < NTC; ++c)
 #pragma unroll
-                                for (int mt = 0; mt < MT; ++mt) acc[c][mt] = HT::mma(wc[mt][j], bl[c], acc[c][mt]);
+                                for (int mt = 0; mt < MT; ++mt) acc[c][mt] = HT::mma(wc[mt][j], b[c], acc[c][mt]);
+                            if (DS) {
+#pragma unroll
+                                for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                                    for (int mt = 0; mt < MT; ++mt)
+                                        acc[c][mt] = HT::mma(wc[mt][j], bl[c], acc[c][mt]);
+                            }
                         }
-                    }
-                };
-                float m0[NTC][MT], m1[NTC][MT];
-                row_dft(k);
-#pragma unroll
-                for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) {
-                        const f4 a = acc[c][mt];
-                        m0[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
-                        m1[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
-                    }
-                if (pair) {
-                    row_dft(L - k);
+                    };
+                    float m0[NTC][MT], m1[NTC][MT];
+                    row_dft(pa);
 #pragma unroll
                     for (int c = 0; c < NTC; ++c)
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
                             const f4 a = acc[c][mt];
-                            m0[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
-                            m1[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
+                            m0[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                            m1[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
                         }
+                    if (pair) {
+                        row_dft(pb);
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) {
+                                const f4 a = acc[c][mt];
+                                m0[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                                m1[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
+                            }
+                    }
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                            for (int m = 0; m < 3; ++m)
+                                e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
                 }
-#pragma unroll
-                for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                        for (int m = 0; m < 3; ++m)
-                            e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
+                // the next half's stage B overwrites B_s
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (t0 + S < t_end) load_a(t0 + S);
         const int x = x_base + S * wave;
@@ -382,11 +417,11 @@ static hipError_t launch_h(const sal_ctx *c, const float *V, int64_t n0, int64_t
     if (c->p.stride == 2)
         hipLaunchKernelGGL((k_energy_h<L, T, DS, 2>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s,
                            V, (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
-                           c->t.w_bin, E, vmax_part);
+                           c->t.w_c16b, c->t.w_bin, E, vmax_part);
     else
         hipLaunchKernelGGL((k_energy_h<L, T, DS, 1>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s,
                            V, (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c16, c->t.w_a16,
-                           c->t.w_bin, E, vmax_part);
+                           c->t.w_c16b, c->t.w_bin, E, vmax_part);
     return hipGetLastError();
 }
 

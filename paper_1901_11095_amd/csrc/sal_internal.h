@@ -24,6 +24,9 @@ struct sal_tables {
     uint32_t *w_c16;  // 16-bit forms: per M tile, MFMA and lane, the eight 16-bit A-operand
                       // values (W_hi | W_lo halves) of the x and y contractions
     uint32_t *w_a16;  // likewise for the t contraction
+    uint32_t *w_c16b;  // cube 16: w_c16 with the rows of each M tile ordered as the stage-B
+                       // halves of the 16-bit kernel (rows nu = k and L - k of a weight group
+                       // in the same tile)
     float *w_gen;     // vector-ALU kernel (L < 8): [mu <= L/2][nu][om][3] projection weights
                       // times the conjugate multiplicity of mu, / (L^3 (L^3 - 1)), DC = 0
 };
