@@ -1,6 +1,7 @@
 """The library used from C through its ABI alone (tests/c_abi_client.c): device buffers
 from the HIP runtime, sal_saliency on a small volume compared with the FP64 oracle at
-cube 8, the paper's cube 5 and split-BF16 at cube 16, and the refusal paths."""
+cube 8, the paper's cube 5 and split-BF16 at cube 16, the batched tile check against
+sal_raw_box and the whole-volume maps (bit for bit), and the refusal paths."""
 import os
 import subprocess
 
