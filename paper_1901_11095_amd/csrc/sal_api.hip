@@ -245,8 +245,21 @@ hipError_t build_tables(sal_ctx *c)
                 }
             }
     }
+    // the FP32 kernel's stage-B halves at cube 16: lane (g, n) of K step kk holds row n of
+    // the half's tile at K = KS g + kk, the tile's rows being (nu, re|im) of the half's list
+    const long KSF = 2 * L / 4;
+    std::vector<float> wcb(L == 16 ? (size_t)2 * KSF * 64 : 1, 0.f);
+    if (L == 16)
+        for (long hp = 0; hp < 2; ++hp)
+            for (long kk = 0; kk < KSF; ++kk)
+                for (long lane = 0; lane < 64; ++lane) {
+                    const long g = lane / 16, i = lane % 16;
+                    const long row = 2 * half_nu[hp][i / 2] + (i & 1);
+                    wcb[(hp * KSF + kk) * 64 + lane] = (float)wc[row * 2 * L + KSF * g + kk];
+                }
     hipError_t e;
     if ((e = upload(&c->t.w_c, wcf)) != hipSuccess) return e;
+    if ((e = upload(&c->t.w_cb, wcb)) != hipSuccess) return e;
     if ((e = upload(&c->t.w_a, waf)) != hipSuccess) return e;
     if ((e = upload(&c->t.w_bin, wb)) != hipSuccess) return e;
     if ((e = upload(&c->t.twiddle, tw)) != hipSuccess) return e;
@@ -260,7 +273,7 @@ hipError_t build_tables(sal_ctx *c)
 
 void free_tables(sal_tables *t)
 {
-    float **fp[] = {&t->w_c, &t->w_a, &t->w_bin, &t->twiddle, &t->w_proj, &t->w_gen};
+    float **fp[] = {&t->w_c, &t->w_a, &t->w_bin, &t->twiddle, &t->w_proj, &t->w_gen, &t->w_cb};
     for (float **p : fp)
         if (*p) {
             (void)hipFree(*p);

@@ -66,15 +66,15 @@ struct Geo {
 #ifndef SAL_TY16
 #define SAL_TY16 16
 #endif
-// WPE: waves per SIMD the register allocation must allow.  At L = 8 the LDS of a workgroup
-// admits three per CU, i.e. six waves per SIMD; the registers are capped to match (a few
-// per-t0 address values then live in scratch, outside the inner loops).  At L = 16 the LDS
-// admits one workgroup per CU.
+// WPE: waves per SIMD the register allocation must allow (unit-stride tiles; strided ones
+// are LDS-bound at two).  At L = 8 the LDS of a workgroup admits three per CU, i.e. six
+// waves per SIMD; at L = 16 (stage B in two halves) two per CU, i.e. four waves per SIMD.
+// The registers are capped to match.
 #ifndef SAL_WPE8
 #define SAL_WPE8 6
 #endif
 #ifndef SAL_WPE16
-#define SAL_WPE16 2
+#define SAL_WPE16 4
 #endif
 template <int L>
 struct TileCfg;

@@ -27,6 +27,8 @@ struct sal_tables {
     uint32_t *w_c16b;  // cube 16: w_c16 with the rows of each M tile ordered as the stage-B
                        // halves of the 16-bit kernel (rows nu = k and L - k of a weight group
                        // in the same tile)
+    float *w_cb;       // cube 16, FP32 kernel: the stage-B matrix of the two halves, rows in
+                       // the halves' order, as per-lane A operands [half][K step][lane]
     float *w_gen;     // vector-ALU kernel (L < 8): [mu <= L/2][nu][om][3] projection weights
                       // times the conjugate multiplicity of mu, / (L^3 (L^3 - 1)), DC = 0
 };

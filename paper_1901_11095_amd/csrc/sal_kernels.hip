@@ -36,9 +36,9 @@
 // Floating-point MFMA and VALU work serialise on a SIMD on this chip, so the per-bin VALU
 // count (|F|^2, sqrt, three weighted sums) is kept minimal.
 template <int L, int S>
-__global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
+__global__ __attribute__((amdgpu_waves_per_eu(S == 1 ? TileCfg<L>::WPE : 2))) __launch_bounds__(64 * TileCfg<L>::NW) void k_energy_f32(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int tt_len, int nby, int nbx,
-    const float *__restrict__ w_c, const float *__restrict__ w_a,
+    const float *__restrict__ w_c, const float *__restrict__ w_a, const float *__restrict__ w_cb,
     const float *__restrict__ w_grp, float *__restrict__ E, float *__restrict__ vmax_part)
 {
     using G = Geo<L>;
@@ -53,8 +53,14 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
     constexpr int NGK = L / 2 + 1;  // groups per mu
     constexpr int NWB = C::W_LDS ? h * NGK * MT * 32 : 1;
 
+    // At cube 16, stage B runs in two halves of eight frequency rows, each followed by the
+    // stage C of the weight groups whose rows it holds, so B_s keeps eight rows at a time
+    // and two workgroups fit a CU.  The stage-B matrix of the halves (rows in the halves'
+    // order) is read from LDS when used.
+    constexpr int NH = L == 16 ? 2 : 1, NROW = NH > 1 ? 8 : L;
     __shared__ float2 A_s[NPOS * h];
-    __shared__ float2 B_s[NW][L * PYB];
+    __shared__ float2 B_s[NW][NROW * PYB];
+    __shared__ float wcb_s[NH > 1 ? NH * KS * 64 : 1];
     __shared__ float wb_s[NWB];
     __shared__ float wa_s[16 * MTA * L];
     __shared__ float red_s[NW];
@@ -86,6 +92,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
         for (int kk = 0; kk < KS; ++kk) wc[mt][kk] = w_c[(16 * mt + n) * (2 * L) + KS * g + kk];
     // the stage-A matrix is read from LDS when used (it is needed once per t0 only)
     for (int i = threadIdx.x; i < 16 * MTA * L; i += 64 * NW) wa_s[i] = w_a[i];
+    if (NH > 1)
+        for (int i = threadIdx.x; i < NH * KS * 64; i += 64 * NW) wcb_s[i] = w_cb[i];
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
@@ -157,127 +165,154 @@ __global__ __attribute__((amdgpu_waves_per_eu(TileCfg<L>::WPE))) __launch_bounds
         float e[NTC][3];
 #pragma unroll
         for (int c = 0; c < NTC; ++c) e[c][0] = e[c][1] = e[c][2] = 0.f;
-        int grp = 0;
 #pragma unroll 1
         for (int mu = 0; mu < h; ++mu) {
             const bool self = (mu == 0 || mu == L / 2);  // real stage-A output
-            // ---------------- stage B: complex DFT along x for this mu ------------------
-#pragma unroll
-            for (int nb = 0; nb < NTB; ++nb) {
-                const int yp = min(nb * 16 + n, PY - 1);
-                f4 acc[MT];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
-                if (self) {
-#pragma unroll
-                    for (int kk = 0; kk < KS; kk += 2) {
-                        const float a = A_s[((S * wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu].x;
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma4(wc[mt][kk], a, acc[mt]);
-                    }
-                } else {
-#pragma unroll
-                    for (int kk = 0; kk < KS; kk += 2) {
-                        const float2 a = A_s[((S * wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu];
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) {
-                            acc[mt] = mfma4(wc[mt][kk], a.x, acc[mt]);
-                            acc[mt] = mfma4(wc[mt][kk + 1], a.y, acc[mt]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const int nu0 = 8 * mt + 2 * g;
-                    Bw[nu0 * PYB + nb * 16 + n] = make_float2(acc[mt][0], acc[mt][1]);
-                    Bw[(nu0 + 1) * PYB + nb * 16 + n] = make_float2(acc[mt][2], acc[mt][3]);
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // ---------------- stage C: complex DFT along y, projections, energies -------
-            // The NTC voxel tiles of a row run as independent MFMA chains, interleaved, so
-            // each tile's dependent steps and result latency overlap the other tiles'.
 #pragma unroll 1
-            for (int k = 0; k < NGK; ++k, ++grp) {
-                const bool pair = !self && k > 0 && k < L / 2;
-                // for mu, nu in {0, L/2} the stage-B row is real (the quarter-turn twiddles
-                // are exact, so its imaginary part is an exact zero): skip those K steps
-                const bool real_row = self && (k == 0 || k == L / 2);
-                float wv[MT][6];
+            for (int hp = 0; hp < NH; ++hp) {
+                // ---------- stage B: complex DFT along x for this mu (rows of half hp) ------
+                // one pass: row nu at position nu; halves: position i holds the i-th frequency
+                // of the half's list (the matrix rows of w_cb are ordered the same way)
+                constexpr int BT = NH > 1 ? 1 : MT;  // M tiles per pass
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const int wo = ((grp * MT + mt) * 4 + g) * 8;
+                for (int nb = 0; nb < NTB; ++nb) {
+                    const int yp = min(nb * 16 + n, PY - 1);
+                    f4 acc[BT];
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
-                }
-                f4 acc[NTC][MT];
-                auto row_dft = [&](int nu, bool real) {
+                    for (int mt = 0; mt < BT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+                    auto wstage = [&](int mt, int kk) -> float {
+                        return NH > 1 ? wcb_s[(hp * KS + kk) * 64 + lane] : wc[mt][kk];
+                    };
+                    if (self) {
 #pragma unroll
-                    for (int c = 0; c < NTC; ++c)
+                        for (int kk = 0; kk < KS; kk += 2) {
+                            const float a = A_s[((S * wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu].x;
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[c][mt] = f4{0.f, 0.f, 0.f, 0.f};
-                    const float2 *Brow = Bw + nu * PYB + S * n + ((KS * g) >> 1);
-                    if (real) {
-#pragma unroll
-                        for (int kk = 0; kk < KS; kk += 2)
-#pragma unroll
-                            for (int c = 0; c < NTC; ++c) {
-                                const float b = Brow[S * c * 16 + (kk >> 1)].x;
-#pragma unroll
-                                for (int mt = 0; mt < MT; ++mt) acc[c][mt] = mfma4(wc[mt][kk], b, acc[c][mt]);
-                            }
+                            for (int mt = 0; mt < BT; ++mt) acc[mt] = mfma4(wstage(mt, kk), a, acc[mt]);
+                        }
                     } else {
 #pragma unroll
                         for (int kk = 0; kk < KS; kk += 2) {
-                            float2 b[NTC];
+                            const float2 a = A_s[((S * wave + ((KS * g + kk) >> 1)) * PY + yp) * h + mu];
 #pragma unroll
-                            for (int c = 0; c < NTC; ++c) b[c] = Brow[S * c * 16 + (kk >> 1)];
-#pragma unroll
-                            for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                                for (int mt = 0; mt < MT; ++mt) acc[c][mt] = mfma4(wc[mt][kk], b[c].x, acc[c][mt]);
-#pragma unroll
-                            for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                                for (int mt = 0; mt < MT; ++mt)
-                                    acc[c][mt] = mfma4(wc[mt][kk + 1], b[c].y, acc[c][mt]);
+                            for (int mt = 0; mt < BT; ++mt) {
+                                acc[mt] = mfma4(wstage(mt, kk), a.x, acc[mt]);
+                                acc[mt] = mfma4(wstage(mt, kk + 1), a.y, acc[mt]);
+                            }
                         }
                     }
-                };
-                float m0[NTC][MT], m1[NTC][MT];
-                row_dft(k, real_row);
 #pragma unroll
-                for (int c = 0; c < NTC; ++c)
+                    for (int mt = 0; mt < BT; ++mt) {
+                        const int nu0 = 8 * mt + 2 * g;
+                        Bw[nu0 * PYB + nb * 16 + n] = make_float2(acc[mt][0], acc[mt][1]);
+                        Bw[(nu0 + 1) * PYB + nb * 16 + n] = make_float2(acc[mt][2], acc[mt][3]);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // ---------- stage C: complex DFT along y, projections, energies -------------
+                // weight group (mu, k) of entry ei of the pass: rows nu = k at position pa and,
+                // unless mu is 0 or L/2 or k is 0 or L/2, nu = L - k at position pb.  The NTC
+                // voxel tiles of a row run as independent MFMA chains, interleaved, so each
+                // tile's dependent steps and result latency overlap the other tiles'.
+                const int nent = NH == 1 ? NGK : (hp == 0 ? 5 : 4);
+#pragma unroll 1
+                for (int ei = 0; ei < nent; ++ei) {
+                    int k, pa, pb;
+                    if (NH == 1) {
+                        k = ei;
+                        pa = ei;
+                        pb = L - ei;
+                    } else if (hp == 0) {
+                        k = ei < 4 ? ei : 8;
+                        pa = ei == 0 ? 0 : (ei < 4 ? 2 * ei - 1 : 7);
+                        pb = 2 * ei;
+                    } else {
+                        k = 4 + ei;
+                        pa = 2 * ei;
+                        pb = 2 * ei + 1;
+                    }
+                    const int grp = mu * NGK + k;
+                    const bool pair = !self && k > 0 && k < L / 2;
+                    // for mu, nu in {0, L/2} the stage-B row is real (the quarter-turn twiddles
+                    // are exact, so its imaginary part is an exact zero): skip those K steps
+                    const bool real_row = self && (k == 0 || k == L / 2);
+                    float wv[MT][6];
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) {
-                        const f4 a = acc[c][mt];
-                        m0[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
-                        m1[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
+                        const int wo = ((grp * MT + mt) * 4 + g) * 8;
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
                     }
-                if (pair) {
-                    row_dft(L - k, false);
+                    f4 acc[NTC][MT];
+                    auto row_dft = [&](int pos, bool real) {
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) acc[c][mt] = f4{0.f, 0.f, 0.f, 0.f};
+                        const float2 *Brow = Bw + pos * PYB + S * n + ((KS * g) >> 1);
+                        if (real) {
+#pragma unroll
+                            for (int kk = 0; kk < KS; kk += 2)
+#pragma unroll
+                                for (int c = 0; c < NTC; ++c) {
+                                    const float b = Brow[S * c * 16 + (kk >> 1)].x;
+#pragma unroll
+                                    for (int mt = 0; mt < MT; ++mt) acc[c][mt] = mfma4(wc[mt][kk], b, acc[c][mt]);
+                                }
+                        } else {
+#pragma unroll
+                            for (int kk = 0; kk < KS; kk += 2) {
+                                float2 b[NTC];
+#pragma unroll
+                                for (int c = 0; c < NTC; ++c) b[c] = Brow[S * c * 16 + (kk >> 1)];
+#pragma unroll
+                                for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                                    for (int mt = 0; mt < MT; ++mt) acc[c][mt] = mfma4(wc[mt][kk], b[c].x, acc[c][mt]);
+#pragma unroll
+                                for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                                    for (int mt = 0; mt < MT; ++mt)
+                                        acc[c][mt] = mfma4(wc[mt][kk + 1], b[c].y, acc[c][mt]);
+                            }
+                        }
+                    };
+                    float m0[NTC][MT], m1[NTC][MT];
+                    row_dft(pa, real_row);
 #pragma unroll
                     for (int c = 0; c < NTC; ++c)
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
                             const f4 a = acc[c][mt];
-                            m0[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
-                            m1[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
+                            m0[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                            m1[c][mt] = __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
                         }
+                    if (pair) {
+                        row_dft(pb, false);
+#pragma unroll
+                        for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) {
+                                const f4 a = acc[c][mt];
+                                m0[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[0], a[0], a[1] * a[1]));
+                                m1[c][mt] += __builtin_amdgcn_sqrtf(fmaf(a[2], a[2], a[3] * a[3]));
+                            }
+                    }
+#pragma unroll
+                    for (int c = 0; c < NTC; ++c)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                            for (int m = 0; m < 3; ++m)
+                                e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
                 }
-#pragma unroll
-                for (int c = 0; c < NTC; ++c)
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                        for (int m = 0; m < 3; ++m)
-                            e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
+                // the next pass's stage B overwrites B_s
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (t0 + S < t_end) load_a(t0 + S);
         // reduce the four lane groups (lanes n, n+16, n+32, n+48 hold the same voxel)
@@ -907,11 +942,11 @@ static hipError_t launch_energy_L(const sal_ctx *c, const float *V, int64_t n0, 
         return launch_energy16(c, V, n0, n1, n2, bx, E, vmax_part, nby, nbx, tt, nb, s);
     if (S == 2)
         hipLaunchKernelGGL((k_energy_f32<L, 2>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s, V,
-                           (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_bin, E,
+                           (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_cb, c->t.w_bin, E,
                            vmax_part);
     else
         hipLaunchKernelGGL((k_energy_f32<L, 1>), dim3((unsigned)nb), dim3(64 * TileCfg<L>::NW), 0, s, V,
-                           (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_bin, E,
+                           (int)n0, (int)n1, (int)n2, bx, tt, nby, nbx, c->t.w_c, c->t.w_a, c->t.w_cb, c->t.w_bin, E,
                            vmax_part);
     return hipGetLastError();
 }
