@@ -39,8 +39,8 @@ def _one_by_one(ctx, V, P, stats, tiles, tile, bound):
     return P, errs, exact
 
 
-@pytest.mark.parametrize("L,prec,rays", [(8, sal.FP32, None), (16, sal.BF16_SPLIT, None), (5, sal.FP32, None),
-                                         (8, sal.FP32, (sal.RAY_ALL,) * 3)])
+@pytest.mark.parametrize("L,prec,rays", [(8, sal.FP32, None), (16, sal.FP32, None), (16, sal.BF16_SPLIT, None),
+                                         (5, sal.FP32, None), (8, sal.FP32, (sal.RAY_ALL,) * 3)])
 def test_batch_equals_one_by_one(L, prec, rays):
     shape = (52, 44, 60)
     tile = 16
