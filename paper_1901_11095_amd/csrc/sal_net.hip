@@ -31,9 +31,16 @@ namespace {
 
 constexpr int NL = 5;
 constexpr int CH[NL + 1] = {1, 24, 24, 24, 24, 3};
-constexpr int TT = 4, TU = 4, TW = 16;                  // output tile of a workgroup
+constexpr int TT = 4, TU = 4, TW = 16;                  // output tile of a weight-gradient workgroup
 constexpr int PT = TT + 2, PU = TU + 2, PW = TW + 2;    // input tile with the 1-voxel halo
 constexpr int NPOS = PT * PU * PW;
+// Output tile of a convolution workgroup: FT x FU x FW voxels, one wave per 4 rows of FW.
+// Layers with 24 output channels take 4 x 8 x 16 (eight waves; the 6 x 10 x 18 input tile
+// is 2.1 times the output instead of 2.5 times for 4 x 4 x 16), the 3-channel output layer
+// keeps 4 x 4 x 16 (four waves), which measured faster there.
+constexpr int FT = 4, FW = 16, FPT = FT + 2, FPW = FW + 2;
+__host__ __device__ constexpr int conv_fu(int co) { return co >= 16 ? 8 : 4; }
+__host__ __device__ constexpr int conv_threads(int co) { return 64 * FT * conv_fu(co) / 4; }
 constexpr int WG_BLOCKS = 512;                          // workgroups of the weight-gradient pass
 constexpr unsigned CONV_BLOCKS = 2048;                  // persistent workgroups of a convolution
 
@@ -88,14 +95,14 @@ __device__ __forceinline__ int map_idx(int u, int n, int mode)
 // 3x3x3 convolution as an implicit GEMM on 16x16x32 BF16 MFMA: D[co][voxel] =
 // sum_K A[co][K] B[K][voxel], K = (tap, input channel).  A (the weights) stays in registers
 // for the whole workgroup; B is read from the LDS input tile, 8 channels of one tap = 16
-// bytes per lane.  Each of the 4 waves computes 4 rows of 16 voxels.
+// bytes per lane.  Each wave computes 4 rows of 16 voxels.
 //   in:   CI == 1: float [nb][n0][n1][n2]; else bf16 [nb][...][CI]
 //   wtab: bf16 [MT*16][ksteps*32] (rows >= CO and K past the taps are zero)
 //   EPI_GELU:   z = acc + bias -> out0 (bf16, optional), GELU(z) -> out1 (bf16)
 //   EPI_LINEAR: (acc + bias) * oscale[c] -> out0 (float), element (v, c) at v*vstride + c*cstride
 //   EPI_DGELU:  acc * GELU'(zprev) -> out0 (bf16)
 template <int CI, int CO, int MODE, int EPI>
-__global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int nb, int n0, int n1,
+__global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restrict__ in, int nb, int n0, int n1,
                                                int n2, const uint16_t *__restrict__ wtab,
                                                const float *__restrict__ bias,
                                                const uint16_t *__restrict__ zprev, void *out0,
@@ -104,28 +111,30 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
 {
     constexpr int CIP = CI == 1 ? 1 : pad8(CI);
     constexpr int KS = ksteps(CI), MT = (CO + 15) / 16;
+    constexpr int FU = conv_fu(CO), FPU = FU + 2, FNPOS = FPT * FPU * FPW;
+    constexpr int FWAVES = FT * FU / 4, FTHREADS = conv_threads(CO);
     // multi-channel layers with reflected borders (the forward pass) stream the next tile
     // into a second LDS buffer by direct global-to-LDS loads while the current one computes
     constexpr bool ASYNC = CI > 1 && CI % 8 == 0 && MODE == MODE_REFLECT;
     // two separate LDS objects, so the compiler can tell reads of one from the loads landing
     // in the other (a read of the same object would wait for them)
-    __shared__ uint16_t tileA[NPOS * CIP];
-    __shared__ uint16_t tileB[ASYNC ? NPOS * CIP : 8];
+    __shared__ uint16_t tileA[FNPOS * CIP];
+    __shared__ uint16_t tileB[ASYNC ? FNPOS * CIP : 8];
     // biases in LDS: a global load in the epilogue would wait for the tile in flight
     __shared__ float bias_s[MT * 16];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, n = lane & 15;
-    const int ntw = (n2 + TW - 1) / TW, ntu = (n1 + TU - 1) / TU, ntt = (n0 + TT - 1) / TT;
+    const int ntw = (n2 + FW - 1) / FW, ntu = (n1 + FU - 1) / FU, ntt = (n0 + FT - 1) / FT;
     const int ntiles = nb * ntt * ntu * ntw;
     const int64_t vol = (int64_t)n0 * n1 * n2;
 
-    // asynchronous load of tile `id` into buffer `bf`: each wave takes whole rows of PW
-    // positions; lane j < PW * CIP / 8 brings 16 bytes (8 channels) and the hardware puts
+    // asynchronous load of tile `id` into buffer `bf`: each wave takes whole rows of FPW
+    // positions; lane j < FPW * CIP / 8 brings 16 bytes (8 channels) and the hardware puts
     // them at row base + 16 j, which is the row's layout in LDS
     auto issue = [&](int id, uint16_t *dst) {
         if constexpr (ASYNC) {
-            constexpr int CHK = CIP / 8, ROWLEN = PW * CHK;
+            constexpr int CHK = CIP / 8, ROWLEN = FPW * CHK;
             int bi = id;
             const int tw2 = bi % ntw;
             bi /= ntw;
@@ -135,23 +144,23 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
             const int b2 = bi / ntt;
             const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b2 * vol * CI;
             const int pw = lane / CHK, ch = lane - (lane / CHK) * CHK;
-            const int gw = refl_idx(tw2 * TW - 1 + pw, n2);
+            const int gw = refl_idx(tw2 * FW - 1 + pw, n2);
             const int wv = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
-            for (int it = 0; it < (PT * PU + 3) / 4; ++it) {
-                const int row = 4 * it + wv;
-                if (row < PT * PU) {
-                    const int pt = row / PU, pu = row - pt * PU;
-                    const int gt = refl_idx(tt2 * TT - 1 + pt, n0), gu = refl_idx(tu2 * TU - 1 + pu, n1);
+            for (int it = 0; it < (FPT * FPU + FWAVES - 1) / FWAVES; ++it) {
+                const int row = FWAVES * it + wv;
+                if (row < FPT * FPU) {
+                    const int pt = row / FPU, pu = row - pt * FPU;
+                    const int gt = refl_idx(tt2 * FT - 1 + pt, n0), gu = refl_idx(tu2 * FU - 1 + pu, n1);
                     if (lane < ROWLEN)
                         __builtin_amdgcn_global_load_lds(
                             src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch,
-                            (__attribute__((address_space(3))) void *)&dst[row * PW * CIP], 16, 0, 0);
+                            (__attribute__((address_space(3))) void *)&dst[row * FPW * CIP], 16, 0, 0);
                 }
             }
         }
     };
-    for (int i = threadIdx.x; i < MT * 16; i += 256) bias_s[i] = (bias && i < CO) ? bias[i] : 0.f;
+    for (int i = threadIdx.x; i < MT * 16; i += FTHREADS) bias_s[i] = (bias && i < CO) ? bias[i] : 0.f;
     __syncthreads();
     if (ASYNC && (int)blockIdx.x < ntiles) issue(blockIdx.x, tileA);
 
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
     bid /= ntu;
     const int tt_ = bid % ntt;
     const int b = bid / ntt;
-    const int t0 = tt_ * TT, u0 = tu_ * TU, w0 = tw_ * TW;
+    const int t0 = tt_ * FT, u0 = tu_ * FU, w0 = tw_ * FW;
     if (ASYNC) {
         // this tile's loads have landed (every wave waits for its own, then the barrier);
         // the other buffer is free again, so the next tile's loads can start
@@ -184,30 +193,30 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
         __syncthreads();  // the previous tile is no longer read
     }
 
-    // input tile with halo: one row of PW positions per (pt, pu).  Each wave loads whole
+    // input tile with halo: one row of FPW positions per (pt, pu).  Each wave loads whole
     // rows, so the row's (t, u) source index is wave-uniform and a lane's position along
     // w is fixed for the tile.
     if (CI == 1) {
-        // three rows of PW floats per wave and step
+        // three rows of FPW floats per wave and step
         const float *src = reinterpret_cast<const float *>(in) + b * vol;
-        const int r3 = lane / PW, pw = lane - r3 * PW;
+        const int r3 = lane / FPW, pw = lane - r3 * FPW;
         const bool act = r3 < 3;
         const int gw = map_idx(w0 - 1 + pw, n2, MODE);
 #pragma unroll
-        for (int it = 0; it < (PT * PU + 11) / 12; ++it) {
-            const int row = 12 * it + 3 * wave + r3;
-            if (act && row < PT * PU) {
-                const int pt = row / PU, pu = row - pt * PU;
+        for (int it = 0; it < (FPT * FPU + 3 * FWAVES - 1) / (3 * FWAVES); ++it) {
+            const int row = 3 * FWAVES * it + 3 * wave + r3;
+            if (act && row < FPT * FPU) {
+                const int pt = row / FPU, pu = row - pt * FPU;
                 const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE);
                 const float v = (gt < 0 || gu < 0 || gw < 0) ? 0.f : src[((int64_t)gt * n1 + gu) * n2 + gw];
-                tile[row * PW + pw] = f2bf(v);
+                tile[row * FPW + pw] = f2bf(v);
             }
         }
     } else if (ASYNC) {
         // loaded by issue()
     } else if (CI % 8 == 0) {
-        // 16-byte chunks of 8 channels; a row of PW positions is ROWLEN <= 64 chunks
-        constexpr int CHK = CIP / 8, ROWLEN = PW * CHK;
+        // 16-byte chunks of 8 channels; a row of FPW positions is ROWLEN <= 64 chunks
+        constexpr int CHK = CIP / 8, ROWLEN = FPW * CHK;
         static_assert(ROWLEN <= 64, "one wave loads a whole row");
         const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
         const bool act = lane < ROWLEN;
@@ -215,23 +224,23 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
         const int gw = map_idx(w0 - 1 + pw, n2, MODE);
         const int wv = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
-        for (int it = 0; it < (PT * PU + 3) / 4; ++it) {
-            const int row = 4 * it + wv;
-            if (row < PT * PU) {
-                const int pt = row / PU, pu = row - pt * PU;
+        for (int it = 0; it < (FPT * FPU + FWAVES - 1) / FWAVES; ++it) {
+            const int row = FWAVES * it + wv;
+            if (row < FPT * FPU) {
+                const int pt = row / FPU, pu = row - pt * FPU;
                 const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE);
                 u32x4 val = u32x4{0u, 0u, 0u, 0u};
                 if (act && gt >= 0 && gu >= 0 && gw >= 0)
                     val = *reinterpret_cast<const u32x4 *>(src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch);
-                if (act) *reinterpret_cast<u32x4 *>(&tile[(row * PW + pw) * CIP + 8 * ch]) = val;
+                if (act) *reinterpret_cast<u32x4 *>(&tile[(row * FPW + pw) * CIP + 8 * ch]) = val;
             }
         }
     } else {
         const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
-        for (int i = threadIdx.x; i < NPOS * CIP; i += 256) {
+        for (int i = threadIdx.x; i < FNPOS * CIP; i += FTHREADS) {
             const int p = i / CIP, c = i - p * CIP;
-            const int row = p / PW, pw = p - row * PW;
-            const int pt = row / PU, pu = row - pt * PU;
+            const int row = p / FPW, pw = p - row * FPW;
+            const int pt = row / FPU, pu = row - pt * FPU;
             const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE),
                       gw = map_idx(w0 - 1 + pw, n2, MODE);
             tile[i] = (c >= CI || gt < 0 || gu < 0 || gw < 0)
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
 
 #pragma unroll 1
     for (int row = 0; row < 4; ++row) {
-        const int lt = wave, lu = row;  // output voxel (lt, lu, n) of the tile
+        const int lt = wave % FT, lu = (wave / FT) * 4 + row;  // output voxel (lt, lu, n) of the tile
         f4 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
@@ -262,7 +271,7 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
                         const int k = 8 * g + 2 * e2 + h;
                         uint32_t val = 0;
                         if (k < 27) {
-                            const int p = ((lt + k / 9) * PU + (lu + (k / 3) % 3)) * PW + n + k % 3;
+                            const int p = ((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3;
                             val = tile[p];
                         }
                         pr |= val << (16 * h);
@@ -273,7 +282,7 @@ __global__ __launch_bounds__(256) void k_conv3(const void *__restrict__ in, int 
                 const int q = 4 * s + g;  // K group: tap q / (CIP/8), channels 8*(q % (CIP/8))
                 if (q < kgroups(CI)) {
                     const int k = q / (CIP / 8), c0 = 8 * (q % (CIP / 8));
-                    const int p = ((lt + k / 9) * PU + (lu + (k / 3) % 3)) * PW + n + k % 3;
+                    const int p = ((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3;
                     bv = *reinterpret_cast<const u32x4 *>(&tile[p * CIP + c0]);
                 } else {
                     bv = u32x4{0u, 0u, 0u, 0u};
@@ -600,6 +609,11 @@ unsigned conv_grid(int64_t nb, int64_t n0, int64_t n1, int64_t n2)
 {
     return (unsigned)(nb * ((n0 + TT - 1) / TT) * ((n1 + TU - 1) / TU) * ((n2 + TW - 1) / TW));
 }
+unsigned conv_tiles_fwd(int co, int64_t nb, int64_t n0, int64_t n1, int64_t n2)
+{
+    const int fu = conv_fu(co);
+    return (unsigned)(nb * ((n0 + FT - 1) / FT) * ((n1 + fu - 1) / fu) * ((n2 + FW - 1) / FW));
+}
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -640,9 +654,9 @@ void conv(const void *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, const 
           hipStream_t s, float3 oscale = make_float3(1.f, 1.f, 1.f))
 {
     // persistent workgroups: a few per CU, each walking tiles with its weights in registers
-    const unsigned tiles = conv_grid(nb, n0, n1, n2);
+    const unsigned tiles = conv_tiles_fwd(CO, nb, n0, n1, n2);
     const unsigned grid = tiles < CONV_BLOCKS ? tiles : CONV_BLOCKS;
-    hipLaunchKernelGGL((k_conv3<CI, CO, MODE, EPI>), dim3(grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_conv3<CI, CO, MODE, EPI>), dim3(grid), dim3(conv_threads(CO)), 0, s,
                        in, (int)nb, (int)n0, (int)n1, (int)n2, w, bias, zprev, o0, o1, vs, cs, oscale);
 }
 
