@@ -16,5 +16,14 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle
-    oracle.build()
+    mutant = os.environ.get("SAL_ORACLE_MUTANT_LIB")
+    if mutant:
+        # a deliberately broken copy of the oracle, compiled by test_oracle_mutants.py to
+        # show that the pins notice the mistake
+        import oracle.oracle as impl
+        impl._LIB = mutant
+        impl._lib = None
+        impl.build = lambda force=False: mutant
+    else:
+        oracle.build()
     return oracle

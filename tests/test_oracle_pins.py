@@ -272,13 +272,14 @@ def test_dcs_constant_energy_oriented(oracle_mod, mask):
     assert np.abs(S - expect).max() <= 1e-14
 
 
-@pytest.mark.parametrize("mask", ["tx", "xy_body", "all26"])
+@pytest.mark.parametrize("mask", ["tx", "xy_body", "all26"] + ["bit%d" % b for b in range(26)])
 def test_dcs_spike_oriented(oracle_mod, mask):
     """A unit spike of E at c, far from the faces: the spike sees S = 1; a voxel v sees one
     term g(s |e|) for every ray e and step s with v + s e = c, so S(v) is the sum of those
-    terms over Q (each voxel's value is built here from the spike's side)."""
+    terms over Q (each voxel's value is built here from the spike's side).  Single-bit
+    masks pin the step of every ray bit on its own."""
     m = {"tx": oracle_mod.RAY_DIAG_TX, "xy_body": oracle_mod.RAY_DIAG_XY | oracle_mod.RAY_BODY,
-         "all26": (1 << 26) - 1}[mask]
+         "all26": (1 << 26) - 1}.get(mask) or 1 << int(mask[3:])
     r, sigma = 3, 1.7
     shape, c = (13, 14, 15), (6, 7, 7)
     E = np.zeros((3,) + shape)
