@@ -35,6 +35,22 @@ def test_dcs_vs_oracle(name):
     assert relmax(S, ref) <= TOL
 
 
+@pytest.mark.parametrize("d", [8, 32])
+def test_dcs_single_rays_vs_oracle(d):
+    """Every ray bit on its own, so a step assigned to the wrong bit cannot hide inside a
+    symmetric set.  d = 8 (r = 4) runs the tiled kernel; d = 32 (r = 16) sends the rays with
+    a t step to the grid-stride kernel, whose ring of t-planes would not fit in LDS."""
+    r = d // 2
+    E = np.random.default_rng(11).random((3, 2 * r + 3, 2 * r + 5, 2 * r + 7)).astype(np.float32)
+    Eg = torch.from_numpy(E).cuda()
+    for b in range(26):
+        rays = (1 << b,) * 3
+        ctx = sal.Saliency(L=8, d=d, rays=rays)
+        S = ctx.directional_compare(Eg).cpu().numpy()
+        ref = O.dcs(E.astype(np.float64), r, d / 4.0, rays)
+        assert relmax(S, ref) <= TOL, (d, b, relmax(S, ref))
+
+
 def test_dcs_bit_exact_unweighted():
     """sigma = inf, integer E, four t-x diagonals with r = 4 (Q = 16): every partial sum
     is an exact integer and the division by 16 is exact."""
