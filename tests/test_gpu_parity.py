@@ -188,6 +188,49 @@ def test_saliency_survey_subblock(dev, L):
     assert stats[6] == np.abs(V).max()
 
 
+PARAM_CASES = [
+    # (L, d, sigma, abc, normalize): Eq. (5) line length and Gaussian width, Eq. (6) weights
+    (8, 6, 1.3, (0.5, 0.3, 0.2), 1),
+    (8, None, None, (0.2, 0.7, 0.1), 0),
+    (16, 10, 3.0, (1.0, 0.0, 0.0), 1),
+    (5, 4, None, (0.25, 0.25, 0.5), 1),
+]
+
+
+@pytest.mark.parametrize("L,d,sigma,abc,normalize", PARAM_CASES)
+def test_saliency_parameters_vs_oracle(dev, L, d, sigma, abc, normalize):
+    """Non-default parameters of the method (the top-down tuning of Sec. 2: line length,
+    Gaussian width, unequal weights of Eq. (6), raw combination) on the GPU against the
+    oracle."""
+    print("parameters", L, d, sigma, abc, normalize, flush=True)
+    shape = (21, 23, 34) if L < 16 else (20, 22, 33)
+    V = synth.make_volume(shape, seed=17, n_faults=1)
+    ctx = sal.Saliency(L=L, d=d, sigma=sigma, abc=abc, normalize=bool(normalize))
+    ref = O.saliency(V, O.Params(L=L, d=d, sigma=sigma, abc=abc, normalize=normalize))
+    S, E, Sr, st = ctx.saliency_maps(gpu(V, dev))
+    torch.cuda.synchronize()
+    for m in range(3):
+        assert relmax(Sr[m].cpu().numpy(), ref["S_raw"][m]) <= TOL, ("S_raw", m)
+    assert relmax(S.cpu().numpy(), ref["S"]) <= TOL
+
+
+def test_zero_contrast_guard_threshold(dev, ctx8):
+    """zero_range placed between the smallest and the middle component range (relative
+    to max|V|): exactly one component is treated as having no contrast, on both sides."""
+    V = synth.make_volume((22, 20, 35), seed=23, n_faults=1)
+    ref = O.saliency(V, O.Params(L=8))
+    st = ref["stats"]
+    vmax = float(np.abs(V).max())
+    rel = sorted((st[2 * m + 1] - st[2 * m]) / vmax for m in range(3))
+    zr = 0.5 * (rel[0] + rel[1])
+    ctx = sal.Saliency(L=8, zero_range=zr)
+    ref = O.saliency(V, O.Params(L=8, zero_range=zr))
+    S, E, Sr, st_g = ctx.saliency_maps(gpu(V, dev))
+    assert relmax(S.cpu().numpy(), ref["S"]) <= TOL
+    # the dropped component leaves S in [0, 2/3]
+    assert float(S.max()) <= 2.0 / 3.0 + 1e-6
+
+
 # ------------------------------------------------------------ invariants on GPU --------
 
 def test_constant_volume(dev, ctx8):
