@@ -148,3 +148,24 @@ def test_tile_minmax(shape, tile):
                 blk = S_raw[:, t:t + tile, x:x + tile, y:y + tile].reshape(3, -1).cpu()
                 ref.append(torch.stack([blk.amin(1), blk.amax(1)], 1).reshape(6))
     assert torch.equal(out, torch.stack(ref))
+
+
+def test_params_roundtrip_and_output_scale(net):
+    """sal_net_params writes and reads back the FP32 masters unchanged; the inference output
+    is the network output times sal_net_set_output_scale per channel (powers of two here, so
+    the products are exact)."""
+    p = net.get_params()
+    net.set_params(p)
+    assert np.array_equal(net.get_params(), p)
+    V = torch.from_numpy(np.random.default_rng(9).standard_normal((10, 12, 18)).astype(np.float32)).cuda()
+    old = getattr(net, "out_scale", (1.0, 1.0, 1.0))
+    try:
+        net.set_output_scale((1.0, 1.0, 1.0))
+        Y1 = net.infer(V).clone()
+        net.set_output_scale((2.0, 0.5, 0.25))
+        Y2 = net.infer(V)
+        torch.cuda.synchronize()
+        for c, s in enumerate((2.0, 0.5, 0.25)):
+            assert torch.equal(Y2[c], Y1[c] * s), c
+    finally:
+        net.set_output_scale(old)

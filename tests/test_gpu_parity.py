@@ -319,3 +319,22 @@ def test_size_limits(dev, ctx8):
     with pytest.raises(sal.SalError) as ei:
         ctx8.workspace_size((4, 100, 100))
     assert ei.value.status == sal.SAL_E_INVAL
+
+
+def test_profile_counts_and_reset(dev, ctx8):
+    """sal_profile_*: every timed saliency() call adds to the four kernel timers and the call
+    count; a read with reset starts them again from zero."""
+    V = gpu(synth.make_volume((20, 21, 33), seed=2), dev)
+    ctx8.profile(True)
+    ctx8.profile_read(reset=True)
+    for _ in range(3):
+        ctx8.saliency(V)
+    torch.cuda.synchronize()
+    ms, n = ctx8.profile_read(reset=True)
+    assert n == 3 and all(v > 0.0 for v in ms.values()), (ms, n)
+    ms, n = ctx8.profile_read(reset=True)
+    assert n == 0 and all(v == 0.0 for v in ms.values()), (ms, n)
+    ctx8.profile(False)
+    ctx8.saliency(V)
+    torch.cuda.synchronize()
+    assert ctx8.profile_read(reset=True)[1] == 0
