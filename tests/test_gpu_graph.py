@@ -42,3 +42,33 @@ def test_graph_replay_matches_eager(L, prec, stride):
         assert torch.equal(got[0], S_e), rep
         assert torch.equal(got[1], Sr_e), rep
         assert torch.equal(got[2][:7], st_e[:7]), rep
+
+
+def test_two_contexts_on_two_streams():
+    """Two contexts driven concurrently from two streams (each call on its caller's stream,
+    no hidden device-wide synchronisation or shared state) give exactly the results each
+    gives alone."""
+    shape = (36, 40, 52)
+    V1 = torch.from_numpy(synth.make_volume(shape, seed=4, n_faults=1)).cuda()
+    V2 = torch.from_numpy(synth.make_volume(shape, seed=5, n_faults=2)).cuda()
+    c1 = sal.Saliency(L=8)
+    c2 = sal.Saliency(L=16, precision=sal.BF16_SPLIT)
+    ref1 = c1.saliency_maps(V1)
+    ref2 = c2.saliency_maps(V2)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    outs1, outs2 = [], []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            outs1.append(c1.saliency_maps(V1))
+        with torch.cuda.stream(s2):
+            outs2.append(c2.saliency_maps(V2))
+    torch.cuda.synchronize()
+    for got in outs1:
+        for a, b in zip(got, ref1):
+            assert torch.equal(a, b)
+    for got in outs2:
+        for a, b in zip(got, ref2):
+            assert torch.equal(a, b)
