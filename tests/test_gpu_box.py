@@ -43,3 +43,36 @@ def test_raw_box_rejects():
         ctx.raw_box(V, (10, 0, 0), (11, 4, 4))
     with pytest.raises(sal.SalError):
         ctx.raw_box(V, (-1, 0, 0), (4, 4, 4))
+
+
+ORACLE_BOX_CASES = [
+    # (L, rays, box origin, box dims): corner, far corner, faces, ragged sides, interior
+    (5, None, (0, 0, 0), (6, 7, 9)),
+    (5, "all26", (30, 41, 0), (6, 7, 9)),
+    (8, None, (0, 20, 44), (9, 12, 4)),
+    (8, None, (17, 3, 19), (8, 8, 16)),
+    (8, "all26", (0, 0, 0), (5, 6, 7)),
+    (8, "all26", (39, 40, 41), (9, 8, 7)),
+    (16, None, (40, 0, 17), (8, 13, 6)),
+    (16, None, (20, 21, 22), (7, 6, 9)),
+    (16, "all26", (0, 43, 0), (5, 5, 7)),
+]
+
+
+@pytest.mark.parametrize("L,rays,lo,dims", ORACLE_BOX_CASES)
+def test_raw_box_vs_oracle(L, rays, lo, dims):
+    """sal_raw_box (energies of the grown box by the fused kernels, then k_dcs_box) against the
+    oracle's raw maps of the same box, FP32, within 1e-5 of the map maximum."""
+    import numpy as np
+
+    import oracle as O
+    print("raw_box vs oracle L=%d rays=%s lo=%s dims=%s" % (L, rays, lo, dims), flush=True)
+    shape = (48, 48, 48)
+    Vn = synth.make_volume(shape, seed=11, n_faults=2, throw=3, n_chaotic=1, chaotic_size=12)
+    ray_masks = (sal.RAY_ALL,) * 3 if rays == "all26" else sal.RAYS_AXIS
+    ctx = sal.Saliency(L=L, rays=ray_masks)
+    box = ctx.raw_box(torch.from_numpy(Vn).cuda(), lo, dims).cpu().numpy()
+    _, ref = O.raw_box(Vn, O.Params(L=L, rays=ray_masks), lo, dims)
+    for m in range(3):
+        err = np.abs(box[m] - ref[m]).max() / np.abs(ref[m]).max()
+        assert err <= 1e-5, (m, err)

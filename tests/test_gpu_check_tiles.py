@@ -156,3 +156,51 @@ def test_streamed_restream_equals_kept(net):
     assert sorted(t for t, _ in a["tiles"]) == sorted(t for t, _ in b["tiles"])
     assert torch.equal(a["S_raw"], b["S_raw"])
     assert torch.equal(a["S"], b["S"])
+
+
+@pytest.mark.parametrize("L,rays", [(5, None), (8, None), (16, None), (8, "all26"), (16, "all26")])
+def test_check_tiles_vs_oracle(L, rays):
+    """The batched check's exact maps (energy launch over the box table, k_dcs_boxes) against
+    the oracle's raw maps of each tile, FP32, within 1e-5 of each map's maximum; the error of
+    each tile against max |pred - exact| / range computed on the host from the oracle's maps;
+    and the replacement of exactly the tiles over the bound."""
+    import oracle as O
+    print("check_tiles vs oracle L=%d rays=%s" % (L, rays), flush=True)
+    shape = (44, 40, 52)
+    Vn = synth.make_volume(shape, seed=21, n_faults=2, throw=3, n_chaotic=1, chaotic_size=10)
+    V = torch.from_numpy(Vn).cuda()
+    ray_masks = (sal.RAY_ALL,) * 3 if rays == "all26" else sal.RAYS_AXIS
+    ctx = sal.Saliency(L=L, rays=ray_masks)
+    _, _, Sr, st = ctx.saliency_maps(V)
+    P = _perturbed(Sr, 7 + L)
+    Pn = P.cpu().numpy().astype(np.float64)
+    stats = st.cpu().numpy()
+    rng = np.array([stats[2 * m + 1] - stats[2 * m] for m in range(3)])
+    td = (8, 9, 7)
+    # corner, far corner (ragged against the sides), faces, interior
+    tiles = [(0, 0, 0), (36, 31, 45), (0, 15, 45), (20, 0, 22), (14, 12, 20), (36, 31, 0)]
+    bound = 0.02
+    X = torch.empty((len(tiles), 3) + td, dtype=torch.float32, device="cuda")
+    err = torch.zeros(len(tiles), dtype=torch.float32, device="cuda")
+    P2 = P.clone()
+    sal.check_tiles(ctx, V, tiles, P2, tiles, td, st, bound, err, exact_out=X)
+    torch.cuda.synchronize()
+    Xn, errn, P2n = X.cpu().numpy(), err.cpu().numpy(), P2.cpu().numpy()
+    p = O.Params(L=L, rays=ray_masks)
+    replaced = 0
+    for k, lo in enumerate(tiles):
+        _, ref = O.raw_box(Vn, p, lo, td)
+        sl = tuple(slice(a, a + d) for a, d in zip(lo, td))
+        for m in range(3):
+            e = np.abs(Xn[k, m] - ref[m]).max() / np.abs(ref[m]).max()
+            assert e <= 1e-5, (lo, m, e)
+        host_err = max(float(np.abs(Pn[(m,) + sl] - ref[m]).max() / rng[m]) for m in range(3))
+        # the exact maps differ from the oracle's by at most 1e-5 of each map's maximum
+        tol = max(1e-5 * float(np.abs(ref[m]).max()) / rng[m] for m in range(3)) + 1e-6 * host_err
+        assert abs(float(errn[k]) - host_err) <= tol, (lo, errn[k], host_err, tol)
+        if errn[k] > bound:
+            replaced += 1
+            assert np.array_equal(P2n[(slice(None),) + sl], Xn[k])
+        else:
+            assert np.array_equal(P2n[(slice(None),) + sl], P.cpu().numpy()[(slice(None),) + sl])
+    assert 0 < replaced < len(tiles)

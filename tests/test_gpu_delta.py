@@ -1,0 +1,97 @@
+"""Window membership and reflection of the fused energy kernels, pinned with unit spikes.
+
+For a volume that is zero except for a unit spike at s, the window of voxel v (Sec. 2, first
+step; start v - floor(L/2), samples outside the volume reflected) holds the spike c(v) times,
+c(v) = prod over axes a of #{p in [0, L): refl(v_a - floor(L/2) + p) = s_a}.  A window without
+it is all zeros, so every bin of its spectrum and every E_m is an exact zero in any precision;
+a window holding it once has |F| = L^-3 in every bin, so E_m(v) = L^-3 / (L^3 - 1) times the sum
+of the projection weight w_m over the bins other than DC (Eqs. (1)-(4)), the same constant for
+every such voxel.
+
+The bar: the set of voxels with E_m != 0 equals {c(v) > 0} bit for bit, in every precision
+form of the fused kernels (FP32, the 16-bit forms, the vector-ALU kernel of small cubes); the
+FP32 values equal the oracle within 1e-5 of the map maximum, and where c(v) = 1 they equal the
+constant above within the same bound.  Spikes sit on corners, edges, faces and inside.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1901_11095_amd import sal
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _refl(u, n):
+    u = np.where(u < 0, -u, u)
+    return np.where(u >= n, 2 * (n - 1) - u, u)
+
+
+def membership(shape, spike, L):
+    """c(v) for every voxel: the number of window samples that are the spike."""
+    H = L // 2
+    per_axis = []
+    for n, s in zip(shape, spike):
+        v = np.arange(n)[:, None]
+        p = np.arange(L)[None, :]
+        per_axis.append((_refl(v - H + p, n) == s).sum(1))
+    return per_axis[0][:, None, None] * per_axis[1][None, :, None] * per_axis[2][None, None, :]
+
+
+def single_spike_constant(L):
+    """E_m of a window holding the spike once: |F| = L^-3 on every bin (from the oracle's
+    projection of the spectrum of a window that is one unit sample)."""
+    F = np.zeros((L, L, L), np.complex128)
+    F[...] = L ** -3.0
+    return O.project(F)
+
+
+SHAPES = {5: (13, 11, 17), 8: (19, 17, 35), 16: (21, 26, 40)}
+
+
+def spikes(shape):
+    n0, n1, n2 = shape
+    return [(0, 0, 0), (n0 - 1, n1 - 1, n2 - 1), (0, n1 // 2, n2 - 1), (n0 // 2, 0, n2 // 3),
+            (n0 - 2, n1 // 3, 1), (n0 // 2, n1 // 2, n2 // 2), (1, n1 - 1, 0)]
+
+
+FORMS = [(5, sal.FP32), (8, sal.FP32), (16, sal.FP32), (8, sal.BF16_SPLIT), (16, sal.BF16_SPLIT),
+         (8, sal.FP16), (16, sal.BF16)]
+
+
+@pytest.mark.parametrize("L,prec", FORMS)
+def test_spike_window_membership(L, prec):
+    shape = SHAPES[L]
+    ctx = sal.Saliency(L=L, precision=prec)
+    const = single_spike_constant(L)
+    for s in spikes(shape):
+        print("spike L=%d prec=%s at %s" % (L, sal.PRECISION_NAMES[prec], s), flush=True)
+        V = np.zeros(shape, np.float32)
+        V[s] = 1.0
+        _, E, _, _ = ctx.saliency_maps(torch.from_numpy(V).cuda())
+        E = E.cpu().numpy()
+        c = membership(shape, s, L)
+        assert c.max() >= 1
+        for m in range(3):
+            # window membership and reflection: bit-exact support
+            assert np.array_equal(E[m] != 0, c > 0), ("support", m, s)
+            assert np.all(E[m] >= 0)
+        if prec != sal.FP32:
+            continue
+        # the oracle on the bounding box of the support (zero outside it on both sides)
+        idx = np.nonzero(c)
+        lo = [int(a.min()) for a in idx]
+        bn = [int(a.max()) + 1 - l for a, l in zip(idx, lo)]
+        ref = O.energy_box(V, L, lo, bn)
+        sl = tuple(slice(l, l + b) for l, b in zip(lo, bn))
+        cb = c[sl]
+        for m in range(3):
+            got = E[m][sl]
+            err = np.abs(got - ref[m]).max() / np.abs(ref[m]).max()
+            assert err <= TOL, ("value", m, s, err)
+            one = cb == 1
+            if one.any():
+                assert np.abs(got[one] - const[m]).max() <= TOL * const[m], ("constant", m, s)
+                assert np.abs(ref[m][one] - const[m]).max() <= 1e-12 * const[m]
