@@ -83,7 +83,7 @@ enum {
 
 typedef struct {
     int32_t L;          /* cube side of the local DFT (Sec. 2 step 1; the paper uses 5).
-                           GPU build: 8 or 16. */
+                           GPU build: 2..8 and 16 (2..7 in FP32 only). */
     int32_t d;          /* length of the d x 1 comparison line (after Fig. 3), default L;
                            the line is r = floor(d/2) neighbours on each enabled ray. */
     double sigma;       /* width of the Gaussian neighbour weight w(s) = exp(-s^2/(2 sigma^2))
@@ -108,8 +108,9 @@ void sal_default_params(sal_params *p, int32_t L);
 
 /* Validate *p (copied) and create a context on HIP device `device`.  Builds the DFT
  * matrices and projection weight tables on that device.  Errors: SAL_E_INVAL (null out,
- * L < 2, d < 2, sigma <= 0, a ray mask with bits above 63 or empty, bad precision),
- * SAL_E_UNSUPPORTED (L not in {8, 16}), SAL_E_DEVICE. */
+ * L < 2, d outside [2, 64], sigma <= 0, an empty ray mask or one with bits above 25, bad
+ * precision, stride < 1 or not below L/2), SAL_E_UNSUPPORTED (L in 9..15 or above 16, a
+ * 16-bit precision with L < 8, a stride this build does not implement), SAL_E_DEVICE. */
 sal_status sal_create(const sal_params *p, int device, sal_ctx **out);
 
 /* Free the context and its device tables (waits for nothing; the caller must ensure no
@@ -196,6 +197,16 @@ sal_status sal_raw_box(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, int
                        void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * Largest magnitude of a device array, the scale of the zero-contrast rule of
+ * sal_normalize_combine when the volume is not resident (e.g. reduced slab by slab while a
+ * host volume streams through HBM).  V: DEVICE float [n] (may be NULL when n = 0);
+ * vmax_out: DEVICE float, set to
+ * max |V[i]| (accumulate == 0) or to max(*vmax_out, max |V[i]|) (accumulate != 0, *vmax_out
+ * >= 0 before the call).  NaN elements are ignored.  Errors: SAL_E_INVAL, SAL_E_DEVICE.
+ */
+sal_status sal_absmax(sal_ctx *ctx, const float *V, int64_t n, float *vmax_out, int accumulate, void *stream);
+
+/*
  * Steps 4b-5 on given raw maps S_raw float [3][n0][n1][n2]: the FP64 volume-wide statistics
  * and the normalised combination of Eq. (6) (same arithmetic as sal_saliency).  The scale of
  * the zero-contrast rule is max|V| over V (float [n0][n1][n2]) when V is given, else the
@@ -215,6 +226,8 @@ sal_status sal_normalize_combine(sal_ctx *ctx, const float *V, double vmax, cons
  * err to *err_out (DEVICE float) and, when err > bound, overwrites the tile of S_raw with
  * the exact values.  The tile must lie inside both the volume and the crop.
  */
+/* A difference that is not finite (a NaN or infinite prediction) counts as an infinite error,
+ * so such a tile is always replaced. */
 sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, int64_t n2,
                           const float *exact, const int64_t crop_lo[3], const int64_t crop_dims[3],
                           const int64_t tile_lo[3], const int64_t tile_dims[3],
@@ -240,9 +253,13 @@ sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, in
  *   workspace   DEVICE, at least sal_check_tiles_workspace_size() bytes for the same
  *               n0..n2, nbox and tile_dims
  * Tiles must not overlap (the replacement of one would otherwise race with the check of
- * another).  Requires stride 1.  Errors: SAL_E_INVAL (a tile outside its volume or the map,
- * nbox outside [1, 2^20], tile sides outside [1, 1024], or a batch whose energy boxes hold
- * more than 2^31 - 1 voxels: split it over several calls), SAL_E_UNSUPPORTED (stride 2),
+ * another).  The tile tables are copied from host memory into the workspace at call time
+ * (through a pinned staging buffer of the context, reused only after the previous copy from
+ * it has completed, which may wait for that copy); the call therefore cannot be captured
+ * into a HIP graph and is refused on a capturing stream.  Requires stride 1.
+ * Errors: SAL_E_INVAL (a tile outside its volume or the map, nbox outside [1, 2^20], tile
+ * sides outside [1, 1024], or a batch whose energy boxes hold more than 2^31 - 1 voxels:
+ * split it over several calls), SAL_E_UNSUPPORTED (stride 2, a capturing stream),
  * SAL_E_WORKSPACE, SAL_E_DEVICE.
  */
 sal_status sal_check_tiles_workspace_size(sal_ctx *ctx, int64_t n0, int64_t n1, int64_t n2, int64_t nbox,
@@ -299,9 +316,20 @@ sal_status sal_net_forward(sal_net *net, const float *X, int64_t nb, int64_t n0,
 sal_status sal_net_backward(sal_net *net, const float *X, const float *dY, int64_t nb, int64_t n0,
                             int64_t n1, int64_t n2, void *workspace, size_t ws_bytes,
                             void *stream);
-/* One Adam step (lr, betas 0.9/0.999, eps 1e-8) on the mean squared error between the
+/* Arithmetic of the network's convolutions: SAL_BF16 (default; BF16 weights and activations,
+ * FP32 accumulation) or SAL_FP32 (the same kernels with FP32 weights and activations, for
+ * element-wise checks against an FP64 reference).  Applies to every later call; workspace
+ * sizes depend on it.  Errors: SAL_E_INVAL. */
+sal_status sal_net_set_precision(sal_net *net, int32_t precision);
+/* One Adam step (betas 0.9/0.999, eps 1e-8, bias-corrected with the net's step count) of
+ * learning rate lr >= 0 on the FP32 master parameters from the gradient accumulated by
+ * sal_net_backward, which it then clears; rebuilds the operand tables.  Asynchronous on
+ * `stream`.  Errors: SAL_E_INVAL, SAL_E_DEVICE. */
+sal_status sal_net_adam(sal_net *net, float lr, void *stream);
+/* One training step: forward, the gradient of the mean squared error between the
  * network output and T float [nb][S][S][S][3] over the voxels at least `margin` (>= 5)
- * from every face of their S^3 block.  loss_out: optional DEVICE float. */
+ * from every face of their S^3 block, then sal_net_adam(lr).  loss_out: optional DEVICE
+ * float. */
 sal_status sal_net_train_step(sal_net *net, const float *X, const float *T, int64_t nb, int64_t S,
                               int32_t margin, float lr, float *loss_out, void *workspace,
                               size_t ws_bytes, void *stream);

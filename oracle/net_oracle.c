@@ -117,6 +117,44 @@ void oracle_net_forward(const double *x, long nb, long S, long nl, const long *c
     free(a);
 }
 
+/*
+ * The same network in the arithmetic it is specified with (BF16 weights and activations,
+ * wider accumulation): every value that the specification keeps in BF16 is rounded to BF16
+ * (8 significant bits, round to nearest, ties to even) where it is formed -- the input, each
+ * layer's weights, each pre-activation z = conv + bias and each activation GELU(z) -- and
+ * everything else stays FP64 (sums, biases, the output of the last layer).
+ */
+double oracle_round_bf16(double v)
+{
+    if (v == 0.0 || !isfinite(v)) return v;
+    int e;
+    const double m = frexp(v, &e); /* v = m 2^e, 0.5 <= |m| < 1 */
+    return ldexp(nearbyint(ldexp(m, 8)), e - 8);
+}
+
+void oracle_net_forward_bf16(const double *x, long nb, long S, long nl, const long *ch,
+                             const double *params, double *y)
+{
+    const long S3 = S * S * S;
+    double *a = (double *)malloc(sizeof(double) * nb * S3 * ch[0]);
+    for (long i = 0; i < nb * S3 * ch[0]; ++i) a[i] = oracle_round_bf16(x[i]);
+    for (long l = 0; l < nl; ++l) {
+        const long o = layer_offset(ch, l), nw = ch[l + 1] * 27 * ch[l];
+        double *W = (double *)malloc(sizeof(double) * nw);
+        for (long i = 0; i < nw; ++i) W[i] = oracle_round_bf16(params[o + i]);
+        double *z = (double *)malloc(sizeof(double) * nb * S3 * ch[l + 1]);
+        oracle_conv3d(a, nb, S, ch[l], W, params + o + nw, ch[l + 1], z);
+        free(W);
+        free(a);
+        a = z;
+        if (l + 1 < nl)
+            for (long i = 0; i < nb * S3 * ch[l + 1]; ++i)
+                a[i] = oracle_round_bf16(oracle_gelu(oracle_round_bf16(a[i])));
+    }
+    memcpy(y, a, sizeof(double) * nb * S3 * ch[nl]);
+    free(a);
+}
+
 /* Gradient of sum(dy * y) w.r.t. every parameter (backpropagation of the forward above). */
 void oracle_net_backward(const double *x, long nb, long S, long nl, const long *ch,
                          const double *params, const double *dy, double *grads)

@@ -86,6 +86,9 @@ def lib() -> ctypes.CDLL:
         l.oracle_conv3d_backward.argtypes = [_dp, _L, _L, _L, _dp, _L, _dp, _dp, _dp, _dp]
         l.oracle_net_forward.argtypes = [_dp, _L, _L, _L, _lp, _dp, _dp, _dp]
         l.oracle_net_backward.argtypes = [_dp, _L, _L, _L, _lp, _dp, _dp, _dp]
+        l.oracle_net_forward_bf16.argtypes = [_dp, _L, _L, _L, _lp, _dp, _dp]
+        l.oracle_round_bf16.argtypes = [ctypes.c_double]
+        l.oracle_round_bf16.restype = ctypes.c_double
         _lib = l
     return _lib
 
@@ -310,6 +313,23 @@ def net_forward(x, params, ch=SURROGATE_CHANNELS):
     y = np.zeros((nb, S, S, S, ch[-1]), np.float64)
     cha = (ctypes.c_long * len(ch))(*ch)
     lib().oracle_net_forward(_d(x), nb, S, len(ch) - 1, cha, _d(p), _d(y), None)
+    return y
+
+
+def round_bf16(v: float) -> float:
+    """v rounded to 8 significant bits, to nearest, ties to even (the BF16 values)."""
+    return lib().oracle_round_bf16(float(v))
+
+
+def net_forward_bf16(x, params, ch=SURROGATE_CHANNELS):
+    """net_forward in the network's specified arithmetic: input, weights, pre-activations and
+    activations rounded to BF16 where they are formed, sums and biases in FP64."""
+    x = np.ascontiguousarray(x, np.float64)
+    p = np.ascontiguousarray(params, np.float64)
+    nb, S = x.shape[0], x.shape[1]
+    y = np.zeros((nb, S, S, S, ch[-1]), np.float64)
+    cha = (ctypes.c_long * len(ch))(*ch)
+    lib().oracle_net_forward_bf16(_d(x), nb, S, len(ch) - 1, cha, _d(p), _d(y))
     return y
 
 

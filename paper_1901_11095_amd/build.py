@@ -24,6 +24,9 @@ FLAGS = [
     # MFMA accumulators in ordinary VGPRs: the magnitudes are computed from them directly
     "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-result",
+    # every symbol resolved at link time (a kernel whose host stub failed to instantiate
+    # would otherwise leave an undefined reference in the library)
+    "-Wl,-z,defs",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

@@ -422,7 +422,6 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
         int nr = 0;
         for (int b = 0; b < 26; ++b) nr += (p->rays[m] >> b) & 1;
         c->Q[m] = (float)(nr * c->r);
-        c->q_inv[m] = 1.0f / c->Q[m];
     }
     hipError_t e = build_tables(c);
     if (e != hipSuccess) {
@@ -440,6 +439,11 @@ void sal_destroy(sal_ctx *c)
     DevScope ds(c->device);
     release_events(c);
     free_tables(&c->t);
+    if (c->tab_done) {
+        (void)hipEventSynchronize(c->tab_done);
+        (void)hipEventDestroy(c->tab_done);
+    }
+    if (c->tab_host) (void)hipHostFree(c->tab_host);
     delete c;
 }
 
@@ -764,21 +768,54 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
     if (ws_bytes < w.total) return fail(c, SAL_E_WORKSPACE, "workspace too small: need " + std::to_string(w.total) + " bytes");
     DevScope ds(c->device);
     if ((st = sticky(c)) != SAL_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // The box tables come from host memory at call time, so a captured graph would replay
+    // the upload of whatever the staging buffer holds then: refuse capture.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return dev_fail(c, e, "stream capture query");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(c, SAL_E_UNSUPPORTED, "sal_check_tiles cannot be captured into a graph");
     char *ws = (char *)workspace;
     float *Eb = (float *)(ws + w.e);
     float *X = exact_out ? exact_out : (float *)(ws + w.exact);
     int *etab_d = (int *)(ws + w.table), *ttab_d = etab_d + etab.size();
     etab.insert(etab.end(), ttab.begin(), ttab.end());
-    hipStream_t s = (hipStream_t)stream;
-    // the tables are staged from pageable memory before the call returns
-    hipError_t e = hipMemcpyAsync(etab_d, etab.data(), etab.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    // stage the tables in the context's pinned buffer, once the previous upload from it is done
+    if (!c->tab_done && (e = hipEventCreateWithFlags(&c->tab_done, hipEventDisableTiming)) != hipSuccess)
+        return dev_fail(c, e, "event create");
+    if ((e = hipEventSynchronize(c->tab_done)) != hipSuccess) return dev_fail(c, e, "staging wait");
+    if (c->tab_cap < etab.size()) {
+        if (c->tab_host) (void)hipHostFree(c->tab_host);
+        c->tab_host = nullptr;
+        c->tab_cap = 0;
+        if ((e = hipHostMalloc((void **)&c->tab_host, etab.size() * sizeof(int), hipHostMallocDefault)) != hipSuccess)
+            return dev_fail(c, e, "pinned staging");
+        c->tab_cap = etab.size();
+    }
+    std::memcpy(c->tab_host, etab.data(), etab.size() * sizeof(int));
+    e = hipMemcpyAsync(etab_d, c->tab_host, etab.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return dev_fail(c, e, "box table upload");
+    if ((e = hipEventRecord(c->tab_done, s)) != hipSuccess) return dev_fail(c, e, "event record");
     e = launch_energy_boxes(c, V, n0, n1, n2, vol_stride, etab_d, nent, maxd, Eb, w.estride, nullptr, nullptr, s);
     if (e != hipSuccess) return dev_fail(c, e, "energy launch");
     e = launch_dcs_boxes(c, Eb, w.estride, ttab_d, (int)nbox, n, tile_dims, X, s);
     if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
     e = launch_tile_merge_boxes(S_raw, m0, m1, m2, X, ttab_d, (int)nbox, tile_dims, stats, bound, err_out, s);
     if (e != hipSuccess) return dev_fail(c, e, "tile merge launch");
+    return SAL_OK;
+}
+
+sal_status sal_absmax(sal_ctx *c, const float *V, int64_t n, float *vmax_out, int accumulate, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if ((!V && n > 0) || !vmax_out) return fail(c, SAL_E_INVAL, "null pointer");
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(c, SAL_E_INVAL, "bad count");
+    DevScope ds(c->device);
+    sal_status st;
+    if ((st = sticky(c)) != SAL_OK) return st;
+    hipError_t e = launch_absmax_acc(V, n, vmax_out, accumulate, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(c, e, "absmax launch");
     return SAL_OK;
 }
 

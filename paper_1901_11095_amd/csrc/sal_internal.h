@@ -38,7 +38,6 @@ struct sal_ctx {
     int device;
     int L, H, h, r, nrows;
     float g[96];       // Gaussian neighbour weights w(s |e|), s = 1..r (index 32 (|e|^2 - 1) + s - 1)
-    float q_inv[3];    // unused by the kernels (kept for diagnostics)
     float Q[3];        // number of terms of Eq. (5) per component
     float tw_host[32]; // e^{-2 pi i k / L} (re, im), k < L
     sal_tables t;
@@ -47,6 +46,11 @@ struct sal_ctx {
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;  // 5 events per timed call
     size_t ev_used = 0;
+    // pinned staging of the box tables of sal_check_tiles, reused once the event recorded
+    // after the last upload from it has completed
+    int *tab_host = nullptr;
+    size_t tab_cap = 0;
+    hipEvent_t tab_done = nullptr;
 };
 
 // Arguments of the directional comparison kernel.
@@ -194,6 +198,8 @@ hipError_t launch_combine(const float *S_raw, int64_t nvox, const double *stats,
                           hipStream_t s);
 
 int64_t merge_red_blocks(int64_t N);
+// out[0] = max(out[0], max |V[0..N)|) (accumulate != 0) or max |V[0..N)| (accumulate == 0)
+hipError_t launch_absmax_acc(const float *V, int64_t N, float *out, int accumulate, hipStream_t s);
 hipError_t launch_minmax_absmax(const float *V, float vmax, const float *S_raw, int64_t N,
                                 float *mm_part, float *vmax_part, hipStream_t s);
 hipError_t launch_tile_merge(float *S_raw, int64_t n0, int64_t n1, int64_t n2, const float *exact,

@@ -65,6 +65,31 @@ __global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ V, int
 
 __global__ void k_fill_f32(float *p, float v) { *p = v; }
 
+// out[0] = max(out[0], max |V|): block maxima joined by an atomic max on the bit pattern (the
+// values are non-negative, so float order equals unsigned order)
+__global__ __launch_bounds__(256) void k_absmax_acc(const float *__restrict__ V, int64_t N, float *__restrict__ out)
+{
+    float m = 0.f;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256)
+        m = fmaxf(m, fabsf(V[v]));
+    __shared__ float red[4];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned int *>(out),
+                  __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
+}
+
+// |pred - exact| * inv for the tile check; a non-finite difference (a NaN or infinite
+// prediction) counts as +inf, so its tile is always over the bound and replaced
+__device__ __forceinline__ float tile_diff(float pred, float exact, float inv)
+{
+    const float d = fabsf(pred - exact) * inv;
+    return d <= FLT_MAX ? d : __int_as_float(0x7f800000);
+}
+
 struct box3 {
     int64_t lo[3], d[3];
 };
@@ -90,7 +115,7 @@ __global__ __launch_bounds__(256) void k_tile_err(const float *__restrict__ S, i
         const int64_t vo = (t * n1 + x) * n2 + y;
         const int64_t co = ((t - crop.lo[0]) * crop.d[1] + (x - crop.lo[1])) * crop.d[2] + (y - crop.lo[2]);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) e = fmaxf(e, fabsf(S[m * N + vo] - X[m * NC + co]) * inv[m]);
+        for (int m = 0; m < 3; ++m) e = fmaxf(e, tile_diff(S[m * N + vo], X[m * NC + co], inv[m]));
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) e = fmaxf(e, __shfl_xor(e, o));
@@ -144,7 +169,7 @@ __global__ __launch_bounds__(256) void k_tile_err_boxes(const float *__restrict_
         const int t = q[9] + i / (td.y * td.z), x = q[10] + (i / td.z) % td.y, y = q[11] + i % td.z;
         const int64_t vo = ((int64_t)t * n1 + x) * n2 + y;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) e = fmaxf(e, fabsf(S[m * N + vo] - X[m * nt + i]) * inv[m]);
+        for (int m = 0; m < 3; ++m) e = fmaxf(e, tile_diff(S[m * N + vo], X[m * nt + i], inv[m]));
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) e = fmaxf(e, __shfl_xor(e, o));
@@ -170,7 +195,9 @@ __global__ __launch_bounds__(256) void k_tile_copy_boxes(float *__restrict__ S, 
     }
 }
 
-// {min, max} of each raw map over one tile per workgroup; tiles numbered (t, x, y), y fastest
+// {min, max} of each raw map over one tile per workgroup; tiles numbered (t, x, y), y fastest.
+// A NaN in a tile makes its extremes -inf and +inf, so the check of the tiles that pass the
+// checked tiles' extremes always takes it.
 __global__ __launch_bounds__(256) void k_tile_minmax(const float *__restrict__ S, int n0, int n1, int n2, int tile,
                                                      int ntx, int nty, float *__restrict__ out)
 {
@@ -188,8 +215,9 @@ __global__ __launch_bounds__(256) void k_tile_minmax(const float *__restrict__ S
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const float s = S[m * N + v];
-            mn[m] = fminf(mn[m], s);
-            mx[m] = fmaxf(mx[m], s);
+            const bool nan = !(s == s);
+            mn[m] = nan ? -__int_as_float(0x7f800000) : fminf(mn[m], s);
+            mx[m] = nan ? __int_as_float(0x7f800000) : fmaxf(mx[m], s);
         }
     }
     __shared__ float red[4][6];
@@ -219,6 +247,13 @@ int64_t merge_red_blocks(int64_t N)
 {
     const int64_t nb = (N + 255) / 256;
     return nb < RED_BLOCKS ? nb : RED_BLOCKS;
+}
+
+hipError_t launch_absmax_acc(const float *V, int64_t N, float *out, int accumulate, hipStream_t s)
+{
+    if (!accumulate) hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(1), 0, s, out, 0.f);
+    if (N > 0) hipLaunchKernelGGL(k_absmax_acc, dim3((unsigned)merge_red_blocks(N)), dim3(256), 0, s, V, N, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_minmax_absmax(const float *V, float vmax, const float *S_raw, int64_t N,

@@ -83,6 +83,66 @@ __device__ __forceinline__ float gelu_grad_f(float z)
     return 0.5f * (1.0f + e) + z * gs * 0.39894228040143268f;
 }
 
+// Storage type of activations and gradients: BF16 (the network's arithmetic) or FP32 (the
+// FP32-operand mode, which runs the same kernels with FP32 operands for element-wise checks)
+template <bool F32>
+struct ActT {
+    using type = uint16_t;
+};
+template <>
+struct ActT<true> {
+    using type = float;
+};
+template <bool F32>
+__device__ __forceinline__ typename ActT<F32>::type to_act(float f)
+{
+    if constexpr (F32)
+        return f;
+    else
+        return f2bf(f);
+}
+template <bool F32>
+__device__ __forceinline__ float from_act(typename ActT<F32>::type a)
+{
+    if constexpr (F32)
+        return a;
+    else
+        return bf2f(a);
+}
+
+// 16 bytes from global memory straight into LDS at the row base `dst` + 16 * lane
+__device__ __forceinline__ void load16_to_lds(const uint16_t *src, uint16_t *dst)
+{
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+// four consecutive channels of one voxel (16-byte aligned in FP32, 8-byte in BF16)
+template <bool F32>
+__device__ __forceinline__ void store4(typename ActT<F32>::type *p, const typename ActT<F32>::type r[4])
+{
+    if constexpr (F32)
+        *reinterpret_cast<float4 *>(p) = make_float4(r[0], r[1], r[2], r[3]);
+    else
+        *reinterpret_cast<uint2 *>(p) = make_uint2(r[0] | ((uint32_t)r[1] << 16), r[2] | ((uint32_t)r[3] << 16));
+}
+template <bool F32>
+__device__ __forceinline__ void load4(const typename ActT<F32>::type *p, typename ActT<F32>::type r[4])
+{
+    if constexpr (F32) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        r[0] = v.x;
+        r[1] = v.y;
+        r[2] = v.z;
+        r[3] = v.w;
+    } else {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        r[0] = (uint16_t)(v.x & 0xffff);
+        r[1] = (uint16_t)(v.x >> 16);
+        r[2] = (uint16_t)(v.y & 0xffff);
+        r[3] = (uint16_t)(v.y >> 16);
+    }
+}
+
 __device__ __forceinline__ int map_idx(int u, int n, int mode)
 {
     if (mode == MODE_ZERO) return (u < 0 || u >= n) ? -1 : u;
@@ -96,30 +156,36 @@ __device__ __forceinline__ int map_idx(int u, int n, int mode)
 // sum_K A[co][K] B[K][voxel], K = (tap, input channel).  A (the weights) stays in registers
 // for the whole workgroup; B is read from the LDS input tile, 8 channels of one tap = 16
 // bytes per lane.  Each wave computes 4 rows of 16 voxels.
-//   in:   CI == 1: float [nb][n0][n1][n2]; else bf16 [nb][...][CI]
-//   wtab: bf16 [MT*16][ksteps*32] (rows >= CO and K past the taps are zero)
-//   EPI_GELU:   z = acc + bias -> out0 (bf16, optional), GELU(z) -> out1 (bf16)
+//   in:   CI == 1: float [nb][n0][n1][n2]; else Act [nb][...][CI]
+//   wtab: Act [MT*16][ksteps*32] (rows >= CO and K past the taps are zero)
+//   EPI_GELU:   z = acc + bias -> out0 (Act, optional), GELU(z) -> out1 (Act)
 //   EPI_LINEAR: (acc + bias) * oscale[c] -> out0 (float), element (v, c) at v*vstride + c*cstride
-//   EPI_DGELU:  acc * GELU'(zprev) -> out0 (bf16)
-template <int CI, int CO, int MODE, int EPI>
+//   EPI_DGELU:  acc * GELU'(zprev) -> out0 (Act)
+// Act is BF16, or FP32 with F32: the same tiles, K order and epilogues, each 16x16x32 step
+// done as eight 16x16x4 FP32 MFMAs over the eight K elements a lane holds (a lane of group g
+// holds K = 8g + e, e < 8, in both forms), the weights read from the table at each step,
+// the tiles loaded synchronously (two FP32 buffers would not fit the LDS).
+template <int CI, int CO, int MODE, int EPI, bool F32>
 __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restrict__ in, int nb, int n0, int n1,
-                                               int n2, const uint16_t *__restrict__ wtab,
+                                               int n2, const void *__restrict__ wtab,
                                                const float *__restrict__ bias,
-                                               const uint16_t *__restrict__ zprev, void *out0,
+                                               const void *__restrict__ zprev, void *out0,
                                                void *out1, int64_t vstride, int64_t cstride,
                                                float3 oscale)
 {
+    using Act = typename ActT<F32>::type;
     constexpr int CIP = CI == 1 ? 1 : pad8(CI);
     constexpr int KS = ksteps(CI), MT = (CO + 15) / 16;
     constexpr int FU = conv_fu(CO), FPU = FU + 2, FNPOS = FPT * FPU * FPW;
     constexpr int FWAVES = FT * FU / 4, FTHREADS = conv_threads(CO);
-    // multi-channel layers with reflected borders (the forward pass) stream the next tile
-    // into a second LDS buffer by direct global-to-LDS loads while the current one computes
-    constexpr bool ASYNC = CI > 1 && CI % 8 == 0 && MODE == MODE_REFLECT;
+    // multi-channel BF16 layers with reflected borders (the forward pass) stream the next
+    // tile into a second LDS buffer by direct global-to-LDS loads while the current one
+    // computes
+    constexpr bool ASYNC = !F32 && CI > 1 && CI % 8 == 0 && MODE == MODE_REFLECT;
     // two separate LDS objects, so the compiler can tell reads of one from the loads landing
     // in the other (a read of the same object would wait for them)
-    __shared__ uint16_t tileA[FNPOS * CIP];
-    __shared__ uint16_t tileB[ASYNC ? FNPOS * CIP : 8];
+    __shared__ __attribute__((aligned(16))) Act tileA[FNPOS * CIP];
+    __shared__ __attribute__((aligned(16))) Act tileB[ASYNC ? FNPOS * CIP : 8];
     // biases in LDS: a global load in the epilogue would wait for the tile in flight
     __shared__ float bias_s[MT * 16];
 
@@ -128,11 +194,12 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
     const int ntw = (n2 + FW - 1) / FW, ntu = (n1 + FU - 1) / FU, ntt = (n0 + FT - 1) / FT;
     const int ntiles = nb * ntt * ntu * ntw;
     const int64_t vol = (int64_t)n0 * n1 * n2;
+    const Act *act_in = reinterpret_cast<const Act *>(in);
 
     // asynchronous load of tile `id` into buffer `bf`: each wave takes whole rows of FPW
     // positions; lane j < FPW * CIP / 8 brings 16 bytes (8 channels) and the hardware puts
     // them at row base + 16 j, which is the row's layout in LDS
-    auto issue = [&](int id, uint16_t *dst) {
+    auto issue = [&](int id, Act *dst) {
         if constexpr (ASYNC) {
             constexpr int CHK = CIP / 8, ROWLEN = FPW * CHK;
             int bi = id;
@@ -142,7 +209,7 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
             bi /= ntu;
             const int tt2 = bi % ntt;
             const int b2 = bi / ntt;
-            const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b2 * vol * CI;
+            const Act *src = act_in + b2 * vol * CI;
             const int pw = lane / CHK, ch = lane - (lane / CHK) * CHK;
             const int gw = refl_idx(tw2 * FW - 1 + pw, n2);
             const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -153,9 +220,7 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
                     const int pt = row / FPU, pu = row - pt * FPU;
                     const int gt = refl_idx(tt2 * FT - 1 + pt, n0), gu = refl_idx(tu2 * FU - 1 + pu, n1);
                     if (lane < ROWLEN)
-                        __builtin_amdgcn_global_load_lds(
-                            src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch,
-                            (__attribute__((address_space(3))) void *)&dst[row * FPW * CIP], 16, 0, 0);
+                        load16_to_lds(src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch, &dst[row * FPW * CIP]);
                 }
             }
         }
@@ -164,17 +229,19 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
     __syncthreads();
     if (ASYNC && (int)blockIdx.x < ntiles) issue(blockIdx.x, tileA);
 
-    // the weights stay in registers while the workgroup walks its tiles
-    u32x4 A[MT][KS];
+    // BF16: the weights stay in registers while the workgroup walks its tiles
+    u32x4 A[MT][F32 ? 1 : KS];
+    if constexpr (!F32) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
-            A[mt][s] = reinterpret_cast<const u32x4 *>(wtab)[((mt * 16 + n) * KS * 32 + s * 32 + 8 * g) / 8];
+            for (int s = 0; s < KS; ++s)
+                A[mt][s] = reinterpret_cast<const u32x4 *>(wtab)[((mt * 16 + n) * KS * 32 + s * 32 + 8 * g) / 8];
+    }
 
     // one tile: wait for its input, start the next tile's loads into the other buffer,
     // convolve, write the epilogue
-    auto process = [&](int tile_id, uint16_t *tile, uint16_t *other) __attribute__((always_inline)) {
+    auto process = [&](int tile_id, Act *tile, Act *other) __attribute__((always_inline)) {
     int bid = tile_id;
     const int tw_ = bid % ntw;
     bid /= ntw;
@@ -209,16 +276,17 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
                 const int pt = row / FPU, pu = row - pt * FPU;
                 const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE);
                 const float v = (gt < 0 || gu < 0 || gw < 0) ? 0.f : src[((int64_t)gt * n1 + gu) * n2 + gw];
-                tile[row * FPW + pw] = f2bf(v);
+                tile[row * FPW + pw] = to_act<F32>(v);
             }
         }
     } else if (ASYNC) {
         // loaded by issue()
     } else if (CI % 8 == 0) {
-        // 16-byte chunks of 8 channels; a row of FPW positions is ROWLEN <= 64 chunks
-        constexpr int CHK = CIP / 8, ROWLEN = FPW * CHK;
+        // chunks of 8 channels (16 bytes in BF16, two 16-byte halves in FP32); a row of FPW
+        // positions is ROWLEN <= 64 chunks
+        constexpr int CHK = CIP / 8, ROWLEN = FPW * CHK, NQ = F32 ? 2 : 1;
         static_assert(ROWLEN <= 64, "one wave loads a whole row");
-        const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
+        const Act *src = act_in + b * vol * CI;
         const bool act = lane < ROWLEN;
         const int pw = lane / CHK, ch = lane - (lane / CHK) * CHK;
         const int gw = map_idx(w0 - 1 + pw, n2, MODE);
@@ -229,23 +297,30 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
             if (row < FPT * FPU) {
                 const int pt = row / FPU, pu = row - pt * FPU;
                 const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE);
-                u32x4 val = u32x4{0u, 0u, 0u, 0u};
-                if (act && gt >= 0 && gu >= 0 && gw >= 0)
-                    val = *reinterpret_cast<const u32x4 *>(src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch);
-                if (act) *reinterpret_cast<u32x4 *>(&tile[(row * FPW + pw) * CIP + 8 * ch]) = val;
+                u32x4 val[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) val[q] = u32x4{0u, 0u, 0u, 0u};
+                if (act && gt >= 0 && gu >= 0 && gw >= 0) {
+                    const u32x4 *p = reinterpret_cast<const u32x4 *>(src + (((int64_t)gt * n1 + gu) * n2 + gw) * CI + 8 * ch);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) val[q] = p[q];
+                }
+                if (act) {
+                    u32x4 *d = reinterpret_cast<u32x4 *>(&tile[(row * FPW + pw) * CIP + 8 * ch]);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) d[q] = val[q];
+                }
             }
         }
     } else {
-        const uint16_t *src = reinterpret_cast<const uint16_t *>(in) + b * vol * CI;
+        const Act *src = act_in + b * vol * CI;
         for (int i = threadIdx.x; i < FNPOS * CIP; i += FTHREADS) {
             const int p = i / CIP, c = i - p * CIP;
             const int row = p / FPW, pw = p - row * FPW;
             const int pt = row / FPU, pu = row - pt * FPU;
             const int gt = map_idx(t0 - 1 + pt, n0, MODE), gu = map_idx(u0 - 1 + pu, n1, MODE),
                       gw = map_idx(w0 - 1 + pw, n2, MODE);
-            tile[i] = (c >= CI || gt < 0 || gu < 0 || gw < 0)
-                          ? (uint16_t)0
-                          : src[(((int64_t)gt * n1 + gu) * n2 + gw) * CI + c];
+            tile[i] = (c >= CI || gt < 0 || gu < 0 || gw < 0) ? (Act)0 : src[(((int64_t)gt * n1 + gu) * n2 + gw) * CI + c];
         }
     }
     // (asynchronous tiles were complete at the barrier above; a barrier here would wait for
@@ -260,39 +335,71 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
         for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            u32x4 bv;
-            if (CI == 1) {
-                // K element e of group g is tap 8g + e
+            if constexpr (F32) {
+                // the eight K elements of this lane, K = 32 s + 8 g + e, as FP32
+                float bk[8];
+                if (CI == 1) {
+                    // K element e of group g is tap 8g + e
 #pragma unroll
-                for (int e2 = 0; e2 < 4; ++e2) {
-                    uint32_t pr = 0;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int k = 8 * g + 2 * e2 + h;
-                        uint32_t val = 0;
-                        if (k < 27) {
-                            const int p = ((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3;
-                            val = tile[p];
-                        }
-                        pr |= val << (16 * h);
+                    for (int e = 0; e < 8; ++e) {
+                        const int k = 8 * g + e;
+                        bk[e] = 0.f;
+                        if (k < 27) bk[e] = tile[((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3];
                     }
-                    bv[e2] = pr;
+                } else {
+                    const int q = 4 * s + g;  // K group: tap q / (CIP/8), channels 8*(q % (CIP/8))
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) bk[e] = 0.f;
+                    if (q < kgroups(CI)) {
+                        const int k = q / (CIP / 8), c0 = 8 * (q % (CIP / 8));
+                        const int p = ((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3;
+                        const float4 *src4 = reinterpret_cast<const float4 *>(&tile[p * CIP + c0]);
+                        const float4 lo = src4[0], hi = src4[1];
+                        bk[0] = lo.x; bk[1] = lo.y; bk[2] = lo.z; bk[3] = lo.w;
+                        bk[4] = hi.x; bk[5] = hi.y; bk[6] = hi.z; bk[7] = hi.w;
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const float *wr = reinterpret_cast<const float *>(wtab) + (mt * 16 + n) * KS * 32 + s * 32 + 8 * g;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) acc[mt] = mfma4(wr[e], bk[e], acc[mt]);
                 }
             } else {
-                const int q = 4 * s + g;  // K group: tap q / (CIP/8), channels 8*(q % (CIP/8))
-                if (q < kgroups(CI)) {
-                    const int k = q / (CIP / 8), c0 = 8 * (q % (CIP / 8));
-                    const int p = ((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3;
-                    bv = *reinterpret_cast<const u32x4 *>(&tile[p * CIP + c0]);
-                } else {
-                    bv = u32x4{0u, 0u, 0u, 0u};
-                }
-            }
+                u32x4 bv;
+                if (CI == 1) {
+                    // K element e of group g is tap 8g + e
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[mt][s]),
-                                                                  __builtin_bit_cast(bf16x8, bv), acc[mt], 0,
-                                                                  0, 0);
+                    for (int e2 = 0; e2 < 4; ++e2) {
+                        uint32_t pr = 0;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int k = 8 * g + 2 * e2 + h;
+                            uint32_t val = 0;
+                            if (k < 27) {
+                                const int p = ((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3;
+                                val = tile[p];
+                            }
+                            pr |= val << (16 * h);
+                        }
+                        bv[e2] = pr;
+                    }
+                } else {
+                    const int q = 4 * s + g;  // K group: tap q / (CIP/8), channels 8*(q % (CIP/8))
+                    if (q < kgroups(CI)) {
+                        const int k = q / (CIP / 8), c0 = 8 * (q % (CIP / 8));
+                        const int p = ((lt + k / 9) * FPU + (lu + (k / 3) % 3)) * FPW + n + k % 3;
+                        bv = *reinterpret_cast<const u32x4 *>(&tile[p * CIP + c0]);
+                    } else {
+                        bv = u32x4{0u, 0u, 0u, 0u};
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[mt][s]),
+                                                                      __builtin_bit_cast(bf16x8, bv), acc[mt], 0,
+                                                                      0, 0);
+            }
         }
         // epilogue: lane (g, n) holds channels 16mt + 4g + j of voxel n
         const int gt = t0 + lt, gu = u0 + lu, gw = w0 + n;
@@ -310,28 +417,23 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
                             o[v * vstride + (cb + j) * cstride] = (acc[mt][j] + bias_s[cb + j]) * sc;
                         }
                 } else if (cb < CO) {  // CO is a multiple of 4 here
-                    uint16_t r[4];
+                    Act r[4];
                     if (EPI == EPI_GELU) {
-                        uint16_t zz[4];
+                        Act zz[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const float z = acc[mt][j] + bias_s[cb + j];
-                            zz[j] = f2bf(z);
-                            r[j] = f2bf(gelu_f(bf2f(zz[j])));
+                            zz[j] = to_act<F32>(z);
+                            r[j] = to_act<F32>(gelu_f(from_act<F32>(zz[j])));
                         }
-                        if (out0)
-                            *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(out0) + v * CO + cb) =
-                                make_uint2(zz[0] | ((uint32_t)zz[1] << 16), zz[2] | ((uint32_t)zz[3] << 16));
-                        *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(out1) + v * CO + cb) =
-                            make_uint2(r[0] | ((uint32_t)r[1] << 16), r[2] | ((uint32_t)r[3] << 16));
+                        if (out0) store4<F32>(reinterpret_cast<Act *>(out0) + v * CO + cb, zz);
+                        store4<F32>(reinterpret_cast<Act *>(out1) + v * CO + cb, r);
                     } else {
-                        const uint2 zp = *reinterpret_cast<const uint2 *>(zprev + v * CO + cb);
-                        const uint16_t zv[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
-                                                (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
+                        Act zv[4];
+                        load4<F32>(reinterpret_cast<const Act *>(zprev) + v * CO + cb, zv);
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) r[j] = f2bf(acc[mt][j] * gelu_grad_f(bf2f(zv[j])));
-                        *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(out0) + v * CO + cb) =
-                            make_uint2(r[0] | ((uint32_t)r[1] << 16), r[2] | ((uint32_t)r[3] << 16));
+                        for (int j = 0; j < 4; ++j) r[j] = to_act<F32>(acc[mt][j] * gelu_grad_f(from_act<F32>(zv[j])));
+                        store4<F32>(reinterpret_cast<Act *>(out0) + v * CO + cb, r);
                     }
                 }
             }
@@ -360,11 +462,13 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
 // db[co] = sum_v dz[v][co].  FP32 16x16x4 MFMA with M = co, N = ci, K = 4 voxels; wave w
 // owns taps w, w+8, w+16, w+24.  Each workgroup walks a fixed stride of tiles and writes
 // its own partial sums (summed afterwards in a fixed order: deterministic).
-template <int CI, int CO>
+template <int CI, int CO, bool F32>
 __global__ __launch_bounds__(512) void k_conv3_wgrad(const void *__restrict__ in,
-                                                     const uint16_t *__restrict__ dz, int nb, int n0,
+                                                     const void *__restrict__ dz_, int nb, int n0,
                                                      int n1, int n2, float *__restrict__ part)
 {
+    using Act = typename ActT<F32>::type;
+    const Act *dz = reinterpret_cast<const Act *>(dz_);
     constexpr int MT = (CO + 15) / 16, NT = (CI + 15) / 16, NKW = 4;
     constexpr int NPAR = CO * 27 * CI + CO;
     __shared__ float tin[NPOS * CI];
@@ -400,13 +504,13 @@ __global__ __launch_bounds__(512) void k_conv3_wgrad(const void *__restrict__ in
             const int64_t gi = b * vol + ((int64_t)refl_idx(t0 - 1 + pt, n0) * n1 + refl_idx(u0 - 1 + pu, n1)) * n2 +
                                refl_idx(w0 - 1 + pw, n2);
             tin[i] = CI == 1 ? reinterpret_cast<const float *>(in)[gi]
-                             : bf2f(reinterpret_cast<const uint16_t *>(in)[gi * CI + c]);
+                             : from_act<F32>(reinterpret_cast<const Act *>(in)[gi * CI + c]);
         }
         for (int i = threadIdx.x; i < TT * TU * TW * CO; i += 512) {
             const int vv = i / CO, c = i - vv * CO;
             const int gt = t0 + vv / (TU * TW), gu = u0 + (vv / TW) % TU, gw = w0 + vv % TW;
             tdz[i] = (gt < n0 && gu < n1 && gw < n2)
-                         ? bf2f(dz[(b * vol + ((int64_t)gt * n1 + gu) * n2 + gw) * CO + c])
+                         ? from_act<F32>(dz[(b * vol + ((int64_t)gt * n1 + gu) * n2 + gw) * CO + c])
                          : 0.f;
         }
         __syncthreads();
@@ -466,9 +570,10 @@ __global__ __launch_bounds__(256) void k_sum_partials(const float *__restrict__ 
 
 // Masked mean squared error: dY = 2 (Y - T) / count on voxels at least `margin` from every
 // face of their block (0 elsewhere), as bf16 [..][3]; loss partial sums per workgroup.
+template <bool F32>
 __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Y, const float *__restrict__ T,
                                              int nb, int S, int margin, float inv_count,
-                                             uint16_t *__restrict__ dY, float *__restrict__ loss_part)
+                                             typename ActT<F32>::type *__restrict__ dY, float *__restrict__ loss_part)
 {
     const int64_t tot = (int64_t)nb * S * S * S;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -481,7 +586,7 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Y, const 
         for (int c = 0; c < 3; ++c) {
             const float d = in ? Y[i * 3 + c] - T[i * 3 + c] : 0.f;
             l += d * d;
-            dY[i * 3 + c] = f2bf(2.f * d * inv_count);
+            dY[i * 3 + c] = to_act<F32>(2.f * d * inv_count);
         }
     }
     __shared__ float red[4];
@@ -529,11 +634,13 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, float *__re
     gr[i] = 0.f;
 }
 
-// BF16 operand tables of one layer from the FP32 master: forward [rows][ksteps*32] and the
-// flipped/transposed kernel of the input-gradient conv.
+// Operand tables of one layer from the FP32 master, in BF16 and in FP32 (the FP32-operand
+// mode): forward [rows][ksteps*32] and the flipped/transposed kernel of the input-gradient
+// conv.
 __global__ __launch_bounds__(256) void k_prep_tables(const float *__restrict__ W, int ci, int co,
-                                                     uint16_t *__restrict__ fwd, int fwd_rows, int fwd_k,
-                                                     uint16_t *__restrict__ bwd, int bwd_rows, int bwd_k)
+                                                     uint16_t *__restrict__ fwd, float *__restrict__ fwd32,
+                                                     int fwd_rows, int fwd_k, uint16_t *__restrict__ bwd,
+                                                     float *__restrict__ bwd32, int bwd_rows, int bwd_k)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     // forward: row co, K index = tap * pad8(ci) + c (ci > 1) or tap (ci == 1)
@@ -549,6 +656,7 @@ __global__ __launch_bounds__(256) void k_prep_tables(const float *__restrict__ W
             }
         }
         fwd[i] = f2bf(w);
+        fwd32[i] = w;
     }
     // backward (input gradient): row = input channel c, K = tap' * pad8(co) + o, weight
     // W[o][26 - tap'][c]
@@ -558,6 +666,7 @@ __global__ __launch_bounds__(256) void k_prep_tables(const float *__restrict__ W
         float w = 0.f;
         if (r < ci && k < 27 && o < co) w = W[(o * 27 + (26 - k)) * ci + r];
         bwd[i] = f2bf(w);
+        bwd32[i] = w;
     }
 }
 
@@ -569,6 +678,8 @@ struct sal_net {
     int64_t npar;
     float *p, *gr, *m, *v;            // FP32 master, gradient, Adam moments
     uint16_t *fwd[NL], *bwd[NL];      // BF16 operand tables
+    float *fwd32[NL], *bwd32[NL];     // FP32 operand tables (FP32-operand mode)
+    bool f32 = false;                 // operands and activations in FP32 instead of BF16
     int64_t step;
     float out_scale[3];               // inference output = network output * out_scale
     std::string err;
@@ -598,8 +709,8 @@ hipError_t prep_tables(sal_net *n, hipStream_t s)
         const int nf = fwd_rows(l) * fwd_k(l), nbk = l > 0 ? bwd_rows(l) * bwd_k(l) : 0;
         const int tot = nf > nbk ? nf : nbk;
         hipLaunchKernelGGL(k_prep_tables, dim3((tot + 255) / 256), dim3(256), 0, s, n->p + n->woff[l],
-                           CH[l], CH[l + 1], n->fwd[l], fwd_rows(l), fwd_k(l), l > 0 ? n->bwd[l] : nullptr,
-                           bwd_rows(l), bwd_k(l));
+                           CH[l], CH[l + 1], n->fwd[l], n->fwd32[l], fwd_rows(l), fwd_k(l),
+                           l > 0 ? n->bwd[l] : nullptr, l > 0 ? n->bwd32[l] : nullptr, bwd_rows(l), bwd_k(l));
     }
     return hipGetLastError();
 }
@@ -617,29 +728,30 @@ unsigned conv_tiles_fwd(int co, int64_t nb, int64_t n0, int64_t n1, int64_t n2)
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Training workspace: z1..z4, a1..a4 (bf16, 24 ch), Y (f32, 3 ch), dY (bf16, 3 ch),
-// two gradient buffers (bf16, 24 ch), weight-gradient partials, loss partials.
+// Training workspace: z1..z4, a1..a4 (24 ch), Y (f32, 3 ch), dY (3 ch), two gradient buffers
+// (24 ch), weight-gradient partials, loss partials; activations and gradients take `es`
+// bytes per value (2: BF16, 4: the FP32-operand mode).
 struct TrainWs {
     size_t z[4], a[4], y, dy, g0, g1, part, lossp, total;
 };
-TrainWs train_ws(int64_t nv)
+TrainWs train_ws(int64_t nv, size_t es)
 {
     TrainWs w;
     size_t o = 0;
     for (int l = 0; l < 4; ++l) {
         w.z[l] = o;
-        o += al(nv * 24 * 2);
+        o += al(nv * 24 * es);
         w.a[l] = o;
-        o += al(nv * 24 * 2);
+        o += al(nv * 24 * es);
     }
     w.y = o;
     o += al(nv * 3 * 4);
     w.dy = o;
-    o += al(nv * 3 * 2);
+    o += al(nv * 3 * es);
     w.g0 = o;
-    o += al(nv * 24 * 2);
+    o += al(nv * 24 * es);
     w.g1 = o;
-    o += al(nv * 24 * 2);
+    o += al(nv * 24 * es);
     w.part = o;
     o += al((size_t)WG_BLOCKS * (24 * 27 * 24 + 24) * 4);
     w.lossp = o;
@@ -647,75 +759,114 @@ TrainWs train_ws(int64_t nv)
     w.total = o;
     return w;
 }
+size_t act_bytes(const sal_net *n) { return n->f32 ? 4 : 2; }
+// inference workspace: two ping-pong activation buffers of 24 channels
+size_t infer_ws(const sal_net *n, int64_t nv) { return 2 * al(nv * 24 * act_bytes(n)); }
 
-template <int CI, int CO, int MODE, int EPI>
-void conv(const void *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, const uint16_t *w,
-          const float *bias, const uint16_t *zprev, void *o0, void *o1, int64_t vs, int64_t cs,
+template <int CI, int CO, int MODE, int EPI, bool F32>
+void conv(const void *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, const void *w,
+          const float *bias, const void *zprev, void *o0, void *o1, int64_t vs, int64_t cs,
           hipStream_t s, float3 oscale = make_float3(1.f, 1.f, 1.f))
 {
     // persistent workgroups: a few per CU, each walking tiles with its weights in registers
     const unsigned tiles = conv_tiles_fwd(CO, nb, n0, n1, n2);
     const unsigned grid = tiles < CONV_BLOCKS ? tiles : CONV_BLOCKS;
-    hipLaunchKernelGGL((k_conv3<CI, CO, MODE, EPI>), dim3(grid), dim3(conv_threads(CO)), 0, s,
+    hipLaunchKernelGGL((k_conv3<CI, CO, MODE, EPI, F32>), dim3(grid), dim3(conv_threads(CO)), 0, s,
                        in, (int)nb, (int)n0, (int)n1, (int)n2, w, bias, zprev, o0, o1, vs, cs, oscale);
 }
 
 // forward through all layers; stores z/a (training) or ping-pongs (inference)
-hipError_t net_forward(sal_net *n, const float *X, int64_t nb, int64_t n0, int64_t n1, int64_t n2,
-                       char *ws, const TrainWs *tw, float *Y, int64_t vs, int64_t cs, float3 oscale,
-                       hipStream_t s)
+template <bool F32>
+hipError_t net_forward_t(sal_net *n, const float *X, int64_t nb, int64_t n0, int64_t n1, int64_t n2,
+                         char *ws, const TrainWs *tw, float *Y, int64_t vs, int64_t cs, float3 oscale,
+                         hipStream_t s)
 {
+    using Act = typename ActT<F32>::type;
     const float *b[NL];
-    for (int l = 0; l < NL; ++l) b[l] = n->p + n->boff[l];
-    uint16_t *z[4], *a[4];
-    for (int l = 0; l < 4; ++l) {
-        z[l] = tw ? (uint16_t *)(ws + tw->z[l]) : nullptr;
-        a[l] = (uint16_t *)(ws + (tw ? tw->a[l] : (l % 2) * al(nvox_of(nb, n0, n1, n2) * 48)));
+    const void *w[NL];
+    for (int l = 0; l < NL; ++l) {
+        b[l] = n->p + n->boff[l];
+        w[l] = F32 ? (const void *)n->fwd32[l] : (const void *)n->fwd[l];
     }
-    conv<1, 24, MODE_REFLECT, EPI_GELU>(X, nb, n0, n1, n2, n->fwd[0], b[0], nullptr, z[0], a[0], 0, 0, s);
+    Act *z[4], *a[4];
+    for (int l = 0; l < 4; ++l) {
+        z[l] = tw ? (Act *)(ws + tw->z[l]) : nullptr;
+        a[l] = (Act *)(ws + (tw ? tw->a[l] : (l % 2) * al(nvox_of(nb, n0, n1, n2) * 24 * sizeof(Act))));
+    }
+    conv<1, 24, MODE_REFLECT, EPI_GELU, F32>(X, nb, n0, n1, n2, w[0], b[0], nullptr, z[0], a[0], 0, 0, s);
     for (int l = 1; l < 4; ++l)
-        conv<24, 24, MODE_REFLECT, EPI_GELU>(a[l - 1], nb, n0, n1, n2, n->fwd[l], b[l], nullptr, z[l], a[l], 0, 0, s);
-    conv<24, 3, MODE_REFLECT, EPI_LINEAR>(a[3], nb, n0, n1, n2, n->fwd[4], b[4], nullptr, Y, nullptr, vs, cs, s,
-                                          oscale);
+        conv<24, 24, MODE_REFLECT, EPI_GELU, F32>(a[l - 1], nb, n0, n1, n2, w[l], b[l], nullptr, z[l], a[l], 0, 0, s);
+    conv<24, 3, MODE_REFLECT, EPI_LINEAR, F32>(a[3], nb, n0, n1, n2, w[4], b[4], nullptr, Y, nullptr, vs, cs, s,
+                                               oscale);
     return hipGetLastError();
 }
+hipError_t net_forward(sal_net *n, const float *X, int64_t nb, int64_t n0, int64_t n1, int64_t n2, char *ws,
+                       const TrainWs *tw, float *Y, int64_t vs, int64_t cs, float3 oscale, hipStream_t s)
+{
+    return n->f32 ? net_forward_t<true>(n, X, nb, n0, n1, n2, ws, tw, Y, vs, cs, oscale, s)
+                  : net_forward_t<false>(n, X, nb, n0, n1, n2, ws, tw, Y, vs, cs, oscale, s);
+}
 
-template <int CI, int CO>
-void wgrad(sal_net *n, int l, const void *in, const uint16_t *dz, int64_t nb, int64_t n0, int64_t n1, int64_t n2,
+template <int CI, int CO, bool F32>
+void wgrad(sal_net *n, int l, const void *in, const void *dz, int64_t nb, int64_t n0, int64_t n1, int64_t n2,
            float *part, hipStream_t s)
 {
     const int64_t tiles = conv_grid(nb, n0, n1, n2);
     const int grid = (int)(tiles < WG_BLOCKS ? tiles : WG_BLOCKS);
-    hipLaunchKernelGGL((k_conv3_wgrad<CI, CO>), dim3(grid), dim3(512), 0, s, in, dz, (int)nb, (int)n0,
+    hipLaunchKernelGGL((k_conv3_wgrad<CI, CO, F32>), dim3(grid), dim3(512), 0, s, in, dz, (int)nb, (int)n0,
                        (int)n1, (int)n2, part);
     const int npar = CO * 27 * CI + CO;
     hipLaunchKernelGGL(k_sum_partials, dim3((npar + 255) / 256), dim3(256), 0, s, part, grid, npar,
                        n->gr + n->woff[l]);
 }
 
-// backward from dY (bf16 [..][3]) through all layers, accumulating the gradient
-hipError_t net_backward(sal_net *n, const float *X, const uint16_t *dY, int64_t nb, int64_t n0, int64_t n1,
-                        int64_t n2, char *ws, const TrainWs &tw, hipStream_t s)
+// backward from dY ([..][3] in the activation type) through all layers, accumulating the
+// gradient
+template <bool F32>
+hipError_t net_backward_t(sal_net *n, const float *X, const void *dY, int64_t nb, int64_t n0, int64_t n1,
+                          int64_t n2, char *ws, const TrainWs &tw, hipStream_t s)
 {
-    uint16_t *z[4], *a[4];
+    using Act = typename ActT<F32>::type;
+    Act *z[4], *a[4];
     for (int l = 0; l < 4; ++l) {
-        z[l] = (uint16_t *)(ws + tw.z[l]);
-        a[l] = (uint16_t *)(ws + tw.a[l]);
+        z[l] = (Act *)(ws + tw.z[l]);
+        a[l] = (Act *)(ws + tw.a[l]);
     }
-    uint16_t *gbuf[2] = {(uint16_t *)(ws + tw.g0), (uint16_t *)(ws + tw.g1)};
+    const void *wb[NL];
+    for (int l = 1; l < NL; ++l) wb[l] = F32 ? (const void *)n->bwd32[l] : (const void *)n->bwd[l];
+    Act *gbuf[2] = {(Act *)(ws + tw.g0), (Act *)(ws + tw.g1)};
     float *part = (float *)(ws + tw.part);
     // layer 5 (index 4): dW from a4 and dY; input gradient -> dz4 = (W5^T * dY) . GELU'(z4)
-    wgrad<24, 3>(n, 4, a[3], dY, nb, n0, n1, n2, part, s);
-    conv<3, 24, MODE_ZERO, EPI_DGELU>(dY, nb, n0, n1, n2, n->bwd[4], nullptr, z[3], gbuf[0], nullptr, 0, 0, s);
-    const uint16_t *dz = gbuf[0];
+    wgrad<24, 3, F32>(n, 4, a[3], dY, nb, n0, n1, n2, part, s);
+    conv<3, 24, MODE_ZERO, EPI_DGELU, F32>(dY, nb, n0, n1, n2, wb[4], nullptr, z[3], gbuf[0], nullptr, 0, 0, s);
+    const Act *dz = gbuf[0];
     for (int l = 3; l >= 1; --l) {
-        wgrad<24, 24>(n, l, a[l - 1], dz, nb, n0, n1, n2, part, s);
-        uint16_t *dst = gbuf[(4 - l) % 2];
-        conv<24, 24, MODE_ZERO, EPI_DGELU>(dz, nb, n0, n1, n2, n->bwd[l], nullptr, z[l - 1], dst, nullptr, 0, 0, s);
+        wgrad<24, 24, F32>(n, l, a[l - 1], dz, nb, n0, n1, n2, part, s);
+        Act *dst = gbuf[(4 - l) % 2];
+        conv<24, 24, MODE_ZERO, EPI_DGELU, F32>(dz, nb, n0, n1, n2, wb[l], nullptr, z[l - 1], dst, nullptr, 0, 0, s);
         dz = dst;
     }
-    wgrad<1, 24>(n, 0, X, dz, nb, n0, n1, n2, part, s);
+    wgrad<1, 24, F32>(n, 0, X, dz, nb, n0, n1, n2, part, s);
     return hipGetLastError();
+}
+hipError_t net_backward(sal_net *n, const float *X, const void *dY, int64_t nb, int64_t n0, int64_t n1,
+                        int64_t n2, char *ws, const TrainWs &tw, hipStream_t s)
+{
+    return n->f32 ? net_backward_t<true>(n, X, dY, nb, n0, n1, n2, ws, tw, s)
+                  : net_backward_t<false>(n, X, dY, nb, n0, n1, n2, ws, tw, s);
+}
+
+// One Adam step on the accumulated gradient (which it clears), then the operand tables.
+hipError_t adam_step(sal_net *n, float lr, hipStream_t s)
+{
+    n->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f / (1.0f - std::pow(b1, (float)n->step)), c2 = 1.0f / (1.0f - std::pow(b2, (float)n->step));
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->npar + 255) / 256)), dim3(256), 0, s, n->p, n->gr, n->m, n->v,
+                       (int)n->npar, lr, b1, b2, 1e-8f, c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = prep_tables(n, s);
+    return e;
 }
 
 struct NetDev {
@@ -757,6 +908,11 @@ sal_status sal_net_create(int device, uint64_t seed, sal_net **out)
     n->device = device;
     n->step = 0;
     n->out_scale[0] = n->out_scale[1] = n->out_scale[2] = 1.f;
+    n->p = n->gr = n->m = n->v = nullptr;
+    for (int l = 0; l < NL; ++l) {
+        n->fwd[l] = n->bwd[l] = nullptr;
+        n->fwd32[l] = n->bwd32[l] = nullptr;
+    }
     int64_t o = 0;
     for (int l = 0; l < NL; ++l) {
         n->woff.push_back(o);
@@ -783,13 +939,14 @@ sal_status sal_net_create(int device, uint64_t seed, sal_net **out)
     if (e == hipSuccess) e = hipMemcpy(n->p, h.data(), sizeof(float) * o, hipMemcpyHostToDevice);
     for (int l = 0; l < NL && e == hipSuccess; ++l) {
         e = hipMalloc((void **)&n->fwd[l], 2 * (size_t)fwd_rows(l) * fwd_k(l));
-        n->bwd[l] = nullptr;
+        if (e == hipSuccess) e = hipMalloc((void **)&n->fwd32[l], 4 * (size_t)fwd_rows(l) * fwd_k(l));
         if (e == hipSuccess && l > 0) e = hipMalloc((void **)&n->bwd[l], 2 * (size_t)bwd_rows(l) * bwd_k(l));
+        if (e == hipSuccess && l > 0) e = hipMalloc((void **)&n->bwd32[l], 4 * (size_t)bwd_rows(l) * bwd_k(l));
     }
     if (e == hipSuccess) e = prep_tables(n, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        delete n;
+        sal_net_destroy(n);
         return nfail(nullptr, SAL_E_DEVICE, std::string("net create: ") + hipGetErrorString(e));
     }
     *out = n;
@@ -806,8 +963,19 @@ void sal_net_destroy(sal_net *n)
     for (int l = 0; l < NL; ++l) {
         if (n->fwd[l]) (void)hipFree(n->fwd[l]);
         if (n->bwd[l]) (void)hipFree(n->bwd[l]);
+        if (n->fwd32[l]) (void)hipFree(n->fwd32[l]);
+        if (n->bwd32[l]) (void)hipFree(n->bwd32[l]);
     }
     delete n;
+}
+
+sal_status sal_net_set_precision(sal_net *n, int32_t precision)
+{
+    if (!n) return nfail(n, SAL_E_INVAL, "null argument");
+    if (precision != SAL_BF16 && precision != SAL_FP32)
+        return nfail(n, SAL_E_INVAL, "the network runs in SAL_BF16 or SAL_FP32");
+    n->f32 = precision == SAL_FP32;
+    return SAL_OK;
 }
 
 sal_status sal_net_params(sal_net *n, float *host, int64_t count, int write)
@@ -849,7 +1017,7 @@ sal_status sal_net_workspace_size(sal_net *n, int64_t nb, int64_t n0, int64_t n1
 {
     if (!n || !bytes || nb < 1 || n0 < 2 || n1 < 2 || n2 < 2) return nfail(n, SAL_E_INVAL, "bad argument");
     const int64_t nv = nvox_of(nb, n0, n1, n2);
-    *bytes = train ? train_ws(nv).total : 2 * al(nv * 48);
+    *bytes = train ? train_ws(nv, act_bytes(n)).total : infer_ws(n, nv);
     return SAL_OK;
 }
 
@@ -867,7 +1035,7 @@ sal_status sal_net_forward(sal_net *n, const float *X, int64_t nb, int64_t n0, i
     if (!n || !X || !Y || !ws) return nfail(n, SAL_E_INVAL, "null argument");
     sal_status st = check_blocks(n, nb, n0, n1, n2);
     if (st != SAL_OK) return st;
-    const TrainWs tw = train_ws(nvox_of(nb, n0, n1, n2));
+    const TrainWs tw = train_ws(nvox_of(nb, n0, n1, n2), act_bytes(n));
     if (ws_bytes < tw.total) return nfail(n, SAL_E_WORKSPACE, "workspace too small");
     NetDev nd(n->device);
     hipError_t e = net_forward(n, X, nb, n0, n1, n2, (char *)ws, &tw, Y, 3, 1, make_float3(1.f, 1.f, 1.f),
@@ -882,14 +1050,27 @@ sal_status sal_net_backward(sal_net *n, const float *X, const float *dY, int64_t
     sal_status st = check_blocks(n, nb, n0, n1, n2);
     if (st != SAL_OK) return st;
     const int64_t nv = nvox_of(nb, n0, n1, n2);
-    const TrainWs tw = train_ws(nv);
+    const TrainWs tw = train_ws(nv, act_bytes(n));
     if (ws_bytes < tw.total) return nfail(n, SAL_E_WORKSPACE, "workspace too small");
     NetDev nd(n->device);
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
-    hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((nv * 3 + 255) / 256)), dim3(256), 0, s, dY, nv * 3,
-                       (uint16_t *)(w + tw.dy));
-    hipError_t e = net_backward(n, X, (const uint16_t *)(w + tw.dy), nb, n0, n1, n2, w, tw, s);
+    const void *dYa = dY;  // the FP32-operand mode reads the caller's FP32 gradient directly
+    if (!n->f32) {
+        hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((nv * 3 + 255) / 256)), dim3(256), 0, s, dY, nv * 3,
+                           (uint16_t *)(w + tw.dy));
+        dYa = w + tw.dy;
+    }
+    hipError_t e = net_backward(n, X, dYa, nb, n0, n1, n2, w, tw, s);
+    return e == hipSuccess ? SAL_OK : nfail(n, SAL_E_DEVICE, hipGetErrorString(e));
+}
+
+sal_status sal_net_adam(sal_net *n, float lr, void *stream)
+{
+    if (!n) return nfail(n, SAL_E_INVAL, "null argument");
+    if (!(lr >= 0.f)) return nfail(n, SAL_E_INVAL, "lr must be >= 0");
+    NetDev nd(n->device);
+    hipError_t e = adam_step(n, lr, (hipStream_t)stream);
     return e == hipSuccess ? SAL_OK : nfail(n, SAL_E_DEVICE, hipGetErrorString(e));
 }
 
@@ -898,10 +1079,11 @@ sal_status sal_net_train_step(sal_net *n, const float *X, const float *T, int64_
 {
     if (!n || !X || !T || !ws) return nfail(n, SAL_E_INVAL, "null argument");
     if (margin < NL || 2 * margin >= S) return nfail(n, SAL_E_INVAL, "margin must be >= 5 and < S/2");
+    if (!(lr >= 0.f)) return nfail(n, SAL_E_INVAL, "lr must be >= 0");
     sal_status st = check_blocks(n, nb, S, S, S);
     if (st != SAL_OK) return st;
     const int64_t nv = nvox_of(nb, S, S, S);
-    const TrainWs tw = train_ws(nv);
+    const TrainWs tw = train_ws(nv, act_bytes(n));
     if (ws_bytes < tw.total) return nfail(n, SAL_E_WORKSPACE, "workspace too small");
     NetDev nd(n->device);
     hipStream_t s = (hipStream_t)stream;
@@ -911,17 +1093,16 @@ sal_status sal_net_train_step(sal_net *n, const float *X, const float *T, int64_
     const int64_t inner = S - 2 * margin;
     const float inv = 1.0f / (float)(nb * inner * inner * inner * 3);
     const unsigned nblk = (unsigned)((nv + 255) / 256);
-    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, s, Y, T, (int)nb, (int)S, margin, inv,
-                       (uint16_t *)(w + tw.dy), (float *)(w + tw.lossp));
+    if (n->f32)
+        hipLaunchKernelGGL(k_mse<true>, dim3(nblk), dim3(256), 0, s, Y, T, (int)nb, (int)S, margin, inv,
+                           (float *)(w + tw.dy), (float *)(w + tw.lossp));
+    else
+        hipLaunchKernelGGL(k_mse<false>, dim3(nblk), dim3(256), 0, s, Y, T, (int)nb, (int)S, margin, inv,
+                           (uint16_t *)(w + tw.dy), (float *)(w + tw.lossp));
     if (loss_out)
         hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, (const float *)(w + tw.lossp), (int)nblk, loss_out);
-    if (e == hipSuccess) e = net_backward(n, X, (const uint16_t *)(w + tw.dy), nb, S, S, S, w, tw, s);
-    n->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f / (1.0f - std::pow(b1, (float)n->step)), c2 = 1.0f / (1.0f - std::pow(b2, (float)n->step));
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->npar + 255) / 256)), dim3(256), 0, s, n->p, n->gr, n->m, n->v,
-                       (int)n->npar, lr, b1, b2, 1e-8f, c1, c2);
-    if (e == hipSuccess) e = prep_tables(n, s);
+    if (e == hipSuccess) e = net_backward(n, X, w + tw.dy, nb, S, S, S, w, tw, s);
+    if (e == hipSuccess) e = adam_step(n, lr, s);
     if (e == hipSuccess) e = hipGetLastError();
     return e == hipSuccess ? SAL_OK : nfail(n, SAL_E_DEVICE, hipGetErrorString(e));
 }
@@ -935,7 +1116,7 @@ sal_status sal_net_infer(sal_net *n, const float *V, int64_t n0, int64_t n1, int
     sal_status st = check_blocks(n, 1, n0, n1, n2);
     if (st != SAL_OK) return st;
     const int64_t nv = nvox_of(1, n0, n1, n2);
-    if (ws_bytes < 2 * al(nv * 48)) return nfail(n, SAL_E_WORKSPACE, "workspace too small");
+    if (ws_bytes < infer_ws(n, nv)) return nfail(n, SAL_E_WORKSPACE, "workspace too small");
     NetDev nd(n->device);
     hipError_t e = net_forward(n, V, 1, n0, n1, n2, (char *)ws, nullptr, S_raw, 1, nv,
                                make_float3(n->out_scale[0], n->out_scale[1], n->out_scale[2]), (hipStream_t)stream);

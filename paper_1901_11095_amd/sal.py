@@ -32,11 +32,11 @@ EXPORTS = ("sal_default_params", "sal_create", "sal_destroy", "sal_last_error",
            "sal_workspace_size", "sal_local_spectra", "sal_project", "sal_directional_compare",
            "sal_saliency", "sal_profile_enable", "sal_profile_read", "sal_normalize_combine",
            "sal_tile_merge", "sal_tile_minmax", "sal_raw_box_workspace_size", "sal_raw_box",
-           "sal_check_tiles_workspace_size", "sal_check_tiles",
+           "sal_check_tiles_workspace_size", "sal_check_tiles", "sal_absmax",
            "sal_net_num_params", "sal_net_last_error", "sal_net_create",
            "sal_net_destroy", "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
            "sal_net_workspace_size", "sal_net_forward", "sal_net_backward", "sal_net_train_step",
-           "sal_net_infer")
+           "sal_net_infer", "sal_net_set_precision", "sal_net_adam")
 KERNELS = ("energy", "dcs", "stats", "combine")
 
 
@@ -98,6 +98,9 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     l.sal_check_tiles_workspace_size.argtypes = [vp, i64, i64, i64, i64, _i64p, ctypes.POINTER(sz)]
     l.sal_check_tiles.argtypes = [vp, vp, i64, i64, i64, i64, _i64p, vp, i64, i64, i64, _i64p, i64,
                                   _i64p, vp, ctypes.c_double, vp, vp, vp, sz, vp]
+    l.sal_absmax.argtypes = [vp, vp, i64, vp, ctypes.c_int, vp]
+    l.sal_net_set_precision.argtypes = [vp, ctypes.c_int32]
+    l.sal_net_adam.argtypes = [vp, ctypes.c_float, vp]
     l.sal_net_num_params.argtypes = []
     l.sal_net_num_params.restype = i64
     l.sal_net_last_error.argtypes = [vp]
@@ -119,7 +122,7 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
               "sal_directional_compare", "sal_saliency", "sal_profile_enable",
               "sal_profile_read", "sal_normalize_combine", "sal_tile_merge", "sal_tile_minmax",
               "sal_raw_box_workspace_size", "sal_raw_box", "sal_check_tiles_workspace_size",
-              "sal_check_tiles", "sal_net_create",
+              "sal_check_tiles", "sal_absmax", "sal_net_create", "sal_net_set_precision", "sal_net_adam",
               "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
               "sal_net_workspace_size", "sal_net_forward", "sal_net_backward",
               "sal_net_train_step", "sal_net_infer"):
@@ -362,6 +365,18 @@ def check_tiles(ctx: "Saliency", V: torch.Tensor, box_lo, S_raw: torch.Tensor, t
         _ptr(workspace), workspace.numel(), _stream(V.device)))
 
 
+def absmax(ctx: "Saliency", V: torch.Tensor, out: torch.Tensor, accumulate: bool = False) -> torch.Tensor:
+    """out[0] = max |V| (accumulate: max(out[0], max |V|)); V any contiguous float32 CUDA
+    tensor, out a CUDA float32 tensor of at least one element."""
+    if not (V.is_cuda and V.dtype == torch.float32 and V.is_contiguous()):
+        raise ValueError("V must be a contiguous float32 CUDA tensor")
+    if not (out.is_cuda and out.dtype == torch.float32 and out.numel() >= 1):
+        raise ValueError("out must be a float32 CUDA tensor")
+    ctx._raise(ctx._lib.sal_absmax(ctx._h, _ptr(V), V.numel(), _ptr(out), int(bool(accumulate)),
+                                   _stream(V.device)))
+    return out
+
+
 def tile_minmax(ctx: "Saliency", S_raw: torch.Tensor, tile: int,
                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Per-tile {min, max} of each raw map: float32 [ntiles, 6] on the device."""
@@ -407,6 +422,15 @@ class Net:
     def _raise(self, st):
         if st != SAL_OK:
             raise SalError(st, self._lib.sal_net_last_error(self._h).decode())
+
+    def set_precision(self, precision: int):
+        """FP32 (the FP32-operand mode of the same kernels) or BF16 (default)."""
+        self._raise(self._lib.sal_net_set_precision(self._h, int(precision)))
+        self._ws = None
+
+    def adam(self, lr: float):
+        """One Adam step on the accumulated gradient (cleared afterwards)."""
+        self._raise(self._lib.sal_net_adam(self._h, float(lr), _stream(self.device)))
 
     def get_params(self):
         import numpy as np

@@ -35,11 +35,12 @@ def _slabs(n0: int, slab: int, halo: int):
 
 def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
                       S_raw: Optional[torch.Tensor] = None, device="cuda",
-                      keep: Optional[torch.Tensor] = None):
+                      keep: Optional[torch.Tensor] = None, ctx: Optional[sal.Saliency] = None):
     """Raw maps [3, n0, n1, n2] (device) of a pinned host volume; `compute(Vslab)` returns
     the raw maps [3, m, n1, n2] of a device slab [m, n1, n2].  With `keep` (device
-    [n0, n1, n2]) the rows of every slab are also kept there as they pass.  Returns
-    (S_raw, max|V|)."""
+    [n0, n1, n2]) the rows of every slab are also kept there as they pass.  max|V| is
+    reduced slab by slab by the library (sal_absmax on `ctx`, or a plain FP32 context).
+    Returns (S_raw, max|V|)."""
     n0, n1, n2 = V_host.shape
     dev = torch.device(device)
     if S_raw is None:
@@ -51,7 +52,8 @@ def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
     done = [torch.cuda.Event(), torch.cuda.Event()]     # buffer free again
     ready = [torch.cuda.Event(), torch.cuda.Event()]    # buffer filled
     slabs = list(_slabs(n0, slab, halo))
-    vmax = torch.zeros(len(slabs), dtype=torch.float32, device=dev)
+    vmax = torch.zeros(1, dtype=torch.float32, device=dev)
+    red = ctx if ctx is not None else sal.Saliency(L=8, device=dev.index or 0)
 
     def upload(i):
         _, _, a, b = slabs[i]
@@ -73,9 +75,9 @@ def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
         S_raw[:, s0:s1].copy_(out[:, s0 - a:s1 - a])
         if keep is not None:
             keep[s0:s1].copy_(Vs[s0 - a:s1 - a])
-        vmax[i] = Vs[s0 - a:s1 - a].abs().max()
+        sal.absmax(red, Vs[s0 - a:s1 - a], vmax, accumulate=i > 0)
         done[k].record(comp)
-    return S_raw, float(vmax.max())
+    return S_raw, float(vmax.item())
 
 
 def plain_streamed(ctx: sal.Saliency, V_host: torch.Tensor, slab: int = 64):
@@ -87,7 +89,7 @@ def plain_streamed(ctx: sal.Saliency, V_host: torch.Tensor, slab: int = 64):
         ctx.saliency(Vs, S_raw_out=o)
         return o
 
-    S_raw, vmax = raw_maps_streamed(V_host, compute, halo, slab)
+    S_raw, vmax = raw_maps_streamed(V_host, compute, halo, slab, ctx=ctx)
     stats = torch.zeros(8, dtype=torch.float64, device=S_raw.device)
     S = sal.normalize_combine(ctx, S_raw, None, stats_out=stats, vmax=vmax)
     return S, S_raw, stats
@@ -125,7 +127,7 @@ def surrogate_streamed(net: sal.Net, ctx_fallback: sal.Saliency, V_host: torch.T
     the rows holding checked tiles are streamed again (halo floor(L/2) + r)."""
     dev = torch.device("cuda")
     keep = torch.empty(tuple(V_host.shape), dtype=torch.float32, device=dev) if keep_volume else None
-    S_raw, vmax = raw_maps_streamed(V_host, net.infer, 5, slab, keep=keep)
+    S_raw, vmax = raw_maps_streamed(V_host, net.infer, 5, slab, keep=keep, ctx=ctx_fallback)
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
     S = sal.normalize_combine(ctx_fallback, S_raw, None, stats_out=stats, vmax=vmax)
     n_all = len(surrogate.tiles_of(tuple(V_host.shape), tile))

@@ -29,7 +29,7 @@ def test_plain_streamed_equals_resident(L, shape, slab):
     S2, Sr2, st2 = stream.plain_streamed(ctx, stream.pinned(V), slab=slab)
     torch.cuda.synchronize()
     assert torch.equal(Sr2, Sr)
-    assert torch.equal(st2[:6], st[:6])
+    assert torch.equal(st2[:7], st[:7])   # max|V| reduced slab by slab by sal_absmax
     assert torch.equal(S2, S)
 
 

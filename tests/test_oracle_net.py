@@ -95,3 +95,46 @@ def test_net_gradient_finite_difference(oracle_mod):
         pm[i] -= h
         fd = (f(pp) - f(pm)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_round_bf16_matches_library(oracle_mod):
+    """BF16 rounding of the oracle against torch's float32 -> bfloat16 conversion (round to
+    nearest, ties to even) over magnitudes from 1e-9 to 1e9, plus exact ties."""
+    import torch
+    rng = np.random.default_rng(4)
+    x = (rng.standard_normal(20000) * np.exp(rng.uniform(-20, 20, 20000))).astype(np.float32)
+    # exact ties: halfway between two BF16 neighbours with an even and an odd lower neighbour
+    ties = np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(2.0 + 2.0 ** -7), 3.0 + 2.0 ** -7],
+                    np.float32)
+    x = np.concatenate([x, ties, np.array([0.0, -0.0], np.float32)])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([oracle_mod.round_bf16(float(v)) for v in x])
+    assert np.array_equal(got, ref)
+    assert oracle_mod.round_bf16(1.0 + 2.0 ** -8) == 1.0          # tie to the even neighbour
+    assert oracle_mod.round_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+
+
+def test_net_bf16_exact_on_representable_single_layer(oracle_mod):
+    """One layer (no activation) whose input and weights are BF16 values: the BF16 network
+    rounds nothing, so it equals the FP64 network exactly."""
+    rng = np.random.default_rng(5)
+    ch = (2, 3)
+    r = np.vectorize(oracle_mod.round_bf16)
+    p = _small_net(rng, ch)
+    p[:3 * 27 * 2] = r(p[:3 * 27 * 2])
+    x = r(rng.standard_normal((1, 5, 5, 5, 2)))
+    assert np.array_equal(oracle_mod.net_forward_bf16(x, p, ch), oracle_mod.net_forward(x, p, ch))
+
+
+def test_net_bf16_within_rounding_bound(oracle_mod):
+    """The BF16 network differs from the FP64 one by the BF16 roundings only: relative to the
+    output scale, a few units of 2^-9 per layer (here at most 4 layers of rounded values), and
+    it is not the FP64 network (the roundings are really applied)."""
+    rng = np.random.default_rng(6)
+    ch = (1, 4, 4, 3)
+    p = _small_net(rng, ch)
+    x = rng.standard_normal((2, 6, 6, 6, 1))
+    y = oracle_mod.net_forward(x, p, ch)
+    yb = oracle_mod.net_forward_bf16(x, p, ch)
+    rel = np.abs(yb - y).max() / np.abs(y).max()
+    assert 0 < rel <= 4 * 3 * 2.0 ** -9, rel
