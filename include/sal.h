@@ -171,6 +171,23 @@ sal_status sal_saliency(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, in
                         void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sal_saliency without a workspace.  The
+ * energies and raw maps are required outputs (E_out, S_raw_out, DEVICE float
+ * [3][n0][n1][n2]); the per-block partial reductions and, when stats_out is NULL, the
+ * statistics go to a 16 MiB device scratch array that the library holds on each GPU for the
+ * life of the process.  Nothing is allocated or freed.  Every call on one GPU shares that
+ * GPU's scratch and leaves its last contents there: calls that overlap on one GPU (several
+ * streams, threads or contexts) race and must be serialised by the caller.  Stride 1 only.
+ * Results equal those of sal_saliency bit for bit.  Errors: SAL_E_INVAL (null or misaligned
+ * pointers, bad dimensions, a volume whose partials need more than the 16 MiB scratch),
+ * SAL_E_UNSUPPORTED (stride > 1), SAL_E_DEVICE.
+ */
+sal_status sal_saliency_noalloc(sal_ctx *ctx, const float *V, int64_t n0, int64_t n1, int64_t n2,
+                                float *S, float *E_out, float *S_raw_out, double *stats_out,
+                                void *stream);
+
+/*
  * Per-kernel timing of sal_saliency.  While enabled (on != 0), every sal_saliency call
  * records HIP events on its stream around each of its kernels: [0] the fused steps 1-3
  * kernel, [1] the comparison of Eq. (5), [2] the FP64 statistics, [3] the FP64

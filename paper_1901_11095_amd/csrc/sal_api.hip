@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -358,6 +359,34 @@ sal_status sticky(sal_ctx *c)
 
 }  // namespace
 
+// Device scratch of sal_saliency_noalloc (per-block partials and statistics), one copy per
+// GPU for the life of the process.  Host code never uses this name as an address: the
+// device address of each GPU's copy is looked up once per device (with that device current)
+// and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[SAL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch;  // device address of `scratch` per device, NULL until looked up
+
+// With `dev` current: the address of this device's scratch (looked up on first use).
+hipError_t scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 void sal_default_params(sal_params *p, int32_t L)
@@ -428,6 +457,11 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
         free_tables(&c->t);
         delete c;
         return fail(nullptr, SAL_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    }
+    if ((e = scratch_address(device, &c->scratch)) != hipSuccess) {
+        free_tables(&c->t);
+        delete c;
+        return fail(nullptr, SAL_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
     }
     *out = c;
     return SAL_OK;
@@ -510,6 +544,41 @@ sal_status sal_directional_compare(sal_ctx *c, const float *E, int64_t n0, int64
     return SAL_OK;
 }
 
+// The launch sequence of the whole method (steps 1-5) on caller-placed buffers: E and Sr
+// the maps, vmax and mm the per-block partials of the energy and comparison kernels, stats
+// the FP64 statistics, El the lattice energies (stride > 1); ev (optional) five events.
+static sal_status run_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, float *S, float *E,
+                               float *Sr, float *vmax, float *mm, double *stats, float *El, hipStream_t s,
+                               hipEvent_t *ev)
+{
+    const int64_t N = n0 * n1 * n2;
+    int nv = 0;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipError_t e;
+    if (c->p.stride > 1) {
+        // windows on the lattice, energies interpolated onto every voxel
+        int64_t K[3];
+        lattice_dims(c, n0, n1, n2, K);
+        e = launch_energy(c, V, n0, n1, n2, nullptr, El, vmax, &nv, s);
+        if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+        e = launch_upsample(El, K[0], K[1], K[2], c->p.stride, n0, n1, n2, E, s);
+    } else {
+        e = launch_energy(c, V, n0, n1, n2, nullptr, E, vmax, &nv, s);
+    }
+    if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    if (ev) (void)hipEventRecord(ev[1], s);
+    e = launch_dcs(c, E, n0, n1, n2, Sr, mm, s);
+    if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
+    if (ev) (void)hipEventRecord(ev[2], s);
+    e = launch_stats(vmax, nv, mm, dcs_num_blocks(c, n0, n1, n2), stats, s);
+    if (e != hipSuccess) return dev_fail(c, e, "stats launch");
+    if (ev) (void)hipEventRecord(ev[3], s);
+    e = launch_combine(Sr, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);
+    if (e != hipSuccess) return dev_fail(c, e, "combine launch");
+    if (ev) (void)hipEventRecord(ev[4], s);
+    return SAL_OK;
+}
+
 sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, float *S,
                         float *E_out, float *S_raw_out, double *stats_out, void *workspace,
                         size_t ws_bytes, void *stream)
@@ -529,38 +598,35 @@ sal_status sal_saliency(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int6
     char *ws = (char *)workspace;
     float *E = E_out ? E_out : (float *)(ws + w.e);
     float *Sr = S_raw_out ? S_raw_out : (float *)(ws + w.s_raw);
-    float *vmax = (float *)(ws + w.vmax);
-    float *mm = (float *)(ws + w.mm);
     double *stats = stats_out ? stats_out : (double *)(ws + w.stats);
-    const int64_t N = n0 * n1 * n2;
-    hipStream_t s = (hipStream_t)stream;
-    hipEvent_t *ev = take_events(c);
-    int nv = 0;
-    if (ev) (void)hipEventRecord(ev[0], s);
-    hipError_t e;
-    if (c->p.stride > 1) {
-        // windows on the lattice, energies interpolated onto every voxel
-        int64_t K[3];
-        lattice_dims(c, n0, n1, n2, K);
-        float *El = (float *)(ws + w.e_lat);
-        e = launch_energy(c, V, n0, n1, n2, nullptr, El, vmax, &nv, s);
-        if (e != hipSuccess) return dev_fail(c, e, "energy launch");
-        e = launch_upsample(El, K[0], K[1], K[2], c->p.stride, n0, n1, n2, E, s);
-    } else {
-        e = launch_energy(c, V, n0, n1, n2, nullptr, E, vmax, &nv, s);
-    }
-    if (e != hipSuccess) return dev_fail(c, e, "energy launch");
-    if (ev) (void)hipEventRecord(ev[1], s);
-    e = launch_dcs(c, E, n0, n1, n2, Sr, mm, s);
-    if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
-    if (ev) (void)hipEventRecord(ev[2], s);
-    e = launch_stats(vmax, nv, mm, dcs_num_blocks(c, n0, n1, n2), stats, s);
-    if (e != hipSuccess) return dev_fail(c, e, "stats launch");
-    if (ev) (void)hipEventRecord(ev[3], s);
-    e = launch_combine(Sr, N, stats, c->p.a, c->p.b, c->p.c, c->p.normalize, c->p.zero_range, S, s);
-    if (e != hipSuccess) return dev_fail(c, e, "combine launch");
-    if (ev) (void)hipEventRecord(ev[4], s);
-    return SAL_OK;
+    return run_saliency(c, V, n0, n1, n2, S, E, Sr, (float *)(ws + w.vmax), (float *)(ws + w.mm), stats,
+                        (float *)(ws + w.e_lat), (hipStream_t)stream, take_events(c));
+}
+
+sal_status sal_saliency_noalloc(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, float *S,
+                                float *E_out, float *S_raw_out, double *stats_out, void *stream)
+{
+    if (!c) return fail(c, SAL_E_INVAL, "null context");
+    if (!V || !S || !E_out || !S_raw_out) return fail(c, SAL_E_INVAL, "null pointer (V, S, E_out and S_raw_out are required)");
+    if (!aligned16(V) || !aligned16(S) || !aligned16(E_out) || !aligned16(S_raw_out) ||
+        (stats_out && !aligned16(stats_out)))
+        return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
+    if (c->p.stride != 1) return fail(c, SAL_E_UNSUPPORTED, "sal_saliency_noalloc computes stride 1 only");
+    sal_status st = check_dims(c, n0, n1, n2);
+    if (st != SAL_OK) return st;
+    // the per-block partials and the statistics live in the library's device scratch
+    const size_t o_mm = align256((size_t)energy_num_blocks(c, n0, n1, n2) * sizeof(float));
+    const size_t o_st = o_mm + align256((size_t)dcs_num_blocks(c, n0, n1, n2) * 6 * sizeof(float));
+    const size_t need = o_st + align256(8 * sizeof(double));
+    if (need > SAL_NOALLOC_SCRATCH_BYTES)
+        return fail(c, SAL_E_INVAL, "volume needs " + std::to_string(need) + " bytes of scratch; the limit is " +
+                                        std::to_string((size_t)SAL_NOALLOC_SCRATCH_BYTES));
+    DevScope ds(c->device);
+    if ((st = sticky(c)) != SAL_OK) return st;
+    char *ws = (char *)c->scratch;
+    double *stats = stats_out ? stats_out : (double *)(ws + o_st);
+    return run_saliency(c, V, n0, n1, n2, S, E_out, S_raw_out, (float *)ws, (float *)(ws + o_mm), stats, nullptr,
+                        (hipStream_t)stream, nullptr);
 }
 
 // The box grown by r along every axis, clipped to the volume: E of these positions holds

@@ -51,7 +51,11 @@ struct sal_ctx {
     int *tab_host = nullptr;
     size_t tab_cap = 0;
     hipEvent_t tab_done = nullptr;
+    void *scratch = nullptr;  // device address of this device's sal_saliency_noalloc scratch
 };
+
+// Bytes of the device scratch of sal_saliency_noalloc (one static array per GPU).
+#define SAL_NOALLOC_SCRATCH_BYTES (16u << 20)
 
 // Arguments of the directional comparison kernel.
 struct dcs_args {

@@ -32,7 +32,7 @@ EXPORTS = ("sal_default_params", "sal_create", "sal_destroy", "sal_last_error",
            "sal_workspace_size", "sal_local_spectra", "sal_project", "sal_directional_compare",
            "sal_saliency", "sal_profile_enable", "sal_profile_read", "sal_normalize_combine",
            "sal_tile_merge", "sal_tile_minmax", "sal_raw_box_workspace_size", "sal_raw_box",
-           "sal_check_tiles_workspace_size", "sal_check_tiles", "sal_absmax",
+           "sal_check_tiles_workspace_size", "sal_check_tiles", "sal_absmax", "sal_saliency_noalloc",
            "sal_net_num_params", "sal_net_last_error", "sal_net_create",
            "sal_net_destroy", "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
            "sal_net_workspace_size", "sal_net_forward", "sal_net_backward", "sal_net_train_step",
@@ -99,6 +99,7 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
     l.sal_check_tiles.argtypes = [vp, vp, i64, i64, i64, i64, _i64p, vp, i64, i64, i64, _i64p, i64,
                                   _i64p, vp, ctypes.c_double, vp, vp, vp, sz, vp]
     l.sal_absmax.argtypes = [vp, vp, i64, vp, ctypes.c_int, vp]
+    l.sal_saliency_noalloc.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp, vp, vp]
     l.sal_net_set_precision.argtypes = [vp, ctypes.c_int32]
     l.sal_net_adam.argtypes = [vp, ctypes.c_float, vp]
     l.sal_net_num_params.argtypes = []
@@ -122,7 +123,7 @@ def load(path: str = _LIB_PATH) -> ctypes.CDLL:
               "sal_directional_compare", "sal_saliency", "sal_profile_enable",
               "sal_profile_read", "sal_normalize_combine", "sal_tile_merge", "sal_tile_minmax",
               "sal_raw_box_workspace_size", "sal_raw_box", "sal_check_tiles_workspace_size",
-              "sal_check_tiles", "sal_absmax", "sal_net_create", "sal_net_set_precision", "sal_net_adam",
+              "sal_check_tiles", "sal_absmax", "sal_saliency_noalloc", "sal_net_create", "sal_net_set_precision", "sal_net_adam",
               "sal_net_params", "sal_net_grads", "sal_net_set_output_scale",
               "sal_net_workspace_size", "sal_net_forward", "sal_net_backward",
               "sal_net_train_step", "sal_net_infer"):
@@ -254,6 +255,18 @@ class Saliency:
         self._raise(self._lib.sal_saliency(self._h, _ptr(V), *V.shape, _ptr(S), _ptr(E_out),
                                            _ptr(S_raw_out), _ptr(stats_out), _ptr(ws),
                                            ws.numel() * ws.element_size(), _stream(V.device)))
+        return S
+
+    def saliency_noalloc(self, V: torch.Tensor, S: torch.Tensor, E_out: torch.Tensor,
+                         S_raw_out: torch.Tensor, stats_out: Optional[torch.Tensor] = None):
+        """sal_saliency_noalloc: the library allocates nothing; S [n0, n1, n2] and E_out,
+        S_raw_out [3, n0, n1, n2] are caller buffers, the partials use the library's scratch."""
+        _check_vol(V)
+        for t, shp in ((S, V.shape), (E_out, (3,) + tuple(V.shape)), (S_raw_out, (3,) + tuple(V.shape))):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == tuple(shp)):
+                raise ValueError("output buffers must be contiguous float32 CUDA tensors of the volume's shape")
+        self._raise(self._lib.sal_saliency_noalloc(self._h, _ptr(V), *V.shape, _ptr(S), _ptr(E_out),
+                                                   _ptr(S_raw_out), _ptr(stats_out), _stream(V.device)))
         return S
 
     def raw_box(self, V: torch.Tensor, box_lo, box_dims, out: Optional[torch.Tensor] = None,
