@@ -3,13 +3,17 @@
 
 One step = one sal_saliency pass (local 3D DFT spectra -> plane projections -> spectral
 energies -> directional comparisons -> FP64 normalisation and combination) over the
-256 x 512 x 512 synthetic survey volume with an 8^3 cube, FP32 contractions.  Prints one
-JSON line (see the "metric" field).  Inputs are resident in HBM before timing starts.
+512 x 1024 x 1024 synthetic survey volume (2 GiB, six faults, two chaotic bodies, 5 dB)
+with a 16^3 cube, FP32 contractions.  On the same volume the split-BF16 form and the
+learned surrogate (with its tile checks and exact fallback) are timed too, each with its
+error against the FP32 map and the oracle.  Prints one JSON line (see the "metric" field).
+Inputs are resident in HBM before timing starts.
 
 Per-kernel durations come from HIP events the library records around each of its kernels
-on the launch stream; the roofline of the dominant kernel (the fused steps 1-3 kernel) is
-its algorithmic flop count (separable DFT contraction per voxel: 4hL + 8hL^2 + 8hL^3 with
-h = L/2 + 1) over its measured average duration, against the FP32 MFMA peak.
+on the launch stream; the roofline of a fused kernel is its algorithmic flop count (the
+separable DFT contraction per voxel with the first two axes shared between windows and the
+Hermitian half along t: 4hL + 8hL^2 + 8hL^3 with h = L/2 + 1) over its measured average
+duration, against the matrix-core peak of its operand type.
 """
 from __future__ import annotations
 
@@ -33,8 +37,23 @@ def dft_flops_per_voxel(L: int) -> int:
     return 4 * h * L + 8 * h * L * L + 8 * h * L ** 3
 
 
+def dft_flops_per_voxel_min(L: int) -> int:
+    """The same contraction with real rows at real cost and conjugate rows skipped: stage A
+    real input (rows mu = 0, L/2 with real twiddles); stage B keeps nu <= L/2 for mu = 0, L/2
+    (real input); stage C computes omega <= L/2 only for the four real rows.  This is the
+    least work any separable form of the definition does."""
+    h = L // 2 + 1
+    a = 4 * L * (h - 1)
+    b = 4 * L * L + 8 * L * L * (h - 2)
+    c = 8 * L * L + 8 * L * L * (L - 2) + 8 * L ** 3 * (h - 2)
+    return a + b + c
+
+
 # sources that define the FP32 fused kernel (its code, device helpers and launch set-up)
 ENERGY_F32_SOURCES = ("sal_kernels.hip", "sal_device.h", "sal_internal.h")
+ENERGY_H_SOURCES = ("sal_energy16.hip", "sal_device.h", "sal_internal.h")
+CONV_SOURCES = ("sal_net.hip", "sal_device.h", "sal_internal.h")
+SURROGATE_FLOPS = 2 * 47952  # multiply-adds of the five convolutions per voxel
 
 
 def kernel_source_hash(files=ENERGY_F32_SOURCES) -> str:
@@ -46,7 +65,7 @@ def kernel_source_hash(files=ENERGY_F32_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def counters_from_profiles(kernel_tag: str):
+def counters_from_profiles(kernel_tag: str, files=ENERGY_F32_SOURCES):
     """The committed rocprofv3 counter summary of the kernel (HBM bytes per launch scaled by
     a copy-kernel calibration, MFMA busy fraction), if it was taken on the current kernel
     sources; else None."""
@@ -55,28 +74,70 @@ def counters_from_profiles(kernel_tag: str):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != kernel_source_hash():
+    if rec.get("source_hash") != kernel_source_hash(files):
         return None
     return rec
 
 
-def cpu_baseline(V, L: int, sample_shape=(160, 192, 192)):
-    """The FP64 oracle (unmodified) on a bounded sub-block of the same volume: energies on
-    the block plus the comparison halo, Eq. (5) and the normalised combination."""
+def roofline_block(kernel: str, ms: float, nvox: int, flops_per_voxel: int, peak_key: str, tag: str,
+                   files, min_flops_per_voxel=None):
+    """Roofline of one kernel: algorithmic flops per launch over the measured launch time."""
+    achieved = flops_per_voxel * nvox / (ms * 1e-3) / 1e12
+    prof = counters_from_profiles(tag, files) or {}
+    rec = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[peak_key], "unit": "TFLOP/s",
+           "frac": achieved / PEAK_TFLOPS[peak_key], "traffic": prof.get("bytes_per_launch"),
+           "kernel": kernel, "kernel_ms": ms, "flops_per_voxel": flops_per_voxel,
+           "mfma_busy": prof.get("mfma_busy"), "counters": "profiles/traffic_%s.json" % tag if prof else None}
+    if min_flops_per_voxel:
+        rec["flops_per_voxel_min"] = min_flops_per_voxel
+        rec["frac_min"] = rec["frac"] * min_flops_per_voxel / flops_per_voxel
+    if prof.get("algorithmic_bytes_per_launch"):
+        rec["algorithmic_bytes"] = prof["algorithmic_bytes_per_launch"]
+    return rec
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(V, L: int, shape_all=(64, 96, 96), shape_one=(24, 32, 48)):
+    """The FP64 oracle (unmodified) on centred crops of the same volume, each computed as a
+    volume of its own (every voxel's window DFT, projections, Eq. (5), Eq. (6)): the same
+    per-voxel work as the GPU step.  Once with every OpenMP thread, once with one."""
+    import ctypes
     import numpy as np
     import oracle as O
-    p = O.Params(L=L)
-    lo = tuple((n - s) // 2 for n, s in zip(V.shape, sample_shape))
-    t0 = time.perf_counter()
-    E, Sr = O.raw_box(V, p, lo, sample_shape)
-    S, _ = O.combine(Sr, vmax=float(np.abs(V).max()))
-    dt = time.perf_counter() - t0
-    nvox = int(np.prod(sample_shape))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nvox / dt, "unit": "voxels/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 oracle, %dx%dx%d sub-block at %s of the same volume (energies on "
-                      "the block plus an r-voxel halo, Eq. (5), normalised Eq. (6)); %.1f s"
-                      % (sample_shape + (lo, dt))}
+    O.lib()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    nmax = int(gomp.omp_get_max_threads())
+
+    def run(shape, threads):
+        gomp.omp_set_num_threads(int(threads))
+        lo = tuple((n - s) // 2 for n, s in zip(V.shape, shape))
+        crop = np.ascontiguousarray(V[lo[0]:lo[0] + shape[0], lo[1]:lo[1] + shape[1], lo[2]:lo[2] + shape[2]])
+        t0 = time.perf_counter()
+        O.saliency(crop, O.Params(L=L))
+        dt = time.perf_counter() - t0
+        return crop.size / dt, dt, lo
+
+    try:
+        v_all, dt_all, lo_all = run(shape_all, nmax)
+        v_one, dt_one, lo_one = run(shape_one, 1)
+    finally:
+        gomp.omp_set_num_threads(nmax)
+    return {"value": v_all, "unit": "voxels/s", "cores": nmax, "kind": "oracle",
+            "value_1_thread": v_one, "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": "FP64 oracle, the whole method at cube %d on a %dx%dx%d crop at %s of the "
+                      "same volume (%.1f s, %d threads) and on a %dx%dx%d crop at %s (%.1f s, 1 "
+                      "thread), each crop computed as a volume" % ((L,) + tuple(shape_all) + (lo_all, dt_all, nmax)
+                                                                    + tuple(shape_one) + (lo_one, dt_one))}
 
 
 def parity_sample(V, S, E, Sr, stats, L: int, seed: int = 7, b: int = 24, keep=None):
@@ -134,6 +195,81 @@ def sampled_error(ctx, V, Vg, L, seed=7, b=24):
     err = parity_sample(V, S, E, Sr, st, L, seed=seed, b=b)
     del E, Sr
     return err
+
+
+def surrogate_same_volume(V, Vg, S_ref, Sr_ref, st_ref, ms_fp32, ms_split, steps, warmup):
+    """The learned surrogate on the headline volume (resident): inference, the seeded 2 %
+    tile check, the check of the 5 % of tiles with the highest predicted saliency and of the
+    tiles holding each map's extremes, split-BF16 fallback on tiles over the bound, exact
+    FP64 normalisation.  Errors against the plain FP32 map everywhere, split by checked and
+    unchecked tiles (the bound holds on checked tiles by construction; unchecked tiles are
+    not verified)."""
+    import numpy as np
+    import torch
+    from paper_1901_11095_amd import sal, surrogate
+    dev = Vg.device
+    N = Vg.numel()
+    net = surrogate.load()
+    ctx_fb = sal.Saliency(L=16, precision=sal.BF16_SPLIT)
+    S_raw = torch.empty((3,) + tuple(Vg.shape), dtype=torch.float32, device=dev)
+    for _ in range(max(1, warmup)):
+        res = surrogate.infer_with_fallback(net, ctx_fb, Vg, S_raw=S_raw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = surrogate.infer_with_fallback(net, ctx_fb, Vg, S_raw=S_raw)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / steps
+    # the network alone (five convolution launches on the current stream)
+    pred = torch.empty_like(S_raw)
+    net.infer(Vg, out=pred)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(3):
+        net.infer(Vg, out=pred)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_net = ev[0].elapsed_time(ev[1]) / 3
+    # errors against the plain FP32 GPU map, per 32^3 tile
+    t = 32
+    n0, n1, n2 = Vg.shape
+    rng = (st_ref[1:6:2] - st_ref[0:6:2]).float().reshape(3, 1, 1, 1)
+
+    def tile_max(x):
+        return x.reshape(n0 // t, t, n1 // t, t, n2 // t, t).amax(dim=(1, 3, 5)).flatten()
+    raw_pre = tile_max(((pred - Sr_ref).abs() / rng).amax(0))
+    raw_post = tile_max(((res["S_raw"] - Sr_ref).abs() / rng).amax(0))
+    dS = (res["S"] - S_ref).abs()
+    dS_tile = tile_max(dS)
+    nt1, nt2 = n1 // t, n2 // t
+    checked = torch.zeros(dS_tile.numel(), dtype=torch.bool, device=dev)
+    idx = [(lo[0] // t * nt1 + lo[1] // t) * nt2 + lo[2] // t for lo, _ in res["tiles"]]
+    checked[torch.tensor(idx, dtype=torch.long, device=dev)] = True
+    S_pre = sal.normalize_combine(ctx_fb, pred, Vg)
+    dS_pre = (S_pre - S_ref).abs()
+    unchecked = ~checked
+    out = {
+        "voxels_per_s": N / t_sur, "ms": 1e3 * t_sur, "speedup_vs_plain_fp32": ms_fp32 / (1e3 * t_sur),
+        "speedup_vs_plain_bf16_split": ms_split / (1e3 * t_sur), "tile": t, "bound": 0.02,
+        "bound_scope": "raw maps within 2% of each map's range on every checked tile (exact "
+                       "replacement); unchecked tiles are not verified",
+        "checked_tiles": int(checked.sum()), "n_tiles": int(checked.numel()),
+        "checked_over_bound_replaced": int((res["tile_err"] > 0.02).sum()),
+        "tiles_within_bound_vs_plain_fp32": {"before_fallback": float((raw_pre <= 0.02).float().mean()),
+                                             "after_fallback": float((raw_post <= 0.02).float().mean()),
+                                             "unchecked_over_bound": int(((raw_post > 0.02) & unchecked).sum())},
+        "S_abs_err_vs_plain_fp32": {"max": float(dS.max()), "mean": float(dS.mean()),
+                                    "max_on_checked_tiles": float(dS_tile[checked].max()),
+                                    "max_on_unchecked_tiles": float(dS_tile[unchecked].max()),
+                                    "max_before_fallback": float(dS_pre.max()),
+                                    "mean_before_fallback": float(dS_pre.mean())},
+        "net_inference_ms": t_net,
+        "roofline": roofline_block("k_conv3 x 5 (network inference, sum of the five launches)", t_net, N,
+                                   SURROGATE_FLOPS, "bf16", "conv3_survey512x1024x1024", CONV_SOURCES),
+    }
+    out["roofline"]["bound"] = "mfma"
+    del res, pred, S_raw, dS, S_pre, dS_pre
+    return out
 
 
 def surrogate_leg(args, dev):
@@ -305,7 +441,7 @@ def precision_table(dev):
             "maps": table}
 
 
-def stream_leg(args, dev):
+def stream_leg(args, dev, V=None):
     """The 512 x 1024 x 1024 survey (2 GiB, cube 16) from pinned host memory: the surrogate
     streamed through HBM in t-slabs with split-BF16 fallback tiles, against the plain method
     resident and streamed; errors against the plain FP32 GPU map and the oracle."""
@@ -313,8 +449,9 @@ def stream_leg(args, dev):
     import torch
     from paper_1901_11095_amd import sal, stream, surrogate, synth
     name = "survey512x1024x1024"
-    print("# stream: generating %s" % name, file=sys.stderr, flush=True)
-    V = synth.workload(name)
+    if V is None:
+        print("# stream: generating %s" % name, file=sys.stderr, flush=True)
+        V = synth.workload(name)
     N = V.size
     Vh = stream.pinned(V)
     net = surrogate.load()
@@ -400,18 +537,68 @@ def stream_leg(args, dev):
     }
 
 
+def survey_L8_leg(args, dev):
+    """The 256 x 512 x 512 survey volume at cube 8 (FP32 and every 16-bit form, the paper's
+    5^3 cube, stride-2 windows): the smaller survey configuration."""
+    import torch
+    from paper_1901_11095_amd import sal, synth
+    name, L = "survey256x512x512", 8
+    print("# %s: generating" % name, file=sys.stderr, flush=True)
+    V = synth.workload(name)
+    N = V.size
+    Vg = torch.from_numpy(V).to(dev)
+    ctx = sal.Saliency(L=L)
+    steps = max(3, args.steps // 2)
+    ms, km = time_form(ctx, Vg, steps, 2)
+    fpv = dft_flops_per_voxel(L)
+    out = {"workload": name, "shape": list(V.shape), "L": L, "voxels_per_s": N / (ms * 1e-3),
+           "ms_per_step": ms, "kernels_ms": km,
+           "roofline": roofline_block("k_energy_f32<%d>" % L, km["energy"], N, fpv, "f32",
+                                      "energy_f32_L%d_%s" % (L, name), ENERGY_F32_SOURCES,
+                                      dft_flops_per_voxel_min(L)),
+           "max_rel_err_vs_oracle": None if args.no_check else sampled_error(ctx, V, Vg, L)}
+    forms = {}
+    if not args.no_forms:
+        for prec in (sal.BF16_SPLIT, sal.FP16_SPLITW, sal.FP16_SPLIT, sal.BF16, sal.FP16):
+            pname = sal.PRECISION_NAMES[prec]
+            print("# %s: form %s" % (name, pname), file=sys.stderr, flush=True)
+            c = sal.Saliency(L=L, precision=prec)
+            ms_f, kmf = time_form(c, Vg, max(3, args.steps // 4), 2)
+            forms[pname] = {
+                "voxels_per_s": N / (ms_f * 1e-3), "ms_per_step": ms_f, "speedup_vs_fp32": ms / ms_f,
+                "kernels_ms": kmf,
+                "roofline": roofline_block("k_energy_h<%d>" % L, kmf["energy"], N, fpv,
+                                           "bf16" if "bf16" in pname else "f16",
+                                           "energy_h_%s_L%d_%s" % (pname, L, name), ENERGY_H_SOURCES,
+                                           dft_flops_per_voxel_min(L)),
+                "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, L)}
+            del c
+        print("# %s: paper cube 5^3" % name, file=sys.stderr, flush=True)
+        forms["fp32_paper_cube_L5"] = small_cube_leg(args, V, Vg, 5)
+        print("# %s: stride-2 windows" % name, file=sys.stderr, flush=True)
+        args_l8 = argparse.Namespace(**vars(args))
+        args_l8.L = L
+        forms["stride2"] = strided_leg(args_l8, V, Vg)
+    out["forms"] = forms
+    del Vg, ctx
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="survey256x512x512")
-    ap.add_argument("--L", type=int, default=8)
+    ap.add_argument("--workload", default="survey512x1024x1024")
+    ap.add_argument("--L", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle checks")
     ap.add_argument("--no-forms", action="store_true", help="only the FP32 form")
-    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned surrogate leg")
-    ap.add_argument("--sur-n", type=int, default=512, help="side of the surrogate's volume")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned surrogate legs")
+    ap.add_argument("--no-l8", action="store_true", help="skip the 256x512x512 cube-8 leg")
+    ap.add_argument("--no-vol512", action="store_true", help="skip the held-out 512^3 surrogate leg")
+    ap.add_argument("--sur-n", type=int, default=512, help="side of the held-out surrogate volume")
     ap.add_argument("--no-stream", action="store_true",
                     help="skip the 512x1024x1024 host-streamed leg")
     ap.add_argument("--slab", type=int, default=128, help="t-rows per streamed slab")
@@ -450,47 +637,58 @@ def main(argv=None):
     print("# fp32: timing %d steps" % args.steps, file=sys.stderr, flush=True)
     ms_step, kms = time_form(ctx, Vg, args.steps, args.warmup)
     value = N / (ms_step * 1e-3)
-
     fpv = dft_flops_per_voxel(args.L)
-    e_ms = kms["energy"]
-    achieved = fpv * N / (e_ms * 1e-3) / 1e12
     tag = "energy_f32_L%d_%s" % (args.L, args.workload)
-    prof = counters_from_profiles(tag) or {}
-    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS["f32"], "traffic": prof.get("bytes_per_launch"),
-            "kernel": "k_energy_f32<%d>" % args.L, "kernel_ms": e_ms, "flops_per_voxel": fpv,
-            "mfma_busy": prof.get("mfma_busy"), "kernels_ms": kms}
+    roof = roofline_block("k_energy_f32<%d>" % args.L, kms["energy"], N, fpv, "f32", tag, ENERGY_F32_SOURCES,
+                          dft_flops_per_voxel_min(args.L))
+    roof["kernels_ms"] = kms
+    roof["flops_convention"] = ("4hL + 8hL^2 + 8hL^3 per voxel, h = L/2 + 1: the separable DFT contraction "
+                                "with real rows counted at complex cost; frac_min uses the count with "
+                                "real rows at real cost and conjugate rows skipped")
 
+    # the plain FP32 map with every intermediate: reference of the other forms' errors
+    S_ref, E_ref, Sr_ref, st_ref = ctx.saliency_maps(Vg)
+    torch.cuda.synchronize()
     err = None
     if not args.no_check:
         print("# fp32: sampled oracle check", file=sys.stderr, flush=True)
-        err = sampled_error(ctx, V, Vg, args.L)
+        err = parity_sample(V, S_ref, E_ref, Sr_ref, st_ref, args.L)
+    del E_ref
+    torch.cuda.empty_cache()
 
     forms = {}
+    ms_split = None
     if not args.no_forms:
-        for prec in (sal.BF16_SPLIT, sal.FP16_SPLITW, sal.FP16_SPLIT, sal.BF16, sal.FP16):
-            name = sal.PRECISION_NAMES[prec]
-            print("# form %s" % name, file=sys.stderr, flush=True)
-            c = sal.Saliency(L=args.L, precision=prec)
-            ms_f, km = time_form(c, Vg, max(3, args.steps // 4), 2)
-            dt = "bf16" if "bf16" in name else "f16"
-            ach = fpv * N / (km["energy"] * 1e-3) / 1e12
-            forms[name] = {
-                "voxels_per_s": N / (ms_f * 1e-3), "ms_per_step": ms_f,
-                "speedup_vs_fp32": ms_step / ms_f, "kernels_ms": km,
-                "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[dt],
-                             "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[dt],
-                             "kernel": "k_energy_h<%d>" % args.L},
-                "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, args.L),
-            }
-            del c
-    if not args.no_forms:
-        print("# paper cube 5^3", file=sys.stderr, flush=True)
-        forms["fp32_paper_cube_L5"] = small_cube_leg(args, V, Vg, 5)
-        print("# stride-2 windows", file=sys.stderr, flush=True)
-        forms["stride2"] = strided_leg(args, V, Vg)
-    if not args.no_surrogate:
-        forms["surrogate"] = surrogate_leg(args, dev)
+        print("# form bf16_split", file=sys.stderr, flush=True)
+        c = sal.Saliency(L=args.L, precision=sal.BF16_SPLIT)
+        ms_split, km = time_form(c, Vg, max(3, args.steps // 4), 2)
+        Ssp = c.saliency(Vg)
+        forms["bf16_split"] = {
+            "voxels_per_s": N / (ms_split * 1e-3), "ms_per_step": ms_split,
+            "speedup_vs_fp32": ms_step / ms_split, "kernels_ms": km,
+            "roofline": roofline_block("k_energy_h<%d, bf16, split>" % args.L, km["energy"], N, fpv, "bf16",
+                                       "energy_h_bf16_split_L%d_%s" % (args.L, args.workload),
+                                       ENERGY_H_SOURCES, dft_flops_per_voxel_min(args.L)),
+            "S_abs_err_vs_plain_fp32": float((Ssp - S_ref).abs().max()),
+            "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, args.L),
+        }
+        del c, Ssp
+        torch.cuda.empty_cache()
+    if not args.no_surrogate and args.L == 16:
+        print("# surrogate on the same volume", file=sys.stderr, flush=True)
+        forms["surrogate"] = surrogate_same_volume(V, Vg, S_ref, Sr_ref, st_ref, ms_step,
+                                                   ms_split if ms_split else float("nan"),
+                                                   max(2, args.steps // 5), 1)
+        torch.cuda.empty_cache()
+    del S_ref, Sr_ref, ctx
+    torch.cuda.empty_cache()
+
+    legs = {}
+    if not args.no_l8:
+        legs["survey256x512x512_L8"] = survey_L8_leg(args, dev)
+    if not args.no_surrogate and not args.no_vol512:
+        legs["surrogate_vol512"] = surrogate_leg(args, dev)
+        torch.cuda.empty_cache()
     table = None
     if not args.no_table and not args.no_check:
         table = precision_table(dev)
@@ -498,7 +696,7 @@ def main(argv=None):
     if not args.no_stream:
         del Vg
         torch.cuda.empty_cache()
-        streamed = stream_leg(args, dev)
+        streamed = stream_leg(args, dev, V if args.workload == "survey512x1024x1024" else None)
 
     cpu = None
     if not args.no_cpu:
@@ -516,6 +714,7 @@ def main(argv=None):
         "max_rel_err_vs_oracle": err,
         "roofline": roof,
         "forms": forms,
+        "legs": legs,
         "streamed": streamed,
         "precision_table": table,
         "cpu_baseline": cpu,
