@@ -49,41 +49,68 @@ def dft_flops_per_voxel_min(L: int) -> int:
     return a + b + c
 
 
-# sources that define the FP32 fused kernel (its code, device helpers and launch set-up)
-ENERGY_F32_SOURCES = ("sal_kernels.hip", "sal_device.h", "sal_internal.h")
-ENERGY_H_SOURCES = ("sal_energy16.hip", "sal_device.h", "sal_internal.h")
-CONV_SOURCES = ("sal_net.hip", "sal_device.h", "sal_internal.h")
-SURROGATE_FLOPS = 2 * 47952  # multiply-adds of the five convolutions per voxel
+# What a committed counter record covers: the kernel template's own text, the device helpers
+# and the box geometry it reads (a launcher or host-side change leaves the record valid).
+KERNEL_TEXT = {
+    "k_energy_f32": ("sal_kernels.hip", "k_energy_f32"),
+    "k_energy_h": ("sal_energy16.hip", "k_energy_h"),
+    "k_conv3": ("sal_net.hip", "k_conv3"),
+}
+CSRC = os.path.join(ROOT, "paper_1901_11095_amd", "csrc")
 
 
-def kernel_source_hash(files=ENERGY_F32_SOURCES) -> str:
+def _function_text(path: str, name: str) -> str:
+    """The definition of the __global__ function `name` in `path`: from its declarator to the
+    brace that closes its body."""
+    with open(path) as fh:
+        src = fh.read()
+    i = src.find("void %s(" % name)
+    if i < 0:
+        raise KeyError(name)
+    j = src.index("{", i)
+    depth = 0
+    for k in range(j, len(src)):
+        if src[k] == "{":
+            depth += 1
+        elif src[k] == "}":
+            depth -= 1
+            if depth == 0:
+                return src[i:k + 1]
+    raise ValueError("unbalanced braces in %s" % path)
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1901_11095_amd", "csrc")
-    for f in files:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+    fname, func = KERNEL_TEXT[kernel]
+    h.update(_function_text(os.path.join(CSRC, fname), func).encode())
+    with open(os.path.join(CSRC, "sal_device.h"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(CSRC, "sal_internal.h")) as fh:
+        txt = fh.read()
+    a, b = txt.find("struct ebox {"), txt.find("// ------------------------------------------------------------------ launchers")
+    h.update(txt[a:b].encode())
     return h.hexdigest()[:16]
 
 
-def counters_from_profiles(kernel_tag: str, files=ENERGY_F32_SOURCES):
+def counters_from_profiles(kernel_tag: str, kernel: str):
     """The committed rocprofv3 counter summary of the kernel (HBM bytes per launch scaled by
     a copy-kernel calibration, MFMA busy fraction), if it was taken on the current kernel
-    sources; else None."""
+    text; else None."""
     path = os.path.join(PROFILES, "traffic_%s.json" % kernel_tag)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != kernel_source_hash(files):
+    if rec.get("source_hash") != kernel_source_hash(kernel):
         return None
     return rec
 
 
 def roofline_block(kernel: str, ms: float, nvox: int, flops_per_voxel: int, peak_key: str, tag: str,
-                   files, min_flops_per_voxel=None):
+                   kernel_fn: str, min_flops_per_voxel=None):
     """Roofline of one kernel: algorithmic flops per launch over the measured launch time."""
     achieved = flops_per_voxel * nvox / (ms * 1e-3) / 1e12
-    prof = counters_from_profiles(tag, files) or {}
+    prof = counters_from_profiles(tag, kernel_fn) or {}
     rec = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[peak_key], "unit": "TFLOP/s",
            "frac": achieved / PEAK_TFLOPS[peak_key], "traffic": prof.get("bytes_per_launch"),
            "kernel": kernel, "kernel_ms": ms, "flops_per_voxel": flops_per_voxel,
@@ -265,7 +292,7 @@ def surrogate_same_volume(V, Vg, S_ref, Sr_ref, st_ref, ms_fp32, ms_split, steps
                                     "mean_before_fallback": float(dS_pre.mean())},
         "net_inference_ms": t_net,
         "roofline": roofline_block("k_conv3 x 5 (network inference, sum of the five launches)", t_net, N,
-                                   SURROGATE_FLOPS, "bf16", "conv3_survey512x1024x1024", CONV_SOURCES),
+                                   SURROGATE_FLOPS, "bf16", "conv3_survey512x1024x1024", "k_conv3"),
     }
     out["roofline"]["bound"] = "mfma"
     del res, pred, S_raw, dS, S_pre, dS_pre
@@ -554,7 +581,7 @@ def survey_L8_leg(args, dev):
     out = {"workload": name, "shape": list(V.shape), "L": L, "voxels_per_s": N / (ms * 1e-3),
            "ms_per_step": ms, "kernels_ms": km,
            "roofline": roofline_block("k_energy_f32<%d>" % L, km["energy"], N, fpv, "f32",
-                                      "energy_f32_L%d_%s" % (L, name), ENERGY_F32_SOURCES,
+                                      "energy_f32_L%d_%s" % (L, name), "k_energy_f32",
                                       dft_flops_per_voxel_min(L)),
            "max_rel_err_vs_oracle": None if args.no_check else sampled_error(ctx, V, Vg, L)}
     forms = {}
@@ -569,7 +596,7 @@ def survey_L8_leg(args, dev):
                 "kernels_ms": kmf,
                 "roofline": roofline_block("k_energy_h<%d>" % L, kmf["energy"], N, fpv,
                                            "bf16" if "bf16" in pname else "f16",
-                                           "energy_h_%s_L%d_%s" % (pname, L, name), ENERGY_H_SOURCES,
+                                           "energy_h_%s_L%d_%s" % (pname, L, name), "k_energy_h",
                                            dft_flops_per_voxel_min(L)),
                 "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, L)}
             del c
@@ -639,7 +666,7 @@ def main(argv=None):
     value = N / (ms_step * 1e-3)
     fpv = dft_flops_per_voxel(args.L)
     tag = "energy_f32_L%d_%s" % (args.L, args.workload)
-    roof = roofline_block("k_energy_f32<%d>" % args.L, kms["energy"], N, fpv, "f32", tag, ENERGY_F32_SOURCES,
+    roof = roofline_block("k_energy_f32<%d>" % args.L, kms["energy"], N, fpv, "f32", tag, "k_energy_f32",
                           dft_flops_per_voxel_min(args.L))
     roof["kernels_ms"] = kms
     roof["flops_convention"] = ("4hL + 8hL^2 + 8hL^3 per voxel, h = L/2 + 1: the separable DFT contraction "
@@ -668,7 +695,7 @@ def main(argv=None):
             "speedup_vs_fp32": ms_step / ms_split, "kernels_ms": km,
             "roofline": roofline_block("k_energy_h<%d, bf16, split>" % args.L, km["energy"], N, fpv, "bf16",
                                        "energy_h_bf16_split_L%d_%s" % (args.L, args.workload),
-                                       ENERGY_H_SOURCES, dft_flops_per_voxel_min(args.L)),
+                                       "k_energy_h", dft_flops_per_voxel_min(args.L)),
             "S_abs_err_vs_plain_fp32": float((Ssp - S_ref).abs().max()),
             "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, args.L),
         }
