@@ -57,6 +57,7 @@ KERNEL_TEXT = {
     "k_conv3": ("sal_net.hip", "k_conv3"),
 }
 CSRC = os.path.join(ROOT, "paper_1901_11095_amd", "csrc")
+SURROGATE_FLOPS = 2 * 47952  # multiply-adds of the five convolutions per voxel
 
 
 def _function_text(path: str, name: str) -> str:
@@ -564,6 +565,32 @@ def stream_leg(args, dev, V=None):
     }
 
 
+def strides_same_volume(Vg, S_ref, ms_fp32, L, strides=(2, 4, 8, 16)):
+    """Windows on the stride-s lattice of the headline volume (FP32), energies interpolated
+    back to every voxel: speed against stride 1 and the difference of the final map from the
+    stride-1 map.  Stride 2 runs on the fused kernel, larger strides and the non-overlapping
+    s = L on the window-by-window kernel."""
+    import torch
+    from paper_1901_11095_amd import sal
+    out = {}
+    N = Vg.numel()
+    for st in strides:
+        if st != L and 2 * st >= L:
+            continue
+        print("# stride %d" % st, file=sys.stderr, flush=True)
+        c = sal.Saliency(L=L, stride=st)
+        ms, km = time_form(c, Vg, 3, 1)
+        S = c.saliency(Vg)
+        d = (S - S_ref).abs()
+        out["s%d" % st] = {"voxels_per_s": N / (ms * 1e-3), "ms_per_step": ms, "kernels_ms": km,
+                           "speedup_vs_stride1": ms_fp32 / ms,
+                           "kernel": "k_energy_f32<%d, 2>" % L if st == 2 else "k_energy_win<%d>" % L,
+                           "S_abs_diff_vs_stride1": {"max": float(d.max()), "mean": float(d.mean())}}
+        del c, S, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def survey_L8_leg(args, dev):
     """The 256 x 512 x 512 survey volume at cube 8 (FP32 and every 16-bit form, the paper's
     5^3 cube, stride-2 windows): the smaller survey configuration."""
@@ -707,6 +734,8 @@ def main(argv=None):
                                                    ms_split if ms_split else float("nan"),
                                                    max(2, args.steps // 5), 1)
         torch.cuda.empty_cache()
+    if not args.no_forms:
+        forms["strides"] = strides_same_volume(Vg, S_ref, ms_step, args.L)
     del S_ref, Sr_ref, ctx
     torch.cuda.empty_cache()
 

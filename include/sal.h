@@ -82,8 +82,9 @@ enum {
 #define SAL_STATS_LEN 7
 
 typedef struct {
-    int32_t L;          /* cube side of the local DFT (Sec. 2 step 1; the paper uses 5).
-                           GPU build: 2..8 and 16 (2..7 in FP32 only). */
+    int32_t L;          /* cube side of the local DFT (Sec. 2 step 1; the paper uses 5; the
+                           last paragraph sets the resolution by the cube size).  GPU build:
+                           2..20; the 16-bit forms at 8 and 16 only. */
     int32_t d;          /* length of the d x 1 comparison line (after Fig. 3), default L;
                            the line is r = floor(d/2) neighbours on each enabled ray. */
     double sigma;       /* width of the Gaussian neighbour weight w(s) = exp(-s^2/(2 sigma^2))
@@ -96,11 +97,13 @@ typedef struct {
     double zero_range;  /* a component whose range is <= zero_range * max|V| has no
                            contrast and contributes 0 (default 1e-6). */
     int32_t precision;  /* sal_precision, default SAL_FP32 */
-    int32_t stride;     /* window stride s (Sec. 2 step 1 needs more than 50% overlap, s < L/2):
-                           1 (default) = one window per voxel; 2 = windows on the lattice of
-                           even positions (L >= 5), energies interpolated trilinearly to every
-                           voxel, the last lattice value held at the far faces; Eq. (5) and
-                           Eq. (6) on the full grid.  Other values: SAL_E_UNSUPPORTED. */
+    int32_t stride;     /* window stride s: 1 (default) = one window per voxel; 2 <= s < L/2
+                           (Sec. 2 step 1 asks for more than 50% overlap) or s = L (the
+                           non-overlapping cubes of the predecessor method, Sec. 1) = windows
+                           on the lattice of multiples of s, energies interpolated trilinearly
+                           to every voxel, the last lattice value held at the far faces;
+                           Eq. (5) and Eq. (6) on the full grid.  Strides above 2 run in FP32;
+                           the box and tile-check entry points need stride 1. */
 } sal_params;
 
 /* Fill *p with the defaults above for cube side L. */

@@ -174,21 +174,20 @@ hipError_t build_tables(sal_ctx *c)
         c->tw_host[2 * k] = (float)cs;
         c->tw_host[2 * k + 1] = (float)sn;
     }
-    // vector-ALU kernel (L < 8): weights of every bin (mu <= L/2, nu, om) with the
-    // multiplicity of the conjugate bin (-mu, -nu, -om) the half spectrum leaves out, and
-    // 1/L^3 of the DFT and 1/(L^3 - 1) of the mean
+    // vector-ALU kernels (L < 8, and the window-by-window kernel of every L): weights of
+    // every bin (mu <= L/2, nu, om) with the multiplicity of the conjugate bin (-mu, -nu, -om)
+    // the half spectrum leaves out, and 1/L^3 of the DFT and 1/(L^3 - 1) of the mean
     std::vector<float> wg;
-    if (L < 8)
-        for (long mu = 0; mu < h; ++mu) {
-            const double mult = (mu == 0 || 2 * mu == L) ? 1.0 : 2.0;
-            for (long nu = 0; nu < L; ++nu)
-                for (long om = 0; om < L; ++om) {
-                    double w[3];
-                    proj_w(sfreq(mu, L), sfreq(nu, L), sfreq(om, L), w);
-                    for (int m = 0; m < 3; ++m)
-                        wg.push_back((float)(w[m] * mult / ((double)L3 * (double)(L3 - 1))));
-                }
-        }
+    for (long mu = 0; mu < h; ++mu) {
+        const double mult = (mu == 0 || 2 * mu == L) ? 1.0 : 2.0;
+        for (long nu = 0; nu < L; ++nu)
+            for (long om = 0; om < L; ++om) {
+                double w[3];
+                proj_w(sfreq(mu, L), sfreq(nu, L), sfreq(om, L), w);
+                for (int m = 0; m < 3; ++m)
+                    wg.push_back((float)(w[m] * mult / ((double)L3 * (double)(L3 - 1))));
+            }
+    }
     std::vector<float> wp((size_t)4 * L3, 0.f);
     for (long mu = 0; mu < L; ++mu)
         for (long nu = 0; nu < L; ++nu)
@@ -419,14 +418,15 @@ sal_status sal_create(const sal_params *p, int device, sal_ctx **out)
     if (p->precision < SAL_FP32 || p->precision > SAL_FP16_SPLITW)
         return fail(nullptr, SAL_E_INVAL, "unknown precision");
     if (!(p->zero_range >= 0.0)) return fail(nullptr, SAL_E_INVAL, "zero_range must be >= 0");
-    if (p->L > 8 && p->L != 16)
-        return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements L = 2..8 and L = 16");
-    if (p->L < 8 && p->precision != SAL_FP32)
-        return fail(nullptr, SAL_E_UNSUPPORTED, "L < 8 runs in FP32 only");
+    if (p->L > 20) return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements L = 2..20");
     if (p->stride < 1) return fail(nullptr, SAL_E_INVAL, "stride must be >= 1");
-    if (p->stride > 2) return fail(nullptr, SAL_E_UNSUPPORTED, "the GPU build implements stride 1 and 2");
-    if (p->stride == 2 && 2 * p->stride >= p->L)
-        return fail(nullptr, SAL_E_INVAL, "stride must be below L/2 (windows overlap by more than half)");
+    if (p->stride > 1 && 2 * p->stride >= p->L && p->stride != p->L)
+        return fail(nullptr, SAL_E_INVAL,
+                    "stride must be below L/2 (windows overlap by more than half) or equal L (no overlap)");
+    if (p->precision != SAL_FP32 && (p->L != 8 && p->L != 16))
+        return fail(nullptr, SAL_E_UNSUPPORTED, "16-bit forms exist for L = 8 and 16 only");
+    if (p->precision != SAL_FP32 && p->stride > 2)
+        return fail(nullptr, SAL_E_UNSUPPORTED, "strides above 2 run in FP32 only");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(nullptr, SAL_E_DEVICE, "no such HIP device");

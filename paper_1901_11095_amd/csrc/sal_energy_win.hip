@@ -1,0 +1,229 @@
+// Steps 1-3 of the saliency method (Shafiq et al., ICIP 2017, Sec. 2) window by window:
+// the local 3D DFT of each window (DFT definition after Eq. (2)), its plane projections
+// with DC excluded (Eqs. (1)-(4)) and the mean magnitudes E_t, E_x, E_y, with nothing
+// shared between windows.  Used where the fused kernels' sharing of the first two axes
+// between neighbouring windows does not apply or does not fit:
+//   * windows on a lattice of stride s >= 3 (Sec. 2 asks only for more than 50 % overlap,
+//     s < L/2) and the non-overlapping s = L of the predecessor method (Sec. 1): the work
+//     falls by s^3 while unshared windows cost 2.5 times the shared contraction per window;
+//   * cube sides without a fused kernel (9..15, 17..20).
+// FP32 on the vector ALUs.  A workgroup walks windows (grid-stride over the windows of its
+// box); per window:
+//   load    the L^3 samples, reflected at the volume faces, into LDS;
+//   stage A per column (q, r): A[mu][q][r] = sum_p W[mu, p] win[p][q][r], mu <= L/2;
+//   stage B per (mu, r): B[mu][nu][r] = sum_q W[nu, q] A[mu][q][r], every nu;
+//   stage C per row (mu, nu): F[om] = sum_r W[om, r] B[mu][nu][r], |F| weighted by the
+//           projections (times the conjugate multiplicity of mu and 1/(L^3 (L^3 - 1))),
+//           summed over the workgroup into E_t, E_x, E_y.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sal_device.h"
+#include "sal_internal.h"
+
+namespace {
+
+template <int L>
+struct WinCfg {
+    static constexpr int h = L / 2 + 1;
+    static constexpr int NT = 64 * ((h * L + 63) / 64);  // one thread per (mu, r) / (mu, nu)
+    static constexpr int LP = L + 1;                      // padded row of B (LDS banks)
+};
+
+template <int L>
+struct WinTw {
+    float2 w[L];  // e^{-2 pi i k / L}, k = 0..L-1
+};
+
+__device__ __forceinline__ float2 cmad_w(float2 a, float2 w, float2 acc)
+{
+    acc.x = fmaf(a.x, w.x, fmaf(-a.y, w.y, acc.x));
+    acc.y = fmaf(a.x, w.y, fmaf(a.y, w.x, acc.y));
+    return acc;
+}
+
+}  // namespace
+
+// bx: the windows of the volume positions o + S k, k < ceil(d / S), E stored in the frame
+// (fo, fk) at index (p - fo) / S; with a table, workgroups [e * per_box, (e+1) * per_box)
+// serve entry e.
+template <int L>
+__global__ __launch_bounds__(WinCfg<L>::NT) void k_energy_win(const float *__restrict__ V, int n0, int n1, int n2,
+                                                              ebox bx, int S, WinTw<L> tw,
+                                                              const float *__restrict__ wgen, float *__restrict__ E,
+                                                              float *__restrict__ vmax_part)
+{
+    using C = WinCfg<L>;
+    constexpr int H = L / 2, h = C::h, NT = C::NT, LP = C::LP, L2 = L * L, L3 = L * L * L;
+    constexpr int NWV = NT / 64;
+    __shared__ float win[L3];            // [p][q][r]
+    __shared__ float2 A_s[h * L2];       // [mu][q][r]
+    __shared__ float2 B_s[h * L * LP];   // [mu][nu][r], rows padded
+    __shared__ float red_s[NWV][4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int box;
+    const int blk = box_tile(bx, &box);
+    V += box * bx.vstride;
+    E += box * bx.estride;
+    const int nblk = bx.table ? bx.per_box : (int)gridDim.x;
+    const int kd0 = (bx.d0 + S - 1) / S, kd1 = (bx.d1 + S - 1) / S, kd2 = (bx.d2 + S - 1) / S;
+    const int nwin = kd0 * kd1 * kd2;
+    const int K1 = bx.fk1, K2 = bx.fk2;
+    const int64_t nfr = (int64_t)bx.fk0 * K1 * K2;
+    const int64_t plane = (int64_t)n1 * n2;
+    float vmax = 0.f;
+
+    for (int w = blk; w < nwin; w += nblk) {
+        const int k2 = w % kd2, k1 = (w / kd2) % kd1, k0 = w / (kd2 * kd1);
+        const int p0 = bx.o0 + S * k0, p1 = bx.o1 + S * k1, p2 = bx.o2 + S * k2;
+        __syncthreads();  // the previous window is done with win, A_s, B_s and red_s
+        for (int i = tid; i < L3; i += NT) {
+            const int r = i % L, q = (i / L) % L, p = i / L2;
+            const float v = V[(int64_t)refl_idx(p0 - H + p, n0) * plane + (int64_t)refl_idx(p1 - H + q, n1) * n2 +
+                              refl_idx(p2 - H + r, n2)];
+            vmax = fmaxf(vmax, fabsf(v));
+            win[i] = v;
+        }
+        __syncthreads();
+        // ---------------- stage A: real DFT along t, mu <= L/2 ---------------------------
+        for (int c = tid; c < L2; c += NT) {
+            float v[L];
+#pragma unroll
+            for (int p = 0; p < L; ++p) v[p] = win[p * L2 + c];
+#pragma unroll
+            for (int mu = 0; mu < h; ++mu) {
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int p = 0; p < L; ++p) {
+                    re = fmaf(v[p], tw.w[(mu * p) % L].x, re);
+                    im = fmaf(v[p], tw.w[(mu * p) % L].y, im);
+                }
+                A_s[mu * L2 + c] = make_float2(re, im);
+            }
+        }
+        __syncthreads();
+        // ---------------- stage B: DFT along x per (mu, r), every nu ---------------------
+        if (tid < h * L) {
+            const int mu = tid / L, r = tid - (tid / L) * L;
+            float2 a[L];
+#pragma unroll
+            for (int q = 0; q < L; ++q) a[q] = A_s[(mu * L + q) * L + r];
+#pragma unroll
+            for (int nu = 0; nu < L; ++nu) {
+                float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int q = 0; q < L; ++q) acc = cmad_w(a[q], tw.w[(nu * q) % L], acc);
+                B_s[(mu * L + nu) * LP + r] = acc;
+            }
+        }
+        __syncthreads();
+        // ---------------- stage C: DFT along y per row (mu, nu), projections -------------
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+        if (tid < h * L) {
+            const int mu = tid / L, nu = tid - (tid / L) * L;
+            float2 b[L];
+#pragma unroll
+            for (int r = 0; r < L; ++r) b[r] = B_s[(mu * L + nu) * LP + r];
+            const float *wr = wgen + (int64_t)(mu * L + nu) * L * 3;
+#pragma unroll
+            for (int om = 0; om < L; ++om) {
+                float2 f = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int r = 0; r < L; ++r) f = cmad_w(b[r], tw.w[(om * r) % L], f);
+                const float m = __builtin_amdgcn_sqrtf(fmaf(f.x, f.x, f.y * f.y));
+                e0 = fmaf(wr[3 * om], m, e0);
+                e1 = fmaf(wr[3 * om + 1], m, e1);
+                e2 = fmaf(wr[3 * om + 2], m, e2);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            e0 += __shfl_xor(e0, o);
+            e1 += __shfl_xor(e1, o);
+            e2 += __shfl_xor(e2, o);
+        }
+        if (lane == 0) {
+            red_s[wave][0] = e0;
+            red_s[wave][1] = e1;
+            red_s[wave][2] = e2;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+            for (int v = 0; v < NWV; ++v) {
+                s0 += red_s[v][0];
+                s1 += red_s[v][1];
+                s2 += red_s[v][2];
+            }
+            const int64_t o = ((int64_t)((p0 - bx.fo0) / S) * K1 + (p1 - bx.fo1) / S) * K2 + (p2 - bx.fo2) / S;
+            E[o] = s0;
+            E[nfr + o] = s1;
+            E[2 * nfr + o] = s2;
+        }
+    }
+    // max |V| of everything this workgroup read (all of it lies in the volume)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    __syncthreads();
+    if (lane == 0) red_s[wave][3] = vmax;
+    __syncthreads();
+    if (tid == 0 && vmax_part) {
+        float m = red_s[0][3];
+        for (int v = 1; v < NWV; ++v) m = fmaxf(m, red_s[v][3]);
+        vmax_part[blockIdx.x] = m;
+    }
+}
+
+// ====================================================================== launchers
+
+namespace {
+
+constexpr int64_t WIN_BLOCKS = 4096;   // workgroups of a whole-volume launch
+constexpr int64_t WIN_PER_BOX = 64;    // workgroups per box of a batch
+
+int64_t win_blocks(int64_t nwin, int64_t nbox)
+{
+    if (nbox > 1) return (nwin < WIN_PER_BOX ? (nwin > 0 ? nwin : 1) : WIN_PER_BOX) * nbox;
+    return nwin < WIN_BLOCKS ? (nwin > 0 ? nwin : 1) : WIN_BLOCKS;
+}
+
+template <int L>
+hipError_t launch_win_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx, int S,
+                        float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
+{
+    const int64_t nwin = ((bx.d0 + S - 1) / S) * ((bx.d1 + S - 1) / S) * ((bx.d2 + S - 1) / S);
+    const int64_t nb = win_blocks(nwin, bx.table ? nbox : 1);
+    if (bx.table) bx.per_box = (int)(nb / nbox);
+    if (nparts) *nparts = (int)nb;
+    WinTw<L> tw;
+    for (int k = 0; k < L; ++k) tw.w[k] = make_float2(c->tw_host[2 * k], c->tw_host[2 * k + 1]);
+    hipLaunchKernelGGL(k_energy_win<L>, dim3((unsigned)nb), dim3(WinCfg<L>::NT), 0, s, V, (int)n0, (int)n1, (int)n2,
+                       bx, S, tw, c->t.w_gen, E, vmax_part);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t energy_win_num_blocks(const sal_ctx *c, int64_t k0, int64_t k1, int64_t k2)
+{
+    (void)c;
+    return win_blocks(k0 * k1 * k2, 1);
+}
+
+hipError_t launch_energy_win(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
+                             float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
+{
+    const int S = c->p.stride;
+#define SAL_WIN(LL) \
+    case LL: return launch_win_L<LL>(c, V, n0, n1, n2, bx, S, E, vmax_part, nparts, s, nbox)
+    switch (c->L) {
+        SAL_WIN(2); SAL_WIN(3); SAL_WIN(4); SAL_WIN(5); SAL_WIN(6); SAL_WIN(7); SAL_WIN(8);
+        SAL_WIN(9); SAL_WIN(10); SAL_WIN(11); SAL_WIN(12); SAL_WIN(13); SAL_WIN(14); SAL_WIN(15);
+        SAL_WIN(16); SAL_WIN(17); SAL_WIN(18); SAL_WIN(19); SAL_WIN(20);
+    default: return hipErrorInvalidValue;
+    }
+#undef SAL_WIN
+}

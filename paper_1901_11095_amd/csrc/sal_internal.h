@@ -39,7 +39,7 @@ struct sal_ctx {
     int L, H, h, r, nrows;
     float g[96];       // Gaussian neighbour weights w(s |e|), s = 1..r (index 32 (|e|^2 - 1) + s - 1)
     float Q[3];        // number of terms of Eq. (5) per component
-    float tw_host[32]; // e^{-2 pi i k / L} (re, im), k < L
+    float tw_host[64]; // e^{-2 pi i k / L} (re, im), k < L
     sal_tables t;
     std::string err;
     // per-kernel timing of sal_saliency (sal_profile_enable / sal_profile_read)
@@ -181,6 +181,18 @@ hipError_t launch_tile_merge_boxes(float *S_raw, int64_t n0, int64_t n1, int64_t
                                    double bound, float *err, hipStream_t s);
 
 int64_t energy_gen_num_blocks(int L, int64_t d0, int64_t d1, int64_t d2, int64_t nbox = 1);
+// Window-by-window energies (strides >= 3, the non-overlapping stride L, cube sides without a
+// fused kernel): bx as for the fused kernels, windows at o + stride k.
+hipError_t launch_energy_win(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
+                             float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox = 1);
+int64_t energy_win_num_blocks(const sal_ctx *c, int64_t k0, int64_t k1, int64_t k2);
+// Whether the energies of this context come from the window-by-window kernel.
+inline bool uses_window_kernel(const sal_ctx *c)
+{
+    const int L = c->L, S = c->p.stride;
+    if (S >= 3 || (S > 1 && S == L)) return true;
+    return !(L <= 8 || L == 16);
+}
 // bx.table set: nbox boxes of at most bx.d voxels per axis (the grid is nbox times that of one)
 hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
                              float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox = 1);

@@ -915,6 +915,7 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
     const int64_t k0 = (n0 + S - 1) / S, k1 = (n1 + S - 1) / S, k2 = (n2 + S - 1) / S;
     int nby, nbx, tt;
     int64_t nb;
+    if (uses_window_kernel(c)) return energy_win_num_blocks(c, k0, k1, k2);
     if (c->L == 8)
         energy_grid<8>(k0, k1, k2, &nby, &nbx, &tt, &nb);
     else if (c->L == 16)
@@ -958,6 +959,7 @@ hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n
     const int S = c->p.stride;
     ebox bx = box ? framed_box((int)box[0], (int)box[1], (int)box[2], (int)box[3], (int)box[4], (int)box[5], S)
                   : framed_box(0, 0, 0, (int)n0, (int)n1, (int)n2, S);
+    if (uses_window_kernel(c)) return launch_energy_win(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
@@ -971,6 +973,7 @@ hipError_t launch_energy_boxes(const sal_ctx *c, const float *V, int64_t n0, int
     bx.table = table;
     bx.vstride = vstride;
     bx.estride = estride;
+    if (uses_window_kernel(c)) return launch_energy_win(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
@@ -1066,7 +1069,19 @@ hipError_t launch_local_spectra(const sal_ctx *c, const float *V, int64_t n0, in
     case 6: SAL_SPECTRA(6); break;
     case 7: SAL_SPECTRA(7); break;
     case 8: SAL_SPECTRA(8); break;
-    default: SAL_SPECTRA(16); break;
+    case 9: SAL_SPECTRA(9); break;
+    case 10: SAL_SPECTRA(10); break;
+    case 11: SAL_SPECTRA(11); break;
+    case 12: SAL_SPECTRA(12); break;
+    case 13: SAL_SPECTRA(13); break;
+    case 14: SAL_SPECTRA(14); break;
+    case 15: SAL_SPECTRA(15); break;
+    case 16: SAL_SPECTRA(16); break;
+    case 17: SAL_SPECTRA(17); break;
+    case 18: SAL_SPECTRA(18); break;
+    case 19: SAL_SPECTRA(19); break;
+    case 20: SAL_SPECTRA(20); break;
+    default: return hipErrorInvalidValue;
     }
 #undef SAL_SPECTRA
     return hipGetLastError();
@@ -1087,7 +1102,19 @@ hipError_t launch_project(const sal_ctx *c, const float *spectra, int64_t nvox, 
     case 6: SAL_PROJECT(6); break;
     case 7: SAL_PROJECT(7); break;
     case 8: SAL_PROJECT(8); break;
-    default: SAL_PROJECT(16); break;
+    case 9: SAL_PROJECT(9); break;
+    case 10: SAL_PROJECT(10); break;
+    case 11: SAL_PROJECT(11); break;
+    case 12: SAL_PROJECT(12); break;
+    case 13: SAL_PROJECT(13); break;
+    case 14: SAL_PROJECT(14); break;
+    case 15: SAL_PROJECT(15); break;
+    case 16: SAL_PROJECT(16); break;
+    case 17: SAL_PROJECT(17); break;
+    case 18: SAL_PROJECT(18); break;
+    case 19: SAL_PROJECT(19); break;
+    case 20: SAL_PROJECT(20); break;
+    default: return hipErrorInvalidValue;
     }
 #undef SAL_PROJECT
     return hipGetLastError();

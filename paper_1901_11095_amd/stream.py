@@ -49,6 +49,12 @@ def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
     bufs = [torch.empty((rows, n1, n2), dtype=torch.float32, device=dev) for _ in range(2)]
     comp = torch.cuda.current_stream(dev)
     copy = torch.cuda.Stream(dev)
+    # The staging buffers come from the compute stream's pool and may reuse memory that work
+    # still queued there reads (a map the caller has just dropped): the copy stream starts
+    # after that work, and the buffers are marked as used by the copy stream.
+    copy.wait_stream(comp)
+    for b in bufs:
+        b.record_stream(copy)
     done = [torch.cuda.Event(), torch.cuda.Event()]     # buffer free again
     ready = [torch.cuda.Event(), torch.cuda.Event()]    # buffer filled
     slabs = list(_slabs(n0, slab, halo))

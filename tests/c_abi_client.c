@@ -342,9 +342,9 @@ int main(void)
     /* parameters the build does not implement, and invalid ones */
     sal_params p;
     sal_ctx *ctx = NULL;
-    sal_default_params(&p, 9);
+    sal_default_params(&p, 21);
     if (sal_create(&p, 0, &ctx) != SAL_E_UNSUPPORTED || ctx != NULL || strlen(sal_last_error(NULL)) == 0) {
-        fprintf(stderr, "L = 9 not refused as unsupported\n");
+        fprintf(stderr, "L = 21 not refused as unsupported\n");
         bad = 1;
     }
     sal_default_params(&p, 8);

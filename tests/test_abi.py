@@ -42,13 +42,15 @@ def test_default_params(lib):
 
 
 @pytest.mark.parametrize("fields,status", [
-    ({"L": 1}, 1), ({"d": 1}, 1), ({"sigma": 0.0}, 1), ({"precision": 9}, 1), ({"L": 9}, 2),
-    ({"L": 12}, 2), ({"L": 32}, 2), ({"L": 5, "precision": 2}, 2), ({"L": 4, "precision": 1}, 2),
-    ({"stride": 0}, 1), ({"stride": 3}, 2), ({"L": 4, "stride": 2}, 1), ({"rays": 1 << 26}, 1),
+    ({"L": 1}, 1), ({"d": 1}, 1), ({"sigma": 0.0}, 1), ({"precision": 9}, 1), ({"L": 21}, 2),
+    ({"L": 32}, 2), ({"L": 12, "precision": 2}, 2), ({"L": 5, "precision": 2}, 2), ({"L": 4, "precision": 1}, 2),
+    ({"stride": 0}, 1), ({"stride": 3, "precision": 2}, 2), ({"stride": 4}, 1), ({"stride": 5}, 1),
+    ({"L": 4, "stride": 2}, 1), ({"rays": 1 << 26}, 1),
 ])
 def test_create_rejects(lib, fields, status):
-    """Invalid parameters are rejected before any device call; cube sides without a GPU
-    kernel (9..15, > 16) and 16-bit forms below L = 8 are unsupported."""
+    """Invalid parameters are rejected before any device call (a stride neither below L/2 nor
+    equal to L); cube sides above 20 and 16-bit forms other than at L = 8 and 16 or with
+    strides above 2 are unsupported."""
     from paper_1901_11095_amd import sal
     p = sal.default_params(8)
     for k, v in fields.items():

@@ -40,7 +40,8 @@ def _one_by_one(ctx, V, P, stats, tiles, tile, bound):
 
 
 @pytest.mark.parametrize("L,prec,rays", [(8, sal.FP32, None), (16, sal.FP32, None), (16, sal.BF16_SPLIT, None),
-                                         (5, sal.FP32, None), (8, sal.FP32, (sal.RAY_ALL,) * 3)])
+                                         (5, sal.FP32, None), (8, sal.FP32, (sal.RAY_ALL,) * 3),
+                                         (12, sal.FP32, None)])
 def test_batch_equals_one_by_one(L, prec, rays):
     shape = (52, 44, 60)
     tile = 16
@@ -158,7 +159,7 @@ def test_streamed_restream_equals_kept(net):
     assert torch.equal(a["S"], b["S"])
 
 
-@pytest.mark.parametrize("L,rays", [(5, None), (8, None), (16, None), (8, "all26"), (16, "all26")])
+@pytest.mark.parametrize("L,rays", [(5, None), (8, None), (16, None), (8, "all26"), (16, "all26"), (11, None)])
 def test_check_tiles_vs_oracle(L, rays):
     """The batched check's exact maps (energy launch over the box table, k_dcs_boxes) against
     the oracle's raw maps of each tile, FP32, within 1e-5 of each map's maximum; the error of

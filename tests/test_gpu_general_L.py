@@ -1,9 +1,11 @@
-"""Cube sides below 8, on the vector-ALU kernel, against the FP64 oracle.
+"""Cube sides other than 8 and 16 against the FP64 oracle: 2..7 on the fused vector-ALU
+kernel, 9..15 and 17..20 on the window-by-window kernel (Sec. 2, last paragraph: the
+resolution is set by the cube size).
 
-Includes the paper's own 5 x 5 x 5 cube (Sec. 2, last paragraph) and odd sides, whose
-windows have no Nyquist row: every map within 1e-5 of the oracle, statistics exact, and
-the same mirror symmetry the oracle is pinned to.  Ragged volumes span several
-workgroup tiles (16 x 16 for L <= 5, 8 x 32 above).
+Includes the paper's own 5 x 5 x 5 cube and odd sides, whose windows have no Nyquist row:
+every map within 1e-5 of the oracle, statistics exact, and the same mirror symmetry the
+oracle is pinned to.  Ragged volumes span several workgroup tiles (16 x 16 for L <= 5,
+8 x 32 above).
 """
 import numpy as np
 import pytest
@@ -45,6 +47,31 @@ def test_saliency_vs_oracle(L, shape):
     full_check(L, V)
 
 
+@pytest.mark.parametrize("L", [9, 10, 11, 12, 13, 14, 15])
+def test_saliency_vs_oracle_window_kernel(L):
+    print("general L=%d" % L, flush=True)
+    V = synth.make_volume((21, 19, 35), seed=L + 3, n_faults=1, throw=2)
+    full_check(L, V)
+
+
+@pytest.mark.parametrize("L", [17, 18, 19, 20])
+def test_saliency_vs_oracle_above_16(L):
+    print("general L=%d" % L, flush=True)
+    V = synth.make_volume((13, 17, 24), seed=L + 3, n_faults=1, throw=2)
+    full_check(L, V)
+
+
+@pytest.mark.parametrize("L", [9, 11, 13, 15])
+@pytest.mark.parametrize("axis", [0, 2])
+def test_mirror_odd_L_window_kernel(L, axis):
+    """Odd L: the window is centred, so flipping V along an axis flips every map."""
+    V = synth.random_volume((17, 18, 19), seed=axis + L)
+    ctx = sal.Saliency(L=L)
+    S = ctx.saliency(torch.from_numpy(V).cuda()).cpu().numpy()
+    Sf = ctx.saliency(torch.from_numpy(np.ascontiguousarray(np.flip(V, axis))).cuda()).cpu().numpy()
+    assert relmax(np.flip(Sf, axis), S) <= TOL
+
+
 def test_paper_cube_vol64():
     """The paper's 5 x 5 x 5 cube on the whole 64^3 volume."""
     full_check(5, synth.workload("vol64"))
@@ -65,7 +92,7 @@ def test_mirror_odd_L(axis):
     assert relmax(np.flip(Sf, axis), S) <= TOL
 
 
-@pytest.mark.parametrize("L", [4, 5, 7])
+@pytest.mark.parametrize("L", [4, 5, 7, 12, 20])
 def test_local_spectra_and_project(L):
     ctx = sal.Saliency(L=L)
     V = synth.random_volume((13, 12, 14), seed=L)
@@ -87,9 +114,13 @@ def test_dc_bit_exact_L4():
     assert np.array_equal(F[..., 0, 0, 0].real.astype(np.float64), ref.real)
 
 
-@pytest.mark.parametrize("L", [5, 7])
+@pytest.mark.parametrize("L", [5, 7, 12])
 def test_box_and_stream(L):
-    """Box raw maps and host-streamed slabs equal the resident whole volume, bit for bit."""
+    """Box raw maps and host-streamed slabs equal the resident whole volume, bit for bit.
+    The energies are dropped right after the call that reads them, so the streaming's
+    staging buffers may reuse their memory while that read is still queued (the copy
+    stream must wait for it)."""
+    print("box and stream L=%d" % L, flush=True)
     V = synth.make_volume((40, 36, 44), seed=L, n_faults=2, throw=3)
     ctx = sal.Saliency(L=L)
     Vd = torch.from_numpy(V).cuda()
@@ -97,5 +128,13 @@ def test_box_and_stream(L):
     box = ctx.raw_box(Vd, (5, 0, 30), (20, 17, 14))
     S2, Sr2, _ = stream.plain_streamed(ctx, stream.pinned(V), slab=9)
     torch.cuda.synchronize()
+    d = (box - Sr[:, 5:25, 0:17, 30:44]).abs()
+    if float(d.max()) > 0:
+        bad = torch.nonzero(d)
+        print("box mismatch at", bad[:8].tolist(), "of", len(bad), flush=True)
     assert torch.equal(box, Sr[:, 5:25, 0:17, 30:44])
     assert torch.equal(Sr2, Sr) and torch.equal(S2, S)
+    # and the whole-volume maps are Eq. (5) of the energies
+    _, E, Sr3, _ = ctx.saliency_maps(Vd)
+    assert torch.equal(Sr3, Sr)
+    assert relmax(Sr.cpu().numpy(), O.dcs(E.cpu().numpy().astype(np.float64), L // 2, L / 4.0)) <= TOL

@@ -275,7 +275,7 @@ def test_error_paths(dev, ctx8):
         ctx8.saliency(big[1:].view(20, 20, 20))
     assert ei.value.status == sal.SAL_E_INVAL
     with pytest.raises(sal.SalError) as ei:
-        sal.Saliency(L=9)
+        sal.Saliency(L=21)
     assert ei.value.status == sal.SAL_E_UNSUPPORTED
     with pytest.raises(sal.SalError) as ei:
         sal.Saliency(L=5, precision=sal.BF16_SPLIT)

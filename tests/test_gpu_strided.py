@@ -1,7 +1,8 @@
-"""Strided windows (stride 2, the half-resolution lattice) on the GPU against the FP64
-oracle: energies on the lattice, trilinear interpolation to every voxel, Eq. (5) and
-Eq. (6) on the full grid.  Ragged volumes put lattice points and held values at every
-face."""
+"""Strided windows on the GPU against the FP64 oracle: energies of the windows on the
+stride-s lattice, trilinear interpolation to every voxel, Eq. (5) and Eq. (6) on the full
+grid.  Stride 2 runs on the fused kernels; strides 3 .. ceil(L/2) - 1 (overlap above one
+half) and the non-overlapping s = L on the window-by-window kernel.  Ragged volumes put
+lattice points and held values at every face."""
 import numpy as np
 import pytest
 import torch
@@ -17,11 +18,11 @@ def relmax(got, ref):
     return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
 
 
-def check(L, shape, prec=sal.FP32, tol=1e-5, seed=3):
-    print("strided L=%d shape %s precision %d" % (L, shape, prec), flush=True)
+def check(L, shape, prec=sal.FP32, tol=1e-5, seed=3, stride=2):
+    print("strided L=%d s=%d shape %s precision %d" % (L, stride, shape, prec), flush=True)
     V = synth.make_volume(shape, seed=seed + L, n_faults=1, throw=2, n_chaotic=1, chaotic_size=8)
-    ctx = sal.Saliency(L=L, stride=2, precision=prec)
-    ref = O.saliency(V, O.Params(L=L, stride=2))
+    ctx = sal.Saliency(L=L, stride=stride, precision=prec)
+    ref = O.saliency(V, O.Params(L=L, stride=stride))
     S, E, Sr, st = ctx.saliency_maps(torch.from_numpy(V).cuda())
     E, Sr, S = E.cpu().numpy(), Sr.cpu().numpy(), S.cpu().numpy()
     for m in range(3):
@@ -54,13 +55,33 @@ def test_strided_vol64_paper_cube():
     assert relmax(S, ref["S"]) <= 1e-5
 
 
+STRIDES = [(8, 3), (8, 8), (16, 3), (16, 5), (16, 7), (16, 16), (5, 5), (7, 3), (7, 7), (12, 2), (12, 5),
+           (12, 12), (2, 2), (3, 3), (6, 6)]
+
+
+@pytest.mark.parametrize("L,s", STRIDES)
+def test_strides_vs_oracle(L, s):
+    check(L, (21, 19, 35), stride=s)
+
+
+def test_stride_4_L16_larger_volume():
+    """Stride 4 at cube 16 on a volume of several workgroups' windows per axis."""
+    check(16, (45, 38, 51), stride=4)
+
+
 def test_strided_rejects():
     with pytest.raises(sal.SalError) as ei:
-        sal.Saliency(L=8, stride=3)
-    assert ei.value.status == sal.SAL_E_UNSUPPORTED
+        sal.Saliency(L=8, stride=5)        # neither above half overlap nor non-overlapping
+    assert ei.value.status == sal.SAL_E_INVAL
+    with pytest.raises(sal.SalError) as ei:
+        sal.Saliency(L=8, stride=4)
+    assert ei.value.status == sal.SAL_E_INVAL
     with pytest.raises(sal.SalError) as ei:
         sal.Saliency(L=4, stride=2)
     assert ei.value.status == sal.SAL_E_INVAL
+    with pytest.raises(sal.SalError) as ei:
+        sal.Saliency(L=16, stride=3, precision=sal.BF16_SPLIT)
+    assert ei.value.status == sal.SAL_E_UNSUPPORTED
     ctx = sal.Saliency(L=8, stride=2)
     with pytest.raises(sal.SalError) as ei:
         ctx.raw_box(torch.zeros((20, 20, 20), device="cuda"), (0, 0, 0), (4, 4, 4))
