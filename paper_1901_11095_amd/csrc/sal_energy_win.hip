@@ -75,18 +75,39 @@ __global__ __launch_bounds__(WinCfg<L>::NT) void k_energy_win(const float *__res
     const int64_t plane = (int64_t)n1 * n2;
     float vmax = 0.f;
 
+    // The samples of the next window are loaded into registers while the current one
+    // computes, so their latency is hidden; every thread holds NLD of them.
+    constexpr int NLD = (L3 + NT - 1) / NT;
+    float pre[NLD];
+    auto load_win = [&](int w) {
+        const int k2 = w % kd2, k1 = (w / kd2) % kd1, k0 = w / (kd2 * kd1);
+        const int q0 = bx.o0 + S * k0 - H, q1 = bx.o1 + S * k1 - H, q2 = bx.o2 + S * k2 - H;
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int i = tid + NT * j;
+            if (i < L3) {
+                const int r = i % L, q = (i / L) % L, p = i / L2;
+                pre[j] = V[(int64_t)refl_idx(q0 + p, n0) * plane + (int64_t)refl_idx(q1 + q, n1) * n2 +
+                           refl_idx(q2 + r, n2)];
+            }
+        }
+    };
+    if (blk < nwin) load_win(blk);
+
     for (int w = blk; w < nwin; w += nblk) {
         const int k2 = w % kd2, k1 = (w / kd2) % kd1, k0 = w / (kd2 * kd1);
         const int p0 = bx.o0 + S * k0, p1 = bx.o1 + S * k1, p2 = bx.o2 + S * k2;
         __syncthreads();  // the previous window is done with win, A_s, B_s and red_s
-        for (int i = tid; i < L3; i += NT) {
-            const int r = i % L, q = (i / L) % L, p = i / L2;
-            const float v = V[(int64_t)refl_idx(p0 - H + p, n0) * plane + (int64_t)refl_idx(p1 - H + q, n1) * n2 +
-                              refl_idx(p2 - H + r, n2)];
-            vmax = fmaxf(vmax, fabsf(v));
-            win[i] = v;
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int i = tid + NT * j;
+            if (i < L3) {
+                vmax = fmaxf(vmax, fabsf(pre[j]));
+                win[i] = pre[j];
+            }
         }
         __syncthreads();
+        if (w + nblk < nwin) load_win(w + nblk);
         // ---------------- stage A: real DFT along t, mu <= L/2 ---------------------------
         for (int c = tid; c < L2; c += NT) {
             float v[L];
