@@ -38,18 +38,22 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
 
 @dataclass
 class TrainConfig:
+    """Defaults: the configuration of the committed weights (32 volumes whose faults, chaotic
+    bodies and SNR come from their seeds, 2M labelled voxels per epoch, 96 epochs, cosine
+    learning rate 1e-3 -> 1e-4).  n_volumes=8, seeds 10..17, mix=False is the 8-volume set at
+    one noise level, which does not generalise to the 5 dB survey volume."""
     L: int = 16
-    n_volumes: int = 8
+    n_volumes: int = 32
     shape: tuple = (256, 256, 256)
-    seeds: tuple = (10, 11, 12, 13, 14, 15, 16, 17)
+    seeds: tuple = tuple(range(10, 42))
     pairs_per_epoch: int = 2_000_000
-    epochs: int = 8
+    epochs: int = 96
     batch: int = 64
-    lr: float = 2e-3
+    lr: float = 1e-3
     lr_min: float = 1e-4
     window_seed: int = 18
     init_seed: int = 0
-    mix: bool = False          # draw each training volume's structure and SNR from its seed
+    mix: bool = True           # draw each training volume's structure and SNR from its seed
     history: list = field(default_factory=list)
 
 
@@ -137,6 +141,15 @@ def save(net: sal.Net, cfg: TrainConfig, path: str = WEIGHTS):
     meta = {"config": json.dumps({k: v for k, v in asdict(cfg).items()})}
     save_file({"params": net.get_params(), "out_scale": np.asarray(net.out_scale, np.float32)},
               path, metadata=meta)
+
+
+def training_config(path: str = WEIGHTS) -> dict:
+    """The training configuration stored with the weights (loss history left out)."""
+    from safetensors import safe_open
+    with safe_open(path, "np") as f:
+        cfg = json.loads(f.metadata()["config"])
+    cfg.pop("history", None)
+    return cfg
 
 
 def load(path: str = WEIGHTS, device: int = 0) -> sal.Net:
