@@ -102,8 +102,7 @@ typedef struct {
                            non-overlapping cubes of the predecessor method, Sec. 1) = windows
                            on the lattice of multiples of s, energies interpolated trilinearly
                            to every voxel, the last lattice value held at the far faces;
-                           Eq. (5) and Eq. (6) on the full grid.  Strides above 2 run in FP32;
-                           the box and tile-check entry points need stride 1. */
+                           Eq. (5) and Eq. (6) on the full grid.  Strides above 2 run in FP32. */
 } sal_params;
 
 /* Fill *p with the defaults above for cube side L. */
@@ -208,7 +207,10 @@ sal_status sal_profile_read(sal_ctx *ctx, double ms[4], int64_t *calls, int rese
  * [3][b0][b1][b2]), equal to the same positions of the whole-volume maps of sal_saliency.
  * The energies are computed on the box grown by r = floor(d/2) (clipped to the volume) and
  * windows reflect at the volume faces only, so V may be the whole volume or any crop whose
- * faces inside the volume lie at least floor(L/2) + r from the box.  workspace: at least
+ * faces inside the volume lie at least floor(L/2) + r from the box.  With stride s > 1 the
+ * energies of the grown box are interpolated from the lattice windows around it, the lattice
+ * starting at the first sample of V (a crop must start on a multiple of s, and lie at least
+ * floor(L/2) + r + s from the box, for the whole volume's values).  workspace: at least
  * sal_raw_box_workspace_size(box_dims) bytes, DEVICE, 16-byte aligned.
  */
 sal_status sal_raw_box_workspace_size(sal_ctx *ctx, const int64_t box_dims[3], size_t *bytes);
@@ -276,10 +278,11 @@ sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, in
  * another).  The tile tables are copied from host memory into the workspace at call time
  * (through a pinned staging buffer of the context, reused only after the previous copy from
  * it has completed, which may wait for that copy); the call therefore cannot be captured
- * into a HIP graph and is refused on a capturing stream.  Requires stride 1.
+ * into a HIP graph and is refused on a capturing stream.  With stride s > 1 each tile's
+ * energies come from the lattice windows around its grown box, as in sal_raw_box.
  * Errors: SAL_E_INVAL (a tile outside its volume or the map, nbox outside [1, 2^20], tile
  * sides outside [1, 1024], or a batch whose energy boxes hold more than 2^31 - 1 voxels:
- * split it over several calls), SAL_E_UNSUPPORTED (stride 2, a capturing stream),
+ * split it over several calls), SAL_E_UNSUPPORTED (a capturing stream),
  * SAL_E_WORKSPACE, SAL_E_DEVICE.
  */
 sal_status sal_check_tiles_workspace_size(sal_ctx *ctx, int64_t n0, int64_t n1, int64_t n2, int64_t nbox,

@@ -641,22 +641,54 @@ static void grow_box(const sal_ctx *c, const int64_t n[3], const int64_t lo[3], 
     }
 }
 
-static size_t raw_box_ws(const sal_ctx *c, const int64_t bd[3], const int64_t ed[3])
+// Windows on the stride-S lattice: the lattice points whose interpolation reaches the
+// voxels eo + [0, ed) (floor(u/S) and the next one, held at the last point K - 1), as the
+// lattice index range klo + [0, kd) and the voxel box {o, d} whose lattice they are.
+static void lattice_box(const sal_ctx *c, const int64_t n[3], const int64_t eo[3], const int64_t ed[3], int64_t klo[3],
+                        int64_t kd[3], int64_t K[3], int64_t vbox[6])
 {
-    (void)bd;
-    return align256((size_t)3 * ed[0] * ed[1] * ed[2] * sizeof(float)) +
-           align256((size_t)energy_num_blocks(c, ed[0], ed[1], ed[2]) * sizeof(float));
+    const int64_t S = c->p.stride;
+    for (int a = 0; a < 3; ++a) {
+        K[a] = (n[a] + S - 1) / S;
+        klo[a] = eo[a] / S;
+        int64_t khi = (eo[a] + ed[a] - 1) / S + 1;
+        if (khi > K[a] - 1) khi = K[a] - 1;
+        kd[a] = khi - klo[a] + 1;
+        vbox[a] = klo[a] * S;
+        vbox[3 + a] = (kd[a] - 1) * S + 1;
+    }
+}
+
+// An upper bound of the energy kernels' workgroups for a box of k window positions per axis
+// that grows with the box: every fused tile holds at least 8 x 16 positions and walks at
+// least 2 of them along t; the window-by-window kernel launches at most 4096.
+static int64_t energy_blocks_bound(const sal_ctx *c, const int64_t k[3])
+{
+    if (uses_window_kernel(c)) return 4096;
+    return ((k[1] + 7) / 8) * ((k[2] + 15) / 16) * ((k[0] + 1) / 2);
+}
+
+// workspace of sal_raw_box: E of the grown box, then (stride > 1) the lattice energies it
+// interpolates, then the energy kernel's partials; kd bounds the lattice box
+static size_t raw_box_ws(const sal_ctx *c, const int64_t ed[3], const int64_t kd[3])
+{
+    const int64_t S = c->p.stride;
+    size_t w = align256((size_t)3 * ed[0] * ed[1] * ed[2] * sizeof(float));
+    if (S > 1) w += align256((size_t)3 * kd[0] * kd[1] * kd[2] * sizeof(float));
+    const int64_t nb = energy_blocks_bound(c, S > 1 ? kd : ed);
+    return w + align256((size_t)nb * sizeof(float));
 }
 
 sal_status sal_raw_box_workspace_size(sal_ctx *c, const int64_t box_dims[3], size_t *bytes)
 {
     if (!c || !box_dims || !bytes) return fail(c, SAL_E_INVAL, "null argument");
-    int64_t ed[3];
+    int64_t ed[3], kd[3];
     for (int a = 0; a < 3; ++a) {
         if (box_dims[a] < 1 || box_dims[a] > (1 << 20)) return fail(c, SAL_E_INVAL, "bad box size");
         ed[a] = box_dims[a] + 2 * c->r;
+        kd[a] = (ed[a] - 1) / c->p.stride + 3;  // at most this many lattice points reach a box of ed
     }
-    *bytes = raw_box_ws(c, box_dims, ed);
+    *bytes = raw_box_ws(c, ed, kd);
     return SAL_OK;
 }
 
@@ -667,26 +699,37 @@ sal_status sal_raw_box(sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64
     if (!V || !box_lo || !box_dims || !S_raw_box || !workspace) return fail(c, SAL_E_INVAL, "null pointer");
     if (!aligned16(V) || !aligned16(S_raw_box) || !aligned16(workspace))
         return fail(c, SAL_E_INVAL, "pointers must be 16-byte aligned");
-    if (c->p.stride != 1) return fail(c, SAL_E_UNSUPPORTED, "box maps are computed with stride 1 only");
     sal_status st = check_dims(c, n0, n1, n2);
     if (st != SAL_OK) return st;
     const int64_t n[3] = {n0, n1, n2};
     for (int a = 0; a < 3; ++a)
         if (box_lo[a] < 0 || box_dims[a] < 1 || box_lo[a] + box_dims[a] > n[a])
             return fail(c, SAL_E_INVAL, "box outside the volume");
-    int64_t eo[3], ed[3];
+    int64_t eo[3], ed[3], klo[3], kd[3], K[3], vbox[6];
     grow_box(c, n, box_lo, box_dims, eo, ed);
-    const size_t need = raw_box_ws(c, box_dims, ed);
+    lattice_box(c, n, eo, ed, klo, kd, K, vbox);
+    const size_t need = raw_box_ws(c, ed, kd);
     if (ws_bytes < need) return fail(c, SAL_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
     DevScope ds(c->device);
     if ((st = sticky(c)) != SAL_OK) return st;
     char *ws = (char *)workspace;
     float *Eb = (float *)ws;
-    float *vmax = (float *)(ws + align256((size_t)3 * ed[0] * ed[1] * ed[2] * sizeof(float)));
+    size_t off = align256((size_t)3 * ed[0] * ed[1] * ed[2] * sizeof(float));
     hipStream_t s = (hipStream_t)stream;
-    const int64_t box[6] = {eo[0], eo[1], eo[2], ed[0], ed[1], ed[2]};
-    hipError_t e = launch_energy(c, V, n0, n1, n2, box, Eb, vmax, nullptr, s);
-    if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    hipError_t e;
+    if (c->p.stride > 1) {
+        // the lattice energies around the grown box, interpolated onto it
+        float *El = (float *)(ws + off);
+        off += align256((size_t)3 * kd[0] * kd[1] * kd[2] * sizeof(float));
+        e = launch_energy(c, V, n0, n1, n2, vbox, El, (float *)(ws + off), nullptr, s);
+        if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+        e = launch_upsample_box(El, kd, klo, K, c->p.stride, eo, ed, Eb, s);
+        if (e != hipSuccess) return dev_fail(c, e, "upsample launch");
+    } else {
+        const int64_t box[6] = {eo[0], eo[1], eo[2], ed[0], ed[1], ed[2]};
+        e = launch_energy(c, V, n0, n1, n2, box, Eb, (float *)(ws + off), nullptr, s);
+        if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    }
     e = launch_dcs_box(c, Eb, eo, ed, n, box_lo, box_dims, S_raw_box, s);
     if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
     return SAL_OK;
@@ -737,26 +780,33 @@ static int check_boxes(const sal_ctx *c, const int64_t lo[3], const int64_t td[3
 
 // workspace of sal_check_tiles: E of every grown box, the exact tile maps, and the tables
 // (at most five energy boxes per tile)
+// With windows on a lattice (stride > 1), one energy box per tile: its lattice box, whose
+// energies (lstride floats apart) are interpolated onto the grown box (LAT_TABLE ints each).
 struct CheckWs {
-    size_t e, exact, table, total;
-    int64_t maxg[3], estride;
+    size_t e, exact, lat, table, total;
+    int64_t maxg[3], estride, maxkd[3], lstride;
 };
 static CheckWs check_ws(const sal_ctx *c, const int64_t n[3], int64_t nbox, const int64_t td[3])
 {
     CheckWs w;
-    for (int a = 0; a < 3; ++a) w.maxg[a] = td[a] + 2 * c->r < n[a] ? td[a] + 2 * c->r : n[a];
+    const int64_t S = c->p.stride;
+    for (int a = 0; a < 3; ++a) {
+        w.maxg[a] = td[a] + 2 * c->r < n[a] ? td[a] + 2 * c->r : n[a];
+        w.maxkd[a] = S > 1 ? (w.maxg[a] - 1) / S + 3 : 0;
+    }
     w.estride = 3 * w.maxg[0] * w.maxg[1] * w.maxg[2];
+    w.lstride = 3 * w.maxkd[0] * w.maxkd[1] * w.maxkd[2];
     w.e = 0;
     w.exact = w.e + align256((size_t)nbox * w.estride * sizeof(float));
-    w.table = w.exact + align256((size_t)nbox * 3 * td[0] * td[1] * td[2] * sizeof(float));
-    w.total = w.table + align256((size_t)nbox * (5 * ENERGY_TABLE + BOX_TABLE) * sizeof(int));
+    w.lat = w.exact + align256((size_t)nbox * 3 * td[0] * td[1] * td[2] * sizeof(float));
+    w.table = w.lat + (S > 1 ? align256((size_t)nbox * w.lstride * sizeof(float)) : 0);
+    w.total = w.table + align256((size_t)nbox * (5 * ENERGY_TABLE + BOX_TABLE + (S > 1 ? LAT_TABLE : 0)) * sizeof(int));
     return w;
 }
 
 static sal_status check_tile_args(sal_ctx *c, int64_t n0, int64_t n1, int64_t n2, int64_t nbox,
                                   const int64_t td[3])
 {
-    if (c->p.stride != 1) return fail(c, SAL_E_UNSUPPORTED, "tile checks are computed with stride 1 only");
     sal_status st = check_dims(c, n0, n1, n2);
     if (st != SAL_OK) return st;
     if (nbox < 1 || nbox > (1 << 20)) return fail(c, SAL_E_INVAL, "nbox must be in [1, 2^20]");
@@ -797,7 +847,7 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
     if (!(bound >= 0.0)) return fail(c, SAL_E_INVAL, "bound must be >= 0");
     const int64_t n[3] = {n0, n1, n2}, m[3] = {m0, m1, m2};
     // energy boxes (ENERGY_TABLE ints each) first, then one BOX_TABLE entry per tile
-    std::vector<int> etab, ttab((size_t)nbox * BOX_TABLE, 0);
+    std::vector<int> etab, ttab((size_t)nbox * BOX_TABLE, 0), ltab;
     etab.reserve((size_t)nbox * 5 * ENERGY_TABLE);
     int64_t maxd[3] = {1, 1, 1};
     for (int64_t b = 0; b < nbox; ++b) {
@@ -816,6 +866,21 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
             q[3 + a] = (int)ed[a];
             q[6 + a] = (int)lo[a];
             q[9 + a] = (int)to[a];
+        }
+        if (c->p.stride > 1) {
+            // the lattice box around the grown box, framed by itself; then its interpolation
+            int64_t klo[3], kd[3], K[3], vbox[6];
+            lattice_box(c, n, eo, ed, klo, kd, K, vbox);
+            const int e[ENERGY_TABLE] = {(int)vbox[0], (int)vbox[1], (int)vbox[2], (int)vbox[3], (int)vbox[4],
+                                         (int)vbox[5], (int)vbox[0], (int)vbox[1], (int)vbox[2], (int)kd[0],
+                                         (int)kd[1], (int)kd[2], (int)b, 0, 0, 0};
+            etab.insert(etab.end(), e, e + ENERGY_TABLE);
+            const int l[LAT_TABLE] = {(int)kd[0], (int)kd[1], (int)kd[2], (int)klo[0], (int)klo[1], (int)klo[2],
+                                      (int)K[0], (int)K[1], (int)K[2], (int)eo[0], (int)eo[1], (int)eo[2],
+                                      (int)ed[0], (int)ed[1], (int)ed[2]};
+            ltab.insert(ltab.end(), l, l + LAT_TABLE);
+            for (int a = 0; a < 3; ++a) maxd[a] = vbox[3 + a] > maxd[a] ? vbox[3 + a] : maxd[a];
+            continue;
         }
         const int k = check_boxes(c, lo, tile_dims, eo, ed, sub);
         for (int i = 0; i < k; ++i) {
@@ -845,8 +910,9 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
     char *ws = (char *)workspace;
     float *Eb = (float *)(ws + w.e);
     float *X = exact_out ? exact_out : (float *)(ws + w.exact);
-    int *etab_d = (int *)(ws + w.table), *ttab_d = etab_d + etab.size();
+    int *etab_d = (int *)(ws + w.table), *ttab_d = etab_d + etab.size(), *ltab_d = ttab_d + ttab.size();
     etab.insert(etab.end(), ttab.begin(), ttab.end());
+    etab.insert(etab.end(), ltab.begin(), ltab.end());
     // stage the tables in the context's pinned buffer, once the previous upload from it is done
     if (!c->tab_done && (e = hipEventCreateWithFlags(&c->tab_done, hipEventDisableTiming)) != hipSuccess)
         return dev_fail(c, e, "event create");
@@ -863,8 +929,16 @@ sal_status sal_check_tiles(sal_ctx *c, const float *V, int64_t n0, int64_t n1, i
     e = hipMemcpyAsync(etab_d, c->tab_host, etab.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return dev_fail(c, e, "box table upload");
     if ((e = hipEventRecord(c->tab_done, s)) != hipSuccess) return dev_fail(c, e, "event record");
-    e = launch_energy_boxes(c, V, n0, n1, n2, vol_stride, etab_d, nent, maxd, Eb, w.estride, nullptr, nullptr, s);
-    if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    if (c->p.stride > 1) {
+        float *El = (float *)(ws + w.lat);
+        e = launch_energy_boxes(c, V, n0, n1, n2, vol_stride, etab_d, nent, maxd, El, w.lstride, nullptr, nullptr, s);
+        if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+        e = launch_upsample_boxes(El, w.lstride, ltab_d, (int)nbox, w.maxg, (int)c->p.stride, Eb, w.estride, s);
+        if (e != hipSuccess) return dev_fail(c, e, "upsample launch");
+    } else {
+        e = launch_energy_boxes(c, V, n0, n1, n2, vol_stride, etab_d, nent, maxd, Eb, w.estride, nullptr, nullptr, s);
+        if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+    }
     e = launch_dcs_boxes(c, Eb, w.estride, ttab_d, (int)nbox, n, tile_dims, X, s);
     if (e != hipSuccess) return dev_fail(c, e, "dcs launch");
     e = launch_tile_merge_boxes(S_raw, m0, m1, m2, X, ttab_d, (int)nbox, tile_dims, stats, bound, err_out, s);

@@ -202,6 +202,15 @@ hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, 
 int64_t dcs_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
 hipError_t launch_upsample(const float *El, int64_t K0, int64_t K1, int64_t K2, int S, int64_t n0, int64_t n1,
                            int64_t n2, float *E, hipStream_t s);
+// ints per box of the batched interpolation: {kd, klo, K, eo, ed} (three each)
+constexpr int LAT_TABLE = 15;
+// nbox boxes, table entries of LAT_TABLE ints (device), maxed the largest box
+hipError_t launch_upsample_boxes(const float *El, int64_t lstride, const int *table, int nbox, const int64_t maxed[3],
+                                 int S, float *E, int64_t estride, hipStream_t s);
+// El: the lattice points klo + [0, kd) of a volume with lattice dims K; E: the voxels
+// eo + [0, ed), box-local
+hipError_t launch_upsample_box(const float *El, const int64_t kd[3], const int64_t klo[3], const int64_t K[3], int S,
+                               const int64_t eo[3], const int64_t ed[3], float *E, hipStream_t s);
 hipError_t launch_dcs_box(const sal_ctx *c, const float *Eb, const int64_t eo[3], const int64_t ed[3],
                           const int64_t n[3], const int64_t bo[3], const int64_t bd[3], float *S,
                           hipStream_t s);

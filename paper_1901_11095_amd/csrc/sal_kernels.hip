@@ -414,33 +414,69 @@ __global__ __launch_bounds__(256) void k_dcs(const float *__restrict__ E, int n0
 // Strided windows: energies on the lattice of stride S (El [3][K0][K1][K2], positions k S)
 // interpolated trilinearly onto every voxel; beyond the last lattice point of an axis the
 // last value is held.  Corners are summed in the order (t, x, y) = 000, 001, ..., 111.
-__global__ __launch_bounds__(256) void k_upsample(const float *__restrict__ El, int K0, int K1, int K2, int S,
-                                                  int n0, int n1, int n2, float *__restrict__ E)
+// Lattice energies to voxel energies (windows on the stride-S lattice): E at voxel u is the
+// trilinear interpolation of the lattice values at floor(u/S) and the next lattice point
+// along each axis (the last one held past the last lattice point, K = ceil(n/S) of the
+// volume), the weights (u - kS)/S being exact.  El holds the lattice points klo + [0, kd)
+// of the volume; E receives the voxels eo + [0, ed) box-local, [3][ed0][ed1][ed2].
+struct lat_box {
+    int kd0, kd1, kd2, klo0, klo1, klo2, K0, K1, K2, eo0, eo1, eo2, ed0, ed1, ed2;
+};
+static_assert(sizeof(lat_box) == LAT_TABLE * sizeof(int), "lat_box is one table entry");
+
+// voxel v (box-local index) of the box b, from the lattice energies El of b
+__device__ __forceinline__ void upsample_at(const float *__restrict__ El, const lat_box &b, int S, float inv,
+                                            int64_t v, int64_t N, int64_t NK, float *__restrict__ E)
 {
-    const int64_t N = (int64_t)n0 * n1 * n2, NK = (int64_t)K0 * K1 * K2;
-    const float inv = 1.0f / (float)S;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256) {
-        const int y = (int)(v % n2);
-        const int64_t rest = v / n2;
-        const int x = (int)(rest % n1), t = (int)(rest / n1);
-        const int kt = t / S, kx = x / S, ky = y / S;
-        const int kt1 = min(kt + 1, K0 - 1), kx1 = min(kx + 1, K1 - 1), ky1 = min(ky + 1, K2 - 1);
-        const float ft = kt1 == kt ? 0.f : (float)(t - kt * S) * inv;
-        const float fx = kx1 == kx ? 0.f : (float)(x - kx * S) * inv;
-        const float fy = ky1 == ky ? 0.f : (float)(y - ky * S) * inv;
+    const int y = b.eo2 + (int)(v % b.ed2);
+    const int64_t rest = v / b.ed2;
+    const int x = b.eo1 + (int)(rest % b.ed1), t = b.eo0 + (int)(rest / b.ed1);
+    const int kt = t / S, kx = x / S, ky = y / S;
+    const int kt1 = min(kt + 1, b.K0 - 1), kx1 = min(kx + 1, b.K1 - 1), ky1 = min(ky + 1, b.K2 - 1);
+    const float ft = kt1 == kt ? 0.f : (float)(t - kt * S) * inv;
+    const float fx = kx1 == kx ? 0.f : (float)(x - kx * S) * inv;
+    const float fy = ky1 == ky ? 0.f : (float)(y - ky * S) * inv;
+    const int at = kt - b.klo0, ax = kx - b.klo1, ay = ky - b.klo2;
+    const int at1 = kt1 - b.klo0, ax1 = kx1 - b.klo1, ay1 = ky1 - b.klo2;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const float *P = El + m * NK;
-            float acc = 0.f;
+    for (int m = 0; m < 3; ++m) {
+        const float *P = El + m * NK;
+        float acc = 0.f;
 #pragma unroll
-            for (int corner = 0; corner < 8; ++corner) {
-                const int ht = (corner >> 2) & 1, hx = (corner >> 1) & 1, hy = corner & 1;
-                const float w = (ht ? ft : 1.f - ft) * (hx ? fx : 1.f - fx) * (hy ? fy : 1.f - fy);
-                acc = fmaf(w, P[((int64_t)(ht ? kt1 : kt) * K1 + (hx ? kx1 : kx)) * K2 + (hy ? ky1 : ky)], acc);
-            }
-            E[m * N + v] = acc;
+        for (int corner = 0; corner < 8; ++corner) {
+            const int ht = (corner >> 2) & 1, hx = (corner >> 1) & 1, hy = corner & 1;
+            const float w = (ht ? ft : 1.f - ft) * (hx ? fx : 1.f - fx) * (hy ? fy : 1.f - fy);
+            acc = fmaf(w, P[((int64_t)(ht ? at1 : at) * b.kd1 + (hx ? ax1 : ax)) * b.kd2 + (hy ? ay1 : ay)], acc);
         }
+        E[m * N + v] = acc;
     }
+}
+
+__global__ __launch_bounds__(256) void k_upsample(const float *__restrict__ El, lat_box b, int S,
+                                                  float *__restrict__ E)
+{
+    const int64_t N = (int64_t)b.ed0 * b.ed1 * b.ed2, NK = (int64_t)b.kd0 * b.kd1 * b.kd2;
+    const float inv = 1.0f / (float)S;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256)
+        upsample_at(El, b, S, inv, v, N, NK, E);
+}
+
+// The same for the tiles of a batch: workgroups [i * per_box, (i + 1) * per_box) serve box
+// i, whose lat_box is entry i of the table (LAT_TABLE ints), its lattice energies at
+// El + i * lstride and its voxel energies at E + i * estride.
+__global__ __launch_bounds__(256) void k_upsample_boxes(const float *__restrict__ El, int64_t lstride,
+                                                        const int *__restrict__ table, int per_box, int S,
+                                                        float *__restrict__ E, int64_t estride)
+{
+    const int i = blockIdx.x / per_box, blk = blockIdx.x - i * per_box;
+    const int *q = table + LAT_TABLE * i;
+    const lat_box b{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11], q[12], q[13], q[14]};
+    const int64_t N = (int64_t)b.ed0 * b.ed1 * b.ed2, NK = (int64_t)b.kd0 * b.kd1 * b.kd2;
+    const float inv = 1.0f / (float)S;
+    El += i * lstride;
+    E += i * estride;
+    for (int64_t v = (int64_t)blk * 256 + threadIdx.x; v < N; v += (int64_t)per_box * 256)
+        upsample_at(El, b, S, inv, v, N, NK, E);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1160,9 +1196,28 @@ hipError_t launch_dcs_boxes(const sal_ctx *c, const float *Eb, int64_t estride, 
 hipError_t launch_upsample(const float *El, int64_t K0, int64_t K1, int64_t K2, int S, int64_t n0, int64_t n1,
                            int64_t n2, float *E, hipStream_t s)
 {
-    const int64_t N = n0 * n1 * n2;
+    const int64_t z[3] = {0, 0, 0}, K[3] = {K0, K1, K2}, n[3] = {n0, n1, n2};
+    return launch_upsample_box(El, K, z, K, S, z, n, E, s);
+}
+
+hipError_t launch_upsample_boxes(const float *El, int64_t lstride, const int *table, int nbox, const int64_t maxed[3],
+                                 int S, float *E, int64_t estride, hipStream_t s)
+{
+    const int64_t N = maxed[0] * maxed[1] * maxed[2];
+    const int per_box = (int)((N + 255) / 256 < 64 ? (N + 255) / 256 : 64);
+    hipLaunchKernelGGL(k_upsample_boxes, dim3((unsigned)(per_box * nbox)), dim3(256), 0, s, El, lstride, table, per_box,
+                       S, E, estride);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample_box(const float *El, const int64_t kd[3], const int64_t klo[3], const int64_t K[3], int S,
+                               const int64_t eo[3], const int64_t ed[3], float *E, hipStream_t s)
+{
+    const lat_box b{(int)kd[0], (int)kd[1], (int)kd[2], (int)klo[0], (int)klo[1], (int)klo[2], (int)K[0], (int)K[1],
+                    (int)K[2], (int)eo[0], (int)eo[1], (int)eo[2], (int)ed[0], (int)ed[1], (int)ed[2]};
+    const int64_t N = ed[0] * ed[1] * ed[2];
     const unsigned nb = (unsigned)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
-    hipLaunchKernelGGL(k_upsample, dim3(nb), dim3(256), 0, s, El, (int)K0, (int)K1, (int)K2, S, (int)n0, (int)n1,
-                       (int)n2, E);
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upsample, dim3(nb), dim3(256), 0, s, El, b, S, E);
     return hipGetLastError();
 }

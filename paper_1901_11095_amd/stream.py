@@ -27,15 +27,18 @@ def pinned(V: np.ndarray) -> torch.Tensor:
     return t
 
 
-def _slabs(n0: int, slab: int, halo: int):
+def _slabs(n0: int, slab: int, halo: int, align: int = 1):
+    """Output rows [s0, s1) and the rows [a, b) they depend on; a is a multiple of `align`
+    (the window lattice of a strided context starts at row 0 of the volume)."""
     for s0 in range(0, n0, slab):
         s1 = min(n0, s0 + slab)
-        yield s0, s1, max(0, s0 - halo), min(n0, s1 + halo)
+        yield s0, s1, max(0, s0 - halo) // align * align, min(n0, s1 + halo)
 
 
 def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
                       S_raw: Optional[torch.Tensor] = None, device="cuda",
-                      keep: Optional[torch.Tensor] = None, ctx: Optional[sal.Saliency] = None):
+                      keep: Optional[torch.Tensor] = None, ctx: Optional[sal.Saliency] = None,
+                      align: int = 1):
     """Raw maps [3, n0, n1, n2] (device) of a pinned host volume; `compute(Vslab)` returns
     the raw maps [3, m, n1, n2] of a device slab [m, n1, n2].  With `keep` (device
     [n0, n1, n2]) the rows of every slab are also kept there as they pass.  max|V| is
@@ -45,7 +48,7 @@ def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
     dev = torch.device(device)
     if S_raw is None:
         S_raw = torch.empty((3, n0, n1, n2), dtype=torch.float32, device=dev)
-    rows = min(n0, slab + 2 * halo)
+    rows = min(n0, slab + 2 * halo + align - 1)
     bufs = [torch.empty((rows, n1, n2), dtype=torch.float32, device=dev) for _ in range(2)]
     comp = torch.cuda.current_stream(dev)
     copy = torch.cuda.Stream(dev)
@@ -57,7 +60,7 @@ def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
         b.record_stream(copy)
     done = [torch.cuda.Event(), torch.cuda.Event()]     # buffer free again
     ready = [torch.cuda.Event(), torch.cuda.Event()]    # buffer filled
-    slabs = list(_slabs(n0, slab, halo))
+    slabs = list(_slabs(n0, slab, halo, align))
     vmax = torch.zeros(1, dtype=torch.float32, device=dev)
     red = ctx if ctx is not None else sal.Saliency(L=8, device=dev.index or 0)
 
@@ -87,15 +90,18 @@ def raw_maps_streamed(V_host: torch.Tensor, compute, halo: int, slab: int = 64,
 
 
 def plain_streamed(ctx: sal.Saliency, V_host: torch.Tensor, slab: int = 64):
-    """The plain method on a host volume, slab by slab; returns (S, S_raw, stats)."""
-    halo = ctx.L // 2 + ctx.params.d // 2
+    """The plain method on a host volume, slab by slab; returns (S, S_raw, stats).  With
+    windows on the stride-s lattice each slab starts on a lattice row, and its halo also
+    holds the next lattice point of the interpolation (s more rows)."""
+    st = ctx.params.stride
+    halo = ctx.L // 2 + ctx.params.d // 2 + (st if st > 1 else 0)
 
     def compute(Vs):
         o = torch.empty((3,) + tuple(Vs.shape), dtype=torch.float32, device=Vs.device)
         ctx.saliency(Vs, S_raw_out=o)
         return o
 
-    S_raw, vmax = raw_maps_streamed(V_host, compute, halo, slab, ctx=ctx)
+    S_raw, vmax = raw_maps_streamed(V_host, compute, halo, slab, ctx=ctx, align=st)
     stats = torch.zeros(8, dtype=torch.float64, device=S_raw.device)
     S = sal.normalize_combine(ctx, S_raw, None, stats_out=stats, vmax=vmax)
     return S, S_raw, stats

@@ -117,9 +117,6 @@ def test_check_tiles_rejects():
         sal.check_tiles(ctx, V, [(0, 0, 0)], P, [(0, 30, 0)], (16, 16, 16), st, 0.02, err)
     with pytest.raises(sal.SalError):   # no tiles
         sal.check_tiles(ctx, V, np.zeros((0, 3)), P, np.zeros((0, 3)), (16, 16, 16), st, 0.02, err)
-    ctx2 = sal.Saliency(L=8, stride=2)
-    with pytest.raises(sal.SalError):   # stride 2
-        sal.check_tiles(ctx2, V, [(0, 0, 0)], P, [(0, 0, 0)], (16, 16, 16), st, 0.02, err)
 
 
 @pytest.fixture(scope="module")

@@ -82,7 +82,35 @@ def test_strided_rejects():
     with pytest.raises(sal.SalError) as ei:
         sal.Saliency(L=16, stride=3, precision=sal.BF16_SPLIT)
     assert ei.value.status == sal.SAL_E_UNSUPPORTED
-    ctx = sal.Saliency(L=8, stride=2)
-    with pytest.raises(sal.SalError) as ei:
-        ctx.raw_box(torch.zeros((20, 20, 20), device="cuda"), (0, 0, 0), (4, 4, 4))
-    assert ei.value.status == sal.SAL_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("L,s,prec", [(8, 2, sal.FP32), (16, 2, sal.BF16_SPLIT), (8, 3, sal.FP32), (16, 5, sal.FP32),
+                                      (12, 12, sal.FP32), (5, 2, sal.FP32)])
+def test_strided_box_tiles_stream_equal_resident(L, s, prec):
+    """With windows on the lattice, the box maps (lattice windows around the grown box,
+    interpolated onto it), the batched tile checks and the host-streamed slabs (each starting
+    on a lattice row) equal the whole-volume maps bit for bit."""
+    from paper_1901_11095_amd import stream
+    print("strided box/tiles/stream L=%d s=%d" % (L, s), flush=True)
+    shape = (45, 38, 51)
+    V = synth.make_volume(shape, seed=31, n_faults=2, throw=3, n_chaotic=1, chaotic_size=10)
+    ctx = sal.Saliency(L=L, stride=s, precision=prec)
+    Vd = torch.from_numpy(V).cuda()
+    S, _, Sr, st = ctx.saliency_maps(Vd)
+    for lo, dims in [((0, 0, 0), (9, 10, 11)), ((7, 13, 21), (16, 9, 12)), ((36, 29, 40), (9, 9, 11))]:
+        box = ctx.raw_box(Vd, lo, dims)
+        torch.cuda.synchronize()
+        assert torch.equal(box, Sr[:, lo[0]:lo[0] + dims[0], lo[1]:lo[1] + dims[1], lo[2]:lo[2] + dims[2]]), lo
+    td = (8, 8, 8)
+    tiles = [(0, 0, 0), (16, 8, 24), (37, 30, 43)]
+    X = torch.empty((len(tiles), 3) + td, dtype=torch.float32, device="cuda")
+    err = torch.zeros(len(tiles), dtype=torch.float32, device="cuda")
+    P = Sr.clone()
+    sal.check_tiles(ctx, Vd, tiles, P, tiles, td, st, 0.02, err, exact_out=X)
+    torch.cuda.synchronize()
+    for k, lo in enumerate(tiles):
+        assert torch.equal(X[k], Sr[:, lo[0]:lo[0] + 8, lo[1]:lo[1] + 8, lo[2]:lo[2] + 8]), lo
+    assert float(err.max()) == 0.0
+    S2, Sr2, _ = stream.plain_streamed(ctx, stream.pinned(V), slab=10)
+    torch.cuda.synchronize()
+    assert torch.equal(Sr2, Sr) and torch.equal(S2, S)
