@@ -145,8 +145,10 @@ hipError_t build_tables(sal_ctx *c)
     // conjugate bins (-mu, -nu, -om) that the half spectrum leaves out; 1/L^3 of the DFT and
     // 1/(L^3 - 1) of the mean are folded in.
     std::vector<float> wb;
-    // the 16-bit forms scale the t and x stage outputs by 1/L each (range of FP16)
-    const double stage_gain = c->p.precision == SAL_FP32 ? 1.0 : (double)(L * L);
+    // the FP16 forms scale the t and x stage outputs by 1/L each (range of FP16)
+    const int pr = c->p.precision;
+    const bool fp16_form = pr == SAL_FP16 || pr == SAL_FP16_SPLIT || pr == SAL_FP16_SPLITW;
+    const double stage_gain = fp16_form ? (double)(L * L) : 1.0;
     const double scale = stage_gain / ((double)L3 * (double)(L3 - 1));
     for (long mu = 0; mu < h; ++mu) {
         const bool self = (mu == 0 || mu == L / 2);
@@ -201,10 +203,12 @@ hipError_t build_tables(sal_ctx *c)
     for (size_t i = 0; i < wc.size(); ++i) wcf[i] = (float)wc[i];
     for (size_t i = 0; i < wa.size(); ++i) waf[i] = (float)wa[i];
     // 16-bit forms: hi = RNE(w), lo = RNE(w - hi) (lo = 0 when the matrix is not split),
-    // laid out as the per-lane A operands of the 16x16x32 MFMAs (see sal_energy16.hip)
+    // laid out as the per-lane A operands of the 16x16x32 MFMAs in the K orders of
+    // sal_energy16.hip
     const int prec = c->p.precision;
     const bool bf = prec == SAL_BF16 || prec == SAL_BF16_SPLIT || prec == SAL_BF16_SPLITW;
     const bool split = prec != SAL_BF16 && prec != SAL_FP16;
+    const bool dsplit = prec == SAL_BF16_SPLIT || prec == SAL_FP16_SPLIT;
     auto r16 = [&](double v) -> uint16_t { return bf ? to_bf16((float)v) : to_f16((float)v); };
     auto f16v = [&](uint16_t b) -> double { return bf ? (double)from_bf16(b) : (double)from_f16(b); };
     auto part = [&](double v, int s) -> uint16_t {
@@ -212,38 +216,64 @@ hipError_t build_tables(sal_ctx *c)
         if (s == 0) return hi;
         return split ? r16(v - f16v(hi)) : (uint16_t)0;
     };
-    const long J = L / 8;
-    std::vector<uint32_t> c16((size_t)MT * J * 64 * 4, 0u), a16((size_t)MTA * 64 * 4, 0u);
+    auto word = [](uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); };
+    // complex contractions: three products at cube 16 with the data split (A operands W_hi,
+    // W_lo over taps 4g..4g+3), else J = L/8 MFMAs, lane group g holding part g >> 1 of taps
+    // 8j + 4(g & 1)..+3; t contraction: TPL = L/4 taps per lane group, one word per tap
+    // (two with the data split)
+    const bool three = L == 16 && dsplit;
+    const long J = L / 8, NA = three ? 2 : J, TPL = L / 4;
+    const long NWA = dsplit ? 2 * TPL : TPL, JA = (NWA + 3) / 4;
+    std::vector<uint32_t> c16((size_t)MT * NA * 64 * 4, 0u), a16((size_t)MTA * JA * 64 * 4, 0u);
     // cube 16, stage B in two halves of eight rows: half p holds the frequencies nu below,
     // so that the rows nu = k and 16 - k of every weight group lie in the same half
     static const long half_nu[2][8] = {{0, 1, 15, 2, 14, 3, 13, 8}, {4, 12, 5, 11, 6, 10, 7, 9}};
-    std::vector<uint32_t> c16b(L == 16 ? c16.size() : 4, 0u);
+    std::vector<uint32_t> c16b(three ? (size_t)2 * NA * 64 * 4 : 4, 0u);
     if (prec != SAL_FP32) {
+        // A operand of M row `row` (freq, re|im) for lane group g, operand a, word w
+        auto cword = [&](long row, long g, long a, long w) -> uint32_t {
+            long q, prt;
+            if (three) {
+                q = 4 * g + w;
+                prt = a;
+            } else {
+                q = 8 * a + 4 * (g & 1) + w;
+                prt = g >> 1;
+            }
+            return word(part(wc[row * 2 * L + 2 * q], (int)prt), part(wc[row * 2 * L + 2 * q + 1], (int)prt));
+        };
         for (long mt = 0; mt < MT; ++mt)
-            for (long j = 0; j < J; ++j)
+            for (long a = 0; a < NA; ++a)
+                for (long lane = 0; lane < 64; ++lane)
+                    for (long w = 0; w < 4; ++w)
+                        c16[((mt * NA + a) * 64 + lane) * 4 + w] = cword(16 * mt + lane % 16, lane / 16, a, w);
+        if (three)
+            for (long hp = 0; hp < 2; ++hp)
+                for (long a = 0; a < NA; ++a)
+                    for (long lane = 0; lane < 64; ++lane) {
+                        const long i = lane % 16, row = 2 * half_nu[hp][i / 2] + (i & 1);
+                        for (long w = 0; w < 4; ++w) c16b[((hp * NA + a) * 64 + lane) * 4 + w] = cword(row, lane / 16, a, w);
+                    }
+        for (long mt = 0; mt < MTA; ++mt)
+            for (long ja = 0; ja < JA; ++ja)
                 for (long lane = 0; lane < 64; ++lane) {
                     const long g = lane / 16, i = lane % 16;
-                    for (long e = 0; e < 8; ++e) {
-                        const long q = 8 * j + 4 * (g & 1) + e / 2, ci = e & 1;
-                        const uint16_t v = part(wc[(16 * mt + i) * 2 * L + 2 * q + ci], (int)(g >> 1));
-                        c16[((mt * J + j) * 64 + lane) * 4 + e / 2] |= (uint32_t)v << (16 * (e & 1));
-                        if (L == 16) {
-                            const long row = 2 * half_nu[mt][i / 2] + (i & 1);
-                            const uint16_t vb = part(wc[row * 2 * L + 2 * q + ci], (int)(g >> 1));
-                            c16b[((mt * J + j) * 64 + lane) * 4 + e / 2] |= (uint32_t)vb << (16 * (e & 1));
+                    for (long w = 0; w < 4; ++w) {
+                        const long q = 4 * ja + w;
+                        uint32_t v = 0u;
+                        if (dsplit) {
+                            // data word d_hi | d_lo against (W_part, W_part)
+                            const long p = TPL * g + q / 2;
+                            const uint16_t x = part(wa[(16 * mt + i) * L + p], (int)(q & 1));
+                            v = word(x, x);
+                        } else if (q < TPL) {
+                            // data word d | d against (W_hi, W_lo)
+                            const double x = wa[(16 * mt + i) * L + TPL * g + q];
+                            v = word(part(x, 0), part(x, 1));
                         }
+                        a16[((mt * JA + ja) * 64 + lane) * 4 + w] = v;
                     }
                 }
-        for (long mt = 0; mt < MTA; ++mt)
-            for (long lane = 0; lane < 64; ++lane) {
-                const long g = lane / 16, i = lane % 16;
-                for (long e = 0; e < 8; ++e) {
-                    const long p = 4 * g + e / 2;
-                    const double w = (p < L) ? wa[(16 * mt + i) * L + p] : 0.0;
-                    const uint16_t v = part(w, (int)(e & 1));
-                    a16[(mt * 64 + lane) * 4 + e / 2] |= (uint32_t)v << (16 * (e & 1));
-                }
-            }
     }
     // the FP32 kernel's stage-B halves at cube 16: lane (g, n) of K step kk holds row n of
     // the half's tile at K = KS g + kk, the tile's rows being (nu, re|im) of the half's list

@@ -65,7 +65,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(S == 1 ? TileCfg<L>::WPE : 2))) __
     __shared__ float wa_s[16 * MTA * L];
     __shared__ float red_s[NW];
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is uniform: kept in a scalar register, so per-wave offsets are scalar
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, n = lane & 15;
 
     int box;
@@ -97,14 +98,15 @@ __global__ __attribute__((amdgpu_waves_per_eu(S == 1 ? TileCfg<L>::WPE : 2))) __
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
-    const int64_t plane = (int64_t)n1 * n2;
+    const int n12 = n1 * n2;  // the volume holds at most 2^31 - 1 samples
     const int64_t nbox = (int64_t)bx.fk0 * K1 * K2;
     float vmax = 0.0f;
     float2 *Bw = B_s[wave];
 
     // Volume samples of the stage-A positions of this wave for one t0.  The loads for the
     // next t0 are issued after stage C, so they hold no registers through stages B and C.
-    // The 32-bit position offsets are kept; the 64-bit addresses are formed at each load.
+    // The 32-bit position offsets are kept; the row offsets of the lane's taps are formed
+    // once per t0 and each load adds the two.
     int off_xy[NJ];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
@@ -114,14 +116,15 @@ __global__ __attribute__((amdgpu_waves_per_eu(S == 1 ? TileCfg<L>::WPE : 2))) __
     }
     float vnext[NJ][KSA];
     auto load_a = [&](int t0) {
+        int rowo[KSA];
+#pragma unroll
+        for (int kk = 0; kk < KSA; ++kk) rowo[kk] = refl_idx(t0 - H + KSA * g + kk, n0) * n12;
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
             const int off = opaque(off_xy[jj]);
 #pragma unroll
-            for (int kk = 0; kk < KSA; ++kk) {
-                const int tr = refl_idx(t0 - H + KSA * g + kk, n0);
-                vnext[jj][kk] = (wave + NW * jj < NTA) ? V[tr * plane + off] : 0.f;
-            }
+            for (int kk = 0; kk < KSA; ++kk)
+                vnext[jj][kk] = (wave + NW * jj < NTA) ? V[(uint32_t)(rowo[kk] + off)] : 0.f;
         }
     };
     load_a(t_begin);
