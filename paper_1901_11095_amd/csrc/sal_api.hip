@@ -139,6 +139,14 @@ hipError_t build_tables(sal_ctx *c)
             wa[(2 * mu) * L + p] = cs;
             wa[(2 * mu + 1) * L + p] = sn;
         }
+    // Stage-C output order: slot s (M rows 2s, 2s+1, lane group (s mod 8) / 2 of M tile s / 8)
+    // holds frequency ordc[s].  At cube 16 tile 0 pairs om with L - om in every lane (the
+    // projection weights depend on squared frequencies, so both bins share them); the
+    // x-stage matrices keep frequency order.
+    std::vector<long> ordc(L);
+    static const long ord16[16] = {1, 15, 2, 14, 3, 13, 4, 12, 5, 11, 6, 10, 7, 9, 0, 8};
+    for (long s = 0; s < L; ++s) ordc[s] = L == 16 ? ord16[s] : s;
+    auto crow = [&](long r) { return 2 * ordc[r / 2] + (r & 1); };  // stage-C M row -> w_c row
     // Weights of the two bins lane group g owns in M tile mt, for every group (mu, k),
     // k = 0..L/2: the row nu = k, joined by its mirror row nu = L - k when mu is not 0 or
     // L/2 (same squared frequencies, so same weights).  The multiplicity counts the
@@ -158,7 +166,7 @@ hipError_t build_tables(sal_ctx *c)
                 for (long g = 0; g < 4; ++g) {
                     float ent[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                     for (long bb = 0; bb < 2; ++bb) {
-                        const long om = 8 * mt + 2 * g + bb;
+                        const long om = ordc[8 * mt + 2 * g + bb];
                         double w[3];
                         proj_w(sfreq(mu, L), sfreq(nu, L), sfreq(om, L), w);
                         for (int m = 0; m < 3; ++m) ent[3 * bb + m] = (float)(w[m] * mult * scale);
@@ -200,7 +208,8 @@ hipError_t build_tables(sal_ctx *c)
                 for (int m = 0; m < 3; ++m) wp[4 * b + m] = (float)(w[m] / (double)(L3 - 1));
             }
     std::vector<float> wcf(wc.size()), waf(wa.size());
-    for (size_t i = 0; i < wc.size(); ++i) wcf[i] = (float)wc[i];
+    for (long r = 0; r < 2 * L; ++r)
+        for (long q = 0; q < 2 * L; ++q) wcf[r * 2 * L + q] = (float)wc[crow(r) * 2 * L + q];
     for (size_t i = 0; i < wa.size(); ++i) waf[i] = (float)wa[i];
     // 16-bit forms: hi = RNE(w), lo = RNE(w - hi) (lo = 0 when the matrix is not split),
     // laid out as the per-lane A operands of the 16x16x32 MFMAs in the K orders of
@@ -228,7 +237,9 @@ hipError_t build_tables(sal_ctx *c)
     // cube 16, stage B in two halves of eight rows: half p holds the frequencies nu below,
     // so that the rows nu = k and 16 - k of every weight group lie in the same half
     static const long half_nu[2][8] = {{0, 1, 15, 2, 14, 3, 13, 8}, {4, 12, 5, 11, 6, 10, 7, 9}};
-    std::vector<uint32_t> c16b(three ? (size_t)2 * NA * 64 * 4 : 4, 0u);
+    // cube 16: stage-B operands of their own (halves' row order with the data split, else
+    // frequency order per M tile)
+    std::vector<uint32_t> c16b(L == 16 ? (size_t)2 * NA * 64 * 4 : 4, 0u);
     if (prec != SAL_FP32) {
         // A operand of M row `row` (freq, re|im) for lane group g, operand a, word w
         auto cword = [&](long row, long g, long a, long w) -> uint32_t {
@@ -246,7 +257,13 @@ hipError_t build_tables(sal_ctx *c)
             for (long a = 0; a < NA; ++a)
                 for (long lane = 0; lane < 64; ++lane)
                     for (long w = 0; w < 4; ++w)
-                        c16[((mt * NA + a) * 64 + lane) * 4 + w] = cword(16 * mt + lane % 16, lane / 16, a, w);
+                        c16[((mt * NA + a) * 64 + lane) * 4 + w] = cword(crow(16 * mt + lane % 16), lane / 16, a, w);
+        if (L == 16 && !three)
+            for (long mt = 0; mt < MT; ++mt)
+                for (long a = 0; a < NA; ++a)
+                    for (long lane = 0; lane < 64; ++lane)
+                        for (long w = 0; w < 4; ++w)
+                            c16b[((mt * NA + a) * 64 + lane) * 4 + w] = cword(16 * mt + lane % 16, lane / 16, a, w);
         if (three)
             for (long hp = 0; hp < 2; ++hp)
                 for (long a = 0; a < NA; ++a)

@@ -179,6 +179,9 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     constexpr int NTB = (PY + 15) / 16, PYB = NTB * 16, NTC = TY / 16;
     constexpr int NPOS = PX * PY, NTA = (NPOS + 15) / 16, NJ = (NTA + NW - 1) / NW;
     constexpr int NGK = L / 2 + 1;
+    // cube 16: the stage-C matrix rows are ordered so that lane group g of M tile 0 holds the
+    // bins om and L - om (equal weights), and stage B reads its own matrix from LDS
+    constexpr bool FOLD = L == 16;
     constexpr int NWB = C::W_LDS ? h * NGK * MT * 32 : 1;
     constexpr float oscale = HT::SCALE ? 1.0f / (float)L : 1.0f;
     static_assert(3 * PY <= 255, "stage-B operand offsets must fit a paired LDS read");
@@ -191,8 +194,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
     // eight rows at a time and two workgroups fit a CU.  Otherwise one pass over all rows.
     constexpr int NH = (L == 16 && DS) ? 2 : 1, NROW = NH > 1 ? 8 : L;
     __shared__ uint32_t B_s[NW][NROW * NP * PYB];  // per wave [row][part][y']
-    // stage-B matrix of the halves (rows in the halves' order), per half NA operands
-    __shared__ u32x4 wcb_s[NH > 1 ? NH * NA * 64 : 1];
+    // cube 16, stage-B matrix: with the data split per half (rows in the halves' order) NA
+    // operands, else per M tile (rows in frequency order) J operands
+    constexpr int NWCB = L == 16 ? (NH > 1 ? NH * NA : MT * NA) : 0;
+    __shared__ u32x4 wcb_s[NWCB > 0 ? NWCB * 64 : 1];
     __shared__ float wb_s[NWB];
     __shared__ u32x4 wa_s[MTA * JA * 64];
     __shared__ float red_s[NW];
@@ -221,8 +226,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
 #pragma unroll
         for (int j = 0; j < NA; ++j) wc[mt][j] = reinterpret_cast<const u32x4 *>(w_c16)[(mt * NA + j) * 64 + lane];
     for (int i = threadIdx.x; i < MTA * JA * 64; i += 64 * NW) wa_s[i] = reinterpret_cast<const u32x4 *>(w_a16)[i];
-    if (NH > 1)
-        for (int i = threadIdx.x; i < NH * NA * 64; i += 64 * NW) wcb_s[i] = reinterpret_cast<const u32x4 *>(w_c16b)[i];
+    if (NWCB > 0)
+        for (int i = threadIdx.x; i < NWCB * 64; i += 64 * NW) wcb_s[i] = reinterpret_cast<const u32x4 *>(w_c16b)[i];
     if (C::W_LDS)
         for (int i = threadIdx.x; i < NWB; i += 64 * NW) wb_s[i] = w_grp[i];
 
@@ -327,7 +332,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
 #pragma unroll
                     for (int mt = 0; mt < BT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
                     auto wB = [&](int mt, int j) -> u32x4 {
-                        return NH > 1 ? wcb_s[(hp * NA + j) * 64 + lane] : wc[mt][j];
+                        return NWCB > 0 ? wcb_s[((NH > 1 ? hp : mt) * NA + j) * 64 + lane] : wc[mt][j];
                     };
                     if (THREE) {
                         const u32x4 bh = lds4s<PY>(Ab + ctap(0) * PY);
@@ -385,13 +390,15 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
                     }
                     const bool pair = !self && k > 0 && k < L / 2;
                     const int grp = mu * NGK + k;
+                    // weights of the group: a uniform base (scalar register) plus the
+                    // lane's fixed offset; a folded tile needs three per lane
                     float wv[MT][6];
+                    const float *wgp = C::W_LDS ? wb_s + grp * (MT * 32) : w_grp + grp * (MT * 32);
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) {
-                        const int wo = ((grp * MT + mt) * 4 + g) * 8;
+                    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
-                    }
+                        for (int q = 0; q < 6; ++q)
+                            wv[mt][q] = (FOLD && mt == 0 && q >= 3) ? 0.f : wgp[(mt * 4 + g) * 8 + q];
                     f4 acc[NTC][MT];
                     auto row_dft = [&](int pos) {
 #pragma unroll
@@ -466,10 +473,18 @@ __global__ __attribute__((amdgpu_waves_per_eu(HWpe<L, DS, S>::v))) __launch_boun
 #pragma unroll
                     for (int c = 0; c < NTC; ++c)
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
+                        for (int mt = 0; mt < MT; ++mt) {
+                            if (FOLD && mt == 0) {
+                                // the lane's two bins are om and L - om: one set of weights
+                                const float sm = m0[c][mt] + m1[c][mt];
 #pragma unroll
-                            for (int m = 0; m < 3; ++m)
-                                e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
+                                for (int m = 0; m < 3; ++m) e[c][m] = fmaf(wv[mt][m], sm, e[c][m]);
+                            } else {
+#pragma unroll
+                                for (int m = 0; m < 3; ++m)
+                                    e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
+                            }
+                        }
                 }
                 // the next half's stage B overwrites B_s
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -51,6 +51,9 @@ __global__ __attribute__((amdgpu_waves_per_eu(S == 1 ? TileCfg<L>::WPE : 2))) __
     constexpr int NTB = (PY + 15) / 16, PYB = NTB * 16, NTC = TY / 16;
     constexpr int NPOS = PX * PY, NTA = (NPOS + 15) / 16, NJ = (NTA + NW - 1) / NW;
     constexpr int NGK = L / 2 + 1;  // groups per mu
+    // cube 16: the stage-C matrix rows are ordered so that lane group g of M tile 0 holds the
+    // bins om and L - om (equal weights); stage B has its own matrix (the halves' table)
+    constexpr bool FOLD = L == 16;
     constexpr int NWB = C::W_LDS ? h * NGK * MT * 32 : 1;
 
     // At cube 16, stage B runs in two halves of eight frequency rows, each followed by the
@@ -241,13 +244,15 @@ __global__ __attribute__((amdgpu_waves_per_eu(S == 1 ? TileCfg<L>::WPE : 2))) __
                     // for mu, nu in {0, L/2} the stage-B row is real (the quarter-turn twiddles
                     // are exact, so its imaginary part is an exact zero): skip those K steps
                     const bool real_row = self && (k == 0 || k == L / 2);
+                    // weights of the group: a uniform base (scalar register) plus the
+                    // lane's fixed offset; a folded tile needs three per lane
                     float wv[MT][6];
+                    const float *wgp = C::W_LDS ? wb_s + grp * (MT * 32) : w_grp + grp * (MT * 32);
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) {
-                        const int wo = ((grp * MT + mt) * 4 + g) * 8;
+                    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) wv[mt][q] = C::W_LDS ? wb_s[wo + q] : w_grp[wo + q];
-                    }
+                        for (int q = 0; q < 6; ++q)
+                            wv[mt][q] = (FOLD && mt == 0 && q >= 3) ? 0.f : wgp[(mt * 4 + g) * 8 + q];
                     f4 acc[NTC][MT];
                     auto row_dft = [&](int pos, bool real) {
 #pragma unroll
@@ -306,10 +311,18 @@ __global__ __attribute__((amdgpu_waves_per_eu(S == 1 ? TileCfg<L>::WPE : 2))) __
 #pragma unroll
                     for (int c = 0; c < NTC; ++c)
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
+                        for (int mt = 0; mt < MT; ++mt) {
+                            if (FOLD && mt == 0) {
+                                // the lane's two bins are om and L - om: one set of weights
+                                const float sm = m0[c][mt] + m1[c][mt];
 #pragma unroll
-                            for (int m = 0; m < 3; ++m)
-                                e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
+                                for (int m = 0; m < 3; ++m) e[c][m] = fmaf(wv[mt][m], sm, e[c][m]);
+                            } else {
+#pragma unroll
+                                for (int m = 0; m < 3; ++m)
+                                    e[c][m] = fmaf(wv[mt][3 + m], m1[c][mt], fmaf(wv[mt][m], m0[c][mt], e[c][m]));
+                            }
+                        }
                 }
                 // the next pass's stage B overwrites B_s
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
