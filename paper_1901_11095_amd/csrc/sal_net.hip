@@ -125,6 +125,15 @@ __device__ __forceinline__ void store4(typename ActT<F32>::type *p, const typena
     else
         *reinterpret_cast<uint2 *>(p) = make_uint2(r[0] | ((uint32_t)r[1] << 16), r[2] | ((uint32_t)r[3] << 16));
 }
+// two consecutive channels of one voxel (8-byte aligned in FP32, 4-byte in BF16)
+template <bool F32>
+__device__ __forceinline__ void store2(typename ActT<F32>::type *p, const typename ActT<F32>::type r[2])
+{
+    if constexpr (F32)
+        *reinterpret_cast<float2 *>(p) = make_float2(r[0], r[1]);
+    else
+        *reinterpret_cast<uint32_t *>(p) = r[0] | ((uint32_t)r[1] << 16);
+}
 template <bool F32>
 __device__ __forceinline__ void load4(const typename ActT<F32>::type *p, typename ActT<F32>::type r[4])
 {
@@ -401,14 +410,38 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
                                                                       0, 0);
             }
         }
-        // epilogue: lane (g, n) holds channels 16mt + 4g + j of voxel n
+        // epilogue: lane (g, n) holds channels 16mt + 4g + j of voxel n.  With 24 output
+        // channels the last M tile holds 8, all in lane groups 0 and 1: its channels +2 and +3
+        // move to lane groups 2 and 3 (one lane swap per pair, done by every lane), so each lane
+        // evaluates two GELUs there instead of half the lanes evaluating four.
+        constexpr bool SPREAD = EPI == EPI_GELU && CO % 16 == 8;
+        float sp[2] = {0.f, 0.f};
+        if constexpr (SPREAD) {
+            const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[MT - 1][0]),
+                                                             __float_as_uint(acc[MT - 1][2]), false, false);
+            const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[MT - 1][1]),
+                                                             __float_as_uint(acc[MT - 1][3]), false, false);
+            sp[0] = __uint_as_float(s0[0]);
+            sp[1] = __uint_as_float(s1[0]);
+        }
         const int gt = t0 + lt, gu = u0 + lu, gw = w0 + n;
         if (gt < n0 && gu < n1 && gw < n2) {
             const int64_t v = b * vol + ((int64_t)gt * n1 + gu) * n2 + gw;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 const int cb = 16 * mt + 4 * g;
-                if (EPI == EPI_LINEAR) {
+                if (SPREAD && mt == MT - 1) {
+                    // channels c2, c2 + 1 of this voxel
+                    const int c2 = 16 * mt + 4 * (g & 1) + 2 * (g >> 1);
+                    Act zz[2], r[2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        zz[j] = to_act<F32>(sp[j] + bias_s[c2 + j]);
+                        r[j] = to_act<F32>(gelu_f(from_act<F32>(zz[j])));
+                    }
+                    if (out0) store2<F32>(reinterpret_cast<Act *>(out0) + v * CO + c2, zz);
+                    store2<F32>(reinterpret_cast<Act *>(out1) + v * CO + c2, r);
+                } else if (EPI == EPI_LINEAR) {
                     float *o = reinterpret_cast<float *>(out0);
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
