@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "saliency voxels/sec (plain FP32 vs BF16-split vs surrogate) at stated max error"
 PEAK_TFLOPS = {"f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "f32_vector": 78.6}
+HBM_PEAK_TBPS = 8.0  # MI355X HBM3E
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -121,6 +122,10 @@ def roofline_block(kernel: str, ms: float, nvox: int, flops_per_voxel: int, peak
         rec["frac_min"] = rec["frac"] * min_flops_per_voxel / flops_per_voxel
     if prof.get("algorithmic_bytes_per_launch"):
         rec["algorithmic_bytes"] = prof["algorithmic_bytes_per_launch"]
+    if rec["traffic"]:
+        # HBM rate of the measured traffic at this launch time, against the 8 TB/s peak
+        rec["hbm_gbps"] = rec["traffic"] / (ms * 1e-3) / 1e9
+        rec["hbm_frac"] = rec["hbm_gbps"] / (HBM_PEAK_TBPS * 1e3)
     return rec
 
 
