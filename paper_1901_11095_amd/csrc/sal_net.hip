@@ -191,6 +191,10 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
     // tile into a second LDS buffer by direct global-to-LDS loads while the current one
     // computes
     constexpr bool ASYNC = !F32 && CI > 1 && CI % 8 == 0 && MODE == MODE_REFLECT;
+    // forward BF16 layers with 24 input channels: two output rows share their input reads
+    // (the weight table of these layers is laid out in the matching K order)
+    constexpr bool PAIR = !F32 && CI == 24 && MODE == MODE_REFLECT;
+    static_assert(!PAIR || ksteps(CI) == 21, "paired rows expect 27 taps x 3 chunks in 7 x 3 K steps");
     // two separate LDS objects, so the compiler can tell reads of one from the loads landing
     // in the other (a read of the same object would wait for them)
     __shared__ __attribute__((aligned(16))) Act tileA[FNPOS * CIP];
@@ -336,6 +340,111 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
     // the next tile's loads)
     if (!ASYNC) __syncthreads();
 
+    // epilogue of one row of 16 output voxels (lt, lu, n) of the tile
+    auto epilogue = [&](f4(&acc)[MT], int lt, int lu) __attribute__((always_inline)) {
+        // epilogue: lane (g, n) holds channels 16mt + 4g + j of voxel n.  With 24 output
+        // channels the last M tile holds 8, all in lane groups 0 and 1: its channels +2 and +3
+        // move to lane groups 2 and 3 (one lane swap per pair, done by every lane), so each lane
+        // evaluates two GELUs there instead of half the lanes evaluating four.
+        constexpr bool SPREAD = EPI == EPI_GELU && CO % 16 == 8;
+        float sp[2] = {0.f, 0.f};
+        if constexpr (SPREAD) {
+            const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[MT - 1][0]),
+                                                             __float_as_uint(acc[MT - 1][2]), false, false);
+            const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[MT - 1][1]),
+                                                             __float_as_uint(acc[MT - 1][3]), false, false);
+            sp[0] = __uint_as_float(s0[0]);
+            sp[1] = __uint_as_float(s1[0]);
+        }
+        const int gt = t0 + lt, gu = u0 + lu, gw = w0 + n;
+        if (gt < n0 && gu < n1 && gw < n2) {
+            const int64_t v = b * vol + ((int64_t)gt * n1 + gu) * n2 + gw;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int cb = 16 * mt + 4 * g;
+                if (SPREAD && mt == MT - 1) {
+                    // channels c2, c2 + 1 of this voxel
+                    const int c2 = 16 * mt + 4 * (g & 1) + 2 * (g >> 1);
+                    Act zz[2], r[2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        zz[j] = to_act<F32>(sp[j] + bias_s[c2 + j]);
+                        r[j] = to_act<F32>(gelu_f(from_act<F32>(zz[j])));
+                    }
+                    if (out0) store2<F32>(reinterpret_cast<Act *>(out0) + v * CO + c2, zz);
+                    store2<F32>(reinterpret_cast<Act *>(out1) + v * CO + c2, r);
+                } else if (EPI == EPI_LINEAR) {
+                    float *o = reinterpret_cast<float *>(out0);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (cb + j < CO) {
+                            const float sc = cb + j == 0 ? oscale.x : (cb + j == 1 ? oscale.y : oscale.z);
+                            o[v * vstride + (cb + j) * cstride] = (acc[mt][j] + bias_s[cb + j]) * sc;
+                        }
+                } else if (cb < CO) {  // CO is a multiple of 4 here
+                    Act r[4];
+                    if (EPI == EPI_GELU) {
+                        Act zz[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float z = acc[mt][j] + bias_s[cb + j];
+                            zz[j] = to_act<F32>(z);
+                            r[j] = to_act<F32>(gelu_f(from_act<F32>(zz[j])));
+                        }
+                        if (out0) store4<F32>(reinterpret_cast<Act *>(out0) + v * CO + cb, zz);
+                        store4<F32>(reinterpret_cast<Act *>(out1) + v * CO + cb, r);
+                    } else {
+                        Act zv[4];
+                        load4<F32>(reinterpret_cast<const Act *>(zprev) + v * CO + cb, zv);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) r[j] = to_act<F32>(acc[mt][j] * gelu_grad_f(from_act<F32>(zv[j])));
+                        store4<F32>(reinterpret_cast<Act *>(out0) + v * CO + cb, r);
+                    }
+                }
+            }
+        }
+    };
+
+    if constexpr (PAIR) {
+        // Two rows (lu, lu + 1) at a time: for each (dt, dw, channel chunk) a lane reads the
+        // four input rows lu .. lu + 3 once, and the three K steps du = 0, 1, 2 use rows du and
+        // du + 1 for the two output rows (4 LDS reads for 12 MFMAs instead of 6; four
+        // independent accumulator chains).  K slot (3 sg + du, g) of the weight table holds
+        // tap (dt, du, dw) and chunk ch of tc = 4 sg + g = (dt * 3 + dw) * 3 + ch.
+#pragma unroll 1
+        for (int rp = 0; rp < 2; ++rp) {
+            const int lt = wave % FT, lu = (wave / FT) * 4 + 2 * rp;
+            f4 acc0[MT], acc1[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc0[mt] = acc1[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int sg = 0; sg < KS / 3; ++sg) {
+                const int tc = 4 * sg + g;
+                u32x4 P[4];
+                if (tc < 27) {
+                    const int dt = tc / 9, dw = (tc / 3) % 3, ch = tc % 3;
+                    const Act *src = &tile[(((lt + dt) * FPU + lu) * FPW + n + dw) * CIP + 8 * ch];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) P[i] = *reinterpret_cast<const u32x4 *>(src + i * FPW * CIP);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) P[i] = u32x4{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int du = 0; du < 3; ++du) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        acc0[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[mt][3 * sg + du]),
+                                                                           __builtin_bit_cast(bf16x8, P[du]), acc0[mt], 0, 0, 0);
+                        acc1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[mt][3 * sg + du]),
+                                                                           __builtin_bit_cast(bf16x8, P[du + 1]), acc1[mt], 0, 0, 0);
+                    }
+                }
+            }
+            epilogue(acc0, lt, lu);
+            epilogue(acc1, lt, lu + 1);
+        }
+    } else {
 #pragma unroll 1
     for (int row = 0; row < 4; ++row) {
         const int lt = wave % FT, lu = (wave / FT) * 4 + row;  // output voxel (lt, lu, n) of the tile
@@ -410,67 +519,8 @@ __global__ __launch_bounds__(conv_threads(CO)) void k_conv3(const void *__restri
                                                                       0, 0);
             }
         }
-        // epilogue: lane (g, n) holds channels 16mt + 4g + j of voxel n.  With 24 output
-        // channels the last M tile holds 8, all in lane groups 0 and 1: its channels +2 and +3
-        // move to lane groups 2 and 3 (one lane swap per pair, done by every lane), so each lane
-        // evaluates two GELUs there instead of half the lanes evaluating four.
-        constexpr bool SPREAD = EPI == EPI_GELU && CO % 16 == 8;
-        float sp[2] = {0.f, 0.f};
-        if constexpr (SPREAD) {
-            const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[MT - 1][0]),
-                                                             __float_as_uint(acc[MT - 1][2]), false, false);
-            const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[MT - 1][1]),
-                                                             __float_as_uint(acc[MT - 1][3]), false, false);
-            sp[0] = __uint_as_float(s0[0]);
-            sp[1] = __uint_as_float(s1[0]);
-        }
-        const int gt = t0 + lt, gu = u0 + lu, gw = w0 + n;
-        if (gt < n0 && gu < n1 && gw < n2) {
-            const int64_t v = b * vol + ((int64_t)gt * n1 + gu) * n2 + gw;
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const int cb = 16 * mt + 4 * g;
-                if (SPREAD && mt == MT - 1) {
-                    // channels c2, c2 + 1 of this voxel
-                    const int c2 = 16 * mt + 4 * (g & 1) + 2 * (g >> 1);
-                    Act zz[2], r[2];
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        zz[j] = to_act<F32>(sp[j] + bias_s[c2 + j]);
-                        r[j] = to_act<F32>(gelu_f(from_act<F32>(zz[j])));
-                    }
-                    if (out0) store2<F32>(reinterpret_cast<Act *>(out0) + v * CO + c2, zz);
-                    store2<F32>(reinterpret_cast<Act *>(out1) + v * CO + c2, r);
-                } else if (EPI == EPI_LINEAR) {
-                    float *o = reinterpret_cast<float *>(out0);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (cb + j < CO) {
-                            const float sc = cb + j == 0 ? oscale.x : (cb + j == 1 ? oscale.y : oscale.z);
-                            o[v * vstride + (cb + j) * cstride] = (acc[mt][j] + bias_s[cb + j]) * sc;
-                        }
-                } else if (cb < CO) {  // CO is a multiple of 4 here
-                    Act r[4];
-                    if (EPI == EPI_GELU) {
-                        Act zz[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const float z = acc[mt][j] + bias_s[cb + j];
-                            zz[j] = to_act<F32>(z);
-                            r[j] = to_act<F32>(gelu_f(from_act<F32>(zz[j])));
-                        }
-                        if (out0) store4<F32>(reinterpret_cast<Act *>(out0) + v * CO + cb, zz);
-                        store4<F32>(reinterpret_cast<Act *>(out1) + v * CO + cb, r);
-                    } else {
-                        Act zv[4];
-                        load4<F32>(reinterpret_cast<const Act *>(zprev) + v * CO + cb, zv);
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) r[j] = to_act<F32>(acc[mt][j] * gelu_grad_f(from_act<F32>(zv[j])));
-                        store4<F32>(reinterpret_cast<Act *>(out0) + v * CO + cb, r);
-                    }
-                }
-            }
-        }
+        epilogue(acc, lt, lu);
+    }
     }
     };
 
@@ -676,19 +726,33 @@ __global__ __launch_bounds__(256) void k_prep_tables(const float *__restrict__ W
                                                      float *__restrict__ bwd32, int bwd_rows, int bwd_k)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    // forward: row co, K index = tap * pad8(ci) + c (ci > 1) or tap (ci == 1)
+    // forward: row co, K index = tap * pad8(ci) + c (ci > 1) or tap (ci == 1).  The BF16 table
+    // of the 24-channel layers is in the paired-row order of k_conv3: K index 32 s + 8 g + e
+    // holds tap (dt, du, dw) and channel 8 ch + e, with s = 3 sg + du and 4 sg + g =
+    // (dt * 3 + dw) * 3 + ch (zero past the 27 taps x 3 chunks).
     if (i < fwd_rows * fwd_k) {
         const int r = i / fwd_k, kk = i % fwd_k;
-        float w = 0.f;
+        float w = 0.f, wp = 0.f;
         if (r < co) {
             if (ci == 1) {
                 if (kk < 27) w = W[(r * 27 + kk) * ci];
+                wp = w;
             } else {
                 const int cp = pad8(ci), k = kk / cp, c = kk % cp;
                 if (k < 27 && c < ci) w = W[(r * 27 + k) * ci + c];
+                wp = w;
+                if (ci == 24) {
+                    const int st = kk / 32, gg = (kk / 8) % 4, e = kk % 8;
+                    const int tc = 4 * (st / 3) + gg, du = st % 3;
+                    wp = 0.f;
+                    if (tc < 27) {
+                        const int dt = tc / 9, dw = (tc / 3) % 3, ch = tc % 3;
+                        wp = W[(r * 27 + (dt * 3 + du) * 3 + dw) * ci + 8 * ch + e];
+                    }
+                }
             }
         }
-        fwd[i] = f2bf(w);
+        fwd[i] = f2bf(wp);
         fwd32[i] = w;
     }
     // backward (input gradient): row = input channel c, K = tap' * pad8(co) + o, weight
