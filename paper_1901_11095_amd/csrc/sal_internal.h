@@ -13,20 +13,26 @@
 // Device tables built once per context from FP64 values rounded to the kernel's type.
 struct sal_tables {
     float *w_c;      // [2L][2L] real form of the L-point DFT matrix: row (freq, re|im),
-                     // column (tap, re|im); used by the x and y contractions
+                     // column (tap, re|im); the y contraction's A operand (and the x one's at
+                     // cube 8).  At cube 16 the rows are in the folded order (M tile 0 pairs
+                     // om with L - om in each lane group)
     float *w_a;      // [16*MTA][L] real-input DFT along t: row (mu, re|im) for mu <= L/2,
                      // zero rows above
     float *w_bin;    // per weight group (mu, k <= L/2), M tile, lane group: 8 floats holding
-                     // the projection weights (t, x, y) of the two bins a lane owns, times
-                     // the Hermitian multiplicity and 1/(L^3 (L^3-1)); DC has weight 0
+                     // the projection weights (t, x, y) of the two bins a lane owns (one set
+                     // for a folded tile, whose two bins share it), times the Hermitian
+                     // multiplicity and 1/(L^3 (L^3-1)) (and L^2 for the FP16 forms, whose
+                     // stage outputs are scaled by 1/L); DC has weight 0
     float *twiddle;  // [L][2] exp(-2 pi i k / L), for the per-voxel spectra kernel
     float *w_proj;   // [L^3][4] projection weights / (L^3 - 1) of bin (mu,nu,om), DC = 0
-    uint32_t *w_c16;  // 16-bit forms: per M tile, MFMA and lane, the eight 16-bit A-operand
-                      // values (W_hi | W_lo halves) of the x and y contractions
-    uint32_t *w_a16;  // likewise for the t contraction
-    uint32_t *w_c16b;  // cube 16: w_c16 with the rows of each M tile ordered as the stage-B
-                       // halves of the 16-bit kernel (rows nu = k and L - k of a weight group
-                       // in the same tile)
+    uint32_t *w_c16;  // 16-bit forms: per M tile, operand and lane, the eight 16-bit A-operand
+                      // values of the y contraction (and the x one's at cube 8), in the K
+                      // orders of sal_energy16.hip (three products at cube 16 with the data
+                      // split: operands W_hi, W_lo; else J = L/8 operands of W_hi | W_lo)
+    uint32_t *w_a16;  // likewise for the t contraction (one or two words per tap)
+    uint32_t *w_c16b;  // cube 16: the x contraction's operands, in the stage-B halves' row
+                       // order with the data split (rows nu = k and L - k of a weight group in
+                       // the same half), in frequency order without
     float *w_cb;       // cube 16, FP32 kernel: the stage-B matrix of the two halves, rows in
                        // the halves' order, as per-lane A operands [half][K step][lane]
     float *w_gen;     // vector-ALU kernel (L < 8): [mu <= L/2][nu][om][3] projection weights
