@@ -7,8 +7,8 @@
 //     s < L/2) and the non-overlapping s = L of the predecessor method (Sec. 1): the work
 //     falls by s^3 while unshared windows cost 2.5 times the shared contraction per window;
 //   * cube sides without a fused kernel (9..15, 17..20).
-// FP32 on the vector ALUs.  A workgroup walks windows (grid-stride over the windows of its
-// box); per window:
+// FP32; cube 16 on the matrix cores (k_energy_win_mfma below), the other sides on the vector
+// ALUs.  A workgroup walks windows (grid-stride over the windows of its box); per window:
 //   load    the L^3 samples, reflected at the volume faces, into LDS;
 //   stage A per column (q, r): A[mu][q][r] = sum_p W[mu, p] win[p][q][r], mu <= L/2;
 //   stage B per (mu, r): B[mu][nu][r] = sum_q W[nu, q] A[mu][q][r], every nu;
@@ -198,6 +198,216 @@ __global__ __launch_bounds__(WinCfg<L>::NT) void k_energy_win(const float *__res
     }
 }
 
+// ------------------------------------------------------------------------------------
+// Cube 16 on the matrix cores (FP32 16x16x4 MFMA), one window at a time per workgroup of
+// three waves, the three contractions as small matrix products:
+//   stage A (t, real -> half spectrum): rows (x, y) of the window, 16 per M tile (tile = x),
+//           K = t, 16 columns (mu, re|im) for mu <= 8: the imaginary parts of mu = 0 and 8
+//           are zero for a real input, so column 1 carries the real part of mu = 8; the
+//           samples are the A operand straight from global memory (the next window's are
+//           in flight during stages B and C);
+//   stage B (x): rows y for one mu (tile = mu), K = (x, re|im), columns (re|im, nu);
+//   stage C (y): rows nu for one mu (tile = mu), K = (y, re|im), columns (re|im, om): a lane
+//           holds re and im of its bins in its two accumulators, so |F|, the projection
+//           weights and the sums into E_t, E_x, E_y follow in registers.
+// Stage outputs live in one LDS buffer [mu][row][re|im][17 columns] (B in place of A, plane by
+// plane), the per-lane projection weights of stage C in another.  352 MFMAs per window
+// (721 kflop; the separable transform counted with complex mu = 0 and 8 is 737 kflop).
+namespace {
+constexpr int WM_WAVES = 3;
+constexpr int WM_L = 16, WM_H = 8, WM_h = 9, WM_RS = 17;  // row stride of the LDS planes
+constexpr int WM_PLANE = WM_L * 2 * WM_RS;                // floats per mu plane
+}  // namespace
+
+__global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *__restrict__ V, int n0, int n1,
+                                                                   int n2, ebox bx, int S, WinTw<16> tw,
+                                                                   const float *__restrict__ wgen,
+                                                                   float *__restrict__ E,
+                                                                   float *__restrict__ vmax_part)
+{
+    constexpr int L = WM_L, H = WM_H, h = WM_h, RS = WM_RS, PL = WM_PLANE;
+    constexpr int MTA = (L + WM_WAVES - 1) / WM_WAVES;  // stage-A M tiles per wave (at most)
+    constexpr int MTB = (h + WM_WAVES - 1) / WM_WAVES;  // stage-B/C M tiles per wave
+    __shared__ float P[h * PL];                  // [mu][row][re|im][col], see above
+    __shared__ float wl[h * 4 * 3 * 64];         // [mu][j][m][lane] projection weights
+    __shared__ float red_s[WM_WAVES][4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, n = lane & 15;
+    int box;
+    const int blk = box_tile(bx, &box);
+    V += box * bx.vstride;
+    E += box * bx.estride;
+    const int nblk = bx.table ? bx.per_box : (int)gridDim.x;
+    const int kd0 = (bx.d0 + S - 1) / S, kd1 = (bx.d1 + S - 1) / S, kd2 = (bx.d2 + S - 1) / S;
+    const int nwin = kd0 * kd1 * kd2;
+    const int K1 = bx.fk1, K2 = bx.fk2;
+    const int64_t nfr = (int64_t)bx.fk0 * K1 * K2;
+    const int n12 = n1 * n2;  // the volume holds at most 2^31 - 1 samples
+    float vmax = 0.f;
+
+    // weights of the bins (mu, nu = 4g + j, om = n) of this lane, with the conjugate
+    // multiplicity of mu and 1/(L^3 (L^3 - 1)) (DC has weight 0)
+    for (int i = tid; i < h * 4 * 3 * 64; i += 64 * WM_WAVES) {
+        const int ln = i & 63, m = (i >> 6) % 3, j = (i / 192) & 3, mu = i / 768;
+        wl[i] = wgen[((mu * L + 4 * (ln >> 4) + j) * L + (ln & 15)) * 3 + m];
+    }
+    // constant B operands: lane (g, n) at K step ks holds K = 4 ks + g, column n of N tile nt
+    // stage A column n: (mu, re|im) = (n / 2, n % 2), except column 1 = (8, re)
+    const int amu = n == 1 ? L / 2 : n >> 1, aim = n == 1 ? 0 : n & 1;
+    float wa[4], wb[8][2];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const float2 w = tw.w[(amu * (4 * ks + g)) % L];
+        wa[ks] = aim ? w.y : w.x;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            // K = (tap, re|im of the input), column (re|im of the output = nt, frequency n);
+            // out = in * e^{-2 pi i tap f / L}, w = (cos, -sin)
+            const int k = 4 * ks + g, tap = k >> 1, ci = k & 1;
+            const float2 w = tw.w[(tap * n) % L];
+            wb[ks][nt] = nt == 0 ? (ci == 0 ? w.x : -w.y) : (ci == 0 ? w.y : w.x);
+        }
+
+    // samples of this wave's stage-A tiles (x = wave + 3 i) for one window: lane (g, n)
+    // holds V[t = 4 ks + g][x][y = n]
+    float smp[MTA][4];
+    auto load_win = [&](int w) {
+        const int k2 = w % kd2, k1 = (w / kd2) % kd1, k0 = w / (kd2 * kd1);
+        const int q0 = bx.o0 + S * k0 - H, q1 = bx.o1 + S * k1 - H, q2 = bx.o2 + S * k2 - H;
+        const int yo = refl_idx(q2 + n, n2);
+        int rowo[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) rowo[ks] = refl_idx(q0 + 4 * ks + g, n0) * n12 + yo;
+#pragma unroll
+        for (int i = 0; i < MTA; ++i) {
+            const int x = wave + WM_WAVES * i;
+            if (x < L) {
+                const int xo = refl_idx(q1 + x, n1) * n2;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) smp[i][ks] = V[(uint32_t)(rowo[ks] + xo)];
+            }
+        }
+    };
+    if (blk < nwin) load_win(blk);
+    __syncthreads();  // wl complete
+
+    for (int w = blk; w < nwin; w += nblk) {
+        const int k2 = w % kd2, k1 = (w / kd2) % kd1, k0 = w / (kd2 * kd1);
+        const int p0 = bx.o0 + S * k0, p1 = bx.o1 + S * k1, p2 = bx.o2 + S * k2;
+        // ---------------- stage A: real DFT along t --------------------------------------
+#pragma unroll
+        for (int i = 0; i < MTA; ++i) {
+            const int x = wave + WM_WAVES * i;
+            if (x < L) {
+                f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    vmax = fmaxf(vmax, fabsf(smp[i][ks]));
+                    acc = mfma4(smp[i][ks], wa[ks], acc);
+                }
+                // lane (g, n): rows y = 4g + j, column n = (amu, aim); lanes 0 and 1 also
+                // write the zero imaginary parts of mu = 0 and 8
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    P[amu * PL + (x * 2 + aim) * RS + 4 * g + j] = acc[j];
+                    if (n < 2) P[amu * PL + (x * 2 + 1) * RS + 4 * g + j] = 0.f;
+                }
+            }
+        }
+        if (w + nblk < nwin) load_win(w + nblk);
+        __syncthreads();
+        // ---------------- stage B: DFT along x, plane mu in place ------------------------
+#pragma unroll
+        for (int i = 0; i < MTB; ++i) {
+            const int mu = wave + WM_WAVES * i;
+            if (mu < h) {
+                float *pl = P + mu * PL;
+                f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int k = 4 * ks + g;  // (x, re|im) = (k / 2, k % 2), row y = n
+                    const float a = pl[k * RS + n];
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) acc[nt] = mfma4(a, wb[ks][nt], acc[nt]);
+                }
+                // rows y = 4g + j, column nu = n: (re, im) = (acc[0][j], acc[1][j]); every
+                // read of the plane is issued before these writes
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    pl[(n * 2) * RS + 4 * g + j] = acc[0][j];
+                    pl[(n * 2 + 1) * RS + 4 * g + j] = acc[1][j];
+                }
+            }
+        }
+        __syncthreads();
+        // ---------------- stage C: DFT along y, projections, energies -------------------
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < MTB; ++i) {
+            const int mu = wave + WM_WAVES * i;
+            if (mu < h) {
+                const float *pl = P + mu * PL;
+                f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int k = 4 * ks + g;  // (y, re|im) = (k / 2, k % 2), row nu = n
+                    const float a = pl[(n * 2 + (k & 1)) * RS + (k >> 1)];
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) acc[nt] = mfma4(a, wb[ks][nt], acc[nt]);
+                }
+                const float *wr = wl + mu * 768 + lane;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float m = __builtin_amdgcn_sqrtf(fmaf(acc[0][j], acc[0][j], acc[1][j] * acc[1][j]));
+                    e0 = fmaf(wr[(j * 3 + 0) * 64], m, e0);
+                    e1 = fmaf(wr[(j * 3 + 1) * 64], m, e1);
+                    e2 = fmaf(wr[(j * 3 + 2) * 64], m, e2);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            e0 += __shfl_xor(e0, o);
+            e1 += __shfl_xor(e1, o);
+            e2 += __shfl_xor(e2, o);
+        }
+        if (lane == 0) {
+            red_s[wave][0] = e0;
+            red_s[wave][1] = e1;
+            red_s[wave][2] = e2;
+        }
+        __syncthreads();  // red_s complete; every wave is done with P
+        if (tid == 0) {
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+            for (int v = 0; v < WM_WAVES; ++v) {
+                s0 += red_s[v][0];
+                s1 += red_s[v][1];
+                s2 += red_s[v][2];
+            }
+            const int64_t o = ((int64_t)((p0 - bx.fo0) / S) * K1 + (p1 - bx.fo1) / S) * K2 + (p2 - bx.fo2) / S;
+            E[o] = s0;
+            E[nfr + o] = s1;
+            E[2 * nfr + o] = s2;
+        }
+        // (the next window's stage A may write P now; red_s is rewritten two barriers later)
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    __syncthreads();
+    if (lane == 0) red_s[wave][3] = vmax;
+    __syncthreads();
+    if (tid == 0 && vmax_part) {
+        float m = red_s[0][3];
+        for (int v = 1; v < WM_WAVES; ++v) m = fmaxf(m, red_s[v][3]);
+        vmax_part[blockIdx.x] = m;
+    }
+}
+
 // ====================================================================== launchers
 
 namespace {
@@ -221,8 +431,12 @@ hipError_t launch_win_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1
     if (nparts) *nparts = (int)nb;
     WinTw<L> tw;
     for (int k = 0; k < L; ++k) tw.w[k] = make_float2(c->tw_host[2 * k], c->tw_host[2 * k + 1]);
-    hipLaunchKernelGGL(k_energy_win<L>, dim3((unsigned)nb), dim3(WinCfg<L>::NT), 0, s, V, (int)n0, (int)n1, (int)n2,
-                       bx, S, tw, c->t.w_gen, E, vmax_part);
+    if constexpr (L == 16)
+        hipLaunchKernelGGL(k_energy_win_mfma, dim3((unsigned)nb), dim3(64 * WM_WAVES), 0, s, V, (int)n0, (int)n1,
+                           (int)n2, bx, S, tw, c->t.w_gen, E, vmax_part);
+    else
+        hipLaunchKernelGGL(k_energy_win<L>, dim3((unsigned)nb), dim3(WinCfg<L>::NT), 0, s, V, (int)n0, (int)n1,
+                           (int)n2, bx, S, tw, c->t.w_gen, E, vmax_part);
     return hipGetLastError();
 }
 
