@@ -594,7 +594,8 @@ def strides_same_volume(Vg, S_ref, ms_fp32, L, strides=(2, 4, 8, 16)):
         d = (S - S_ref).abs()
         out["s%d" % st] = {"voxels_per_s": N / (ms * 1e-3), "ms_per_step": ms, "kernels_ms": km,
                            "speedup_vs_stride1": ms_fp32 / ms,
-                           "kernel": "k_energy_f32<%d, 2>" % L if st == 2 else "k_energy_win<%d>" % L,
+                           "kernel": "k_energy_f32<%d, 2>" % L if st == 2 else (
+                               "k_energy_win_mfma" if L == 16 else "k_energy_win<%d>" % L),
                            "S_abs_diff_vs_stride1": {"max": float(d.max()), "mean": float(d.mean())}}
         del c, S, d
         torch.cuda.empty_cache()
