@@ -199,8 +199,10 @@ __global__ __launch_bounds__(WinCfg<L>::NT) void k_energy_win(const float *__res
 }
 
 // ------------------------------------------------------------------------------------
-// Cube 16 on the matrix cores (FP32 16x16x4 MFMA), one window at a time per workgroup of
-// three waves, the three contractions as small matrix products:
+// Cube 16 on the matrix cores (FP32 16x16x4 MFMA), one window at a time per group of three
+// waves (WM_GROUPS groups per workgroup would share the weight table; one group per workgroup,
+// three workgroups per CU, measured fastest: 90 ms against 119 ms with two on a stride-4
+// lattice of the 512 x 1024 x 1024 volume), the three contractions as small matrix products:
 //   stage A (t, real -> half spectrum): rows (x, y) of the window, 16 per M tile (tile = x),
 //           K = t, 16 columns (mu, re|im) for mu <= 8: the imaginary parts of mu = 0 and 8
 //           are zero for a real input, so column 1 carries the real part of mu = 8; the
@@ -210,29 +212,31 @@ __global__ __launch_bounds__(WinCfg<L>::NT) void k_energy_win(const float *__res
 //   stage C (y): rows nu for one mu (tile = mu), K = (y, re|im), columns (re|im, om): a lane
 //           holds re and im of its bins in its two accumulators, so |F|, the projection
 //           weights and the sums into E_t, E_x, E_y follow in registers.
-// Stage outputs live in one LDS buffer [mu][row][re|im][17 columns] (B in place of A, plane by
-// plane), the per-lane projection weights of stage C in another.  352 MFMAs per window
-// (721 kflop; the separable transform counted with complex mu = 0 and 8 is 737 kflop).
+// Stage outputs live in one LDS buffer per group [mu][row][re|im][17 columns] (B in place of
+// A, plane by plane), the per-lane projection weights of stage C in another.  The wave that
+// computes plane mu in stage B also reads it in stage C, so only stage A's output needs a
+// barrier.  352 MFMAs per window (721 kflop; the separable transform counted with complex
+// mu = 0 and 8 is 737 kflop).
 namespace {
-constexpr int WM_WAVES = 3;
+constexpr int WM_WAVES = 3, WM_GROUPS = 1;
 constexpr int WM_L = 16, WM_H = 8, WM_h = 9, WM_RS = 17;  // row stride of the LDS planes
 constexpr int WM_PLANE = WM_L * 2 * WM_RS;                // floats per mu plane
 }  // namespace
 
-__global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *__restrict__ V, int n0, int n1,
-                                                                   int n2, ebox bx, int S, WinTw<16> tw,
-                                                                   const float *__restrict__ wgen,
-                                                                   float *__restrict__ E,
-                                                                   float *__restrict__ vmax_part)
+__global__ __launch_bounds__(64 * WM_WAVES * WM_GROUPS) void k_energy_win_mfma(
+    const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int S, WinTw<16> tw,
+    const float *__restrict__ wgen, float *__restrict__ E, float *__restrict__ vmax_part)
 {
-    constexpr int L = WM_L, H = WM_H, h = WM_h, RS = WM_RS, PL = WM_PLANE;
+    constexpr int L = WM_L, H = WM_H, h = WM_h, RS = WM_RS, PL = WM_PLANE, G = WM_GROUPS;
+    constexpr int NWV = WM_WAVES * G;
     constexpr int MTA = (L + WM_WAVES - 1) / WM_WAVES;  // stage-A M tiles per wave (at most)
     constexpr int MTB = (h + WM_WAVES - 1) / WM_WAVES;  // stage-B/C M tiles per wave
-    __shared__ float P[h * PL];                  // [mu][row][re|im][col], see above
+    __shared__ float P[G][h * PL];               // per group [mu][row][re|im][col], see above
     __shared__ float wl[h * 4 * 3 * 64];         // [mu][j][m][lane] projection weights
-    __shared__ float red_s[WM_WAVES][4];
+    __shared__ float red_s[NWV][4];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int grp = wave / WM_WAVES, wv = wave - grp * WM_WAVES;  // group, wave in group
     const int g = lane >> 4, n = lane & 15;
     int box;
     const int blk = box_tile(bx, &box);
@@ -245,14 +249,15 @@ __global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *
     const int64_t nfr = (int64_t)bx.fk0 * K1 * K2;
     const int n12 = n1 * n2;  // the volume holds at most 2^31 - 1 samples
     float vmax = 0.f;
+    float *Pg = P[grp];
 
     // weights of the bins (mu, nu = 4g + j, om = n) of this lane, with the conjugate
     // multiplicity of mu and 1/(L^3 (L^3 - 1)) (DC has weight 0)
-    for (int i = tid; i < h * 4 * 3 * 64; i += 64 * WM_WAVES) {
+    for (int i = tid; i < h * 4 * 3 * 64; i += 64 * NWV) {
         const int ln = i & 63, m = (i >> 6) % 3, j = (i / 192) & 3, mu = i / 768;
         wl[i] = wgen[((mu * L + 4 * (ln >> 4) + j) * L + (ln & 15)) * 3 + m];
     }
-    // constant B operands: lane (g, n) at K step ks holds K = 4 ks + g, column n of N tile nt
+    // constant B operands: lane (g, n) at K step ks holds K = 4 ks + g, column n
     // stage A column n: (mu, re|im) = (n / 2, n % 2), except column 1 = (8, re)
     const int amu = n == 1 ? L / 2 : n >> 1, aim = n == 1 ? 0 : n & 1;
     float wa[4], wb[8][2];
@@ -272,7 +277,7 @@ __global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *
             wb[ks][nt] = nt == 0 ? (ci == 0 ? w.x : -w.y) : (ci == 0 ? w.y : w.x);
         }
 
-    // samples of this wave's stage-A tiles (x = wave + 3 i) for one window: lane (g, n)
+    // samples of this wave's stage-A tiles (x = wv + 3 i) for one window: lane (g, n)
     // holds V[t = 4 ks + g][x][y = n]
     float smp[MTA][4];
     auto load_win = [&](int w) {
@@ -284,7 +289,7 @@ __global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *
         for (int ks = 0; ks < 4; ++ks) rowo[ks] = refl_idx(q0 + 4 * ks + g, n0) * n12 + yo;
 #pragma unroll
         for (int i = 0; i < MTA; ++i) {
-            const int x = wave + WM_WAVES * i;
+            const int x = wv + WM_WAVES * i;
             if (x < L) {
                 const int xo = refl_idx(q1 + x, n1) * n2;
 #pragma unroll
@@ -292,80 +297,81 @@ __global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *
             }
         }
     };
-    if (blk < nwin) load_win(blk);
+    if (G * blk + grp < nwin) load_win(G * blk + grp);
     __syncthreads();  // wl complete
 
-    for (int w = blk; w < nwin; w += nblk) {
+    // every wave of the workgroup takes the same number of steps (the barriers need it); a
+    // group past the last window idles through its step
+    for (int wb0 = G * blk; wb0 < nwin; wb0 += G * nblk) {
+        const int w = wb0 + grp;
+        const bool act = w < nwin;
         const int k2 = w % kd2, k1 = (w / kd2) % kd1, k0 = w / (kd2 * kd1);
         const int p0 = bx.o0 + S * k0, p1 = bx.o1 + S * k1, p2 = bx.o2 + S * k2;
         // ---------------- stage A: real DFT along t --------------------------------------
+        if (act) {
 #pragma unroll
-        for (int i = 0; i < MTA; ++i) {
-            const int x = wave + WM_WAVES * i;
-            if (x < L) {
-                f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+            for (int i = 0; i < MTA; ++i) {
+                const int x = wv + WM_WAVES * i;
+                if (x < L) {
+                    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    vmax = fmaxf(vmax, fabsf(smp[i][ks]));
-                    acc = mfma4(smp[i][ks], wa[ks], acc);
-                }
-                // lane (g, n): rows y = 4g + j, column n = (amu, aim); lanes 0 and 1 also
-                // write the zero imaginary parts of mu = 0 and 8
+                    for (int ks = 0; ks < 4; ++ks) {
+                        vmax = fmaxf(vmax, fabsf(smp[i][ks]));
+                        acc = mfma4(smp[i][ks], wa[ks], acc);
+                    }
+                    // lane (g, n): rows y = 4g + j, column n = (amu, aim); lanes 0 and 1 also
+                    // write the zero imaginary parts of mu = 0 and 8
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    P[amu * PL + (x * 2 + aim) * RS + 4 * g + j] = acc[j];
-                    if (n < 2) P[amu * PL + (x * 2 + 1) * RS + 4 * g + j] = 0.f;
-                }
-            }
-        }
-        if (w + nblk < nwin) load_win(w + nblk);
-        __syncthreads();
-        // ---------------- stage B: DFT along x, plane mu in place ------------------------
-#pragma unroll
-        for (int i = 0; i < MTB; ++i) {
-            const int mu = wave + WM_WAVES * i;
-            if (mu < h) {
-                float *pl = P + mu * PL;
-                f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int k = 4 * ks + g;  // (x, re|im) = (k / 2, k % 2), row y = n
-                    const float a = pl[k * RS + n];
-#pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) acc[nt] = mfma4(a, wb[ks][nt], acc[nt]);
-                }
-                // rows y = 4g + j, column nu = n: (re, im) = (acc[0][j], acc[1][j]); every
-                // read of the plane is issued before these writes
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    pl[(n * 2) * RS + 4 * g + j] = acc[0][j];
-                    pl[(n * 2 + 1) * RS + 4 * g + j] = acc[1][j];
+                    for (int j = 0; j < 4; ++j) {
+                        Pg[amu * PL + (x * 2 + aim) * RS + 4 * g + j] = acc[j];
+                        if (n < 2) Pg[amu * PL + (x * 2 + 1) * RS + 4 * g + j] = 0.f;
+                    }
                 }
             }
+            if (w + G * nblk < nwin) load_win(w + G * nblk);
         }
         __syncthreads();
-        // ---------------- stage C: DFT along y, projections, energies -------------------
         float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+        if (act) {
 #pragma unroll
-        for (int i = 0; i < MTB; ++i) {
-            const int mu = wave + WM_WAVES * i;
-            if (mu < h) {
-                const float *pl = P + mu * PL;
-                f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            for (int i = 0; i < MTB; ++i) {
+                const int mu = wv + WM_WAVES * i;
+                if (mu < h) {
+                    float *pl = Pg + mu * PL;
+                    // ------------ stage B: DFT along x, plane mu in place ------------------
+                    f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int k = 4 * ks + g;  // (y, re|im) = (k / 2, k % 2), row nu = n
-                    const float a = pl[(n * 2 + (k & 1)) * RS + (k >> 1)];
+                    for (int ks = 0; ks < 8; ++ks) {
+                        const int k = 4 * ks + g;  // (x, re|im) = (k / 2, k % 2), row y = n
+                        const float a = pl[k * RS + n];
 #pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) acc[nt] = mfma4(a, wb[ks][nt], acc[nt]);
-                }
-                const float *wr = wl + mu * 768 + lane;
+                        for (int nt = 0; nt < 2; ++nt) acc[nt] = mfma4(a, wb[ks][nt], acc[nt]);
+                    }
+                    // rows y = 4g + j, column nu = n: (re, im) = (acc[0][j], acc[1][j]); every
+                    // read of the plane is issued before these writes
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float m = __builtin_amdgcn_sqrtf(fmaf(acc[0][j], acc[0][j], acc[1][j] * acc[1][j]));
-                    e0 = fmaf(wr[(j * 3 + 0) * 64], m, e0);
-                    e1 = fmaf(wr[(j * 3 + 1) * 64], m, e1);
-                    e2 = fmaf(wr[(j * 3 + 2) * 64], m, e2);
+                    for (int j = 0; j < 4; ++j) {
+                        pl[(n * 2) * RS + 4 * g + j] = acc[0][j];
+                        pl[(n * 2 + 1) * RS + 4 * g + j] = acc[1][j];
+                    }
+                    // ------------ stage C: DFT along y, projections, energies -------------
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < 8; ++ks) {
+                        const int k = 4 * ks + g;  // (y, re|im) = (k / 2, k % 2), row nu = n
+                        const float a = pl[(n * 2 + (k & 1)) * RS + (k >> 1)];
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) acc[nt] = mfma4(a, wb[ks][nt], acc[nt]);
+                    }
+                    const float *wr = wl + mu * 768 + lane;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float m = __builtin_amdgcn_sqrtf(fmaf(acc[0][j], acc[0][j], acc[1][j] * acc[1][j]));
+                        e0 = fmaf(wr[(j * 3 + 0) * 64], m, e0);
+                        e1 = fmaf(wr[(j * 3 + 1) * 64], m, e1);
+                        e2 = fmaf(wr[(j * 3 + 2) * 64], m, e2);
+                    }
                 }
             }
         }
@@ -380,21 +386,21 @@ __global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *
             red_s[wave][1] = e1;
             red_s[wave][2] = e2;
         }
-        __syncthreads();  // red_s complete; every wave is done with P
-        if (tid == 0) {
+        __syncthreads();  // red_s complete; every wave is done with its group's P
+        if (act && wv == 0 && lane == 0) {
             float s0 = 0.f, s1 = 0.f, s2 = 0.f;
 #pragma unroll
             for (int v = 0; v < WM_WAVES; ++v) {
-                s0 += red_s[v][0];
-                s1 += red_s[v][1];
-                s2 += red_s[v][2];
+                s0 += red_s[wave + v][0];
+                s1 += red_s[wave + v][1];
+                s2 += red_s[wave + v][2];
             }
             const int64_t o = ((int64_t)((p0 - bx.fo0) / S) * K1 + (p1 - bx.fo1) / S) * K2 + (p2 - bx.fo2) / S;
             E[o] = s0;
             E[nfr + o] = s1;
             E[2 * nfr + o] = s2;
         }
-        // (the next window's stage A may write P now; red_s is rewritten two barriers later)
+        // (the next step's stage A may write P now; red_s is rewritten one barrier later)
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
@@ -403,7 +409,7 @@ __global__ __launch_bounds__(64 * WM_WAVES) void k_energy_win_mfma(const float *
     __syncthreads();
     if (tid == 0 && vmax_part) {
         float m = red_s[0][3];
-        for (int v = 1; v < WM_WAVES; ++v) m = fmaxf(m, red_s[v][3]);
+        for (int v = 1; v < NWV; ++v) m = fmaxf(m, red_s[v][3]);
         vmax_part[blockIdx.x] = m;
     }
 }
@@ -432,7 +438,7 @@ hipError_t launch_win_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1
     WinTw<L> tw;
     for (int k = 0; k < L; ++k) tw.w[k] = make_float2(c->tw_host[2 * k], c->tw_host[2 * k + 1]);
     if constexpr (L == 16)
-        hipLaunchKernelGGL(k_energy_win_mfma, dim3((unsigned)nb), dim3(64 * WM_WAVES), 0, s, V, (int)n0, (int)n1,
+        hipLaunchKernelGGL(k_energy_win_mfma, dim3((unsigned)nb), dim3(64 * WM_WAVES * WM_GROUPS), 0, s, V, (int)n0, (int)n1,
                            (int)n2, bx, S, tw, c->t.w_gen, E, vmax_part);
     else
         hipLaunchKernelGGL(k_energy_win<L>, dim3((unsigned)nb), dim3(WinCfg<L>::NT), 0, s, V, (int)n0, (int)n1,
