@@ -54,14 +54,16 @@ typedef enum {
     SAL_FP32 = 0,         /* FP32 operands, FP32 accumulation (MFMA f32) */
     SAL_BF16 = 1,         /* BF16 data and DFT matrix, FP32 accumulation */
     SAL_BF16_SPLIT = 2,   /* DFT matrix and data each split into BF16 hi + lo parts; the
-                             four products are accumulated in FP32 */
+                             products W_hi d_hi, W_lo d_hi, W_hi d_lo (and W_lo d_lo where
+                             it costs nothing) are accumulated in FP32 */
     SAL_FP16 = 3,         /* FP16 data and DFT matrix, FP32 accumulation */
     SAL_FP16_SPLIT = 4,   /* as SAL_BF16_SPLIT with FP16 parts */
     SAL_BF16_SPLITW = 5,  /* BF16 data times the DFT matrix split hi + lo (two products) */
     SAL_FP16_SPLITW = 6   /* FP16 data times the DFT matrix split hi + lo */
 } sal_precision;
-/* In every 16-bit form each contraction stage rounds its input to the 16-bit type and
- * scales its FP32 output by 1/L (exact), so FP16 forms need |V| < 65504. */
+/* In every 16-bit form each contraction stage rounds its input to the 16-bit type; the FP16
+ * forms scale each stage's FP32 output by 1/L (exact) to stay in range and need
+ * |V| < 65504. */
 
 /* Rays of the directional comparison of Eq. (5), one bit each.  Bits 0-5: the axis rays
  * +t, -t, +x, -x, +y, -y.  Oriented rays (Fig. 3 shows a t-x diagonal comparison): bits
