@@ -113,8 +113,9 @@ void sal_default_params(sal_params *p, int32_t L);
 /* Validate *p (copied) and create a context on HIP device `device`.  Builds the DFT
  * matrices and projection weight tables on that device.  Errors: SAL_E_INVAL (null out,
  * L < 2, d outside [2, 64], sigma <= 0, an empty ray mask or one with bits above 25, bad
- * precision, stride < 1 or not below L/2), SAL_E_UNSUPPORTED (L in 9..15 or above 16, a
- * 16-bit precision with L < 8, a stride this build does not implement), SAL_E_DEVICE. */
+ * precision, stride < 1, a stride of at least L/2 other than L), SAL_E_UNSUPPORTED (L above
+ * 20, a 16-bit precision with L other than 8 and 16, a 16-bit precision with stride above 2),
+ * SAL_E_DEVICE. */
 sal_status sal_create(const sal_params *p, int device, sal_ctx **out);
 
 /* Free the context and its device tables (waits for nothing; the caller must ensure no
