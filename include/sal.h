@@ -105,6 +105,11 @@ typedef struct {
                            on the lattice of multiples of s, energies interpolated trilinearly
                            to every voxel, the last lattice value held at the far faces;
                            Eq. (5) and Eq. (6) on the full grid.  Strides above 2 run in FP32. */
+    int32_t t_direct;   /* cube 16, FP32, stride 1: 0 (default) = each window's spectrum is the
+                           previous window's along t plus the 2-D DFT of the entering minus the
+                           leaving t-plane (the same DFT, a different rounding; volumes of at
+                           least 32 x 9 x 9); 1 = every window's t contraction computed on its
+                           own.  Ignored elsewhere. */
 } sal_params;
 
 /* Fill *p with the defaults above for cube side L. */

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsal.so")
-SOURCES = ["sal_api.hip", "sal_kernels.hip", "sal_energy16.hip", "sal_energy_gen.hip", "sal_energy_win.hip",
+SOURCES = ["sal_api.hip", "sal_kernels.hip", "sal_energy16.hip", "sal_energy_gen.hip", "sal_energy_win.hip", "sal_energy_slide.hip",
            "sal_merge.hip", "sal_net.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,384 @@
+// Steps 1-3 at cube 16 in FP32 with the window sliding along t (Sec. 2 steps 1-3).
+//
+// The L^3 DFT of the window centred on (t0, x0, y0) factors into a 2-D DFT of each of its
+// L t-planes (x then y) followed by the DFT along t of those plane spectra.  With the
+// t-phase taken from the absolute row index v (a unit-modulus factor per window and
+// frequency, which the magnitudes of Eqs. (1)-(4) do not see),
+//     D_t0[kt, kx, ky] = sum_{v = t0-8}^{t0+7} P_v[kx, ky] e^{-2 pi i kt v / 16},
+// and since e^{-2 pi i kt (v + 16) / 16} = e^{-2 pi i kt v / 16}, the next window's spectrum
+// is this one's plus (P_{v_in} - P_{v_out}) e^{-2 pi i kt v_in / 16}, where the plane
+// leaving (v_out = v_in - 16) and the plane entering share the twiddle.  By linearity
+// P_{v_in} - P_{v_out} is the 2-D DFT of the plane difference V[v_in] - V[v_out], so each
+// window costs one 2-D plane DFT (matrix cores) and one complex multiply-add per bin (vector
+// ALUs) instead of a full DFT along t.  Rows are reflected at the t faces exactly as the
+// window's own rows are.
+//
+// Each product is rounded before it is added, so a plane that enters and later leaves
+// cancels exactly (a unit spike leaves exact zeros behind).  The running sums restart from
+// zero at fixed absolute rows (window t0 = 0, 8, 256, 512, ...; restarting at t0 = 8 keeps
+// the rows reflected at the t = 0 face out of every later window's history), so a window's
+// result does not depend on the box or batch it is computed in, and the rounding drift of
+// the sums stays within 271 steps.
+//
+// Workgroup: one x0, 16 consecutive y0, one t segment; eight waves, wave c owning column
+// c of the 2-D plane spectrum (c = 1..7: the x frequency kx = c; c = 0: kx = 0 and kx = 8
+// packed as one complex column Z = X_0 + i X_8 of two real sequences).  Per t-step:
+//   stage 1 (waves 1 and 2): X[comp, y] = sum_tau M1[comp, tau] dV[x0 - 8 + tau, y] for the
+//     31 positions y of the tile, the real DFT along x packed into 16 real components;
+//   stage 2 (wave c): P[ky, y0] = sum_tau W[ky, tau] X_c[y0 - 8 + tau], complex, 16 ky on two
+//     M tiles whose lane groups hold ky and -ky, the 16 windows on N;
+//   stage 3 (wave c): the lane's 64 bins (two M tiles x two ky x 16 kt) of its window take
+//     their update; at output steps their magnitudes are weighted into E_t, E_x, E_y.
+// In wave 0 the bins (kt, ky) and (-kt, -ky) of the packed column sit in one lane; its
+// update is applied to U = Z[k] + conj Z[-k] = 2 D_{kx=0}[k] and V = Z[k] - conj Z[-k] =
+// 2i D_{kx=8}[k] instead (the plane spectra transformed the same way), so every slot is one
+// bin's magnitude.  On the self-conjugate rows ky in {0, 8} the slots kt and 16 - kt hold U
+// and conj V, and kt in {0, 8} hold Z itself, whose real and imaginary parts are two
+// self-conjugate bins.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sal_device.h"
+#include "sal_internal.h"
+
+namespace {
+
+constexpr int SL = 16;        // cube side
+constexpr int SH = 8;         // window start = centre - 8
+constexpr int STY = 16;       // windows along y per workgroup
+constexpr int SPY = STY + SL - 1;  // stage-1 positions along y
+constexpr int SNW = 8;        // waves
+constexpr int PLS = 48;       // plane row stride (floats): tau rows 16 banks apart
+constexpr int S1S = 18;       // stage-1 output row stride (floats)
+constexpr int SWP = SLIDE_WEIGHTS_PER_GROUP;
+
+__device__ __forceinline__ float mag(float re, float im) { return __builtin_amdgcn_sqrtf(fmaf(re, re, im * im)); }
+
+}  // namespace
+
+__global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) void k_energy_slide(
+    const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int nseg, int nbx, int nby,
+    const float *__restrict__ w_s1, const float *__restrict__ w_s2, const float *__restrict__ w_sp,
+    const float2 *__restrict__ tw, float *__restrict__ E, float *__restrict__ vmax_part)
+{
+    __shared__ float plane_s[2][16 * PLS];
+    __shared__ float s1_s[2][SPY * S1S + 2];
+    __shared__ float wt_s[SNW * 4 * SWP];
+    __shared__ float red_s[2][SNW][3][STY];
+    __shared__ float vred_s[SNW];
+    // constant A operands, per lane: stage 1 [lane][K step], stage 2 [K step / 4][lane][4]
+    __shared__ float4 a1_s[64];
+    __shared__ float4 a2_s[4][64];
+
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, n = lane & 15;
+
+    int box;
+    const int tile = box_tile(bx, &box);
+    V += box * bx.vstride;
+    E += box * bx.estride;
+    const int ty = tile % nby, xr = (tile / nby) % nbx, kr = tile / (nby * nbx);
+    const int y_base = bx.o2 + STY * ty, x0 = bx.o1 + xr;
+    const int k = slide_seg_id(bx.o0) + kr;
+    const int s_start = slide_seg_start(k);
+    const int t_lo = max(s_start, bx.o0), t_hi = min(slide_seg_start(k + 1), min(n0, bx.o0 + bx.d0));
+    if (kr >= nseg || t_lo >= t_hi || x0 >= bx.o1 + bx.d1 || y_base >= bx.o2 + bx.d2) {
+        if (threadIdx.x == 0 && vmax_part) vmax_part[blockIdx.x] = 0.f;
+        return;
+    }
+    const int K1 = bx.fk1, K2 = bx.fk2;
+    const int64_t nbox = (int64_t)bx.fk0 * K1 * K2;
+    const int y_end = bx.o2 + bx.d2;
+
+    for (int i = threadIdx.x; i < SNW * 4 * SWP; i += 64 * SNW) wt_s[i] = w_sp[i];
+    // (the 16 stage-2 operands would not fit the registers beside the 128 of the spectra)
+    if (threadIdx.x < 64)
+        a1_s[lane] = make_float4(w_s1[lane], w_s1[64 + lane], w_s1[128 + lane], w_s1[192 + lane]);
+    else if (threadIdx.x < 320) {
+        const int r = (threadIdx.x - 64) >> 6;  // operands 4 r .. 4 r + 3 in the order (mt, kk)
+        float4 a;
+        a.x = w_s2[(4 * r) * 64 + lane];
+        a.y = w_s2[(4 * r + 1) * 64 + lane];
+        a.z = w_s2[(4 * r + 2) * 64 + lane];
+        a.w = w_s2[(4 * r + 3) * 64 + lane];
+        a2_s[r][lane] = a;
+    }
+
+    // plane samples: thread i < 496 owns (tau, yy) = (i / 31, i % 31)
+    const int n12 = n1 * n2;  // the volume holds at most 2^31 - 1 samples
+    const bool loader = threadIdx.x < 16 * SPY;
+    int off = 0, pidx = 0;
+    if (loader) {
+        const int tau = threadIdx.x / SPY, yy = threadIdx.x - tau * SPY;
+        off = refl_idx(x0 - SH + tau, n1) * n2 + refl_idx(y_base - SH + yy, n2);
+        pidx = tau * PLS + yy;
+    }
+    // step j brings row v_in = s_start - 8 + j in and, from j = 16 on, takes v_in - 16 out;
+    // the window t0 = s_start + j - 15 is complete after step j
+    const int nsteps = t_hi - s_start + SL - 1;
+    float vmax = 0.f;
+    // the samples of step j are loaded two steps ahead and only read when the plane is
+    // written to LDS, so the loads' latency overlaps a whole step
+    float ra = 0.f, rb = 0.f;
+    auto load_plane = [&](int j) {
+        if (!loader) return;
+        const int vin = s_start - SH + j;
+        ra = V[(uint32_t)(refl_idx(vin, n0) * n12 + off)];
+        rb = V[(uint32_t)(refl_idx(vin - SL, n0) * n12 + off)];  // in the volume; unused before j = 16
+    };
+    auto plane_value = [&](int j) {
+        vmax = fmaxf(vmax, fmaxf(fabsf(ra), fabsf(rb)));
+        return j >= SL ? ra - rb : ra;
+    };
+    auto stage1 = [&](int buf) {
+        // waves 1 and 2: positions 16 (wave - 1) + n
+        const int jt = wave - 1;
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+        const float *pl = plane_s[buf] + 16 * jt + n;
+        const float4 a1 = a1_s[lane];
+        acc = mfma4(a1.x, pl[g * PLS], acc);
+        acc = mfma4(a1.y, pl[(4 + g) * PLS], acc);
+        acc = mfma4(a1.z, pl[(8 + g) * PLS], acc);
+        acc = mfma4(a1.w, pl[(12 + g) * PLS], acc);
+        const int yy = 16 * jt + n;
+        if (yy < SPY) {
+            float *o = s1_s[buf] + yy * S1S + 4 * g;
+            *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
+            *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+        }
+    };
+
+    load_plane(0);
+    if (loader) plane_s[0][pidx] = plane_value(0);
+    __syncthreads();
+    if (wave == 1 || wave == 2) stage1(0);
+    if (nsteps > 1) load_plane(1);
+
+    // spectrum state: [M tile][ky slot][kt]
+    float Dr[2][2][16], Di[2][2][16];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int kt = 0; kt < 16; ++kt) Dr[mt][q][kt] = Di[mt][q][kt] = 0.f;
+
+    const float *wl = wt_s + (wave * 4 + g) * SWP;
+    const bool sp_lane = g == 0;  // wave 0: lane group holding the self-conjugate rows 0, 8
+
+    float2 wnext[8];
+#pragma unroll
+    for (int kt = 1; kt < 8; ++kt) wnext[kt] = tw[(kt * (s_start - SH)) & 15];
+#pragma unroll 1
+    for (int j = 0; j < nsteps; ++j) {
+        const int b = j & 1;
+        if (j + 1 < nsteps && loader) plane_s[b ^ 1][pidx] = plane_value(j + 1);
+        __syncthreads();
+        if (j + 2 < nsteps) load_plane(j + 2);
+        if ((wave == 1 || wave == 2) && j + 1 < nsteps) stage1(b ^ 1);
+        // the previous step's energies: sum over the waves in a fixed order
+        if (wave == 3 && j >= SL && s_start + j - SL >= t_lo && lane < 3 * STY) {
+            const int m = lane >> 4, yy = lane & 15;
+            float s = red_s[b ^ 1][0][m][yy];
+#pragma unroll
+            for (int w = 1; w < SNW; ++w) s += red_s[b ^ 1][w][m][yy];
+            const int t0 = s_start + j - SL, y = y_base + yy;
+            if (y < y_end) {
+                const int64_t o = ((int64_t)(t0 - bx.fo0) * K1 + (x0 - bx.fo1)) * K2 + (y - bx.fo2);
+                E[m * nbox + o] = s;
+            }
+        }
+
+        // ---------------- stage 2: DFT along y of column c = wave -----------------------
+        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+        {
+            const float *src = s1_s[b] + (n + g) * S1S + 2 * wave;
+#pragma unroll
+            for (int kh = 0; kh < 2; ++kh) {
+                // operands (mt, kk) for kk = 4 kh .. 4 kh + 3
+                const float4 w0 = a2_s[kh][lane], w1 = a2_s[2 + kh][lane];
+                const float2 x0 = *reinterpret_cast<const float2 *>(src + 8 * kh * S1S);
+                const float2 x1 = *reinterpret_cast<const float2 *>(src + (8 * kh + 4) * S1S);
+                acc[0] = mfma4(w0.x, x0.x, acc[0]);
+                acc[1] = mfma4(w1.x, x0.x, acc[1]);
+                acc[0] = mfma4(w0.y, x0.y, acc[0]);
+                acc[1] = mfma4(w1.y, x0.y, acc[1]);
+                acc[0] = mfma4(w0.z, x1.x, acc[0]);
+                acc[1] = mfma4(w1.z, x1.x, acc[1]);
+                acc[0] = mfma4(w0.w, x1.y, acc[0]);
+                acc[1] = mfma4(w1.w, x1.y, acc[1]);
+            }
+        }
+
+        // ---------------- stage 3: the t update -----------------------------------------
+        const int v = (s_start - SH + j) & 15;
+        const float s8 = (v & 1) ? -1.f : 1.f;
+        float2 w[8];
+#pragma unroll
+        for (int kt = 1; kt < 8; ++kt) w[kt] = wnext[kt];
+        // the next step's twiddles, in flight while this step computes
+#pragma unroll
+        for (int kt = 1; kt < 8; ++kt) wnext[kt] = tw[(kt * (v + 1)) & 15];
+        // D[kt] += lo w(kt), D[16 - kt] += hi conj(w(kt)), D[0] += self, D[8] += self s8; each
+        // product rounded before it is added
+        auto update = [&](int mt, int q, float2 lo, float2 hi, float2 self) __attribute__((always_inline)) {
+            Dr[mt][q][0] += self.x;
+            Di[mt][q][0] += self.y;
+            Dr[mt][q][8] = fmaf(s8, self.x, Dr[mt][q][8]);
+            Di[mt][q][8] = fmaf(s8, self.y, Di[mt][q][8]);
+#pragma unroll
+            for (int kt = 1; kt < 8; ++kt) {
+                const float wr = w[kt].x, wi = w[kt].y;
+                const float b1 = lo.y * wi, d1 = lo.y * wr;
+                Dr[mt][q][kt] += fmaf(lo.x, wr, -b1);
+                Di[mt][q][kt] += fmaf(lo.x, wi, d1);
+                const float b2 = hi.y * wi, d2 = hi.y * wr;
+                Dr[mt][q][16 - kt] += fmaf(hi.x, wr, b2);
+                Di[mt][q][16 - kt] += fmaf(-hi.x, wi, d2);
+            }
+        };
+        const int t0 = s_start + j - (SL - 1);
+        const bool out = j >= SL - 1 && t0 >= t_lo;
+        // Slot inputs.  Columns 1..7: the plane spectrum itself.  Column 0: U = P_a + conj P_b
+        // and V = P_a - conj P_b for the rows (a, b = -a); on the self-conjugate rows (lane
+        // group 0 of M tile 0) Z itself at kt in {0, 8}, 2 Re Z at kt = 1..7 (U) and
+        // -2i Im Z at kt = 9..15 (conj V).  One update code for all waves keeps the 128
+        // spectrum registers in place.
+        {
+            const bool w0 = wave == 0;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const float2 pa = make_float2(acc[mt][0], acc[mt][1]), pb = make_float2(acc[mt][2], acc[mt][3]);
+                const float2 u = make_float2(pa.x + pb.x, pa.y - pb.y), vv = make_float2(pa.x - pb.x, pa.y + pb.y);
+                if (mt == 1) {
+                    const float2 p0 = w0 ? u : pa, p1 = w0 ? vv : pb;
+                    update(1, 0, p0, p0, p0);
+                    update(1, 1, p1, p1, p1);
+                } else {
+                    const bool sp = w0 && sp_lane, rg = w0 && !sp_lane;
+                    const float2 se0 = rg ? u : pa, se1 = rg ? vv : pb;
+                    const float2 lo0 = sp ? make_float2(2.f * pa.x, 0.f) : se0;
+                    const float2 hi0 = sp ? make_float2(0.f, -2.f * pa.y) : se0;
+                    const float2 lo1 = sp ? make_float2(2.f * pb.x, 0.f) : se1;
+                    const float2 hi1 = sp ? make_float2(0.f, -2.f * pb.y) : se1;
+                    update(0, 0, lo0, hi0, se0);
+                    update(0, 1, lo1, hi1, se1);
+                }
+            }
+        }
+        float e[3] = {0.f, 0.f, 0.f};
+        if (out && wave != 0) {
+            // M tile 0: the ky of the two slots differ in lane group 0 (0 and 8): a weight set
+            // per slot; M tile 1: ky and -ky, one set.  kt and 16 - kt share weights.
+#pragma unroll
+            for (int p = 0; p <= 8; ++p) {
+                float m0[2], m1;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    m0[q] = mag(Dr[0][q][p], Di[0][q][p]);
+                    if (p > 0 && p < 8) m0[q] += mag(Dr[0][q][16 - p], Di[0][q][16 - p]);
+                }
+                m1 = mag(Dr[1][0][p], Di[1][0][p]) + mag(Dr[1][1][p], Di[1][1][p]);
+                if (p > 0 && p < 8)
+                    m1 += mag(Dr[1][0][16 - p], Di[1][0][16 - p]) + mag(Dr[1][1][16 - p], Di[1][1][16 - p]);
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    e[m] = fmaf(wl[54 + 3 * p + m], m1,
+                                fmaf(wl[27 + 3 * p + m], m0[1], fmaf(wl[3 * p + m], m0[0], e[m])));
+            }
+        } else if (out) {
+            // M tile 0: weights A (slot kt) and B (slot 16 - kt) per ky slot; at kt in {0, 8}
+            // A weighs |Re Z| and B |Im Z| on the self-conjugate rows, A the magnitude
+            // elsewhere.  M tile 1: one set per ky slot.
+            const float sel = sp_lane ? 0.f : 1.f;
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int p = 0; p <= 8; ++p) {
+                    float ma, mb;
+                    if (p == 0 || p == 8) {
+                        const float re = Dr[0][q][p], im = Di[0][q][p];
+                        ma = __builtin_amdgcn_sqrtf(fmaf(re, re, sel * im * im));
+                        mb = fabsf(im);
+                    } else {
+                        ma = mag(Dr[0][q][p], Di[0][q][p]);
+                        mb = mag(Dr[0][q][16 - p], Di[0][q][16 - p]);
+                    }
+                    float m1 = mag(Dr[1][q][p], Di[1][q][p]);
+                    if (p > 0 && p < 8) m1 += mag(Dr[1][q][16 - p], Di[1][q][16 - p]);
+                    const float *wa = wl + (q * 9 + p) * 6, *wm = wl + 108 + (q * 9 + p) * 3;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+                        e[m] = fmaf(wm[m], m1, fmaf(wa[3 + m], mb, fmaf(wa[m], ma, e[m])));
+                }
+        }
+        if (out) {
+            // lanes n, n + 16, n + 32, n + 48 hold the same window
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                float s = e[m];
+                s += __shfl_xor(s, 16);
+                s += __shfl_xor(s, 32);
+                if (g == 0) red_s[b][wave][m][n] = s;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        const int j = nsteps;
+        if (wave == 3 && s_start + j - SL >= t_lo && lane < 3 * STY) {
+            const int b = j & 1;
+            const int m = lane >> 4, yy = lane & 15;
+            float s = red_s[b ^ 1][0][m][yy];
+#pragma unroll
+            for (int w = 1; w < SNW; ++w) s += red_s[b ^ 1][w][m][yy];
+            const int t0 = s_start + j - SL, y = y_base + yy;
+            if (y < y_end) {
+                const int64_t o = ((int64_t)(t0 - bx.fo0) * K1 + (x0 - bx.fo1)) * K2 + (y - bx.fo2);
+                E[m * nbox + o] = s;
+            }
+        }
+    }
+    // max |V| of everything this workgroup read (all of it lies in the volume)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    if (lane == 0) vred_s[wave] = vmax;
+    __syncthreads();
+    if (threadIdx.x == 0 && vmax_part) {
+        float m = vred_s[0];
+        for (int w = 1; w < SNW; ++w) m = fmaxf(m, vred_s[w]);
+        vmax_part[blockIdx.x] = m;
+    }
+}
+
+// ====================================================================== launcher
+
+// Segments of the t walk (window rows [slide_seg_start(k), slide_seg_start(k + 1)))
+// touched by the box rows [o0, o0 + d0); the grid covers the most any box of the batch needs.
+static int slide_nseg(int o0, int d0) { return slide_seg_id(o0 + d0 - 1) - slide_seg_id(o0) + 1; }
+
+int64_t energy_slide_num_blocks(int64_t n0, int64_t n1, int64_t n2)
+{
+    return (int64_t)slide_nseg(0, (int)n0) * n1 * ((n2 + STY - 1) / STY);
+}
+
+hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
+                               float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
+{
+    int nseg;
+    if (bx.table)
+        nseg = (bx.d0 + SLIDE_SEG - 1) / SLIDE_SEG + 2;  // any o0
+    else
+        nseg = slide_nseg(bx.o0, bx.d0);
+    const int nbx = bx.d1, nby = (bx.d2 + STY - 1) / STY;
+    int64_t nb = (int64_t)nseg * nbx * nby;
+    if (bx.table) {
+        bx.per_box = (int)nb;
+        nb *= nbox;
+    }
+    if (nparts) *nparts = (int)nb;
+    hipLaunchKernelGGL(k_energy_slide, dim3((unsigned)nb), dim3(64 * SNW), 0, s, V, (int)n0, (int)n1, (int)n2, bx,
+                       nseg, nbx, nby, c->t.w_s1, c->t.w_s2, c->t.w_sp, (const float2 *)c->t.twiddle, E, vmax_part);
+    return hipGetLastError();
+}

@@ -37,7 +37,19 @@ struct sal_tables {
                        // the halves' order, as per-lane A operands [half][K step][lane]
     float *w_gen;     // vector-ALU kernel (L < 8): [mu <= L/2][nu][om][3] projection weights
                       // times the conjugate multiplicity of mu, / (L^3 (L^3 - 1)), DC = 0
+    float *w_s1;      // cube 16, FP32 with windows sliding along t: stage-1 (packed real DFT
+                      // along x) A operands [K step][lane]
+    float *w_s2;      // its stage-2 (complex DFT along y) A operands [M tile][K step][lane],
+                      // rows ky and -ky in one lane group
+    float *w_sp;      // its projection weights [column][lane group][SLIDE_WEIGHTS_PER_GROUP]
 };
+
+// Windows sliding along t (cube 16, FP32, stride 1): the running spectra restart from zero at
+// the windows t0 = 0, SLIDE_R and every multiple of SLIDE_SEG from SLIDE_SEG on; segment k
+// covers the windows [slide_seg_start(k), slide_seg_start(k + 1)).
+constexpr int SLIDE_R = 8, SLIDE_SEG = 256, SLIDE_WEIGHTS_PER_GROUP = 168;
+__host__ __device__ inline int slide_seg_id(int t) { return t < SLIDE_R ? 0 : (t < SLIDE_SEG ? 1 : t / SLIDE_SEG + 1); }
+__host__ __device__ inline int slide_seg_start(int k) { return k == 0 ? 0 : (k == 1 ? SLIDE_R : (k - 1) * SLIDE_SEG); }
 
 struct sal_ctx {
     sal_params p;
@@ -199,6 +211,17 @@ inline bool uses_window_kernel(const sal_ctx *c)
     if (S >= 3 || (S > 1 && S == L)) return true;
     return !(L <= 8 || L == 16);
 }
+// Whether the energies of a volume n0 x n1 x n2 come from the kernel whose windows slide
+// along t: cube 16, FP32, stride 1, unless the context asks for the direct t contraction;
+// the t walk needs 32 rows, the reflected window rows 9 samples per axis.
+inline bool uses_slide_kernel(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
+{
+    return c->L == 16 && c->p.precision == SAL_FP32 && c->p.stride == 1 && !c->p.t_direct && n0 >= 32 &&
+           n1 >= 9 && n2 >= 9;
+}
+hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
+                               float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox = 1);
+int64_t energy_slide_num_blocks(int64_t n0, int64_t n1, int64_t n2);
 // bx.table set: nbox boxes of at most bx.d voxels per axis (the grid is nbox times that of one)
 hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
                              float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox = 1);

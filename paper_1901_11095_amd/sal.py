@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
                 ("rays", ctypes.c_uint32 * 3), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("c", ctypes.c_double), ("normalize", ctypes.c_int32),
                 ("zero_range", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("stride", ctypes.c_int32)]
+                ("stride", ctypes.c_int32), ("t_direct", ctypes.c_int32)]
 
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -157,7 +157,7 @@ class Saliency:
     def __init__(self, L: int = 8, d: Optional[int] = None, sigma: Optional[float] = None,
                  rays: Sequence[int] = RAYS_AXIS, abc=(1 / 3, 1 / 3, 1 / 3),
                  normalize: bool = True, zero_range: float = 1e-6, precision: int = FP32,
-                 stride: int = 1, device: int = 0):
+                 stride: int = 1, device: int = 0, t_direct: bool = False):
         self._lib = load()
         p = default_params(L)
         if d is not None:
@@ -172,6 +172,7 @@ class Saliency:
         p.zero_range = float(zero_range)
         p.precision = int(precision)
         p.stride = int(stride)
+        p.t_direct = int(bool(t_direct))
         self.params = p
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()

@@ -29,9 +29,9 @@ void oracle_saliency(const float *V, long n0, long n1, long n2, long L, long r, 
         }                                                                    \
     } while (0)
 
-static int run_case(int L, int32_t precision, double tol)
+static int run_case(int L, int32_t precision, double tol, long n0, int32_t t_direct)
 {
-    const long n0 = 19, n1 = 24, n2 = 29, N = n0 * n1 * n2;
+    const long n1 = 24, n2 = 29, N = n0 * n1 * n2;
     float *V = (float *)malloc(sizeof(float) * N);
     float *S = (float *)malloc(sizeof(float) * N);
     double *S_ref = (double *)malloc(sizeof(double) * N);
@@ -44,6 +44,7 @@ static int run_case(int L, int32_t precision, double tol)
     sal_params p;
     sal_default_params(&p, L);
     p.precision = precision;
+    p.t_direct = t_direct;
     sal_ctx *ctx = NULL;
     if (sal_create(&p, 0, &ctx) != SAL_OK) {
         fprintf(stderr, "sal_create: %s\n", sal_last_error(NULL));
@@ -73,7 +74,8 @@ static int run_case(int L, int32_t precision, double tol)
         ref = fmax(ref, fabs(S_ref[i]));
     }
     const double rel = err / ref;
-    printf("L=%d precision=%d max rel err %.3e (bound %.0e)\n", L, (int)precision, rel, tol);
+    printf("L=%d precision=%d rows=%ld t_direct=%d max rel err %.3e (bound %.0e)\n", L, (int)precision, n0,
+           (int)t_direct, rel, tol);
 
     /* a workspace one byte short is refused before anything is enqueued */
     const int ws_ok = sal_saliency(ctx, dV, n0, n1, n2, dS, NULL, NULL, NULL, dws, ws_bytes - 1, NULL) ==
@@ -333,9 +335,11 @@ static int other_entry_points(void)
 int main(void)
 {
     int bad = 0;
-    bad |= run_case(8, SAL_FP32, 1e-5);
-    bad |= run_case(5, SAL_FP32, 1e-5);
-    bad |= run_case(16, SAL_BF16_SPLIT, 1e-3);
+    bad |= run_case(8, SAL_FP32, 1e-5, 19, 0);
+    bad |= run_case(5, SAL_FP32, 1e-5, 19, 0);
+    bad |= run_case(16, SAL_BF16_SPLIT, 1e-3, 19, 0);
+    bad |= run_case(16, SAL_FP32, 1e-5, 40, 0);  /* windows sliding along t */
+    bad |= run_case(16, SAL_FP32, 1e-5, 40, 1);  /* every window contracted along t */
     bad |= check_tiles_case();
     bad |= other_entry_points();
 

@@ -57,14 +57,19 @@ def spikes(shape):
             (n0 - 2, n1 // 3, 1), (n0 // 2, n1 // 2, n2 // 2), (1, n1 - 1, 0)]
 
 
-FORMS = [(5, sal.FP32), (8, sal.FP32), (16, sal.FP32), (8, sal.BF16_SPLIT), (16, sal.BF16_SPLIT),
-         (8, sal.FP16), (16, sal.BF16)]
+# (L, precision, rows along t or None for SHAPES[L], direct t contraction).  At cube 16 in
+# FP32 a volume of 32 rows or more takes the kernel whose windows slide along t (a spike
+# enters and leaves the running spectra, on both sides of the restart at window t0 = 8);
+# fewer rows, or the direct flag, the kernel that contracts every window along t.
+FORMS = [(5, sal.FP32, None, False), (8, sal.FP32, None, False), (16, sal.FP32, None, False),
+         (16, sal.FP32, 37, False), (16, sal.FP32, 37, True), (8, sal.BF16_SPLIT, None, False),
+         (16, sal.BF16_SPLIT, None, False), (8, sal.FP16, None, False), (16, sal.BF16, None, False)]
 
 
-@pytest.mark.parametrize("L,prec", FORMS)
-def test_spike_window_membership(L, prec):
-    shape = SHAPES[L]
-    ctx = sal.Saliency(L=L, precision=prec)
+@pytest.mark.parametrize("L,prec,rows,direct", FORMS)
+def test_spike_window_membership(L, prec, rows, direct):
+    shape = SHAPES[L] if rows is None else (rows,) + SHAPES[L][1:]
+    ctx = sal.Saliency(L=L, precision=prec, t_direct=direct)
     const = single_spike_constant(L)
     for s in spikes(shape):
         print("spike L=%d prec=%s at %s" % (L, sal.PRECISION_NAMES[prec], s), flush=True)

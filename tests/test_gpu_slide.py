@@ -1,0 +1,84 @@
+"""Cube 16 in FP32 with the windows sliding along t (k_energy_slide) against the oracle.
+
+Each window's spectrum is the previous window's plus the 2-D DFT of the entering minus the
+leaving t-plane; the running sums restart at the windows t0 = 0, 8 and every multiple of 256.
+A volume of 300 rows spans all three kinds of segment (and 12 x 21 positions a ragged y
+tile): E, the raw maps and S within 1e-5 of each map's maximum against the FP64 oracle, and
+within 1e-6 of the kernel that contracts every window along t on its own.  Boxes and batched
+tile checks whose rows straddle the restarts equal the whole-volume maps bit for bit (the
+segments are fixed rows of the volume, so a window's arithmetic does not depend on the box).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1901_11095_amd import sal, synth
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (300, 12, 21)
+
+
+def relmax(got, ref):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def volume():
+    return synth.make_volume(SHAPE, seed=31, n_faults=2, throw=3, n_chaotic=1, chaotic_size=8)
+
+
+@pytest.fixture(scope="module")
+def maps(volume):
+    ctx = sal.Saliency(L=16)
+    Vd = torch.from_numpy(volume).cuda()
+    S, E, Sr, st = ctx.saliency_maps(Vd)
+    torch.cuda.synchronize()
+    return ctx, Vd, S.cpu().numpy(), E.cpu().numpy(), Sr.cpu().numpy(), st.cpu().numpy()
+
+
+def test_slide_vs_oracle(volume, maps):
+    _, _, S, E, Sr, _ = maps
+    print("sliding cube 16 on %s vs oracle" % (SHAPE,), flush=True)
+    ref = O.saliency(volume, O.Params(L=16))
+    for m in range(3):
+        assert relmax(E[m], ref["E"][m]) <= 1e-5, ("E", m, relmax(E[m], ref["E"][m]))
+        assert relmax(Sr[m], ref["S_raw"][m]) <= 1e-5, ("S_raw", m, relmax(Sr[m], ref["S_raw"][m]))
+    assert np.abs(S - ref["S"]).max() <= 1e-5
+
+
+def test_slide_vs_direct(volume, maps):
+    _, Vd, _, E, _, _ = maps
+    cd = sal.Saliency(L=16, t_direct=True)
+    assert cd.params.t_direct == 1
+    _, Ed, _, _ = cd.saliency_maps(Vd)
+    Ed = Ed.cpu().numpy()
+    for m in range(3):
+        assert relmax(E[m], Ed[m]) <= 1e-6, (m, relmax(E[m], Ed[m]))
+
+
+@pytest.mark.parametrize("lo,dims", [((250, 0, 3), (12, 12, 18)), ((2, 5, 0), (10, 7, 21)),
+                                     ((255, 11, 20), (45, 1, 1)), ((0, 0, 0), (300, 3, 17))])
+def test_slide_boxes_equal_whole_volume(maps, lo, dims):
+    ctx, Vd, _, _, Sr, _ = maps
+    box = ctx.raw_box(Vd, lo, dims).cpu().numpy()
+    sl = (slice(None),) + tuple(slice(a, a + d) for a, d in zip(lo, dims))
+    assert np.array_equal(box, Sr[sl])
+
+
+def test_slide_batch_equals_whole_volume(maps):
+    ctx, Vd, _, _, Sr, st = maps
+    tiles = [(248, 0, 0), (0, 4, 5), (7, 0, 13), (284, 4, 13), (120, 4, 0)]
+    td = (16, 8, 8)
+    P = torch.from_numpy(Sr).cuda() + 1.0  # every tile over the bound: replaced by the exact maps
+    X = torch.empty((len(tiles), 3) + td, dtype=torch.float32, device="cuda")
+    err = torch.zeros(len(tiles), dtype=torch.float32, device="cuda")
+    sal.check_tiles(ctx, Vd, tiles, P, tiles, td, torch.from_numpy(st).cuda(), 0.02, err, exact_out=X)
+    torch.cuda.synchronize()
+    X, P = X.cpu().numpy(), P.cpu().numpy()
+    for k, lo in enumerate(tiles):
+        sl = (slice(None),) + tuple(slice(a, a + d) for a, d in zip(lo, td))
+        assert np.array_equal(X[k], Sr[sl]), lo
+        assert np.array_equal(P[sl], Sr[sl]), lo
