@@ -10,10 +10,14 @@ error against the FP32 map and the oracle.  Prints one JSON line (see the "metri
 Inputs are resident in HBM before timing starts.
 
 Per-kernel durations come from HIP events the library records around each of its kernels
-on the launch stream; the roofline of a fused kernel is its algorithmic flop count (the
-separable DFT contraction per voxel with the first two axes shared between windows and the
-Hermitian half along t: 4hL + 8hL^2 + 8hL^3 with h = L/2 + 1) over its measured average
-duration, against the matrix-core peak of its operand type.
+on the launch stream.  The roofline of a fused kernel that contracts every window is its
+algorithmic flop count (the separable DFT contraction per voxel with the first two axes
+shared between windows and the Hermitian half along t: 4hL + 8hL^2 + 8hL^3 with
+h = L/2 + 1) over its measured average duration, against the matrix-core peak of its operand
+type.  At cube 16 in FP32 the windows slide along t (one 2-D plane DFT and one complex
+multiply-add per bin per window, then the magnitudes and projections): its roofline counts
+the flops of that method against the FP32 vector peak, and the direct kernel is timed beside
+it as the form "fp32_direct".
 """
 from __future__ import annotations
 
@@ -50,9 +54,20 @@ def dft_flops_per_voxel_min(L: int) -> int:
     return a + b + c
 
 
+def slide_flops_per_voxel(L: int = 16) -> int:
+    """Flops per window of the kernel whose windows slide along t (cube 16): the packed real
+    DFT along x of one position of the entering-minus-leaving plane (L rows of L taps, real:
+    2 L^2), the complex DFT along y of its L/2 columns (8 L^2 L/2), the update of the L^3/2
+    stored bins (complex multiply 6 + add 2), their magnitudes (3, the square root counted as
+    1) and the three weighted sums (2 each)."""
+    nb = L ** 3 // 2
+    return 2 * L * L + 8 * L * L * (L // 2) + 8 * nb + 4 * nb + 6 * nb
+
+
 # What a committed counter record covers: the kernel template's own text, the device helpers
 # and the box geometry it reads (a launcher or host-side change leaves the record valid).
 KERNEL_TEXT = {
+    "k_energy_slide": ("sal_energy_slide.hip", "k_energy_slide"),
     "k_energy_f32": ("sal_kernels.hip", "k_energy_f32"),
     "k_energy_h": ("sal_energy16.hip", "k_energy_h"),
     "k_conv3": ("sal_net.hip", "k_conv3"),
@@ -109,11 +124,11 @@ def counters_from_profiles(kernel_tag: str, kernel: str):
 
 
 def roofline_block(kernel: str, ms: float, nvox: int, flops_per_voxel: int, peak_key: str, tag: str,
-                   kernel_fn: str, min_flops_per_voxel=None):
+                   kernel_fn: str, min_flops_per_voxel=None, bound: str = "mfma"):
     """Roofline of one kernel: algorithmic flops per launch over the measured launch time."""
     achieved = flops_per_voxel * nvox / (ms * 1e-3) / 1e12
     prof = counters_from_profiles(tag, kernel_fn) or {}
-    rec = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[peak_key], "unit": "TFLOP/s",
+    rec = {"bound": bound, "achieved": achieved, "peak": PEAK_TFLOPS[peak_key], "unit": "TFLOP/s",
            "frac": achieved / PEAK_TFLOPS[peak_key], "traffic": prof.get("bytes_per_launch"),
            "kernel": kernel, "kernel_ms": ms, "flops_per_voxel": flops_per_voxel,
            "mfma_busy": prof.get("mfma_busy"), "counters": "profiles/traffic_%s.json" % tag if prof else None}
@@ -703,13 +718,28 @@ def main(argv=None):
     ms_step, kms = time_form(ctx, Vg, args.steps, args.warmup)
     value = N / (ms_step * 1e-3)
     fpv = dft_flops_per_voxel(args.L)
-    tag = "energy_f32_L%d_%s" % (args.L, args.workload)
-    roof = roofline_block("k_energy_f32<%d>" % args.L, kms["energy"], N, fpv, "f32", tag, "k_energy_f32",
-                          dft_flops_per_voxel_min(args.L))
+    slide = args.L == 16
+    if slide:
+        # the windows slide along t: the flops of that method against the FP32 vector peak
+        # (packed FP32 instructions are not used: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)
+        roof = roofline_block("k_energy_slide (cube 16, windows sliding along t)", kms["energy"], N,
+                              slide_flops_per_voxel(args.L), "f32_vector",
+                              "energy_slide_L%d_%s" % (args.L, args.workload), "k_energy_slide", bound="alu")
+        roof["flops_convention"] = (
+            "per window: 2L^2 (packed real DFT along x of one position of the plane difference) + "
+            "8L^2 L/2 (complex DFT along y of the L/2 packed columns) + 8 per stored bin (complex "
+            "multiply-add of the update, L^3/2 bins) + 4 per bin (magnitude, square root as 1) + "
+            "6 per bin (three weighted sums) = %d; adds and square roots count one flop, so the "
+            "vector-issue use is higher than frac" % slide_flops_per_voxel(args.L))
+        roof["direct_equivalent_tflops"] = fpv * N / (kms["energy"] * 1e-3) / 1e12
+    else:
+        roof = roofline_block("k_energy_f32<%d>" % args.L, kms["energy"], N, fpv, "f32",
+                              "energy_f32_L%d_%s" % (args.L, args.workload), "k_energy_f32",
+                              dft_flops_per_voxel_min(args.L))
+        roof["flops_convention"] = ("4hL + 8hL^2 + 8hL^3 per voxel, h = L/2 + 1: the separable DFT "
+                                    "contraction with real rows counted at complex cost; frac_min uses "
+                                    "the count with real rows at real cost and conjugate rows skipped")
     roof["kernels_ms"] = kms
-    roof["flops_convention"] = ("4hL + 8hL^2 + 8hL^3 per voxel, h = L/2 + 1: the separable DFT contraction "
-                                "with real rows counted at complex cost; frac_min uses the count with "
-                                "real rows at real cost and conjugate rows skipped")
 
     # the plain FP32 map with every intermediate: reference of the other forms' errors
     S_ref, E_ref, Sr_ref, st_ref = ctx.saliency_maps(Vg)
@@ -723,6 +753,21 @@ def main(argv=None):
 
     forms = {}
     ms_split = None
+    if not args.no_forms and slide:
+        print("# form fp32_direct", file=sys.stderr, flush=True)
+        c = sal.Saliency(L=args.L, t_direct=True)
+        ms_d, km = time_form(c, Vg, max(3, args.steps // 4), 2)
+        Sd = c.saliency(Vg)
+        forms["fp32_direct"] = {
+            "voxels_per_s": N / (ms_d * 1e-3), "ms_per_step": ms_d, "speedup_vs_fp32": ms_step / ms_d,
+            "kernels_ms": km,
+            "roofline": roofline_block("k_energy_f32<%d, 1>" % args.L, km["energy"], N, fpv, "f32",
+                                       "energy_f32_L%d_%s" % (args.L, args.workload), "k_energy_f32",
+                                       dft_flops_per_voxel_min(args.L)),
+            "S_abs_err_vs_plain_fp32": float((Sd - S_ref).abs().max()),
+        }
+        del c, Sd
+        torch.cuda.empty_cache()
     if not args.no_forms:
         print("# form bf16_split", file=sys.stderr, flush=True)
         c = sal.Saliency(L=args.L, precision=sal.BF16_SPLIT)

@@ -70,6 +70,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     // constant A operands, per lane: stage 1 [lane][K step], stage 2 [K step / 4][lane][4]
     __shared__ float4 a1_s[64];
     __shared__ float4 a2_s[4][64];
+    __shared__ float2 tw_s[16];
 
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, n = lane & 15;
@@ -92,6 +93,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     const int y_end = bx.o2 + bx.d2;
 
     for (int i = threadIdx.x; i < SNW * 4 * SWP; i += 64 * SNW) wt_s[i] = w_sp[i];
+    if (threadIdx.x < 16) tw_s[threadIdx.x] = tw[threadIdx.x];
     // (the 16 stage-2 operands would not fit the registers beside the 128 of the spectra)
     if (threadIdx.x < 64)
         a1_s[lane] = make_float4(w_s1[lane], w_s1[64 + lane], w_s1[128 + lane], w_s1[192 + lane]);
@@ -167,9 +169,6 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     const float *wl = wt_s + (wave * 4 + g) * SWP;
     const bool sp_lane = g == 0;  // wave 0: lane group holding the self-conjugate rows 0, 8
 
-    float2 wnext[8];
-#pragma unroll
-    for (int kt = 1; kt < 8; ++kt) wnext[kt] = tw[(kt * (s_start - SH)) & 15];
 #pragma unroll 1
     for (int j = 0; j < nsteps; ++j) {
         const int b = j & 1;
@@ -214,12 +213,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
         // ---------------- stage 3: the t update -----------------------------------------
         const int v = (s_start - SH + j) & 15;
         const float s8 = (v & 1) ? -1.f : 1.f;
+        // (from LDS: a scalar load in flight would make every LDS wait of the step wait for it)
         float2 w[8];
 #pragma unroll
-        for (int kt = 1; kt < 8; ++kt) w[kt] = wnext[kt];
-        // the next step's twiddles, in flight while this step computes
-#pragma unroll
-        for (int kt = 1; kt < 8; ++kt) wnext[kt] = tw[(kt * (v + 1)) & 15];
+        for (int kt = 1; kt < 8; ++kt) w[kt] = tw_s[(kt * v) & 15];
         // D[kt] += lo w(kt), D[16 - kt] += hi conj(w(kt)), D[0] += self, D[8] += self s8; each
         // product rounded before it is added
         auto update = [&](int mt, int q, float2 lo, float2 hi, float2 self) __attribute__((always_inline)) {
@@ -255,15 +252,17 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
                     const float2 p0 = w0 ? u : pa, p1 = w0 ? vv : pb;
                     update(1, 0, p0, p0, p0);
                     update(1, 1, p1, p1, p1);
-                } else {
-                    const bool sp = w0 && sp_lane, rg = w0 && !sp_lane;
-                    const float2 se0 = rg ? u : pa, se1 = rg ? vv : pb;
-                    const float2 lo0 = sp ? make_float2(2.f * pa.x, 0.f) : se0;
-                    const float2 hi0 = sp ? make_float2(0.f, -2.f * pa.y) : se0;
-                    const float2 lo1 = sp ? make_float2(2.f * pb.x, 0.f) : se1;
-                    const float2 hi1 = sp ? make_float2(0.f, -2.f * pb.y) : se1;
+                } else if (w0) {
+                    const float2 se0 = sp_lane ? pa : u, se1 = sp_lane ? pb : vv;
+                    const float2 lo0 = sp_lane ? make_float2(2.f * pa.x, 0.f) : se0;
+                    const float2 hi0 = sp_lane ? make_float2(0.f, -2.f * pa.y) : se0;
+                    const float2 lo1 = sp_lane ? make_float2(2.f * pb.x, 0.f) : se1;
+                    const float2 hi1 = sp_lane ? make_float2(0.f, -2.f * pb.y) : se1;
                     update(0, 0, lo0, hi0, se0);
                     update(0, 1, lo1, hi1, se1);
+                } else {
+                    update(0, 0, pa, pa, pa);
+                    update(0, 1, pb, pb, pb);
                 }
             }
         }
