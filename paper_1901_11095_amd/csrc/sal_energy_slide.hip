@@ -79,7 +79,9 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     const int tile = box_tile(bx, &box);
     V += box * bx.vstride;
     E += box * bx.estride;
-    const int ty = tile % nby, xr = (tile / nby) % nbx, kr = tile / (nby * nbx);
+    // x0 fastest: the workgroups of neighbouring x0 (15 of their 16 plane rows shared) run
+    // together on one XCD and meet the rows in its L2
+    const int xr = tile % nbx, ty = (tile / nbx) % nby, kr = tile / (nby * nbx);
     const int y_base = bx.o2 + STY * ty, x0 = bx.o1 + xr;
     const int k = slide_seg_id(bx.o0) + kr;
     const int s_start = slide_seg_start(k);
