@@ -82,3 +82,25 @@ def test_slide_batch_equals_whole_volume(maps):
         sl = (slice(None),) + tuple(slice(a, a + d) for a, d in zip(lo, td))
         assert np.array_equal(X[k], Sr[sl]), lo
         assert np.array_equal(P[sl], Sr[sl]), lo
+
+
+def test_slide_invariants():
+    """The invariants the oracle's pins fix, on the sliding kernel: a constant volume has no
+    energy outside DC and zero saliency; adding a constant changes no energy; exchanging t and
+    x exchanges E_t and E_x (t slides, x is contracted directly, so the two axes go through
+    different arithmetic)."""
+    ctx = sal.Saliency(L=16)
+    C = np.full((36, 40, 37), 2.5, np.float32)
+    S, E, _, _ = ctx.saliency_maps(torch.from_numpy(C).cuda())
+    assert float(E.abs().max()) <= 1e-6 * 2.5
+    assert bool(torch.all(S == 0))
+    V = synth.make_volume((36, 40, 37), seed=17, n_faults=1, throw=3, n_chaotic=1, chaotic_size=8)
+    _, E0, S0, _ = ctx.saliency_maps(torch.from_numpy(V).cuda())
+    _, E1, S1, _ = ctx.saliency_maps(torch.from_numpy(V + 3.0).cuda())
+    assert relmax(E1.cpu().numpy(), E0.cpu().numpy()) <= 1e-5
+    assert relmax(S1.cpu().numpy(), S0.cpu().numpy()) <= 1e-5
+    Vp = np.ascontiguousarray(V.transpose(1, 0, 2))
+    _, Ep, _, _ = ctx.saliency_maps(torch.from_numpy(Vp).cuda())
+    E0, Ep = E0.cpu().numpy(), Ep.cpu().numpy()
+    for m, mp in [(0, 1), (1, 0), (2, 2)]:
+        assert relmax(Ep[mp], E0[m].transpose(1, 0, 2)) <= 1e-5, m
