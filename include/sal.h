@@ -218,7 +218,10 @@ sal_status sal_profile_read(sal_ctx *ctx, double ms[4], int64_t *calls, int rese
  * faces inside the volume lie at least floor(L/2) + r from the box.  With stride s > 1 the
  * energies of the grown box are interpolated from the lattice windows around it, the lattice
  * starting at the first sample of V (a crop must start on a multiple of s, and lie at least
- * floor(L/2) + r + s from the box, for the whole volume's values).  workspace: at least
+ * floor(L/2) + r + s from the box, for the whole volume's values).  Equal means bit for bit,
+ * except where the windows slide along t (cube 16, FP32, stride 1, t_direct = 0): their
+ * running spectra restart at fixed rows of the volume given, so a box of that volume equals
+ * its whole-volume maps bit for bit and a crop equals them to rounding.  workspace: at least
  * sal_raw_box_workspace_size(box_dims) bytes, DEVICE, 16-byte aligned.
  */
 sal_status sal_raw_box_workspace_size(sal_ctx *ctx, const int64_t box_dims[3], size_t *bytes);
@@ -271,7 +274,8 @@ sal_status sal_tile_merge(sal_ctx *ctx, float *S_raw, int64_t n0, int64_t n1, in
  *               (vol_stride = 0: every tile lies in the same volume, else a multiple of 4 of
  *               at least n0 n1 n2 floats).  A volume may be a crop of a larger one: windows
  *               reflect at its faces, so a face inside the larger volume must lie at least
- *               floor(L/2) + r from the tile.
+ *               floor(L/2) + r from the tile (with windows sliding along t the crop's maps
+ *               then equal the larger volume's to rounding, as for sal_raw_box).
  *   box_lo      HOST int64 [nbox][3]: origin of tile b in volume b
  *   S_raw, m0..m2  DEVICE float [3][m0][m1][m2]: the predicted raw maps
  *   tile_lo     HOST int64 [nbox][3]: origin of tile b in S_raw
