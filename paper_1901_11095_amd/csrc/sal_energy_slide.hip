@@ -15,10 +15,10 @@
 //
 // Each product is rounded before it is added, so a plane that enters and later leaves
 // cancels exactly (a unit spike leaves exact zeros behind).  The running sums restart from
-// zero at fixed absolute rows (window t0 = 0, 8, 256, 512, ...; restarting at t0 = 8 keeps
+// zero at fixed absolute rows (window t0 = 0, 8, 512, 1024, ...; restarting at t0 = 8 keeps
 // the rows reflected at the t = 0 face out of every later window's history), so a window's
 // result does not depend on the box or batch it is computed in, and the rounding drift of
-// the sums stays within 271 steps.
+// the sums stays within 527 steps.
 //
 // Workgroup: one x0, 16 consecutive y0, one t segment; eight waves, wave c owning column
 // c of the 2-D plane spectrum (c = 1..7: the x frequency kx = c; c = 0: kx = 0 and kx = 8
@@ -80,8 +80,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     V += box * bx.vstride;
     E += box * bx.estride;
     // x0 fastest: the workgroups of neighbouring x0 (15 of their 16 plane rows shared) run
-    // together on one XCD and meet the rows in its L2
-    const int xr = tile % nbx, ty = (tile / nbx) % nby, kr = tile / (nby * nbx);
+    // together on one XCD and meet the rows in its L2.  The t segment next: each XCD takes a
+    // contiguous range of tiles, which must hold the short first segments and the long ones
+    // in the same mix on every XCD.
+    const int xr = tile % nbx, kr = (tile / nbx) % nseg, ty = tile / (nbx * nseg);
     const int y_base = bx.o2 + STY * ty, x0 = bx.o1 + xr;
     const int k = slide_seg_id(bx.o0) + kr;
     const int s_start = slide_seg_start(k);

@@ -47,7 +47,7 @@ struct sal_tables {
 // Windows sliding along t (cube 16, FP32, stride 1): the running spectra restart from zero at
 // the windows t0 = 0, SLIDE_R and every multiple of SLIDE_SEG from SLIDE_SEG on; segment k
 // covers the windows [slide_seg_start(k), slide_seg_start(k + 1)).
-constexpr int SLIDE_R = 8, SLIDE_SEG = 256, SLIDE_WEIGHTS_PER_GROUP = 168;
+constexpr int SLIDE_R = 8, SLIDE_SEG = 512, SLIDE_WEIGHTS_PER_GROUP = 168;
 __host__ __device__ inline int slide_seg_id(int t) { return t < SLIDE_R ? 0 : (t < SLIDE_SEG ? 1 : t / SLIDE_SEG + 1); }
 __host__ __device__ inline int slide_seg_start(int k) { return k == 0 ? 0 : (k == 1 ? SLIDE_R : (k - 1) * SLIDE_SEG); }
 

@@ -1,8 +1,8 @@
 """Cube 16 in FP32 with the windows sliding along t (k_energy_slide) against the oracle.
 
 Each window's spectrum is the previous window's plus the 2-D DFT of the entering minus the
-leaving t-plane; the running sums restart at the windows t0 = 0, 8 and every multiple of 256.
-A volume of 300 rows spans all three kinds of segment (and 12 x 21 positions a ragged y
+leaving t-plane; the running sums restart at the windows t0 = 0, 8 and every multiple of 512.
+A volume of 560 rows spans all three kinds of segment (and 10 x 19 positions a ragged y
 tile): E, the raw maps and S within 1e-5 of each map's maximum against the FP64 oracle, and
 within 1e-6 of the kernel that contracts every window along t on its own.  Boxes and batched
 tile checks whose rows straddle the restarts equal the whole-volume maps bit for bit (the
@@ -17,7 +17,7 @@ from paper_1901_11095_amd import sal, synth
 
 pytestmark = pytest.mark.gpu
 
-SHAPE = (300, 12, 21)
+SHAPE = (560, 10, 19)
 
 
 def relmax(got, ref):
@@ -59,8 +59,8 @@ def test_slide_vs_direct(volume, maps):
         assert relmax(E[m], Ed[m]) <= 1e-6, (m, relmax(E[m], Ed[m]))
 
 
-@pytest.mark.parametrize("lo,dims", [((250, 0, 3), (12, 12, 18)), ((2, 5, 0), (10, 7, 21)),
-                                     ((255, 11, 20), (45, 1, 1)), ((0, 0, 0), (300, 3, 17))])
+@pytest.mark.parametrize("lo,dims", [((506, 0, 3), (12, 10, 16)), ((2, 5, 0), (10, 5, 19)),
+                                     ((511, 9, 18), (49, 1, 1)), ((0, 0, 0), (560, 3, 17))])
 def test_slide_boxes_equal_whole_volume(maps, lo, dims):
     ctx, Vd, _, _, Sr, _ = maps
     box = ctx.raw_box(Vd, lo, dims).cpu().numpy()
@@ -70,7 +70,7 @@ def test_slide_boxes_equal_whole_volume(maps, lo, dims):
 
 def test_slide_batch_equals_whole_volume(maps):
     ctx, Vd, _, _, Sr, st = maps
-    tiles = [(248, 0, 0), (0, 4, 5), (7, 0, 13), (284, 4, 13), (120, 4, 0)]
+    tiles = [(504, 0, 0), (0, 2, 5), (20, 0, 11), (544, 2, 11), (120, 2, 0)]
     td = (16, 8, 8)
     P = torch.from_numpy(Sr).cuda() + 1.0  # every tile over the bound: replaced by the exact maps
     X = torch.empty((len(tiles), 3) + td, dtype=torch.float32, device="cuda")
