@@ -14,7 +14,7 @@ on the launch stream.  The roofline of a fused kernel that contracts every windo
 algorithmic flop count (the separable DFT contraction per voxel with the first two axes
 shared between windows and the Hermitian half along t: 4hL + 8hL^2 + 8hL^3 with
 h = L/2 + 1) over its measured average duration, against the matrix-core peak of its operand
-type.  At cube 16 in FP32 the windows slide along t (one 2-D plane DFT and one complex
+type.  At cube 8 and 16 in FP32 the windows slide along t (one 2-D plane DFT and one complex
 multiply-add per bin per window, then the magnitudes and projections): its roofline counts
 the flops of that method against the FP32 vector peak, and the direct kernel is timed beside
 it as the form "fp32_direct".
@@ -55,11 +55,11 @@ def dft_flops_per_voxel_min(L: int) -> int:
 
 
 def slide_flops_per_voxel(L: int = 16) -> int:
-    """Flops per window of the kernel whose windows slide along t (cube 16): the packed real
-    DFT along x of one position of the entering-minus-leaving plane (L rows of L taps, real:
-    2 L^2), the complex DFT along y of its L/2 columns (8 L^2 L/2), the update of the L^3/2
-    stored bins (complex multiply 6 + add 2), their magnitudes (3, the square root counted as
-    1) and the three weighted sums (2 each)."""
+    """Flops per window of the kernel whose windows slide along t (cube 8 or 16): the packed
+    real DFT along x of one position of the entering-minus-leaving plane (L rows of L taps,
+    real: 2 L^2), the complex DFT along y of its L/2 columns (8 L^2 L/2), the update of the
+    L^3/2 stored bins (complex multiply 6 + add 2), their magnitudes (3, the square root
+    counted as 1) and the three weighted sums (2 each): 53,760 at L = 16, 6,784 at L = 8."""
     nb = L ** 3 // 2
     return 2 * L * L + 8 * L * L * (L // 2) + 8 * nb + 4 * nb + 6 * nb
 
@@ -631,14 +631,26 @@ def survey_L8_leg(args, dev):
     steps = max(3, args.steps // 2)
     ms, km = time_form(ctx, Vg, steps, 2)
     fpv = dft_flops_per_voxel(L)
+    roof = roofline_block("k_energy_slide<%d> (windows sliding along t)" % L, km["energy"], N,
+                          slide_flops_per_voxel(L), "f32_vector", "energy_slide_L%d_%s" % (L, name),
+                          "k_energy_slide", bound="alu")
+    roof["direct_equivalent_tflops"] = fpv * N / (km["energy"] * 1e-3) / 1e12
     out = {"workload": name, "shape": list(V.shape), "L": L, "voxels_per_s": N / (ms * 1e-3),
-           "ms_per_step": ms, "kernels_ms": km,
-           "roofline": roofline_block("k_energy_f32<%d>" % L, km["energy"], N, fpv, "f32",
-                                      "energy_f32_L%d_%s" % (L, name), "k_energy_f32",
-                                      dft_flops_per_voxel_min(L)),
+           "ms_per_step": ms, "kernels_ms": km, "roofline": roof,
            "max_rel_err_vs_oracle": None if args.no_check else sampled_error(ctx, V, Vg, L)}
     forms = {}
     if not args.no_forms:
+        print("# %s: form fp32_direct" % name, file=sys.stderr, flush=True)
+        c = sal.Saliency(L=L, t_direct=True)
+        ms_d, kmd = time_form(c, Vg, steps, 2)
+        forms["fp32_direct"] = {
+            "voxels_per_s": N / (ms_d * 1e-3), "ms_per_step": ms_d, "speedup_vs_fp32": ms / ms_d,
+            "kernels_ms": kmd,
+            "roofline": roofline_block("k_energy_f32<%d, 1>" % L, kmd["energy"], N, fpv, "f32",
+                                       "energy_f32_L%d_%s" % (L, name), "k_energy_f32",
+                                       dft_flops_per_voxel_min(L)),
+            "max_rel_err_vs_oracle": None if args.no_check else sampled_error(c, V, Vg, L)}
+        del c
         for prec in (sal.BF16_SPLIT, sal.FP16_SPLITW, sal.FP16_SPLIT, sal.BF16, sal.FP16):
             pname = sal.PRECISION_NAMES[prec]
             print("# %s: form %s" % (name, pname), file=sys.stderr, flush=True)
@@ -718,11 +730,11 @@ def main(argv=None):
     ms_step, kms = time_form(ctx, Vg, args.steps, args.warmup)
     value = N / (ms_step * 1e-3)
     fpv = dft_flops_per_voxel(args.L)
-    slide = args.L == 16
+    slide = args.L in (8, 16)
     if slide:
         # the windows slide along t: the flops of that method against the FP32 vector peak
         # (packed FP32 instructions are not used: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)
-        roof = roofline_block("k_energy_slide (cube 16, windows sliding along t)", kms["energy"], N,
+        roof = roofline_block("k_energy_slide<%d> (windows sliding along t)" % args.L, kms["energy"], N,
                               slide_flops_per_voxel(args.L), "f32_vector",
                               "energy_slide_L%d_%s" % (args.L, args.workload), "k_energy_slide", bound="alu")
         roof["flops_convention"] = (

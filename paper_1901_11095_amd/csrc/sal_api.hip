@@ -304,28 +304,32 @@ hipError_t build_tables(sal_ctx *c)
                     const long row = 2 * half_nu[hp][i / 2] + (i & 1);
                     wcb[(hp * KSF + kk) * 64 + lane] = (float)wc[row * 2 * L + KSF * g + kk];
                 }
-    // cube 16, FP32, windows sliding along t (sal_energy_slide.hip).  Stage 1 (real DFT along
-    // x, packed): row 2c + part of column c: c = 0 holds X_0 (part 0) and X_8 (part 1), c >= 1
-    // Re and Im of X_c; A operand of lane (g, n) at K step kk is row n, tap 4 kk + g.
-    std::vector<float> ws1(L == 16 ? 4 * 64 : 1, 0.f), ws2(L == 16 ? 2 * 8 * 64 : 1, 0.f);
-    std::vector<float> wsp(L == 16 ? (size_t)8 * 4 * SLIDE_WEIGHTS_PER_GROUP : 1, 0.f);
-    if (L == 16) {
-        for (long kk = 0; kk < 4; ++kk)
+    // cube 8 and 16, FP32, windows sliding along t (sal_energy_slide.hip).  Stage 1 (real DFT
+    // along x, packed): row 2c + part of column c: c = 0 holds X_0 (part 0) and X_{L/2}
+    // (part 1), c >= 1 Re and Im of X_c; rows from L on are zero; A operand of lane (g, n) at
+    // K step kk is row n, tap 4 kk + g.
+    const bool slide = L == 8 || L == 16;
+    const long SH = L / 2, NP = L / 2 + 1, SMT = L / 8, SWP = slide_weights_per_group((int)L);
+    std::vector<float> ws1(slide ? (size_t)(L / 4) * 64 : 1, 0.f), ws2(slide ? (size_t)SMT * SH * 64 : 1, 0.f);
+    std::vector<float> wsp(slide ? (size_t)SH * 4 * SWP : 1, 0.f);
+    if (slide) {
+        for (long kk = 0; kk < L / 4; ++kk)
             for (long lane = 0; lane < 64; ++lane) {
                 const long g = lane / 16, row = lane % 16, tap = 4 * kk + g, col = row / 2, part = row % 2;
+                if (row >= L) continue;
                 double cs, sn;
-                twiddle(col == 0 ? 8 * part * tap : col * tap, L, &cs, &sn);
+                twiddle(col == 0 ? SH * part * tap : col * tap, L, &cs, &sn);
                 ws1[kk * 64 + lane] = (float)(col == 0 ? cs : (part == 0 ? cs : sn));
             }
         // Stage 2 (complex DFT along y): M tile mt, lane group g' of the tile holds rows
-        // (ky_a re, ky_a im, ky_b re, ky_b im) with (ky_a, ky_b) = (0, 8) for mt = g' = 0,
+        // (ky_a re, ky_a im, ky_b re, ky_b im) with (ky_a, ky_b) = (0, L/2) for mt = g' = 0,
         // else (4 mt + g', L - 4 mt - g'); K step kk of lane group g is tap 4 (kk / 2) + g,
         // input part kk mod 2.
-        auto kyslot = [](long mt, long gg, long q) {
-            return q == 0 ? 4 * mt + gg : (mt == 0 && gg == 0 ? 8 : 16 - (4 * mt + gg));
+        auto kyslot = [L, SH](long mt, long gg, long q) {
+            return q == 0 ? 4 * mt + gg : (mt == 0 && gg == 0 ? SH : L - (4 * mt + gg));
         };
-        for (long mt = 0; mt < 2; ++mt)
-            for (long kk = 0; kk < 8; ++kk)
+        for (long mt = 0; mt < SMT; ++mt)
+            for (long kk = 0; kk < SH; ++kk)
                 for (long lane = 0; lane < 64; ++lane) {
                     const long g = lane / 16, row = lane % 16;
                     const long ky = kyslot(mt, row / 4, (row % 4) / 2), po = row % 2;
@@ -333,48 +337,53 @@ hipError_t build_tables(sal_ctx *c)
                     double cs, sn;  // W = cs + i sn = e^{-2 pi i ky tap / L}
                     twiddle(ky * tap, L, &cs, &sn);
                     const double v = po == 0 ? (pi == 0 ? cs : -sn) : (pi == 0 ? sn : cs);
-                    ws2[(mt * 8 + kk) * 64 + lane] = (float)v;
+                    ws2[(mt * SH + kk) * 64 + lane] = (float)v;
                 }
         // Projection weights per (column c, lane group g), with 1/L^3 of the DFT and
-        // 1/(L^3 - 1) of the mean.  Columns 1..7 (kx = c): each bin stands for itself and its
-        // conjugate (kx = L - c), factor 2; M tile 0 per ky slot [q][p][m] (54 floats), M tile 1
-        // [p][m] at 54 (the two slots are ky and -ky); p = |kt|, the slots kt and L - kt summed.
-        // Column 0 (U = 2 D_{kx=0} and V = 2i D_{kx=8} slots, each standing for a bin and its
-        // conjugate, factor 1): M tile 0 [q][p][A|B][m] at 0 (108 floats), A weighing slot kt = p
-        // and B slot L - p; on the self-conjugate rows (lane group 0: ky = 0, 8) the slot L - p
-        // holds conj V, and at p in {0, 8} A weighs |Re Z| (kx = 0) and B |Im Z| (kx = 8);
-        // M tile 1 [q][p][m] at 108.
+        // 1/(L^3 - 1) of the mean; p = |kt| = 0..L/2, the slots kt and L - kt summed.  Columns
+        // 1..L/2-1 (kx = c): each bin stands for itself and its conjugate (kx = L - c),
+        // factor 2; M tile 0 per ky slot [q][p][m] (6 NP floats, NP = L/2 + 1), the other
+        // M tiles [p][m] at 6 NP (the two slots are ky and -ky).  Column 0 (U = 2 D_{kx=0} and
+        // V = 2i D_{kx=L/2} slots, each standing for a bin and its conjugate, factor 1):
+        // M tile 0 [q][p][A|B][m] at 0 (12 NP floats), A weighing slot kt = p and B slot
+        // L - p; on the self-conjugate rows (lane group 0: ky = 0, L/2) the slot L - p holds
+        // conj V, and at p in {0, L/2} A weighs |Re Z| (kx = 0) and B |Im Z| (kx = L/2); the
+        // other M tiles [q][p][m] at 12 NP.
         const double nrm = 1.0 / ((double)L3 * (double)(L3 - 1));
-        for (long cc = 0; cc < 8; ++cc)
+        for (long cc = 0; cc < SH; ++cc)
             for (long g = 0; g < 4; ++g) {
-                float *o = wsp.data() + (cc * 4 + g) * SLIDE_WEIGHTS_PER_GROUP;
+                float *o = wsp.data() + (cc * 4 + g) * SWP;
                 double w[3];
-                for (long p = 0; p <= 8; ++p) {
+                for (long p = 0; p < NP; ++p) {
                     if (cc > 0) {
                         for (long q = 0; q < 2; ++q) {
                             proj_w(p, cc, sfreq(kyslot(0, g, q), L), w);
-                            for (int m = 0; m < 3; ++m) o[q * 27 + 3 * p + m] = (float)(2.0 * w[m] * nrm);
+                            for (int m = 0; m < 3; ++m) o[q * 3 * NP + 3 * p + m] = (float)(2.0 * w[m] * nrm);
                         }
-                        proj_w(p, cc, sfreq(kyslot(1, g, 0), L), w);
-                        for (int m = 0; m < 3; ++m) o[54 + 3 * p + m] = (float)(2.0 * w[m] * nrm);
+                        if (SMT > 1) {
+                            proj_w(p, cc, sfreq(kyslot(1, g, 0), L), w);
+                            for (int m = 0; m < 3; ++m) o[6 * NP + 3 * p + m] = (float)(2.0 * w[m] * nrm);
+                        }
                         continue;
                     }
                     for (long q = 0; q < 2; ++q) {
                         double wa[3], wbv[3];
                         if (g == 0) {
-                            const long ky = 8 * q;
+                            const long ky = SH * q;
                             proj_w(p, 0, ky, wa);
-                            proj_w(p, 8, ky, wbv);
+                            proj_w(p, SH, ky, wbv);
                         } else {
-                            proj_w(p, 8 * q, g, wa);
-                            for (int m = 0; m < 3; ++m) wbv[m] = (p == 0 || p == 8) ? 0.0 : wa[m];
+                            proj_w(p, SH * q, g, wa);
+                            for (int m = 0; m < 3; ++m) wbv[m] = (p == 0 || p == SH) ? 0.0 : wa[m];
                         }
                         for (int m = 0; m < 3; ++m) {
-                            o[(q * 9 + p) * 6 + m] = (float)(wa[m] * nrm);
-                            o[(q * 9 + p) * 6 + 3 + m] = (float)(wbv[m] * nrm);
+                            o[(q * NP + p) * 6 + m] = (float)(wa[m] * nrm);
+                            o[(q * NP + p) * 6 + 3 + m] = (float)(wbv[m] * nrm);
                         }
-                        proj_w(p, 8 * q, sfreq(kyslot(1, g, 0), L), w);
-                        for (int m = 0; m < 3; ++m) o[108 + (q * 9 + p) * 3 + m] = (float)(w[m] * nrm);
+                        if (SMT > 1) {
+                            proj_w(p, SH * q, sfreq(kyslot(1, g, 0), L), w);
+                            for (int m = 0; m < 3; ++m) o[12 * NP + (q * NP + p) * 3 + m] = (float)(w[m] * nrm);
+                        }
                     }
                 }
             }

@@ -1,13 +1,13 @@
-// Steps 1-3 at cube 16 in FP32 with the window sliding along t (Sec. 2 steps 1-3).
+// Steps 1-3 at cube L = 8 and 16 in FP32 with the window sliding along t (Sec. 2 steps 1-3).
 //
 // The L^3 DFT of the window centred on (t0, x0, y0) factors into a 2-D DFT of each of its
 // L t-planes (x then y) followed by the DFT along t of those plane spectra.  With the
 // t-phase taken from the absolute row index v (a unit-modulus factor per window and
 // frequency, which the magnitudes of Eqs. (1)-(4) do not see),
-//     D_t0[kt, kx, ky] = sum_{v = t0-8}^{t0+7} P_v[kx, ky] e^{-2 pi i kt v / 16},
-// and since e^{-2 pi i kt (v + 16) / 16} = e^{-2 pi i kt v / 16}, the next window's spectrum
-// is this one's plus (P_{v_in} - P_{v_out}) e^{-2 pi i kt v_in / 16}, where the plane
-// leaving (v_out = v_in - 16) and the plane entering share the twiddle.  By linearity
+//     D_t0[kt, kx, ky] = sum_{v = t0-L/2}^{t0+L/2-1} P_v[kx, ky] e^{-2 pi i kt v / L},
+// and since e^{-2 pi i kt (v + L) / L} = e^{-2 pi i kt v / L}, the next window's spectrum
+// is this one's plus (P_{v_in} - P_{v_out}) e^{-2 pi i kt v_in / L}, where the plane
+// leaving (v_out = v_in - L) and the plane entering share the twiddle.  By linearity
 // P_{v_in} - P_{v_out} is the 2-D DFT of the plane difference V[v_in] - V[v_out], so each
 // window costs one 2-D plane DFT (matrix cores) and one complex multiply-add per bin (vector
 // ALUs) instead of a full DFT along t.  Rows are reflected at the t faces exactly as the
@@ -15,25 +15,25 @@
 //
 // Each product is rounded before it is added, so a plane that enters and later leaves
 // cancels exactly (a unit spike leaves exact zeros behind).  The running sums restart from
-// zero at fixed absolute rows (window t0 = 0, 8, 512, 1024, ...; restarting at t0 = 8 keeps
-// the rows reflected at the t = 0 face out of every later window's history), so a window's
-// result does not depend on the box or batch it is computed in, and the rounding drift of
-// the sums stays within 527 steps.
+// zero at fixed absolute rows (window t0 = 0, L/2, 512, 1024, ...; restarting at t0 = L/2
+// keeps the rows reflected at the t = 0 face out of every later window's history), so a
+// window's result does not depend on the box or batch it is computed in, and the rounding
+// drift of the sums stays within 527 steps.
 //
-// Workgroup: one x0, 16 consecutive y0, one t segment; eight waves, wave c owning column
-// c of the 2-D plane spectrum (c = 1..7: the x frequency kx = c; c = 0: kx = 0 and kx = 8
-// packed as one complex column Z = X_0 + i X_8 of two real sequences).  Per t-step:
-//   stage 1 (waves 1 and 2): X[comp, y] = sum_tau M1[comp, tau] dV[x0 - 8 + tau, y] for the
-//     31 positions y of the tile, the real DFT along x packed into 16 real components;
-//   stage 2 (wave c): P[ky, y0] = sum_tau W[ky, tau] X_c[y0 - 8 + tau], complex, 16 ky on two
-//     M tiles whose lane groups hold ky and -ky, the 16 windows on N;
-//   stage 3 (wave c): the lane's 64 bins (two M tiles x two ky x 16 kt) of its window take
-//     their update; at output steps their magnitudes are weighted into E_t, E_x, E_y.
+// Workgroup: one x0, 16 consecutive y0, one t segment; L/2 waves, wave c owning column c of
+// the 2-D plane spectrum (c = 1..L/2-1: the x frequency kx = c; c = 0: kx = 0 and kx = L/2
+// packed as one complex column Z = X_0 + i X_{L/2} of two real sequences).  Per t-step:
+//   stage 1 (waves 1 and 2): X[comp, y] = sum_tau M1[comp, tau] dV[x0 - L/2 + tau, y] for the
+//     L + 15 positions y of the tile, the real DFT along x packed into L real components;
+//   stage 2 (wave c): P[ky, y0] = sum_tau W[ky, tau] X_c[y0 - L/2 + tau], complex, L ky on
+//     L/8 M tiles whose lane groups hold ky and -ky, the 16 windows on N;
+//   stage 3 (wave c): the lane's 4L bins (M tiles x two ky x L kt) of its window take their
+//     update; at output steps their magnitudes are weighted into E_t, E_x, E_y.
 // In wave 0 the bins (kt, ky) and (-kt, -ky) of the packed column sit in one lane; its
 // update is applied to U = Z[k] + conj Z[-k] = 2 D_{kx=0}[k] and V = Z[k] - conj Z[-k] =
-// 2i D_{kx=8}[k] instead (the plane spectra transformed the same way), so every slot is one
-// bin's magnitude.  On the self-conjugate rows ky in {0, 8} the slots kt and 16 - kt hold U
-// and conj V, and kt in {0, 8} hold Z itself, whose real and imaginary parts are two
+// 2i D_{kx=L/2}[k] instead (the plane spectra transformed the same way), so every slot is one
+// bin's magnitude.  On the self-conjugate rows ky in {0, L/2} the slots kt and L - kt hold U
+// and conj V, and kt in {0, L/2} hold Z itself, whose real and imaginary parts are two
 // self-conjugate bins.
 #include <hip/hip_runtime.h>
 
@@ -44,33 +44,44 @@
 
 namespace {
 
-constexpr int SL = 16;        // cube side
-constexpr int SH = 8;         // window start = centre - 8
-constexpr int STY = 16;       // windows along y per workgroup
-constexpr int SPY = STY + SL - 1;  // stage-1 positions along y
-constexpr int SNW = 8;        // waves
-constexpr int PLS = 48;       // plane row stride (floats): tau rows 16 banks apart
-constexpr int S1S = 18;       // stage-1 output row stride (floats)
-constexpr int SWP = SLIDE_WEIGHTS_PER_GROUP;
+constexpr int STY = 16;  // windows along y per workgroup
+constexpr int PLS = 48;  // plane row stride (floats): tau rows 16 banks apart
+
+template <int L>
+struct SlideGeo {
+    static constexpr int H = L / 2;            // window start = centre - H
+    static constexpr int PY = STY + L - 1;     // stage-1 positions along y
+    static constexpr int NW = L / 2;           // waves = packed columns of the x spectrum
+    static constexpr int MT = L / 8;           // M tiles of the y contraction
+    static constexpr int S1S = L + 2;          // stage-1 output row stride (floats)
+    static constexpr int KS1 = L / 4;          // K steps of the x contraction
+    static constexpr int KS2 = L / 2;          // K steps of the y contraction
+    static constexpr int NP = L / 2 + 1;       // |kt| values
+    static constexpr int SWP = slide_weights_per_group(L);
+};
 
 __device__ __forceinline__ float mag(float re, float im) { return __builtin_amdgcn_sqrtf(fmaf(re, re, im * im)); }
 
 }  // namespace
 
-__global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) void k_energy_slide(
+template <int L>
+__global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2)) void k_energy_slide(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int nseg, int nbx, int nby,
     const float *__restrict__ w_s1, const float *__restrict__ w_s2, const float *__restrict__ w_sp,
     const float2 *__restrict__ tw, float *__restrict__ E, float *__restrict__ vmax_part)
 {
-    __shared__ float plane_s[2][16 * PLS];
+    using G = SlideGeo<L>;
+    constexpr int SL = L, SH = G::H, SPY = G::PY, SNW = G::NW, MT = G::MT, S1S = G::S1S;
+    constexpr int KS1 = G::KS1, KS2 = G::KS2, NP = G::NP, SWP = G::SWP;
+    __shared__ float plane_s[2][SL * PLS];
     __shared__ float s1_s[2][SPY * S1S + 2];
     __shared__ float wt_s[SNW * 4 * SWP];
     __shared__ float red_s[2][SNW][3][STY];
     __shared__ float vred_s[SNW];
     // constant A operands, per lane: stage 1 [lane][K step], stage 2 [K step / 4][lane][4]
     __shared__ float4 a1_s[64];
-    __shared__ float4 a2_s[4][64];
-    __shared__ float2 tw_s[16];
+    __shared__ float4 a2_s[MT * KS2 / 4][64];
+    __shared__ float2 tw_s[SL];
 
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, n = lane & 15;
@@ -79,15 +90,15 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     const int tile = box_tile(bx, &box);
     V += box * bx.vstride;
     E += box * bx.estride;
-    // x0 fastest: the workgroups of neighbouring x0 (15 of their 16 plane rows shared) run
+    // x0 fastest: the workgroups of neighbouring x0 (L - 1 of their L plane rows shared) run
     // together on one XCD and meet the rows in its L2.  The t segment next: each XCD takes a
     // contiguous range of tiles, which must hold the short first segments and the long ones
     // in the same mix on every XCD.
     const int xr = tile % nbx, kr = (tile / nbx) % nseg, ty = tile / (nbx * nseg);
     const int y_base = bx.o2 + STY * ty, x0 = bx.o1 + xr;
-    const int k = slide_seg_id(bx.o0) + kr;
-    const int s_start = slide_seg_start(k);
-    const int t_lo = max(s_start, bx.o0), t_hi = min(slide_seg_start(k + 1), min(n0, bx.o0 + bx.d0));
+    const int k = slide_seg_id(bx.o0, SH) + kr;
+    const int s_start = slide_seg_start(k, SH);
+    const int t_lo = max(s_start, bx.o0), t_hi = min(slide_seg_start(k + 1, SH), min(n0, bx.o0 + bx.d0));
     if (kr >= nseg || t_lo >= t_hi || x0 >= bx.o1 + bx.d1 || y_base >= bx.o2 + bx.d2) {
         if (threadIdx.x == 0 && vmax_part) vmax_part[blockIdx.x] = 0.f;
         return;
@@ -97,31 +108,40 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     const int y_end = bx.o2 + bx.d2;
 
     for (int i = threadIdx.x; i < SNW * 4 * SWP; i += 64 * SNW) wt_s[i] = w_sp[i];
-    if (threadIdx.x < 16) tw_s[threadIdx.x] = tw[threadIdx.x];
-    // (the 16 stage-2 operands would not fit the registers beside the 128 of the spectra)
-    if (threadIdx.x < 64)
-        a1_s[lane] = make_float4(w_s1[lane], w_s1[64 + lane], w_s1[128 + lane], w_s1[192 + lane]);
-    else if (threadIdx.x < 320) {
-        const int r = (threadIdx.x - 64) >> 6;  // operands 4 r .. 4 r + 3 in the order (mt, kk)
+    if (threadIdx.x < SL) tw_s[threadIdx.x] = tw[threadIdx.x];
+    // (at cube 16 the 16 stage-2 operands would not fit the registers beside the 128 of the
+    // spectra)
+    if (threadIdx.x < 64) {
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+        a.x = w_s1[lane];
+        a.y = w_s1[64 + lane];
+        if (KS1 > 2) {
+            a.z = w_s1[128 + lane];
+            a.w = w_s1[192 + lane];
+        }
+        a1_s[lane] = a;
+    }
+    for (int i = threadIdx.x; i < MT * KS2 * 16; i += 64 * SNW) {
+        const int r = i >> 6, ln = i & 63;  // operands 4 r .. 4 r + 3 in the order (mt, kk)
         float4 a;
-        a.x = w_s2[(4 * r) * 64 + lane];
-        a.y = w_s2[(4 * r + 1) * 64 + lane];
-        a.z = w_s2[(4 * r + 2) * 64 + lane];
-        a.w = w_s2[(4 * r + 3) * 64 + lane];
-        a2_s[r][lane] = a;
+        a.x = w_s2[(4 * r) * 64 + ln];
+        a.y = w_s2[(4 * r + 1) * 64 + ln];
+        a.z = w_s2[(4 * r + 2) * 64 + ln];
+        a.w = w_s2[(4 * r + 3) * 64 + ln];
+        a2_s[r][ln] = a;
     }
 
-    // plane samples: thread i < 496 owns (tau, yy) = (i / 31, i % 31)
+    // plane samples: thread i < L (L + 15) owns (tau, yy) = (i / (L + 15), i % (L + 15))
     const int n12 = n1 * n2;  // the volume holds at most 2^31 - 1 samples
-    const bool loader = threadIdx.x < 16 * SPY;
+    const bool loader = threadIdx.x < SL * SPY;
     int off = 0, pidx = 0;
     if (loader) {
         const int tau = threadIdx.x / SPY, yy = threadIdx.x - tau * SPY;
         off = refl_idx(x0 - SH + tau, n1) * n2 + refl_idx(y_base - SH + yy, n2);
         pidx = tau * PLS + yy;
     }
-    // step j brings row v_in = s_start - 8 + j in and, from j = 16 on, takes v_in - 16 out;
-    // the window t0 = s_start + j - 15 is complete after step j
+    // step j brings row v_in = s_start - L/2 + j in and, from j = L on, takes v_in - L out;
+    // the window t0 = s_start + j - (L - 1) is complete after step j
     const int nsteps = t_hi - s_start + SL - 1;
     float vmax = 0.f;
     // the samples of step j are loaded two steps ahead and only read when the plane is
@@ -131,7 +151,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
         if (!loader) return;
         const int vin = s_start - SH + j;
         ra = V[(uint32_t)(refl_idx(vin, n0) * n12 + off)];
-        rb = V[(uint32_t)(refl_idx(vin - SL, n0) * n12 + off)];  // in the volume; unused before j = 16
+        rb = V[(uint32_t)(refl_idx(vin - SL, n0) * n12 + off)];  // in the volume; unused before j = L
     };
     auto plane_value = [&](int j) {
         vmax = fmaxf(vmax, fmaxf(fabsf(ra), fabsf(rb)));
@@ -145,10 +165,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
         const float4 a1 = a1_s[lane];
         acc = mfma4(a1.x, pl[g * PLS], acc);
         acc = mfma4(a1.y, pl[(4 + g) * PLS], acc);
-        acc = mfma4(a1.z, pl[(8 + g) * PLS], acc);
-        acc = mfma4(a1.w, pl[(12 + g) * PLS], acc);
+        if (KS1 > 2) {
+            acc = mfma4(a1.z, pl[(8 + g) * PLS], acc);
+            acc = mfma4(a1.w, pl[(12 + g) * PLS], acc);
+        }
         const int yy = 16 * jt + n;
-        if (yy < SPY) {
+        if (yy < SPY && 4 * g < SL) {
             float *o = s1_s[buf] + yy * S1S + 4 * g;
             *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
             *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
@@ -162,16 +184,16 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
     if (nsteps > 1) load_plane(1);
 
     // spectrum state: [M tile][ky slot][kt]
-    float Dr[2][2][16], Di[2][2][16];
+    float Dr[MT][2][SL], Di[MT][2][SL];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int kt = 0; kt < 16; ++kt) Dr[mt][q][kt] = Di[mt][q][kt] = 0.f;
+            for (int kt = 0; kt < SL; ++kt) Dr[mt][q][kt] = Di[mt][q][kt] = 0.f;
 
     const float *wl = wt_s + (wave * 4 + g) * SWP;
-    const bool sp_lane = g == 0;  // wave 0: lane group holding the self-conjugate rows 0, 8
+    const bool sp_lane = g == 0;  // wave 0: lane group holding the self-conjugate rows 0, L/2
 
 #pragma unroll 1
     for (int j = 0; j < nsteps; ++j) {
@@ -194,68 +216,72 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
         }
 
         // ---------------- stage 2: DFT along y of column c = wave -----------------------
-        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+        f4 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
         {
             const float *src = s1_s[b] + (n + g) * S1S + 2 * wave;
 #pragma unroll
-            for (int kh = 0; kh < 2; ++kh) {
+            for (int kh = 0; kh < KS2 / 4; ++kh) {
                 // operands (mt, kk) for kk = 4 kh .. 4 kh + 3
-                const float4 w0 = a2_s[kh][lane], w1 = a2_s[2 + kh][lane];
+                float4 wm[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) wm[mt] = a2_s[mt * (KS2 / 4) + kh][lane];
                 const float2 x0 = *reinterpret_cast<const float2 *>(src + 8 * kh * S1S);
                 const float2 x1 = *reinterpret_cast<const float2 *>(src + (8 * kh + 4) * S1S);
-                acc[0] = mfma4(w0.x, x0.x, acc[0]);
-                acc[1] = mfma4(w1.x, x0.x, acc[1]);
-                acc[0] = mfma4(w0.y, x0.y, acc[0]);
-                acc[1] = mfma4(w1.y, x0.y, acc[1]);
-                acc[0] = mfma4(w0.z, x1.x, acc[0]);
-                acc[1] = mfma4(w1.z, x1.x, acc[1]);
-                acc[0] = mfma4(w0.w, x1.y, acc[0]);
-                acc[1] = mfma4(w1.w, x1.y, acc[1]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma4(wm[mt].x, x0.x, acc[mt]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma4(wm[mt].y, x0.y, acc[mt]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma4(wm[mt].z, x1.x, acc[mt]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma4(wm[mt].w, x1.y, acc[mt]);
             }
         }
 
         // ---------------- stage 3: the t update -----------------------------------------
-        const int v = (s_start - SH + j) & 15;
-        const float s8 = (v & 1) ? -1.f : 1.f;
+        const int v = (s_start - SH + j) & (SL - 1);
+        const float sh = (v & 1) ? -1.f : 1.f;  // the twiddle of kt = L/2
         // (from LDS: a scalar load in flight would make every LDS wait of the step wait for it)
-        float2 w[8];
+        float2 w[SH];
 #pragma unroll
-        for (int kt = 1; kt < 8; ++kt) w[kt] = tw_s[(kt * v) & 15];
-        // D[kt] += lo w(kt), D[16 - kt] += hi conj(w(kt)), D[0] += self, D[8] += self s8; each
+        for (int kt = 1; kt < SH; ++kt) w[kt] = tw_s[(kt * v) & (SL - 1)];
+        // D[kt] += lo w(kt), D[L - kt] += hi conj(w(kt)), D[0] += self, D[L/2] += self sh; each
         // product rounded before it is added
         auto update = [&](int mt, int q, float2 lo, float2 hi, float2 self) __attribute__((always_inline)) {
             Dr[mt][q][0] += self.x;
             Di[mt][q][0] += self.y;
-            Dr[mt][q][8] = fmaf(s8, self.x, Dr[mt][q][8]);
-            Di[mt][q][8] = fmaf(s8, self.y, Di[mt][q][8]);
+            Dr[mt][q][SH] = fmaf(sh, self.x, Dr[mt][q][SH]);
+            Di[mt][q][SH] = fmaf(sh, self.y, Di[mt][q][SH]);
 #pragma unroll
-            for (int kt = 1; kt < 8; ++kt) {
+            for (int kt = 1; kt < SH; ++kt) {
                 const float wr = w[kt].x, wi = w[kt].y;
                 const float b1 = lo.y * wi, d1 = lo.y * wr;
                 Dr[mt][q][kt] += fmaf(lo.x, wr, -b1);
                 Di[mt][q][kt] += fmaf(lo.x, wi, d1);
                 const float b2 = hi.y * wi, d2 = hi.y * wr;
-                Dr[mt][q][16 - kt] += fmaf(hi.x, wr, b2);
-                Di[mt][q][16 - kt] += fmaf(-hi.x, wi, d2);
+                Dr[mt][q][SL - kt] += fmaf(hi.x, wr, b2);
+                Di[mt][q][SL - kt] += fmaf(-hi.x, wi, d2);
             }
         };
         const int t0 = s_start + j - (SL - 1);
         const bool out = j >= SL - 1 && t0 >= t_lo;
-        // Slot inputs.  Columns 1..7: the plane spectrum itself.  Column 0: U = P_a + conj P_b
-        // and V = P_a - conj P_b for the rows (a, b = -a); on the self-conjugate rows (lane
-        // group 0 of M tile 0) Z itself at kt in {0, 8}, 2 Re Z at kt = 1..7 (U) and
-        // -2i Im Z at kt = 9..15 (conj V).  One update code for all waves keeps the 128
+        // Slot inputs.  Columns 1..L/2-1: the plane spectrum itself.  Column 0: U = P_a +
+        // conj P_b and V = P_a - conj P_b for the rows (a, b = -a); on the self-conjugate rows
+        // (lane group 0 of M tile 0) Z itself at kt in {0, L/2}, 2 Re Z at kt = 1..L/2-1 (U)
+        // and -2i Im Z at kt = L/2+1..L-1 (conj V).  One update code for all waves keeps the
         // spectrum registers in place.
         {
             const bool w0 = wave == 0;
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
+            for (int mt = 0; mt < MT; ++mt) {
                 const float2 pa = make_float2(acc[mt][0], acc[mt][1]), pb = make_float2(acc[mt][2], acc[mt][3]);
                 const float2 u = make_float2(pa.x + pb.x, pa.y - pb.y), vv = make_float2(pa.x - pb.x, pa.y + pb.y);
-                if (mt == 1) {
+                if (mt >= 1) {
                     const float2 p0 = w0 ? u : pa, p1 = w0 ? vv : pb;
-                    update(1, 0, p0, p0, p0);
-                    update(1, 1, p1, p1, p1);
+                    update(mt, 0, p0, p0, p0);
+                    update(mt, 1, p1, p1, p1);
                 } else if (w0) {
                     const float2 se0 = sp_lane ? pa : u, se1 = sp_lane ? pb : vv;
                     const float2 lo0 = sp_lane ? make_float2(2.f * pa.x, 0.f) : se0;
@@ -272,48 +298,57 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
         }
         float e[3] = {0.f, 0.f, 0.f};
         if (out && wave != 0) {
-            // M tile 0: the ky of the two slots differ in lane group 0 (0 and 8): a weight set
-            // per slot; M tile 1: ky and -ky, one set.  kt and 16 - kt share weights.
+            // M tile 0: the ky of the two slots differ in lane group 0 (0 and L/2): a weight
+            // set per slot; M tile 1: ky and -ky, one set.  kt and L - kt share weights.
 #pragma unroll
-            for (int p = 0; p <= 8; ++p) {
-                float m0[2], m1;
+            for (int p = 0; p < NP; ++p) {
+                float m0[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     m0[q] = mag(Dr[0][q][p], Di[0][q][p]);
-                    if (p > 0 && p < 8) m0[q] += mag(Dr[0][q][16 - p], Di[0][q][16 - p]);
+                    if (p > 0 && p < SH) m0[q] += mag(Dr[0][q][SL - p], Di[0][q][SL - p]);
                 }
-                m1 = mag(Dr[1][0][p], Di[1][0][p]) + mag(Dr[1][1][p], Di[1][1][p]);
-                if (p > 0 && p < 8)
-                    m1 += mag(Dr[1][0][16 - p], Di[1][0][16 - p]) + mag(Dr[1][1][16 - p], Di[1][1][16 - p]);
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
-                    e[m] = fmaf(wl[54 + 3 * p + m], m1,
-                                fmaf(wl[27 + 3 * p + m], m0[1], fmaf(wl[3 * p + m], m0[0], e[m])));
+                    e[m] = fmaf(wl[3 * NP + 3 * p + m], m0[1], fmaf(wl[3 * p + m], m0[0], e[m]));
+#pragma unroll
+                for (int mt = 1; mt < MT; ++mt) {
+                    float m1 = mag(Dr[mt][0][p], Di[mt][0][p]) + mag(Dr[mt][1][p], Di[mt][1][p]);
+                    if (p > 0 && p < SH)
+                        m1 += mag(Dr[mt][0][SL - p], Di[mt][0][SL - p]) + mag(Dr[mt][1][SL - p], Di[mt][1][SL - p]);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) e[m] = fmaf(wl[6 * NP + 3 * p + m], m1, e[m]);
+                }
             }
         } else if (out) {
-            // M tile 0: weights A (slot kt) and B (slot 16 - kt) per ky slot; at kt in {0, 8}
+            // M tile 0: weights A (slot kt) and B (slot L - kt) per ky slot; at kt in {0, L/2}
             // A weighs |Re Z| and B |Im Z| on the self-conjugate rows, A the magnitude
             // elsewhere.  M tile 1: one set per ky slot.
             const float sel = sp_lane ? 0.f : 1.f;
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int p = 0; p <= 8; ++p) {
+                for (int p = 0; p < NP; ++p) {
                     float ma, mb;
-                    if (p == 0 || p == 8) {
+                    if (p == 0 || p == SH) {
                         const float re = Dr[0][q][p], im = Di[0][q][p];
                         ma = __builtin_amdgcn_sqrtf(fmaf(re, re, sel * im * im));
                         mb = fabsf(im);
                     } else {
                         ma = mag(Dr[0][q][p], Di[0][q][p]);
-                        mb = mag(Dr[0][q][16 - p], Di[0][q][16 - p]);
+                        mb = mag(Dr[0][q][SL - p], Di[0][q][SL - p]);
                     }
-                    float m1 = mag(Dr[1][q][p], Di[1][q][p]);
-                    if (p > 0 && p < 8) m1 += mag(Dr[1][q][16 - p], Di[1][q][16 - p]);
-                    const float *wa = wl + (q * 9 + p) * 6, *wm = wl + 108 + (q * 9 + p) * 3;
+                    const float *wa = wl + (q * NP + p) * 6;
 #pragma unroll
-                    for (int m = 0; m < 3; ++m)
-                        e[m] = fmaf(wm[m], m1, fmaf(wa[3 + m], mb, fmaf(wa[m], ma, e[m])));
+                    for (int m = 0; m < 3; ++m) e[m] = fmaf(wa[3 + m], mb, fmaf(wa[m], ma, e[m]));
+#pragma unroll
+                    for (int mt = 1; mt < MT; ++mt) {
+                        float m1 = mag(Dr[mt][q][p], Di[mt][q][p]);
+                        if (p > 0 && p < SH) m1 += mag(Dr[mt][q][SL - p], Di[mt][q][SL - p]);
+                        const float *wm = wl + 12 * NP + (q * NP + p) * 3;
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) e[m] = fmaf(wm[m], m1, e[m]);
+                    }
                 }
         }
         if (out) {
@@ -359,21 +394,22 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * SNW) v
 
 // Segments of the t walk (window rows [slide_seg_start(k), slide_seg_start(k + 1)))
 // touched by the box rows [o0, o0 + d0); the grid covers the most any box of the batch needs.
-static int slide_nseg(int o0, int d0) { return slide_seg_id(o0 + d0 - 1) - slide_seg_id(o0) + 1; }
+static int slide_nseg(int o0, int d0, int r) { return slide_seg_id(o0 + d0 - 1, r) - slide_seg_id(o0, r) + 1; }
 
-int64_t energy_slide_num_blocks(int64_t n0, int64_t n1, int64_t n2)
+int64_t energy_slide_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 {
-    return (int64_t)slide_nseg(0, (int)n0) * n1 * ((n2 + STY - 1) / STY);
+    return (int64_t)slide_nseg(0, (int)n0, c->L / 2) * n1 * ((n2 + STY - 1) / STY);
 }
 
-hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
-                               float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
+template <int L>
+static hipError_t launch_slide_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
+                                 float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
 {
     int nseg;
     if (bx.table)
         nseg = (bx.d0 + SLIDE_SEG - 1) / SLIDE_SEG + 2;  // any o0
     else
-        nseg = slide_nseg(bx.o0, bx.d0);
+        nseg = slide_nseg(bx.o0, bx.d0, L / 2);
     const int nbx = bx.d1, nby = (bx.d2 + STY - 1) / STY;
     int64_t nb = (int64_t)nseg * nbx * nby;
     if (bx.table) {
@@ -381,7 +417,15 @@ hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int
         nb *= nbox;
     }
     if (nparts) *nparts = (int)nb;
-    hipLaunchKernelGGL(k_energy_slide, dim3((unsigned)nb), dim3(64 * SNW), 0, s, V, (int)n0, (int)n1, (int)n2, bx,
-                       nseg, nbx, nby, c->t.w_s1, c->t.w_s2, c->t.w_sp, (const float2 *)c->t.twiddle, E, vmax_part);
+    hipLaunchKernelGGL(k_energy_slide<L>, dim3((unsigned)nb), dim3(64 * (L / 2)), 0, s, V, (int)n0, (int)n1,
+                       (int)n2, bx, nseg, nbx, nby, c->t.w_s1, c->t.w_s2, c->t.w_sp,
+                       (const float2 *)c->t.twiddle, E, vmax_part);
     return hipGetLastError();
+}
+
+hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
+                               float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
+{
+    if (c->L == 8) return launch_slide_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    return launch_slide_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
 }

@@ -37,19 +37,25 @@ struct sal_tables {
                        // the halves' order, as per-lane A operands [half][K step][lane]
     float *w_gen;     // vector-ALU kernel (L < 8): [mu <= L/2][nu][om][3] projection weights
                       // times the conjugate multiplicity of mu, / (L^3 (L^3 - 1)), DC = 0
-    float *w_s1;      // cube 16, FP32 with windows sliding along t: stage-1 (packed real DFT
-                      // along x) A operands [K step][lane]
+    float *w_s1;      // cube 8 or 16, FP32 with windows sliding along t: stage-1 (packed real
+                      // DFT along x) A operands [K step][lane]
     float *w_s2;      // its stage-2 (complex DFT along y) A operands [M tile][K step][lane],
                       // rows ky and -ky in one lane group
-    float *w_sp;      // its projection weights [column][lane group][SLIDE_WEIGHTS_PER_GROUP]
+    float *w_sp;      // its projection weights [column][lane group][slide_weights_per_group(L)]
 };
 
-// Windows sliding along t (cube 16, FP32, stride 1): the running spectra restart from zero at
-// the windows t0 = 0, SLIDE_R and every multiple of SLIDE_SEG from SLIDE_SEG on; segment k
-// covers the windows [slide_seg_start(k), slide_seg_start(k + 1)).
-constexpr int SLIDE_R = 8, SLIDE_SEG = 512, SLIDE_WEIGHTS_PER_GROUP = 168;
-__host__ __device__ inline int slide_seg_id(int t) { return t < SLIDE_R ? 0 : (t < SLIDE_SEG ? 1 : t / SLIDE_SEG + 1); }
-__host__ __device__ inline int slide_seg_start(int k) { return k == 0 ? 0 : (k == 1 ? SLIDE_R : (k - 1) * SLIDE_SEG); }
+// Windows sliding along t (cube L = 8 or 16, FP32, stride 1): the running spectra restart
+// from zero at the windows t0 = 0, r = L/2 and every multiple of SLIDE_SEG from SLIDE_SEG on;
+// segment k covers the windows [slide_seg_start(k, r), slide_seg_start(k + 1, r)).
+constexpr int SLIDE_SEG = 512;
+__host__ __device__ inline int slide_seg_id(int t, int r) { return t < r ? 0 : (t < SLIDE_SEG ? 1 : t / SLIDE_SEG + 1); }
+__host__ __device__ inline int slide_seg_start(int k, int r) { return k == 0 ? 0 : (k == 1 ? r : (k - 1) * SLIDE_SEG); }
+// Projection weights per (column, lane group) of that kernel: column 0 holds two sets per
+// slot of M tile 0 (A and B, 6 (L/2 + 1)) and one per slot of the others (3 (L/2 + 1) each)
+__host__ __device__ constexpr int slide_weights_per_group(int L)
+{
+    return ((12 * (L / 2 + 1) + (L / 8 - 1) * 6 * (L / 2 + 1)) + 7) / 8 * 8;
+}
 
 struct sal_ctx {
     sal_params p;
@@ -212,16 +218,17 @@ inline bool uses_window_kernel(const sal_ctx *c)
     return !(L <= 8 || L == 16);
 }
 // Whether the energies of a volume n0 x n1 x n2 come from the kernel whose windows slide
-// along t: cube 16, FP32, stride 1, unless the context asks for the direct t contraction;
-// the t walk needs 32 rows, the reflected window rows 9 samples per axis.
+// along t: cube 8 or 16, FP32, stride 1, unless the context asks for the direct t
+// contraction; the t walk needs 2L rows, the reflected window rows L/2 + 1 samples per axis.
 inline bool uses_slide_kernel(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 {
-    return c->L == 16 && c->p.precision == SAL_FP32 && c->p.stride == 1 && !c->p.t_direct && n0 >= 32 &&
-           n1 >= 9 && n2 >= 9;
+    const int L = c->L;
+    return (L == 8 || L == 16) && c->p.precision == SAL_FP32 && c->p.stride == 1 && !c->p.t_direct &&
+           n0 >= 2 * L && n1 >= L / 2 + 1 && n2 >= L / 2 + 1;
 }
 hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
                                float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox = 1);
-int64_t energy_slide_num_blocks(int64_t n0, int64_t n1, int64_t n2);
+int64_t energy_slide_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2);
 // bx.table set: nbox boxes of at most bx.d voxels per axis (the grid is nbox times that of one)
 hipError_t launch_energy_gen(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, const ebox &bx,
                              float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox = 1);

@@ -968,7 +968,7 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
     int nby, nbx, tt;
     int64_t nb;
     if (uses_window_kernel(c)) return energy_win_num_blocks(c, k0, k1, k2);
-    if (uses_slide_kernel(c, n0, n1, n2)) return energy_slide_num_blocks(n0, n1, n2);
+    if (uses_slide_kernel(c, n0, n1, n2)) return energy_slide_num_blocks(c, n0, n1, n2);
     if (c->L == 8)
         energy_grid<8>(k0, k1, k2, &nby, &nbx, &tt, &nb);
     else if (c->L == 16)

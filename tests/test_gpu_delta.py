@@ -57,12 +57,13 @@ def spikes(shape):
             (n0 - 2, n1 // 3, 1), (n0 // 2, n1 // 2, n2 // 2), (1, n1 - 1, 0)]
 
 
-# (L, precision, rows along t or None for SHAPES[L], direct t contraction).  At cube 16 in
-# FP32 a volume of 32 rows or more takes the kernel whose windows slide along t (a spike
-# enters and leaves the running spectra, on both sides of the restart at window t0 = 8);
+# (L, precision, rows along t or None for SHAPES[L], direct t contraction).  At cube 8 and 16
+# in FP32 a volume of 2L rows or more takes the kernel whose windows slide along t (a spike
+# enters and leaves the running spectra, on both sides of the restart at window t0 = L/2);
 # fewer rows, or the direct flag, the kernel that contracts every window along t.
-FORMS = [(5, sal.FP32, None, False), (8, sal.FP32, None, False), (16, sal.FP32, None, False),
-         (16, sal.FP32, 37, False), (16, sal.FP32, 37, True), (8, sal.BF16_SPLIT, None, False),
+FORMS = [(5, sal.FP32, None, False), (8, sal.FP32, None, False), (8, sal.FP32, None, True),
+         (16, sal.FP32, None, False), (16, sal.FP32, 37, False), (16, sal.FP32, 37, True),
+         (8, sal.BF16_SPLIT, None, False),
          (16, sal.BF16_SPLIT, None, False), (8, sal.FP16, None, False), (16, sal.BF16, None, False)]
 
 

@@ -1,7 +1,7 @@
-"""Cube 16 in FP32 with the windows sliding along t (k_energy_slide) against the oracle.
+"""Cube 8 and 16 in FP32 with the windows sliding along t (k_energy_slide) against the oracle.
 
 Each window's spectrum is the previous window's plus the 2-D DFT of the entering minus the
-leaving t-plane; the running sums restart at the windows t0 = 0, 8 and every multiple of 512.
+leaving t-plane; the running sums restart at the windows t0 = 0, L/2 and every multiple of 512.
 A volume of 560 rows spans all three kinds of segment (and 10 x 19 positions a ragged y
 tile): E, the raw maps and S within 1e-5 of each map's maximum against the FP64 oracle, and
 within 1e-6 of the kernel that contracts every window along t on its own.  Boxes and batched
@@ -30,9 +30,10 @@ def volume():
     return synth.make_volume(SHAPE, seed=31, n_faults=2, throw=3, n_chaotic=1, chaotic_size=8)
 
 
-@pytest.fixture(scope="module")
-def maps(volume):
-    ctx = sal.Saliency(L=16)
+@pytest.fixture(scope="module", params=[8, 16])
+def maps(volume, request):
+    L = request.param
+    ctx = sal.Saliency(L=L)
     Vd = torch.from_numpy(volume).cuda()
     S, E, Sr, st = ctx.saliency_maps(Vd)
     torch.cuda.synchronize()
@@ -40,9 +41,9 @@ def maps(volume):
 
 
 def test_slide_vs_oracle(volume, maps):
-    _, _, S, E, Sr, _ = maps
-    print("sliding cube 16 on %s vs oracle" % (SHAPE,), flush=True)
-    ref = O.saliency(volume, O.Params(L=16))
+    ctx, _, S, E, Sr, _ = maps
+    print("sliding cube %d on %s vs oracle" % (ctx.L, SHAPE), flush=True)
+    ref = O.saliency(volume, O.Params(L=ctx.L))
     for m in range(3):
         assert relmax(E[m], ref["E"][m]) <= 1e-5, ("E", m, relmax(E[m], ref["E"][m]))
         assert relmax(Sr[m], ref["S_raw"][m]) <= 1e-5, ("S_raw", m, relmax(Sr[m], ref["S_raw"][m]))
@@ -50,8 +51,8 @@ def test_slide_vs_oracle(volume, maps):
 
 
 def test_slide_vs_direct(volume, maps):
-    _, Vd, _, E, _, _ = maps
-    cd = sal.Saliency(L=16, t_direct=True)
+    ctx, Vd, _, E, _, _ = maps
+    cd = sal.Saliency(L=ctx.L, t_direct=True)
     assert cd.params.t_direct == 1
     _, Ed, _, _ = cd.saliency_maps(Vd)
     Ed = Ed.cpu().numpy()
@@ -84,12 +85,13 @@ def test_slide_batch_equals_whole_volume(maps):
         assert np.array_equal(P[sl], Sr[sl]), lo
 
 
-def test_slide_invariants():
+@pytest.mark.parametrize("L", [8, 16])
+def test_slide_invariants(L):
     """The invariants the oracle's pins fix, on the sliding kernel: a constant volume has no
     energy outside DC and zero saliency; adding a constant changes no energy; exchanging t and
     x exchanges E_t and E_x (t slides, x is contracted directly, so the two axes go through
     different arithmetic)."""
-    ctx = sal.Saliency(L=16)
+    ctx = sal.Saliency(L=L)
     C = np.full((36, 40, 37), 2.5, np.float32)
     S, E, _, _ = ctx.saliency_maps(torch.from_numpy(C).cuda())
     assert float(E.abs().max()) <= 1e-6 * 2.5
