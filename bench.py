@@ -609,7 +609,8 @@ def strides_same_volume(Vg, S_ref, ms_fp32, L, strides=(2, 4, 8, 16)):
         d = (S - S_ref).abs()
         out["s%d" % st] = {"voxels_per_s": N / (ms * 1e-3), "ms_per_step": ms, "kernels_ms": km,
                            "speedup_vs_stride1": ms_fp32 / ms,
-                           "kernel": "k_energy_f32<%d, 2>" % L if st == 2 else (
+                           "kernel": ("k_energy_slide<%d, 2>" if L in (8, 16) else "k_energy_f32<%d, 2>") % L
+                           if st == 2 else (
                                "k_energy_win_mfma" if L == 16 else "k_energy_win<%d>" % L),
                            "S_abs_diff_vs_stride1": {"max": float(d.max()), "mean": float(d.mean())}}
         del c, S, d
@@ -631,7 +632,7 @@ def survey_L8_leg(args, dev):
     steps = max(3, args.steps // 2)
     ms, km = time_form(ctx, Vg, steps, 2)
     fpv = dft_flops_per_voxel(L)
-    roof = roofline_block("k_energy_slide<%d> (windows sliding along t)" % L, km["energy"], N,
+    roof = roofline_block("k_energy_slide<%d, 1> (windows sliding along t)" % L, km["energy"], N,
                           slide_flops_per_voxel(L), "f32_vector", "energy_slide_L%d_%s" % (L, name),
                           "k_energy_slide", bound="alu")
     roof["direct_equivalent_tflops"] = fpv * N / (km["energy"] * 1e-3) / 1e12
@@ -734,7 +735,7 @@ def main(argv=None):
     if slide:
         # the windows slide along t: the flops of that method against the FP32 vector peak
         # (packed FP32 instructions are not used: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)
-        roof = roofline_block("k_energy_slide<%d> (windows sliding along t)" % args.L, kms["energy"], N,
+        roof = roofline_block("k_energy_slide<%d, 1> (windows sliding along t)" % args.L, kms["energy"], N,
                               slide_flops_per_voxel(args.L), "f32_vector",
                               "energy_slide_L%d_%s" % (args.L, args.workload), "k_energy_slide", bound="alu")
         roof["flops_convention"] = (

@@ -796,11 +796,14 @@ static void lattice_box(const sal_ctx *c, const int64_t n[3], const int64_t eo[3
 
 // An upper bound of the energy kernels' workgroups for a box of k window positions per axis
 // that grows with the box: every fused tile holds at least 8 x 16 positions and walks at
-// least 2 of them along t; the window-by-window kernel launches at most 4096.
+// least 2 of them along t; a sliding one holds one x position and 16 y positions for every
+// t segment its k[0] stride rows touch; the window-by-window kernel launches at most 4096.
 static int64_t energy_blocks_bound(const sal_ctx *c, const int64_t k[3])
 {
     if (uses_window_kernel(c)) return 4096;
-    return ((k[1] + 7) / 8) * ((k[2] + 15) / 16) * ((k[0] + 1) / 2);
+    const int64_t fused = ((k[1] + 7) / 8) * ((k[2] + 15) / 16) * ((k[0] + 1) / 2);
+    const int64_t slide = ((k[0] * c->p.stride + SLIDE_SEG - 1) / SLIDE_SEG + 2) * k[1] * ((k[2] + 15) / 16);
+    return fused > slide ? fused : slide;
 }
 
 // workspace of sal_raw_box: E of the grown box, then (stride > 1) the lattice energies it

@@ -1,4 +1,5 @@
-// Steps 1-3 at cube L = 8 and 16 in FP32 with the window sliding along t (Sec. 2 steps 1-3).
+// Steps 1-3 at cube L = 8 and 16 in FP32 with the window sliding along t (Sec. 2 steps 1-3),
+// for windows at every voxel (stride S = 1) or on the stride-2 lattice.
 //
 // The L^3 DFT of the window centred on (t0, x0, y0) factors into a 2-D DFT of each of its
 // L t-planes (x then y) followed by the DFT along t of those plane spectra.  With the
@@ -20,15 +21,19 @@
 // window's result does not depend on the box or batch it is computed in, and the rounding
 // drift of the sums stays within 527 steps.
 //
-// Workgroup: one x0, 16 consecutive y0, one t segment; L/2 waves, wave c owning column c of
+// Workgroup: one x0, 16 y0 S apart, one t segment; L/2 waves, wave c owning column c of
 // the 2-D plane spectrum (c = 1..L/2-1: the x frequency kx = c; c = 0: kx = 0 and kx = L/2
 // packed as one complex column Z = X_0 + i X_{L/2} of two real sequences).  Per t-step:
-//   stage 1 (waves 1 and 2): X[comp, y] = sum_tau M1[comp, tau] dV[x0 - L/2 + tau, y] for the
-//     L + 15 positions y of the tile, the real DFT along x packed into L real components;
+//   stage 1 (waves 1 .. ceil(PY / 16)): X[comp, y] = sum_tau M1[comp, tau] dV[x0 - L/2 + tau, y]
+//     for the PY = 15 S + L positions y of the tile, the real DFT along x packed into L real
+//     components;
 //   stage 2 (wave c): P[ky, y0] = sum_tau W[ky, tau] X_c[y0 - L/2 + tau], complex, L ky on
 //     L/8 M tiles whose lane groups hold ky and -ky, the 16 windows on N;
 //   stage 3 (wave c): the lane's 4L bins (M tiles x two ky x L kt) of its window take their
-//     update; at output steps their magnitudes are weighted into E_t, E_x, E_y.
+//     update; at output steps (every S-th window along t) their magnitudes are weighted into
+//     E_t, E_x, E_y.
+// With S = 2 every row still enters and leaves (the sums slide one row per step), while the
+// workgroups, the y positions and the magnitudes are those of the lattice windows only.
 // In wave 0 the bins (kt, ky) and (-kt, -ky) of the packed column sit in one lane; its
 // update is applied to U = Z[k] + conj Z[-k] = 2 D_{kx=0}[k] and V = Z[k] - conj Z[-k] =
 // 2i D_{kx=L/2}[k] instead (the plane spectra transformed the same way), so every slot is one
@@ -47,10 +52,10 @@ namespace {
 constexpr int STY = 16;  // windows along y per workgroup
 constexpr int PLS = 48;  // plane row stride (floats): tau rows 16 banks apart
 
-template <int L>
+template <int L, int S>
 struct SlideGeo {
     static constexpr int H = L / 2;            // window start = centre - H
-    static constexpr int PY = STY + L - 1;     // stage-1 positions along y
+    static constexpr int PY = S * (STY - 1) + L;  // stage-1 positions along y
     static constexpr int NW = L / 2;           // waves = packed columns of the x spectrum
     static constexpr int MT = L / 8;           // M tiles of the y contraction
     static constexpr int S1S = L + 2;          // stage-1 output row stride (floats)
@@ -58,21 +63,26 @@ struct SlideGeo {
     static constexpr int KS2 = L / 2;          // K steps of the y contraction
     static constexpr int NP = L / 2 + 1;       // |kt| values
     static constexpr int SWP = slide_weights_per_group(L);
+    static constexpr int NS1 = (PY + 15) / 16;  // stage-1 waves (1 .. NS1)
+    static constexpr int NLD = (L * PY + 64 * NW - 1) / (64 * NW);  // plane samples per thread
+    static constexpr int RW = NS1 + 1 < NW ? NS1 + 1 : NW - 1;       // the wave storing E
+    static_assert(PY <= PLS && NS1 < NW, "tile geometry");
 };
 
 __device__ __forceinline__ float mag(float re, float im) { return __builtin_amdgcn_sqrtf(fmaf(re, re, im * im)); }
 
 }  // namespace
 
-template <int L>
+template <int L, int S>
 __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2)) void k_energy_slide(
     const float *__restrict__ V, int n0, int n1, int n2, ebox bx, int nseg, int nbx, int nby,
     const float *__restrict__ w_s1, const float *__restrict__ w_s2, const float *__restrict__ w_sp,
     const float2 *__restrict__ tw, float *__restrict__ E, float *__restrict__ vmax_part)
 {
-    using G = SlideGeo<L>;
+    using G = SlideGeo<L, S>;
     constexpr int SL = L, SH = G::H, SPY = G::PY, SNW = G::NW, MT = G::MT, S1S = G::S1S;
-    constexpr int KS1 = G::KS1, KS2 = G::KS2, NP = G::NP, SWP = G::SWP;
+    constexpr int KS1 = G::KS1, KS2 = G::KS2, NP = G::NP, SWP = G::SWP, NS1 = G::NS1, NLD = G::NLD;
+    constexpr int RW = G::RW;
     __shared__ float plane_s[2][SL * PLS];
     __shared__ float s1_s[2][SPY * S1S + 2];
     __shared__ float wt_s[SNW * 4 * SWP];
@@ -95,7 +105,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
     // contiguous range of tiles, which must hold the short first segments and the long ones
     // in the same mix on every XCD.
     const int xr = tile % nbx, kr = (tile / nbx) % nseg, ty = tile / (nbx * nseg);
-    const int y_base = bx.o2 + STY * ty, x0 = bx.o1 + xr;
+    const int y_base = bx.o2 + S * STY * ty, x0 = bx.o1 + S * xr;
     const int k = slide_seg_id(bx.o0, SH) + kr;
     const int s_start = slide_seg_start(k, SH);
     const int t_lo = max(s_start, bx.o0), t_hi = min(slide_seg_start(k + 1, SH), min(n0, bx.o0 + bx.d0));
@@ -131,14 +141,21 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
         a2_s[r][ln] = a;
     }
 
-    // plane samples: thread i < L (L + 15) owns (tau, yy) = (i / (L + 15), i % (L + 15))
+    // plane samples: sample i = threadIdx.x + 64 NW l < L PY (slot l of the thread) is
+    // (tau, yy) = (i / PY, i % PY)
     const int n12 = n1 * n2;  // the volume holds at most 2^31 - 1 samples
-    const bool loader = threadIdx.x < SL * SPY;
-    int off = 0, pidx = 0;
-    if (loader) {
-        const int tau = threadIdx.x / SPY, yy = threadIdx.x - tau * SPY;
-        off = refl_idx(x0 - SH + tau, n1) * n2 + refl_idx(y_base - SH + yy, n2);
-        pidx = tau * PLS + yy;
+    bool loader[NLD];
+    int off[NLD], pidx[NLD];
+#pragma unroll
+    for (int l = 0; l < NLD; ++l) {
+        const int i = threadIdx.x + 64 * SNW * l;
+        loader[l] = i < SL * SPY;
+        off[l] = pidx[l] = 0;
+        if (loader[l]) {
+            const int tau = i / SPY, yy = i - tau * SPY;
+            off[l] = refl_idx(x0 - SH + tau, n1) * n2 + refl_idx(y_base - SH + yy, n2);
+            pidx[l] = tau * PLS + yy;
+        }
     }
     // step j brings row v_in = s_start - L/2 + j in and, from j = L on, takes v_in - L out;
     // the window t0 = s_start + j - (L - 1) is complete after step j
@@ -146,19 +163,30 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
     float vmax = 0.f;
     // the samples of step j are loaded two steps ahead and only read when the plane is
     // written to LDS, so the loads' latency overlaps a whole step
-    float ra = 0.f, rb = 0.f;
+    float ra[NLD], rb[NLD];
+#pragma unroll
+    for (int l = 0; l < NLD; ++l) ra[l] = rb[l] = 0.f;
     auto load_plane = [&](int j) {
-        if (!loader) return;
         const int vin = s_start - SH + j;
-        ra = V[(uint32_t)(refl_idx(vin, n0) * n12 + off)];
-        rb = V[(uint32_t)(refl_idx(vin - SL, n0) * n12 + off)];  // in the volume; unused before j = L
+        const int r_in = refl_idx(vin, n0) * n12, r_out = refl_idx(vin - SL, n0) * n12;
+#pragma unroll
+        for (int l = 0; l < NLD; ++l)
+            if (loader[l]) {
+                ra[l] = V[(uint32_t)(r_in + off[l])];
+                rb[l] = V[(uint32_t)(r_out + off[l])];  // in the volume; unused before j = L
+            }
     };
-    auto plane_value = [&](int j) {
-        vmax = fmaxf(vmax, fmaxf(fabsf(ra), fabsf(rb)));
-        return j >= SL ? ra - rb : ra;
+    // the plane difference of step j into LDS buffer buf
+    auto store_plane = [&](int j, int buf) {
+#pragma unroll
+        for (int l = 0; l < NLD; ++l)
+            if (loader[l]) {
+                vmax = fmaxf(vmax, fmaxf(fabsf(ra[l]), fabsf(rb[l])));
+                plane_s[buf][pidx[l]] = j >= SL ? ra[l] - rb[l] : ra[l];
+            }
     };
     auto stage1 = [&](int buf) {
-        // waves 1 and 2: positions 16 (wave - 1) + n
+        // waves 1 .. NS1: positions 16 (wave - 1) + n
         const int jt = wave - 1;
         f4 acc = f4{0.f, 0.f, 0.f, 0.f};
         const float *pl = plane_s[buf] + 16 * jt + n;
@@ -177,10 +205,26 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
         }
     };
 
+    // E of the window completed at step jo (red_s[buf]), summed over the waves in a fixed
+    // order, at the lattice windows of the box
+    auto store_energies = [&](int jo, int buf) {
+        const int t0 = s_start + jo - (SL - 1);
+        if (t0 < t_lo || ((t0 - bx.o0) & (S - 1)) != 0 || lane >= 3 * STY) return;
+        const int m = lane >> 4, yy = lane & 15;
+        float e = red_s[buf][0][m][yy];
+#pragma unroll
+        for (int w = 1; w < SNW; ++w) e += red_s[buf][w][m][yy];
+        const int y = y_base + S * yy;
+        if (y < y_end) {
+            const int64_t o = ((int64_t)((t0 - bx.fo0) / S) * K1 + (x0 - bx.fo1) / S) * K2 + (y - bx.fo2) / S;
+            E[m * nbox + o] = e;
+        }
+    };
+
     load_plane(0);
-    if (loader) plane_s[0][pidx] = plane_value(0);
+    store_plane(0, 0);
     __syncthreads();
-    if (wave == 1 || wave == 2) stage1(0);
+    if (wave >= 1 && wave <= NS1) stage1(0);
     if (nsteps > 1) load_plane(1);
 
     // spectrum state: [M tile][ky slot][kt]
@@ -198,29 +242,19 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
 #pragma unroll 1
     for (int j = 0; j < nsteps; ++j) {
         const int b = j & 1;
-        if (j + 1 < nsteps && loader) plane_s[b ^ 1][pidx] = plane_value(j + 1);
+        if (j + 1 < nsteps) store_plane(j + 1, b ^ 1);
         __syncthreads();
         if (j + 2 < nsteps) load_plane(j + 2);
-        if ((wave == 1 || wave == 2) && j + 1 < nsteps) stage1(b ^ 1);
+        if (wave >= 1 && wave <= NS1 && j + 1 < nsteps) stage1(b ^ 1);
         // the previous step's energies: sum over the waves in a fixed order
-        if (wave == 3 && j >= SL && s_start + j - SL >= t_lo && lane < 3 * STY) {
-            const int m = lane >> 4, yy = lane & 15;
-            float s = red_s[b ^ 1][0][m][yy];
-#pragma unroll
-            for (int w = 1; w < SNW; ++w) s += red_s[b ^ 1][w][m][yy];
-            const int t0 = s_start + j - SL, y = y_base + yy;
-            if (y < y_end) {
-                const int64_t o = ((int64_t)(t0 - bx.fo0) * K1 + (x0 - bx.fo1)) * K2 + (y - bx.fo2);
-                E[m * nbox + o] = s;
-            }
-        }
+        if (wave == RW && j >= SL) store_energies(j - 1, b ^ 1);
 
         // ---------------- stage 2: DFT along y of column c = wave -----------------------
         f4 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
         {
-            const float *src = s1_s[b] + (n + g) * S1S + 2 * wave;
+            const float *src = s1_s[b] + (S * n + g) * S1S + 2 * wave;
 #pragma unroll
             for (int kh = 0; kh < KS2 / 4; ++kh) {
                 // operands (mt, kk) for kk = 4 kh .. 4 kh + 3
@@ -266,7 +300,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
             }
         };
         const int t0 = s_start + j - (SL - 1);
-        const bool out = j >= SL - 1 && t0 >= t_lo;
+        const bool out = j >= SL - 1 && t0 >= t_lo && ((t0 - bx.o0) & (S - 1)) == 0;
         // Slot inputs.  Columns 1..L/2-1: the plane spectrum itself.  Column 0: U = P_a +
         // conj P_b and V = P_a - conj P_b for the rows (a, b = -a); on the self-conjugate rows
         // (lane group 0 of M tile 0) Z itself at kt in {0, L/2}, 2 Re Z at kt = 1..L/2-1 (U)
@@ -363,21 +397,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
         }
     }
     __syncthreads();
-    {
-        const int j = nsteps;
-        if (wave == 3 && s_start + j - SL >= t_lo && lane < 3 * STY) {
-            const int b = j & 1;
-            const int m = lane >> 4, yy = lane & 15;
-            float s = red_s[b ^ 1][0][m][yy];
-#pragma unroll
-            for (int w = 1; w < SNW; ++w) s += red_s[b ^ 1][w][m][yy];
-            const int t0 = s_start + j - SL, y = y_base + yy;
-            if (y < y_end) {
-                const int64_t o = ((int64_t)(t0 - bx.fo0) * K1 + (x0 - bx.fo1)) * K2 + (y - bx.fo2);
-                E[m * nbox + o] = s;
-            }
-        }
-    }
+    if (wave == RW) store_energies(nsteps - 1, (nsteps - 1) & 1);
     // max |V| of everything this workgroup read (all of it lies in the volume)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
@@ -398,10 +418,11 @@ static int slide_nseg(int o0, int d0, int r) { return slide_seg_id(o0 + d0 - 1, 
 
 int64_t energy_slide_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 {
-    return (int64_t)slide_nseg(0, (int)n0, c->L / 2) * n1 * ((n2 + STY - 1) / STY);
+    const int64_t S = c->p.stride, k1 = (n1 + S - 1) / S, k2 = (n2 + S - 1) / S;
+    return (int64_t)slide_nseg(0, (int)n0, c->L / 2) * k1 * ((k2 + STY - 1) / STY);
 }
 
-template <int L>
+template <int L, int S>
 static hipError_t launch_slide_L(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
                                  float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
 {
@@ -410,14 +431,15 @@ static hipError_t launch_slide_L(const sal_ctx *c, const float *V, int64_t n0, i
         nseg = (bx.d0 + SLIDE_SEG - 1) / SLIDE_SEG + 2;  // any o0
     else
         nseg = slide_nseg(bx.o0, bx.d0, L / 2);
-    const int nbx = bx.d1, nby = (bx.d2 + STY - 1) / STY;
+    // lattice windows of the box along x, groups of 16 along y
+    const int nbx = (bx.d1 + S - 1) / S, nby = ((bx.d2 + S - 1) / S + STY - 1) / STY;
     int64_t nb = (int64_t)nseg * nbx * nby;
     if (bx.table) {
         bx.per_box = (int)nb;
         nb *= nbox;
     }
     if (nparts) *nparts = (int)nb;
-    hipLaunchKernelGGL(k_energy_slide<L>, dim3((unsigned)nb), dim3(64 * (L / 2)), 0, s, V, (int)n0, (int)n1,
+    hipLaunchKernelGGL((k_energy_slide<L, S>), dim3((unsigned)nb), dim3(64 * (L / 2)), 0, s, V, (int)n0, (int)n1,
                        (int)n2, bx, nseg, nbx, nby, c->t.w_s1, c->t.w_s2, c->t.w_sp,
                        (const float2 *)c->t.twiddle, E, vmax_part);
     return hipGetLastError();
@@ -426,6 +448,10 @@ static hipError_t launch_slide_L(const sal_ctx *c, const float *V, int64_t n0, i
 hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
                                float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
 {
-    if (c->L == 8) return launch_slide_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
-    return launch_slide_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    if (c->p.stride == 2) {
+        if (c->L == 8) return launch_slide_L<8, 2>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+        return launch_slide_L<16, 2>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    }
+    if (c->L == 8) return launch_slide_L<8, 1>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    return launch_slide_L<16, 1>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
 }

@@ -223,7 +223,7 @@ inline bool uses_window_kernel(const sal_ctx *c)
 inline bool uses_slide_kernel(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 {
     const int L = c->L;
-    return (L == 8 || L == 16) && c->p.precision == SAL_FP32 && c->p.stride == 1 && !c->p.t_direct &&
+    return (L == 8 || L == 16) && c->p.precision == SAL_FP32 && (c->p.stride == 1 || c->p.stride == 2) && !c->p.t_direct &&
            n0 >= 2 * L && n1 >= L / 2 + 1 && n2 >= L / 2 + 1;
 }
 hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,

@@ -1,7 +1,8 @@
 """Strided windows on the GPU against the FP64 oracle: energies of the windows on the
 stride-s lattice, trilinear interpolation to every voxel, Eq. (5) and Eq. (6) on the full
-grid.  Stride 2 runs on the fused kernels; strides 3 .. ceil(L/2) - 1 (overlap above one
-half) and the non-overlapping s = L on the window-by-window kernel.  Ragged volumes put
+grid.  Stride 2 runs on the fused kernels (at cube 8 and 16 in FP32 the windows slide along
+t); strides 3 .. ceil(L/2) - 1 (overlap above one half) and the non-overlapping s = L on the
+window-by-window kernel.  Ragged volumes put
 lattice points and held values at every face."""
 import numpy as np
 import pytest
@@ -84,12 +85,15 @@ def test_strided_rejects():
     assert ei.value.status == sal.SAL_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("L,s,prec", [(8, 2, sal.FP32), (16, 2, sal.BF16_SPLIT), (8, 3, sal.FP32), (16, 5, sal.FP32),
-                                      (12, 12, sal.FP32), (5, 2, sal.FP32)])
+@pytest.mark.parametrize("L,s,prec", [(8, 2, sal.FP32), (16, 2, sal.FP32), (16, 2, sal.BF16_SPLIT), (8, 3, sal.FP32),
+                                      (16, 5, sal.FP32), (12, 12, sal.FP32), (5, 2, sal.FP32)])
 def test_strided_box_tiles_stream_equal_resident(L, s, prec):
     """With windows on the lattice, the box maps (lattice windows around the grown box,
     interpolated onto it), the batched tile checks and the host-streamed slabs (each starting
-    on a lattice row) equal the whole-volume maps bit for bit."""
+    on a lattice row) equal the whole-volume maps bit for bit.  Where the windows slide along
+    t (cube 8 and 16, FP32, stride 2) a slab restarts the running sums at its own first row:
+    there the slabs equal the whole volume to rounding, and bit for bit with every window's
+    t contraction computed on its own."""
     from paper_1901_11095_amd import stream
     print("strided box/tiles/stream L=%d s=%d" % (L, s), flush=True)
     shape = (45, 38, 51)
@@ -113,4 +117,14 @@ def test_strided_box_tiles_stream_equal_resident(L, s, prec):
     assert float(err.max()) == 0.0
     S2, Sr2, _ = stream.plain_streamed(ctx, stream.pinned(V), slab=10)
     torch.cuda.synchronize()
-    assert torch.equal(Sr2, Sr) and torch.equal(S2, S)
+    if L in (8, 16) and prec == sal.FP32 and s == 2:
+        for m in range(3):
+            assert float((Sr2[m] - Sr[m]).abs().max()) <= 1e-6 * float(Sr[m].abs().max()), m
+        assert float((S2 - S).abs().max()) <= 1e-5
+        cd = sal.Saliency(L=L, stride=s, t_direct=True)
+        Sd, _, Srd, _ = cd.saliency_maps(Vd)
+        S3, Sr3, _ = stream.plain_streamed(cd, stream.pinned(V), slab=10)
+        torch.cuda.synchronize()
+        assert torch.equal(Sr3, Srd) and torch.equal(S3, Sd)
+    else:
+        assert torch.equal(Sr2, Sr) and torch.equal(S2, S)
