@@ -105,11 +105,11 @@ typedef struct {
                            on the lattice of multiples of s, energies interpolated trilinearly
                            to every voxel, the last lattice value held at the far faces;
                            Eq. (5) and Eq. (6) on the full grid.  Strides above 2 run in FP32. */
-    int32_t t_direct;   /* cube 8 or 16, FP32, stride 1: 0 (default) = each window's spectrum is
-                           the previous window's along t plus the 2-D DFT of the entering minus
-                           the leaving t-plane (the same DFT, a different rounding; volumes of
-                           at least 2L x (L/2 + 1) x (L/2 + 1)); 1 = every window's t
-                           contraction computed on its own.  Ignored elsewhere. */
+    int32_t t_direct;   /* cube 8 or 16, FP32, stride 1 or 2: 0 (default) = each window's
+                           spectrum is the previous window's along t plus the 2-D DFT of the
+                           entering minus the leaving t-plane (the same DFT, a different
+                           rounding; volumes of at least 2L x (L/2 + 1) x (L/2 + 1)); 1 = every
+                           window's t contraction computed on its own.  Ignored elsewhere. */
 } sal_params;
 
 /* Fill *p with the defaults above for cube side L. */
@@ -219,9 +219,9 @@ sal_status sal_profile_read(sal_ctx *ctx, double ms[4], int64_t *calls, int rese
  * energies of the grown box are interpolated from the lattice windows around it, the lattice
  * starting at the first sample of V (a crop must start on a multiple of s, and lie at least
  * floor(L/2) + r + s from the box, for the whole volume's values).  Equal means bit for bit,
- * except where the windows slide along t (cube 8 or 16, FP32, stride 1, t_direct = 0): their
- * running spectra restart at fixed rows of the volume given, so a box of that volume equals
- * its whole-volume maps bit for bit and a crop equals them to rounding.  workspace: at least
+ * except where the windows slide along t (cube 8 or 16, FP32, stride 1 or 2, t_direct = 0):
+ * their running spectra restart at fixed rows of the volume given, so a box of that volume
+ * equals its whole-volume maps bit for bit and a crop equals them to rounding.  workspace: at least
  * sal_raw_box_workspace_size(box_dims) bytes, DEVICE, 16-byte aligned.
  */
 sal_status sal_raw_box_workspace_size(sal_ctx *ctx, const int64_t box_dims[3], size_t *bytes);

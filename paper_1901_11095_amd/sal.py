@@ -270,6 +270,13 @@ class Saliency:
                                                    _ptr(S_raw_out), _ptr(stats_out), _stream(V.device)))
         return S
 
+    def raw_box_workspace_size(self, box_dims) -> int:
+        """Bytes of device workspace raw_box needs for a box of box_dims."""
+        n = ctypes.c_size_t()
+        self._raise(self._lib.sal_raw_box_workspace_size(self._h, _i64x3(tuple(int(d) for d in box_dims)),
+                                                         ctypes.byref(n)))
+        return n.value
+
     def raw_box(self, V: torch.Tensor, box_lo, box_dims, out: Optional[torch.Tensor] = None,
                 workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
         """Raw maps [3, *box_dims] of the positions box_lo + [0, box_dims) of V."""
@@ -278,11 +285,10 @@ class Saliency:
         if out is None:
             out = torch.empty((3,) + dims, dtype=torch.float32, device=V.device)
         if workspace is None:
-            n = ctypes.c_size_t()
-            self._raise(self._lib.sal_raw_box_workspace_size(self._h, _i64x3(dims), ctypes.byref(n)))
+            n = self.raw_box_workspace_size(dims)
             wsb = getattr(self, "_wsb", None)
-            if wsb is None or wsb.numel() < n.value:
-                wsb = self._wsb = torch.empty(max(1, n.value), dtype=torch.uint8, device=V.device)
+            if wsb is None or wsb.numel() < n:
+                wsb = self._wsb = torch.empty(max(1, n), dtype=torch.uint8, device=V.device)
             workspace = wsb
         self._raise(self._lib.sal_raw_box(self._h, _ptr(V), *V.shape, _i64x3(box_lo), _i64x3(dims),
                                           _ptr(out), _ptr(workspace), workspace.numel(),

@@ -42,6 +42,25 @@ def test_raw_box_equals_whole_volume(L, prec, lo, dims):
             assert torch.equal(box2, ref)
 
 
+@pytest.mark.parametrize("L,stride,lo", [(16, 1, (8, 4, 10)), (8, 1, (4, 4, 10)), (16, 2, (8, 4, 10))])
+def test_raw_box_stays_in_its_workspace(L, stride, lo):
+    """A box one row deep along t and long along x, whose grown box crosses the restart of the
+    sliding sums at t0 = L/2: the energy kernel's per-workgroup partials (one x position per
+    sliding workgroup) fit the workspace sal_raw_box_workspace_size gives, and no byte past
+    it changes."""
+    shape, dims = (40, 120, 40), (1, 100, 16)
+    V = torch.from_numpy(synth.make_volume(shape, seed=7, n_faults=1, throw=3, n_chaotic=1,
+                                           chaotic_size=8)).cuda()
+    ctx = sal.Saliency(L=L, stride=stride)
+    _, _, Sr, _ = ctx.saliency_maps(V)
+    need = ctx.raw_box_workspace_size(dims)
+    buf = torch.full((need + 65536,), 0xA5, dtype=torch.uint8, device="cuda")
+    box = ctx.raw_box(V, lo, dims, workspace=buf[:need])
+    torch.cuda.synchronize()
+    assert bool(torch.all(buf[need:] == 0xA5))
+    assert torch.equal(box, Sr[:, lo[0]:lo[0] + dims[0], lo[1]:lo[1] + dims[1], lo[2]:lo[2] + dims[2]])
+
+
 def test_raw_box_rejects():
     ctx = sal.Saliency(L=8)
     V = torch.zeros((20, 20, 20), device="cuda")
