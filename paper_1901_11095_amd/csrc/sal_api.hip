@@ -800,10 +800,9 @@ static void lattice_box(const sal_ctx *c, const int64_t n[3], const int64_t eo[3
 // t segment its k[0] stride rows touch; the window-by-window kernel launches at most 4096.
 static int64_t energy_blocks_bound(const sal_ctx *c, const int64_t k[3])
 {
-    if (uses_window_kernel(c)) return 4096;
-    const int64_t fused = ((k[1] + 7) / 8) * ((k[2] + 15) / 16) * ((k[0] + 1) / 2);
     const int64_t slide = ((k[0] * c->p.stride + SLIDE_SEG - 1) / SLIDE_SEG + 2) * k[1] * ((k[2] + 15) / 16);
-    return fused > slide ? fused : slide;
+    const int64_t other = uses_window_kernel(c) ? 4096 : ((k[1] + 7) / 8) * ((k[2] + 15) / 16) * ((k[0] + 1) / 2);
+    return other > slide ? other : slide;
 }
 
 // workspace of sal_raw_box: E of the grown box, then (stride > 1) the lattice energies it

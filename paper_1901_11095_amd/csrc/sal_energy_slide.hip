@@ -1,5 +1,5 @@
 // Steps 1-3 at cube L = 8 and 16 in FP32 with the window sliding along t (Sec. 2 steps 1-3),
-// for windows at every voxel (stride S = 1) or on the stride-2 lattice.
+// for windows at every voxel (stride S = 1) or on the lattice of a stride S below L/2.
 //
 // The L^3 DFT of the window centred on (t0, x0, y0) factors into a 2-D DFT of each of its
 // L t-planes (x then y) followed by the DFT along t of those plane spectra.  With the
@@ -24,15 +24,15 @@
 // Workgroup: one x0, 16 y0 S apart, one t segment; L/2 waves, wave c owning column c of
 // the 2-D plane spectrum (c = 1..L/2-1: the x frequency kx = c; c = 0: kx = 0 and kx = L/2
 // packed as one complex column Z = X_0 + i X_{L/2} of two real sequences).  Per t-step:
-//   stage 1 (waves 1 .. ceil(PY / 16)): X[comp, y] = sum_tau M1[comp, tau] dV[x0 - L/2 + tau, y]
-//     for the PY = 15 S + L positions y of the tile, the real DFT along x packed into L real
-//     components;
+//   stage 1 (waves 1 .. L/2 - 1, 16 positions at a time): X[comp, y] =
+//     sum_tau M1[comp, tau] dV[x0 - L/2 + tau, y] for the PY = 15 S + L positions y of the
+//     tile, the real DFT along x packed into L real components;
 //   stage 2 (wave c): P[ky, y0] = sum_tau W[ky, tau] X_c[y0 - L/2 + tau], complex, L ky on
 //     L/8 M tiles whose lane groups hold ky and -ky, the 16 windows on N;
 //   stage 3 (wave c): the lane's 4L bins (M tiles x two ky x L kt) of its window take their
 //     update; at output steps (every S-th window along t) their magnitudes are weighted into
 //     E_t, E_x, E_y.
-// With S = 2 every row still enters and leaves (the sums slide one row per step), while the
+// With S > 1 every row still enters and leaves (the sums slide one row per step), while the
 // workgroups, the y positions and the magnitudes are those of the lattice windows only.
 // In wave 0 the bins (kt, ky) and (-kt, -ky) of the packed column sit in one lane; its
 // update is applied to U = Z[k] + conj Z[-k] = 2 D_{kx=0}[k] and V = Z[k] - conj Z[-k] =
@@ -50,12 +50,12 @@
 namespace {
 
 constexpr int STY = 16;  // windows along y per workgroup
-constexpr int PLS = 48;  // plane row stride (floats): tau rows 16 banks apart
 
 template <int L, int S>
 struct SlideGeo {
     static constexpr int H = L / 2;            // window start = centre - H
     static constexpr int PY = S * (STY - 1) + L;  // stage-1 positions along y
+    static constexpr int PLS = (PY + 15) / 32 * 32 + 16;  // plane row stride: tau rows 16 banks apart
     static constexpr int NW = L / 2;           // waves = packed columns of the x spectrum
     static constexpr int MT = L / 8;           // M tiles of the y contraction
     static constexpr int S1S = L + 2;          // stage-1 output row stride (floats)
@@ -63,10 +63,10 @@ struct SlideGeo {
     static constexpr int KS2 = L / 2;          // K steps of the y contraction
     static constexpr int NP = L / 2 + 1;       // |kt| values
     static constexpr int SWP = slide_weights_per_group(L);
-    static constexpr int NS1 = (PY + 15) / 16;  // stage-1 waves (1 .. NS1)
+    static constexpr int NS1 = (PY + 15) / 16;  // stage-1 blocks of 16 positions
     static constexpr int NLD = (L * PY + 64 * NW - 1) / (64 * NW);  // plane samples per thread
     static constexpr int RW = NS1 + 1 < NW ? NS1 + 1 : NW - 1;       // the wave storing E
-    static_assert(PY <= PLS && NS1 < NW, "tile geometry");
+    static_assert(16 * NS1 <= PLS && 2 * S < L, "tile geometry");
 };
 
 __device__ __forceinline__ float mag(float re, float im) { return __builtin_amdgcn_sqrtf(fmaf(re, re, im * im)); }
@@ -82,7 +82,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
     using G = SlideGeo<L, S>;
     constexpr int SL = L, SH = G::H, SPY = G::PY, SNW = G::NW, MT = G::MT, S1S = G::S1S;
     constexpr int KS1 = G::KS1, KS2 = G::KS2, NP = G::NP, SWP = G::SWP, NS1 = G::NS1, NLD = G::NLD;
-    constexpr int RW = G::RW;
+    constexpr int RW = G::RW, PLS = G::PLS;
     __shared__ float plane_s[2][SL * PLS];
     __shared__ float s1_s[2][SPY * S1S + 2];
     __shared__ float wt_s[SNW * 4 * SWP];
@@ -186,22 +186,23 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
             }
     };
     auto stage1 = [&](int buf) {
-        // waves 1 .. NS1: positions 16 (wave - 1) + n
-        const int jt = wave - 1;
-        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-        const float *pl = plane_s[buf] + 16 * jt + n;
+        // waves 1 .. L/2 - 1: positions 16 jt + n for jt = wave - 1, wave - 1 + L/2 - 1, ...
         const float4 a1 = a1_s[lane];
-        acc = mfma4(a1.x, pl[g * PLS], acc);
-        acc = mfma4(a1.y, pl[(4 + g) * PLS], acc);
-        if (KS1 > 2) {
-            acc = mfma4(a1.z, pl[(8 + g) * PLS], acc);
-            acc = mfma4(a1.w, pl[(12 + g) * PLS], acc);
-        }
-        const int yy = 16 * jt + n;
-        if (yy < SPY && 4 * g < SL) {
-            float *o = s1_s[buf] + yy * S1S + 4 * g;
-            *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
-            *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+        for (int jt = wave - 1; jt < NS1; jt += SNW - 1) {
+            f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+            const float *pl = plane_s[buf] + 16 * jt + n;
+            acc = mfma4(a1.x, pl[g * PLS], acc);
+            acc = mfma4(a1.y, pl[(4 + g) * PLS], acc);
+            if (KS1 > 2) {
+                acc = mfma4(a1.z, pl[(8 + g) * PLS], acc);
+                acc = mfma4(a1.w, pl[(12 + g) * PLS], acc);
+            }
+            const int yy = 16 * jt + n;
+            if (yy < SPY && 4 * g < SL) {
+                float *o = s1_s[buf] + yy * S1S + 4 * g;
+                *reinterpret_cast<float2 *>(o) = make_float2(acc[0], acc[1]);
+                *reinterpret_cast<float2 *>(o + 2) = make_float2(acc[2], acc[3]);
+            }
         }
     };
 
@@ -209,7 +210,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
     // order, at the lattice windows of the box
     auto store_energies = [&](int jo, int buf) {
         const int t0 = s_start + jo - (SL - 1);
-        if (t0 < t_lo || ((t0 - bx.o0) & (S - 1)) != 0 || lane >= 3 * STY) return;
+        if (t0 < t_lo || (t0 - bx.o0) % S != 0 || lane >= 3 * STY) return;
         const int m = lane >> 4, yy = lane & 15;
         float e = red_s[buf][0][m][yy];
 #pragma unroll
@@ -224,7 +225,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
     load_plane(0);
     store_plane(0, 0);
     __syncthreads();
-    if (wave >= 1 && wave <= NS1) stage1(0);
+    if (wave >= 1) stage1(0);
     if (nsteps > 1) load_plane(1);
 
     // spectrum state: [M tile][ky slot][kt]
@@ -245,7 +246,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
         if (j + 1 < nsteps) store_plane(j + 1, b ^ 1);
         __syncthreads();
         if (j + 2 < nsteps) load_plane(j + 2);
-        if (wave >= 1 && wave <= NS1 && j + 1 < nsteps) stage1(b ^ 1);
+        if (wave >= 1 && j + 1 < nsteps) stage1(b ^ 1);
         // the previous step's energies: sum over the waves in a fixed order
         if (wave == RW && j >= SL) store_energies(j - 1, b ^ 1);
 
@@ -300,7 +301,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__(64 * (L / 2
             }
         };
         const int t0 = s_start + j - (SL - 1);
-        const bool out = j >= SL - 1 && t0 >= t_lo && ((t0 - bx.o0) & (S - 1)) == 0;
+        const bool out = j >= SL - 1 && t0 >= t_lo && (t0 - bx.o0) % S == 0;
         // Slot inputs.  Columns 1..L/2-1: the plane spectrum itself.  Column 0: U = P_a +
         // conj P_b and V = P_a - conj P_b for the rows (a, b = -a); on the self-conjugate rows
         // (lane group 0 of M tile 0) Z itself at kt in {0, L/2}, 2 Re Z at kt = 1..L/2-1 (U)
@@ -448,10 +449,18 @@ static hipError_t launch_slide_L(const sal_ctx *c, const float *V, int64_t n0, i
 hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,
                                float *E, float *vmax_part, int *nparts, hipStream_t s, int nbox)
 {
-    if (c->p.stride == 2) {
-        if (c->L == 8) return launch_slide_L<8, 2>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
-        return launch_slide_L<16, 2>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
-    }
-    if (c->L == 8) return launch_slide_L<8, 1>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
-    return launch_slide_L<16, 1>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+#define SAL_SLIDE(LL, SS) \
+    if (c->L == LL && c->p.stride == SS) return launch_slide_L<LL, SS>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox)
+    SAL_SLIDE(8, 1);
+    SAL_SLIDE(8, 2);
+    SAL_SLIDE(8, 3);
+    SAL_SLIDE(16, 1);
+    SAL_SLIDE(16, 2);
+    SAL_SLIDE(16, 3);
+    SAL_SLIDE(16, 4);
+    SAL_SLIDE(16, 5);
+    SAL_SLIDE(16, 6);
+    SAL_SLIDE(16, 7);
+#undef SAL_SLIDE
+    return hipErrorInvalidValue;
 }

@@ -218,12 +218,13 @@ inline bool uses_window_kernel(const sal_ctx *c)
     return !(L <= 8 || L == 16);
 }
 // Whether the energies of a volume n0 x n1 x n2 come from the kernel whose windows slide
-// along t: cube 8 or 16, FP32, stride 1, unless the context asks for the direct t
-// contraction; the t walk needs 2L rows, the reflected window rows L/2 + 1 samples per axis.
+// along t: cube 8 or 16, FP32, stride 1 or any overlapping stride below L/2, unless the
+// context asks for the direct t contraction; the t walk needs 2L rows, the reflected window
+// rows L/2 + 1 samples per axis.  Checked before the window-by-window kernel.
 inline bool uses_slide_kernel(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
 {
     const int L = c->L;
-    return (L == 8 || L == 16) && c->p.precision == SAL_FP32 && (c->p.stride == 1 || c->p.stride == 2) && !c->p.t_direct &&
+    return (L == 8 || L == 16) && c->p.precision == SAL_FP32 && 2 * c->p.stride < L && !c->p.t_direct &&
            n0 >= 2 * L && n1 >= L / 2 + 1 && n2 >= L / 2 + 1;
 }
 hipError_t launch_energy_slide(const sal_ctx *c, const float *V, int64_t n0, int64_t n1, int64_t n2, ebox bx,

@@ -967,8 +967,8 @@ int64_t energy_num_blocks(const sal_ctx *c, int64_t n0, int64_t n1, int64_t n2)
     const int64_t k0 = (n0 + S - 1) / S, k1 = (n1 + S - 1) / S, k2 = (n2 + S - 1) / S;
     int nby, nbx, tt;
     int64_t nb;
-    if (uses_window_kernel(c)) return energy_win_num_blocks(c, k0, k1, k2);
     if (uses_slide_kernel(c, n0, n1, n2)) return energy_slide_num_blocks(c, n0, n1, n2);
+    if (uses_window_kernel(c)) return energy_win_num_blocks(c, k0, k1, k2);
     if (c->L == 8)
         energy_grid<8>(k0, k1, k2, &nby, &nbx, &tt, &nb);
     else if (c->L == 16)
@@ -1012,8 +1012,8 @@ hipError_t launch_energy(const sal_ctx *c, const float *V, int64_t n0, int64_t n
     const int S = c->p.stride;
     ebox bx = box ? framed_box((int)box[0], (int)box[1], (int)box[2], (int)box[3], (int)box[4], (int)box[5], S)
                   : framed_box(0, 0, 0, (int)n0, (int)n1, (int)n2, S);
-    if (uses_window_kernel(c)) return launch_energy_win(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     if (uses_slide_kernel(c, n0, n1, n2)) return launch_energy_slide(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
+    if (uses_window_kernel(c)) return launch_energy_win(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
     return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s);
@@ -1027,9 +1027,9 @@ hipError_t launch_energy_boxes(const sal_ctx *c, const float *V, int64_t n0, int
     bx.table = table;
     bx.vstride = vstride;
     bx.estride = estride;
-    if (uses_window_kernel(c)) return launch_energy_win(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     if (uses_slide_kernel(c, n0, n1, n2))
         return launch_energy_slide(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
+    if (uses_window_kernel(c)) return launch_energy_win(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     if (c->L == 8) return launch_energy_L<8>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     if (c->L == 16) return launch_energy_L<16>(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);
     return launch_energy_gen(c, V, n0, n1, n2, bx, E, vmax_part, nparts, s, nbox);

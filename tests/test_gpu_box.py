@@ -42,7 +42,8 @@ def test_raw_box_equals_whole_volume(L, prec, lo, dims):
             assert torch.equal(box2, ref)
 
 
-@pytest.mark.parametrize("L,stride,lo", [(16, 1, (8, 4, 10)), (8, 1, (4, 4, 10)), (16, 2, (8, 4, 10))])
+@pytest.mark.parametrize("L,stride,lo", [(16, 1, (8, 4, 10)), (8, 1, (4, 4, 10)), (16, 2, (8, 4, 10)),
+                                         (16, 5, (8, 4, 10)), (8, 3, (4, 4, 10))])
 def test_raw_box_stays_in_its_workspace(L, stride, lo):
     """A box one row deep along t and long along x, whose grown box crosses the restart of the
     sliding sums at t0 = L/2: the energy kernel's per-workgroup partials (one x position per

@@ -1,5 +1,5 @@
 """Cube 8 and 16 in FP32 with the windows sliding along t (k_energy_slide) against the oracle,
-for windows at every voxel and on the stride-2 lattice.
+for windows at every voxel and on the lattices of the strides below L/2.
 
 Each window's spectrum is the previous window's plus the 2-D DFT of the entering minus the
 leaving t-plane; the running sums restart at the windows t0 = 0, L/2 and every multiple of 512.
@@ -109,31 +109,34 @@ def test_slide_invariants(L):
         assert relmax(Ep[mp], E0[m].transpose(1, 0, 2)) <= 1e-5, m
 
 
-@pytest.fixture(scope="module", params=[8, 16])
+@pytest.fixture(scope="module", params=[(8, 2), (8, 3), (16, 2), (16, 3), (16, 4), (16, 7)])
 def maps2(volume, request):
-    """Windows on the stride-2 lattice: the sums slide one row per step, the magnitudes are
-    taken at every second window."""
-    L = request.param
-    ctx = sal.Saliency(L=L, stride=2)
+    """Windows on the stride-s lattice: the sums slide one row per step, the magnitudes are
+    taken at every s-th window."""
+    L, st = request.param
+    ctx = sal.Saliency(L=L, stride=st)
     Vd = torch.from_numpy(volume).cuda()
     S, E, Sr, st = ctx.saliency_maps(Vd)
     torch.cuda.synchronize()
     return ctx, Vd, S.cpu().numpy(), E.cpu().numpy(), Sr.cpu().numpy()
 
 
-def test_slide_stride2_vs_oracle(volume, maps2):
+def test_slide_strided_vs_oracle(volume, maps2):
     ctx, _, S, E, Sr = maps2
-    print("sliding cube %d stride 2 on %s vs oracle" % (ctx.L, SHAPE), flush=True)
-    ref = O.saliency(volume, O.Params(L=ctx.L, stride=2))
+    st = ctx.params.stride
+    print("sliding cube %d stride %d on %s vs oracle" % (ctx.L, st, SHAPE), flush=True)
+    ref = O.saliency(volume, O.Params(L=ctx.L, stride=st))
     for m in range(3):
         assert relmax(E[m], ref["E"][m]) <= 1e-5, ("E", m, relmax(E[m], ref["E"][m]))
         assert relmax(Sr[m], ref["S_raw"][m]) <= 1e-5, ("S_raw", m, relmax(Sr[m], ref["S_raw"][m]))
     assert np.abs(S - ref["S"]).max() <= 1e-5
 
 
-def test_slide_stride2_vs_direct(maps2):
+def test_slide_strided_vs_direct(maps2):
+    """Against the kernels that contract every window along t on its own (the fused kernel at
+    stride 2, the window-by-window kernel above)."""
     ctx, Vd, _, E, _ = maps2
-    cd = sal.Saliency(L=ctx.L, stride=2, t_direct=True)
+    cd = sal.Saliency(L=ctx.L, stride=ctx.params.stride, t_direct=True)
     _, Ed, _, _ = cd.saliency_maps(Vd)
     Ed = Ed.cpu().numpy()
     for m in range(3):
@@ -142,7 +145,7 @@ def test_slide_stride2_vs_direct(maps2):
 
 @pytest.mark.parametrize("lo,dims", [((500, 1, 3), (20, 8, 16)), ((2, 5, 0), (10, 5, 19)),
                                      ((511, 9, 18), (49, 1, 1))])
-def test_slide_stride2_boxes_equal_whole_volume(maps2, lo, dims):
+def test_slide_strided_boxes_equal_whole_volume(maps2, lo, dims):
     ctx, Vd, _, _, Sr = maps2
     box = ctx.raw_box(Vd, lo, dims).cpu().numpy()
     sl = (slice(None),) + tuple(slice(a, a + d) for a, d in zip(lo, dims))
