@@ -590,11 +590,11 @@ def stream_leg(args, dev, V=None):
     }
 
 
-def strides_same_volume(Vg, S_ref, ms_fp32, L, strides=(2, 4, 8, 16)):
+def strides_same_volume(Vg, S_ref, ms_fp32, L, strides=(2, 3, 4, 7, 8, 16)):
     """Windows on the stride-s lattice of the headline volume (FP32), energies interpolated
     back to every voxel: speed against stride 1 and the difference of the final map from the
-    stride-1 map.  Stride 2 runs on the fused kernel, larger strides and the non-overlapping
-    s = L on the window-by-window kernel."""
+    stride-1 map.  At cube 8 and 16 the strides below L/2 run on the kernel whose windows
+    slide along t, the non-overlapping s = L on the window-by-window kernel."""
     import torch
     from paper_1901_11095_amd import sal
     out = {}
@@ -609,8 +609,8 @@ def strides_same_volume(Vg, S_ref, ms_fp32, L, strides=(2, 4, 8, 16)):
         d = (S - S_ref).abs()
         out["s%d" % st] = {"voxels_per_s": N / (ms * 1e-3), "ms_per_step": ms, "kernels_ms": km,
                            "speedup_vs_stride1": ms_fp32 / ms,
-                           "kernel": ("k_energy_slide<%d, 2>" if L in (8, 16) else "k_energy_f32<%d, 2>") % L
-                           if st == 2 else (
+                           "kernel": "k_energy_slide<%d, %d>" % (L, st) if L in (8, 16) and 2 * st < L else (
+                               "k_energy_f32<%d, 2>" % L if st == 2 else
                                "k_energy_win_mfma" if L == 16 else "k_energy_win<%d>" % L),
                            "S_abs_diff_vs_stride1": {"max": float(d.max()), "mean": float(d.mean())}}
         del c, S, d
