@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("L,prec,stride", [(8, sal.FP32, 1), (16, sal.BF16_SPLIT, 1), (5, sal.FP32, 1),
-                                           (8, sal.FP32, 2), (16, sal.FP32, 1)])
+                                           (8, sal.FP32, 2), (16, sal.FP32, 1), (16, sal.FP32, 4)])
 def test_graph_replay_matches_eager(L, prec, stride):
     shape = (40, 48, 56)
     ctx = sal.Saliency(L=L, precision=prec, stride=stride)
