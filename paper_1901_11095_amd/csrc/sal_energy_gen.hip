@@ -12,9 +12,11 @@
 //   ring    the L t-planes of the (NX + L - 1) x (NY + L - 1) patch the windows cover, one
 //           new plane per t (reflected at the volume faces when loaded);
 //   stage A A[pos][mu] = sum_p W[mu, p] V[t0 - H + p, pos] for every patch position;
-//   stage B per mu: B[x0][y'][nu] = sum_q W[nu, q] A[x0 + q, y'][mu];
+//   stage B per mu: B[x0][y'][nu] = sum_q W[nu, q] A[x0 + q, y'][mu], one thread per
+//           patch position for all nu;
 //   stage C per mu and nu, one thread per voxel (x0, y0): F[om] = sum_r W[om, r]
 //           B[x0][y0 + r][nu], |F| weighted by the projections into E_t, E_x, E_y.
+// Stages B and C take their L-point DFTs with the terms and outputs in conjugate pairs.
 // Bins with mu and L - mu have equal magnitudes and weights (conjugates); the weight table
 // carries that multiplicity, so only mu <= L/2 is computed.
 #include <hip/hip_runtime.h>
@@ -37,11 +39,60 @@ struct GenTw {
     float2 w[L];  // e^{-2 pi i k / L}, k = 0..L-1
 };
 
-__device__ __forceinline__ float2 cmad(float2 a, float2 w, float2 acc)
+// All L outputs F[om] = sum_r b[r] w^(om r) of an L-point complex DFT (w^k = tw.w[k]).
+// Since w^(om (L - r)) = conj w^(om r), the inputs r and L - r enter through their sum u_r
+// and difference d_r: with P = b_0 + sum_r u_r Re w^(om r) (+ b_(L/2) (-1)^om for even L)
+// and Q = sum_r d_r Im w^(om r), F[om] = P + iQ and F[L - om] = P - iQ (as complex
+// numbers, P and Q complex).  4 flops per input pair and output pair instead of 16.
+template <int L>
+__device__ __forceinline__ void dft_pairs(const float2 (&b)[L], const GenTw<L> &tw, float2 (&F)[L])
 {
-    acc.x = fmaf(a.x, w.x, fmaf(-a.y, w.y, acc.x));
-    acc.y = fmaf(a.x, w.y, fmaf(a.y, w.x, acc.y));
-    return acc;
+    constexpr int M = (L - 1) / 2;  // conjugate pairs (r, L - r), r = 1..M
+    constexpr bool EV = L % 2 == 0;
+    float2 u[M + 1], d[M + 1];
+    float2 f0 = b[0];
+#pragma unroll
+    for (int r = 1; r <= M; ++r) {
+        u[r] = make_float2(b[r].x + b[L - r].x, b[r].y + b[L - r].y);
+        d[r] = make_float2(b[r].x - b[L - r].x, b[r].y - b[L - r].y);
+        f0.x += u[r].x;
+        f0.y += u[r].y;
+    }
+    if (EV) {
+        f0.x += b[L / 2].x;
+        f0.y += b[L / 2].y;
+    }
+    F[0] = f0;
+#pragma unroll
+    for (int om = 1; om <= M; ++om) {
+        float2 P = b[0], Q = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int r = 1; r <= M; ++r) {
+            const float2 w = tw.w[(om * r) % L];
+            P.x = fmaf(u[r].x, w.x, P.x);
+            P.y = fmaf(u[r].y, w.x, P.y);
+            Q.x = fmaf(d[r].x, w.y, Q.x);
+            Q.y = fmaf(d[r].y, w.y, Q.y);
+        }
+        if (EV) {
+            const float sg = (om & 1) ? -1.f : 1.f;
+            P.x = fmaf(sg, b[L / 2].x, P.x);
+            P.y = fmaf(sg, b[L / 2].y, P.y);
+        }
+        F[om] = make_float2(P.x - Q.y, P.y + Q.x);
+        F[L - om] = make_float2(P.x + Q.y, P.y - Q.x);
+    }
+    if (EV) {
+        float2 fh = b[0];
+#pragma unroll
+        for (int r = 1; r <= M; ++r) {
+            const float sg = (r & 1) ? -1.f : 1.f;
+            fh.x = fmaf(sg, u[r].x, fh.x);
+            fh.y = fmaf(sg, u[r].y, fh.y);
+        }
+        const float sg = ((L / 2) & 1) ? -1.f : 1.f;
+        F[L / 2] = make_float2(fmaf(sg, b[L / 2].x, fh.x), fmaf(sg, b[L / 2].y, fh.y));
+    }
 }
 
 }  // namespace
@@ -61,7 +112,6 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
     __shared__ float2 A_s[NP * h];
     __shared__ float2 B_s[NX * PY * L];
     __shared__ float wg_s[NW3];
-    __shared__ float2 tw_s[L];
     __shared__ float red_s[4];
 
     const int tid = threadIdx.x;
@@ -84,9 +134,6 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
     const int64_t nbox = (int64_t)bx.fk0 * K1 * K2;
 
     for (int i = tid; i < NW3; i += 256) wg_s[i] = wgen[i];
-    if (tid == 0)
-#pragma unroll
-        for (int k = 0; k < L; ++k) tw_s[k] = tw.w[k];
 
     float vmax = 0.f;
     auto load_plane = [&](int tv) {
@@ -127,32 +174,28 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
         float e0 = 0.f, e1 = 0.f, e2 = 0.f;
 #pragma unroll 1
         for (int mu = 0; mu < h; ++mu) {
-            // ---------------- stage B: DFT along x for this mu ---------------------------
-            for (int i = tid; i < NX * PY * L; i += 256) {
-                const int nu = i % L, rest = i / L;
-                const int yp = rest % PY, xr = rest / PY;
-                float2 acc = make_float2(0.f, 0.f);
+            // ---------------- stage B: DFT along x for this mu, all nu of a position ----
+            for (int j = tid; j < NX * PY; j += 256) {
+                const int yp = j % PY, xr = j / PY;
+                float2 a[L], f[L];
 #pragma unroll
-                for (int q = 0; q < L; ++q) {
-                    // the twiddle index depends on nu, a run-time value here: read it from LDS
-                    acc = cmad(A_s[((S * xr + q) * PY + yp) * h + mu], tw_s[(nu * q) % L], acc);
-                }
-                B_s[i] = acc;
+                for (int q = 0; q < L; ++q) a[q] = A_s[((S * xr + q) * PY + yp) * h + mu];
+                dft_pairs<L>(a, tw, f);
+#pragma unroll
+                for (int nu = 0; nu < L; ++nu) B_s[(xr * PY + yp) * L + nu] = f[nu];
             }
             __syncthreads();
             // ---------------- stage C: DFT along y per voxel, projections, energies ------
 #pragma unroll 1
             for (int nu = 0; nu < L; ++nu) {
-                float2 b[L];
+                float2 b[L], f[L];
 #pragma unroll
                 for (int r = 0; r < L; ++r) b[r] = B_s[(x0 * PY + S * y0 + r) * L + nu];
+                dft_pairs<L>(b, tw, f);
                 const float *w = &wg_s[(mu * L + nu) * L * 3];
 #pragma unroll
                 for (int om = 0; om < L; ++om) {
-                    float2 f = make_float2(0.f, 0.f);
-#pragma unroll
-                    for (int r = 0; r < L; ++r) f = cmad(b[r], tw.w[(om * r) % L], f);
-                    const float m = __builtin_amdgcn_sqrtf(fmaf(f.x, f.x, f.y * f.y));
+                    const float m = __builtin_amdgcn_sqrtf(fmaf(f[om].x, f[om].x, f[om].y * f[om].y));
                     e0 = fmaf(w[3 * om], m, e0);
                     e1 = fmaf(w[3 * om + 1], m, e1);
                     e2 = fmaf(w[3 * om + 2], m, e2);
