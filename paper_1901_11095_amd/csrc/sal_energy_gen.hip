@@ -16,7 +16,7 @@
 //           patch position for all nu;
 //   stage C per mu and nu, one thread per voxel (x0, y0): F[om] = sum_r W[om, r]
 //           B[x0][y0 + r][nu], |F| weighted by the projections into E_t, E_x, E_y.
-// Stages B and C take their L-point DFTs with the terms and outputs in conjugate pairs.
+// Every stage takes its L-point DFTs with the terms and outputs in conjugate pairs.
 // Bins with mu and L - mu have equal magnitudes and weights (conjugates); the weight table
 // carries that multiplicity, so only mu <= L/2 is computed.
 #include <hip/hip_runtime.h>
@@ -24,6 +24,7 @@
 #include <cstdint>
 
 #include "sal_device.h"
+#include "sal_dft.h"
 #include "sal_internal.h"
 
 namespace {
@@ -38,62 +39,6 @@ template <int L>
 struct GenTw {
     float2 w[L];  // e^{-2 pi i k / L}, k = 0..L-1
 };
-
-// All L outputs F[om] = sum_r b[r] w^(om r) of an L-point complex DFT (w^k = tw.w[k]).
-// Since w^(om (L - r)) = conj w^(om r), the inputs r and L - r enter through their sum u_r
-// and difference d_r: with P = b_0 + sum_r u_r Re w^(om r) (+ b_(L/2) (-1)^om for even L)
-// and Q = sum_r d_r Im w^(om r), F[om] = P + iQ and F[L - om] = P - iQ (as complex
-// numbers, P and Q complex).  4 flops per input pair and output pair instead of 16.
-template <int L>
-__device__ __forceinline__ void dft_pairs(const float2 (&b)[L], const GenTw<L> &tw, float2 (&F)[L])
-{
-    constexpr int M = (L - 1) / 2;  // conjugate pairs (r, L - r), r = 1..M
-    constexpr bool EV = L % 2 == 0;
-    float2 u[M + 1], d[M + 1];
-    float2 f0 = b[0];
-#pragma unroll
-    for (int r = 1; r <= M; ++r) {
-        u[r] = make_float2(b[r].x + b[L - r].x, b[r].y + b[L - r].y);
-        d[r] = make_float2(b[r].x - b[L - r].x, b[r].y - b[L - r].y);
-        f0.x += u[r].x;
-        f0.y += u[r].y;
-    }
-    if (EV) {
-        f0.x += b[L / 2].x;
-        f0.y += b[L / 2].y;
-    }
-    F[0] = f0;
-#pragma unroll
-    for (int om = 1; om <= M; ++om) {
-        float2 P = b[0], Q = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int r = 1; r <= M; ++r) {
-            const float2 w = tw.w[(om * r) % L];
-            P.x = fmaf(u[r].x, w.x, P.x);
-            P.y = fmaf(u[r].y, w.x, P.y);
-            Q.x = fmaf(d[r].x, w.y, Q.x);
-            Q.y = fmaf(d[r].y, w.y, Q.y);
-        }
-        if (EV) {
-            const float sg = (om & 1) ? -1.f : 1.f;
-            P.x = fmaf(sg, b[L / 2].x, P.x);
-            P.y = fmaf(sg, b[L / 2].y, P.y);
-        }
-        F[om] = make_float2(P.x - Q.y, P.y + Q.x);
-        F[L - om] = make_float2(P.x + Q.y, P.y - Q.x);
-    }
-    if (EV) {
-        float2 fh = b[0];
-#pragma unroll
-        for (int r = 1; r <= M; ++r) {
-            const float sg = (r & 1) ? -1.f : 1.f;
-            fh.x = fmaf(sg, u[r].x, fh.x);
-            fh.y = fmaf(sg, u[r].y, fh.y);
-        }
-        const float sg = ((L / 2) & 1) ? -1.f : 1.f;
-        F[L / 2] = make_float2(fmaf(sg, b[L / 2].x, fh.x), fmaf(sg, b[L / 2].y, fh.y));
-    }
-}
 
 }  // namespace
 
@@ -157,18 +102,12 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
         // ---------------- stage A: real DFT along t, mu <= L/2 ---------------------------
         for (int p = tid; p < NP; p += 256) {
             float v[L];
+            float2 a[h];
 #pragma unroll
             for (int k = 0; k < L; ++k) v[k] = ring[(((t0 - H + k) % L) + L) % L][p];
+            sal_dft::rdft_half<L>(v, tw.w, a);
 #pragma unroll
-            for (int mu = 0; mu < h; ++mu) {
-                float re = 0.f, im = 0.f;
-#pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    re = fmaf(v[k], tw.w[(mu * k) % L].x, re);
-                    im = fmaf(v[k], tw.w[(mu * k) % L].y, im);
-                }
-                A_s[p * h + mu] = make_float2(re, im);
-            }
+            for (int mu = 0; mu < h; ++mu) A_s[p * h + mu] = a[mu];
         }
         __syncthreads();
         float e0 = 0.f, e1 = 0.f, e2 = 0.f;
@@ -180,7 +119,7 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
                 float2 a[L], f[L];
 #pragma unroll
                 for (int q = 0; q < L; ++q) a[q] = A_s[((S * xr + q) * PY + yp) * h + mu];
-                dft_pairs<L>(a, tw, f);
+                sal_dft::cdft<L>(a, tw.w, f);
 #pragma unroll
                 for (int nu = 0; nu < L; ++nu) B_s[(xr * PY + yp) * L + nu] = f[nu];
             }
@@ -191,7 +130,7 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
                 float2 b[L], f[L];
 #pragma unroll
                 for (int r = 0; r < L; ++r) b[r] = B_s[(x0 * PY + S * y0 + r) * L + nu];
-                dft_pairs<L>(b, tw, f);
+                sal_dft::cdft<L>(b, tw.w, f);
                 const float *w = &wg_s[(mu * L + nu) * L * 3];
 #pragma unroll
                 for (int om = 0; om < L; ++om) {

@@ -4,8 +4,9 @@
 // shared between windows.  Used where the fused kernels' sharing of the first two axes
 // between neighbouring windows does not apply or does not fit:
 //   * windows on a lattice of stride s >= 3 (Sec. 2 asks only for more than 50 % overlap,
-//     s < L/2) and the non-overlapping s = L of the predecessor method (Sec. 1): the work
-//     falls by s^3 while unshared windows cost 2.5 times the shared contraction per window;
+//     s < L/2) where the sliding kernel of cube 8 and 16 does not take them, and the
+//     non-overlapping s = L of the predecessor method (Sec. 1): the work falls by s^3 while
+//     unshared windows cost 2.5 times the shared contraction per window;
 //   * cube sides without a fused kernel (9..15, 17..20).
 // FP32; cube 16 on the matrix cores (k_energy_win_mfma below), the other sides on the vector
 // ALUs.  A workgroup walks windows (grid-stride over the windows of its box); per window:
@@ -15,11 +16,14 @@
 //   stage C per row (mu, nu): F[om] = sum_r W[om, r] B[mu][nu][r], |F| weighted by the
 //           projections (times the conjugate multiplicity of mu and 1/(L^3 (L^3 - 1))),
 //           summed over the workgroup into E_t, E_x, E_y.
+// On the vector ALUs every stage takes its L-point DFTs with the terms and outputs in
+// conjugate pairs (sal_dft.h).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "sal_device.h"
+#include "sal_dft.h"
 #include "sal_internal.h"
 
 namespace {
@@ -35,13 +39,6 @@ template <int L>
 struct WinTw {
     float2 w[L];  // e^{-2 pi i k / L}, k = 0..L-1
 };
-
-__device__ __forceinline__ float2 cmad_w(float2 a, float2 w, float2 acc)
-{
-    acc.x = fmaf(a.x, w.x, fmaf(-a.y, w.y, acc.x));
-    acc.y = fmaf(a.x, w.y, fmaf(a.y, w.x, acc.y));
-    return acc;
-}
 
 }  // namespace
 
@@ -111,49 +108,37 @@ __global__ __launch_bounds__(WinCfg<L>::NT) void k_energy_win(const float *__res
         // ---------------- stage A: real DFT along t, mu <= L/2 ---------------------------
         for (int c = tid; c < L2; c += NT) {
             float v[L];
+            float2 x[h];
 #pragma unroll
             for (int p = 0; p < L; ++p) v[p] = win[p * L2 + c];
+            sal_dft::rdft_half<L>(v, tw.w, x);
 #pragma unroll
-            for (int mu = 0; mu < h; ++mu) {
-                float re = 0.f, im = 0.f;
-#pragma unroll
-                for (int p = 0; p < L; ++p) {
-                    re = fmaf(v[p], tw.w[(mu * p) % L].x, re);
-                    im = fmaf(v[p], tw.w[(mu * p) % L].y, im);
-                }
-                A_s[mu * L2 + c] = make_float2(re, im);
-            }
+            for (int mu = 0; mu < h; ++mu) A_s[mu * L2 + c] = x[mu];
         }
         __syncthreads();
         // ---------------- stage B: DFT along x per (mu, r), every nu ---------------------
         if (tid < h * L) {
             const int mu = tid / L, r = tid - (tid / L) * L;
-            float2 a[L];
+            float2 a[L], f[L];
 #pragma unroll
             for (int q = 0; q < L; ++q) a[q] = A_s[(mu * L + q) * L + r];
+            sal_dft::cdft<L>(a, tw.w, f);
 #pragma unroll
-            for (int nu = 0; nu < L; ++nu) {
-                float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int q = 0; q < L; ++q) acc = cmad_w(a[q], tw.w[(nu * q) % L], acc);
-                B_s[(mu * L + nu) * LP + r] = acc;
-            }
+            for (int nu = 0; nu < L; ++nu) B_s[(mu * L + nu) * LP + r] = f[nu];
         }
         __syncthreads();
         // ---------------- stage C: DFT along y per row (mu, nu), projections -------------
         float e0 = 0.f, e1 = 0.f, e2 = 0.f;
         if (tid < h * L) {
             const int mu = tid / L, nu = tid - (tid / L) * L;
-            float2 b[L];
+            float2 b[L], f[L];
 #pragma unroll
             for (int r = 0; r < L; ++r) b[r] = B_s[(mu * L + nu) * LP + r];
+            sal_dft::cdft<L>(b, tw.w, f);
             const float *wr = wgen + (int64_t)(mu * L + nu) * L * 3;
 #pragma unroll
             for (int om = 0; om < L; ++om) {
-                float2 f = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int r = 0; r < L; ++r) f = cmad_w(b[r], tw.w[(om * r) % L], f);
-                const float m = __builtin_amdgcn_sqrtf(fmaf(f.x, f.x, f.y * f.y));
+                const float m = __builtin_amdgcn_sqrtf(fmaf(f[om].x, f[om].x, f[om].y * f[om].y));
                 e0 = fmaf(wr[3 * om], m, e0);
                 e1 = fmaf(wr[3 * om + 1], m, e1);
                 e2 = fmaf(wr[3 * om + 2], m, e2);
