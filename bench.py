@@ -78,11 +78,17 @@ def pair_dft_flops(L: int) -> int:
 
 def gen_flops_per_voxel(L: int) -> int:
     """Flops per voxel of the vector-ALU kernel of cube sides 2..7: the real DFT along t into
-    h = L/2 + 1 bins (4hL), the paired L-point DFTs along x (h per voxel) and along y (hL
-    per voxel), and per bin (h L^2) the magnitude (3, the square root counted as 1) and the
-    three weighted sums (2 each): 1,746 at L = 5, where the direct contraction counts 3,660."""
+    h = L/2 + 1 bins (4hL), the paired L-point DFTs along x (h per voxel), and per row (mu,
+    nu) of the y stage, with the conjugate rows of the real mu = 0 (and L/2) taken once: its
+    paired DFT, L magnitudes (3 each, the square root counted as 1), the sums of the bins om
+    and L - om that share weights, three weighted sums per weight group om <= L/2 (2 each)
+    and the row's three products into E (2 each): 1,490 at L = 5, where the direct
+    contraction counts 3,660."""
     h = L // 2 + 1
-    return 4 * h * L + h * (L + 1) * pair_dft_flops(L) + 10 * h * L * L
+    real_rows = 1 + (L % 2 == 0)
+    rows = h * L - real_rows * (L - (L // 2 + 1))
+    per_row = pair_dft_flops(L) + 4 * L + (L - 1) // 2 + 6 * (L // 2 + 1) + 6
+    return 4 * h * L + h * pair_dft_flops(L) + rows * per_row
 
 
 # What a committed counter record covers: the kernel template's own text, the device helpers

@@ -18,7 +18,8 @@
 //           B[x0][y0 + r][nu], |F| weighted by the projections into E_t, E_x, E_y.
 // Every stage takes its L-point DFTs with the terms and outputs in conjugate pairs.
 // Bins with mu and L - mu have equal magnitudes and weights (conjugates); the weight table
-// carries that multiplicity, so only mu <= L/2 is computed.
+// carries that multiplicity, so only mu <= L/2 is computed.  Stage C likewise takes the
+// conjugate rows of the real t frequencies mu = 0 (and L/2) once, twice weighted.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -125,20 +126,35 @@ __global__ __launch_bounds__(256) void k_energy_gen(const float *__restrict__ V,
             }
             __syncthreads();
             // ---------------- stage C: DFT along y per voxel, projections, energies ------
+            // The weights depend on the squares of the signed frequencies, so the bins om and
+            // L - om of a row share theirs, and so do the conjugate bins (mu, nu, om) and
+            // (mu, L - nu, L - om).  On the rows mu = 0 (and L/2 for even L) the t spectrum is
+            // real, the row L - nu is the conjugate of the row nu bin for bin, and the rows
+            // past L/2 count as twice the rows 1 .. (L - 1)/2.
+            const bool real_mu = mu == 0 || 2 * mu == L;
+            const int nu_end = real_mu ? L / 2 + 1 : L;
 #pragma unroll 1
-            for (int nu = 0; nu < L; ++nu) {
+            for (int nu = 0; nu < nu_end; ++nu) {
                 float2 b[L], f[L];
 #pragma unroll
                 for (int r = 0; r < L; ++r) b[r] = B_s[(x0 * PY + S * y0 + r) * L + nu];
                 sal_dft::cdft<L>(b, tw.w, f);
                 const float *w = &wg_s[(mu * L + nu) * L * 3];
+                float m[L];
 #pragma unroll
-                for (int om = 0; om < L; ++om) {
-                    const float m = __builtin_amdgcn_sqrtf(fmaf(f[om].x, f[om].x, f[om].y * f[om].y));
-                    e0 = fmaf(w[3 * om], m, e0);
-                    e1 = fmaf(w[3 * om + 1], m, e1);
-                    e2 = fmaf(w[3 * om + 2], m, e2);
+                for (int om = 0; om < L; ++om) m[om] = __builtin_amdgcn_sqrtf(fmaf(f[om].x, f[om].x, f[om].y * f[om].y));
+                float q0 = 0.f, q1 = 0.f, q2 = 0.f;
+#pragma unroll
+                for (int om = 0; om <= L / 2; ++om) {
+                    const float mm = (om == 0 || 2 * om == L) ? m[om] : m[om] + m[L - om];
+                    q0 = fmaf(w[3 * om], mm, q0);
+                    q1 = fmaf(w[3 * om + 1], mm, q1);
+                    q2 = fmaf(w[3 * om + 2], mm, q2);
                 }
+                const float k2 = (real_mu && nu != 0 && 2 * nu != L) ? 2.f : 1.f;
+                e0 = fmaf(k2, q0, e0);
+                e1 = fmaf(k2, q1, e1);
+                e2 = fmaf(k2, q2, e2);
             }
             __syncthreads();
         }

@@ -71,8 +71,9 @@ def test_pair_dft_count_and_value(L, sign):
 
 
 def test_flop_counts_per_voxel():
-    # paper's cube: 4hL + h (L + 1) DFTs of 52 flops + 10 per bin
-    assert bench.gen_flops_per_voxel(5) == 4 * 3 * 5 + 3 * 6 * 52 + 10 * 3 * 25 == 1746
+    # paper's cube: 4hL + h x-DFTs of 52 flops + 13 y rows (rows 3, 4 of mu = 0 skipped), each
+    # a DFT (52), 5 magnitudes (20), 2 pair sums, 3 weight groups (18) and the row factor (6)
+    assert bench.gen_flops_per_voxel(5) == 4 * 3 * 5 + 3 * 52 + 13 * (52 + 20 + 2 + 18 + 6) == 1490
     assert bench.dft_flops_per_voxel(5) == 3660
     assert bench.slide_flops_per_voxel(16) == 53760 and bench.slide_flops_per_voxel(8) == 6784
     assert bench.dft_flops_per_voxel(16) == 313920 and bench.dft_flops_per_voxel(8) == 23200
