@@ -440,13 +440,12 @@ struct lat_box {
 };
 static_assert(sizeof(lat_box) == LAT_TABLE * sizeof(int), "lat_box is one table entry");
 
-// voxel v (box-local index) of the box b, from the lattice energies El of b
-__device__ __forceinline__ void upsample_at(const float *__restrict__ El, const lat_box &b, int S, float inv,
-                                            int64_t v, int64_t N, int64_t NK, float *__restrict__ E)
+// voxel (t, x, y) of the volume, box-local index v of the box b, from the lattice energies
+// El of b
+__device__ __forceinline__ void upsample_voxel(const float *__restrict__ El, const lat_box &b, int S, float inv,
+                                               int t, int x, int y, int64_t v, int64_t N, int64_t NK,
+                                               float *__restrict__ E)
 {
-    const int y = b.eo2 + (int)(v % b.ed2);
-    const int64_t rest = v / b.ed2;
-    const int x = b.eo1 + (int)(rest % b.ed1), t = b.eo0 + (int)(rest / b.ed1);
     const int kt = t / S, kx = x / S, ky = y / S;
     const int kt1 = min(kt + 1, b.K0 - 1), kx1 = min(kx + 1, b.K1 - 1), ky1 = min(ky + 1, b.K2 - 1);
     const float ft = kt1 == kt ? 0.f : (float)(t - kt * S) * inv;
@@ -468,13 +467,30 @@ __device__ __forceinline__ void upsample_at(const float *__restrict__ El, const 
     }
 }
 
+// voxel v (box-local index) of the box b
+__device__ __forceinline__ void upsample_at(const float *__restrict__ El, const lat_box &b, int S, float inv,
+                                            int64_t v, int64_t N, int64_t NK, float *__restrict__ E)
+{
+    const int y = b.eo2 + (int)(v % b.ed2);
+    const int64_t rest = v / b.ed2;
+    const int x = b.eo1 + (int)(rest % b.ed1), t = b.eo0 + (int)(rest / b.ed1);
+    upsample_voxel(El, b, S, inv, t, x, y, v, N, NK, E);
+}
+
+// One box (the whole volume): a workgroup takes rows (t, x) of the box, its threads the
+// voxels along y, so no voxel index is divided (the same arithmetic per voxel as
+// upsample_at).  (Giving each workgroup a run of consecutive rows instead measured slower.)
 __global__ __launch_bounds__(256) void k_upsample(const float *__restrict__ El, lat_box b, int S,
                                                   float *__restrict__ E)
 {
     const int64_t N = (int64_t)b.ed0 * b.ed1 * b.ed2, NK = (int64_t)b.kd0 * b.kd1 * b.kd2;
     const float inv = 1.0f / (float)S;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < N; v += (int64_t)gridDim.x * 256)
-        upsample_at(El, b, S, inv, v, N, NK, E);
+    const int nrows = b.ed0 * b.ed1;
+    for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
+        const int tl = row / b.ed1, xl = row - tl * b.ed1;
+        for (int yl = threadIdx.x; yl < b.ed2; yl += 256)
+            upsample_voxel(El, b, S, inv, b.eo0 + tl, b.eo1 + xl, b.eo2 + yl, (int64_t)row * b.ed2 + yl, N, NK, E);
+    }
 }
 
 // The same for the tiles of a batch: workgroups [i * per_box, (i + 1) * per_box) serve box
@@ -1235,8 +1251,8 @@ hipError_t launch_upsample_box(const float *El, const int64_t kd[3], const int64
 {
     const lat_box b{(int)kd[0], (int)kd[1], (int)kd[2], (int)klo[0], (int)klo[1], (int)klo[2], (int)K[0], (int)K[1],
                     (int)K[2], (int)eo[0], (int)eo[1], (int)eo[2], (int)ed[0], (int)ed[1], (int)ed[2]};
-    const int64_t N = ed[0] * ed[1] * ed[2];
-    const unsigned nb = (unsigned)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
+    const int64_t N = ed[0] * ed[1] * ed[2], rows = ed[0] * ed[1];
+    const unsigned nb = (unsigned)(rows < 32768 ? rows : 32768);
     if (N == 0) return hipSuccess;
     hipLaunchKernelGGL(k_upsample, dim3(nb), dim3(256), 0, s, El, b, S, E);
     return hipGetLastError();
