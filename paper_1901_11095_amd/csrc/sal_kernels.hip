@@ -757,6 +757,167 @@ __global__ __launch_bounds__(256) void k_dcs_tiled(const float *__restrict__ E, 
     }
 }
 
+// Step 4, Eq. (5), for the default rays (map m compared along its own axis, both ways) at a
+// compile-time r: the walk of k_dcs_tiled with every LDS offset a constant.  The t ring
+// holds each plane twice (slots p and p + D, D = 2r + 1), so the 2r + 1 planes of step t sit
+// in consecutive slots from (t - r) mod D and no read wraps; the x and y maps keep one plane
+// with its halo.  The sums run in the order of k_dcs_tiled and dcs_box_at (the + ray before
+// the - ray, s = 1..r), so all three give the same bits.
+template <int R>
+__global__ __launch_bounds__(256) void k_dcs_axis(const float *__restrict__ E, int n0, int n1, int n2,
+                                                  dcs_args a, int nbx, int nby, float *__restrict__ S,
+                                                  float *__restrict__ mm_part)
+{
+    constexpr int D = 2 * R + 1;
+    constexpr int HW0 = DTX * DTY;                        // map t: the tile
+    constexpr int W1 = DTY, HW1 = (DTX + 2 * R) * W1;     // map x: halo along x
+    constexpr int W2 = DTY + 2 * R, HW2 = DTX * W2;       // map y: halo along y
+    constexpr int N0 = (HW0 + 255) / 256, N1 = (HW1 + 255) / 256, N2 = (HW2 + 255) / 256;
+    __shared__ float ring0[2 * D * HW0];
+    __shared__ float pl1[HW1];
+    __shared__ float pl2[HW2];
+    __shared__ float red[4 * 6];
+
+    const int64_t plane = (int64_t)n1 * n2, N = plane * n0;
+    const int bid = blockIdx.x;
+    const int ty = bid % nby, tx = (bid / nby) % nbx, tb = bid / (nby * nbx);
+    const int x_base = tx * DTX, y_base = ty * DTY;
+    const int t_begin = tb * DTT, t_end = min(n0, t_begin + DTT);
+    const int tid = threadIdx.x, lx = tid / DTY, ly = tid % DTY;
+    const int x = x_base + lx, y = y_base + ly;
+    const bool valid = x < n1 && y < n2;
+    float g[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) g[s] = a.g[s];
+
+    // this thread's samples of each plane: volume offset (reflected), or -1
+    int o0[N0], o1[N1], o2[N2];
+#pragma unroll
+    for (int e = 0; e < N0; ++e) {
+        const int i = tid + 256 * e, ix = i / DTY, iy = i % DTY;
+        o0[e] = i < HW0 ? refl_idx(x_base + ix, n1) * n2 + refl_idx(y_base + iy, n2) : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < N1; ++e) {
+        const int i = tid + 256 * e, ix = i / W1, iy = i % W1;
+        o1[e] = i < HW1 ? refl_idx(x_base - R + ix, n1) * n2 + refl_idx(y_base + iy, n2) : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < N2; ++e) {
+        const int i = tid + 256 * e, ix = i / W2, iy = i % W2;
+        o2[e] = i < HW2 ? refl_idx(x_base + ix, n1) * n2 + refl_idx(y_base - R + iy, n2) : -1;
+    }
+    float p0[N0], p1[N1], p2[N2];
+    auto fetch0 = [&](int tl) {
+        const float *src = E + (int64_t)refl_idx(tl, n0) * plane;
+#pragma unroll
+        for (int e = 0; e < N0; ++e) p0[e] = o0[e] >= 0 ? src[o0[e]] : 0.f;
+    };
+    auto fetch12 = [&](int tl) {
+        const float *src1 = E + N + (int64_t)refl_idx(tl, n0) * plane, *src2 = src1 + N;
+#pragma unroll
+        for (int e = 0; e < N1; ++e) p1[e] = o1[e] >= 0 ? src1[o1[e]] : 0.f;
+#pragma unroll
+        for (int e = 0; e < N2; ++e) p2[e] = o2[e] >= 0 ? src2[o2[e]] : 0.f;
+    };
+    auto store0 = [&](int tl) {  // tl >= -R
+        float *pl = ring0 + ((tl + D) % D) * HW0;
+#pragma unroll
+        for (int e = 0; e < N0; ++e)
+            if (o0[e] >= 0) {
+                pl[tid + 256 * e] = p0[e];
+                pl[D * HW0 + tid + 256 * e] = p0[e];
+            }
+    };
+    auto store12 = [&]() {
+#pragma unroll
+        for (int e = 0; e < N1; ++e)
+            if (o1[e] >= 0) pl1[tid + 256 * e] = p1[e];
+#pragma unroll
+        for (int e = 0; e < N2; ++e)
+            if (o2[e] >= 0) pl2[tid + 256 * e] = p2[e];
+    };
+    for (int tl = t_begin - R; tl < t_begin + R; ++tl) {
+        fetch0(tl);
+        store0(tl);
+    }
+    fetch0(t_begin + R);
+    fetch12(t_begin);
+
+    float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    for (int t = t_begin; t < t_end; ++t) {
+        store0(t + R);
+        store12();
+        if (t + 1 < t_end) {
+            fetch0(t + 1 + R);
+            fetch12(t + 1);
+        }
+        __syncthreads();
+        if (valid) {
+            const int64_t ov = ((int64_t)t * n1 + x) * n2 + y;
+            float sum[3];
+            {   // map t: plane t at slot (t - R) mod D + R
+                const float *b = ring0 + ((t - R + D) % D + R) * HW0 + lx * DTY + ly;
+                const float c = b[0];
+                float su = 0.f;
+#pragma unroll
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[s * HW0]);
+#pragma unroll
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[-s * HW0]);
+                sum[0] = su;
+            }
+            {   // map x
+                const float *b = pl1 + (lx + R) * W1 + ly;
+                const float c = b[0];
+                float su = 0.f;
+#pragma unroll
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[s * W1]);
+#pragma unroll
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[-s * W1]);
+                sum[1] = su;
+            }
+            {   // map y
+                const float *b = pl2 + lx * W2 + ly + R;
+                const float c = b[0];
+                float su = 0.f;
+#pragma unroll
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[s]);
+#pragma unroll
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[-s]);
+                sum[2] = su;
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const float sv = a.Q[m] > 0.f ? sum[m] / a.Q[m] : 0.f;
+                S[m * N + ov] = sv;
+                mn[m] = fminf(mn[m], sv);
+                mx[m] = fmaxf(mx[m], sv);
+            }
+        }
+        __syncthreads();
+    }
+    if (mm_part == nullptr) return;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+        for (int q = 32; q >= 1; q >>= 1) {
+            mn[m] = fminf(mn[m], __shfl_xor(mn[m], q));
+            mx[m] = fmaxf(mx[m], __shfl_xor(mx[m], q));
+        }
+        if (lane == 0) {
+            red[wave * 6 + 2 * m] = mn[m];
+            red[wave * 6 + 2 * m + 1] = mx[m];
+        }
+    }
+    __syncthreads();
+    if (tid < 6) {
+        float v = red[tid];
+        for (int w = 1; w < 4; ++w) v = (tid & 1) ? fmaxf(v, red[w * 6 + tid]) : fminf(v, red[w * 6 + tid]);
+        mm_part[(int64_t)bid * 6 + tid] = v;
+    }
+}
+
 // LDS floats the tiled comparison needs for these rays and r, or a huge value when a
 // plane does not fit the per-thread element budget.
 static int64_t dcs_tiled_lds_floats(const uint32_t rays[3], int r)
@@ -1074,6 +1235,25 @@ hipError_t launch_dcs(const sal_ctx *c, const float *E, int64_t n0, int64_t n1, 
     if (nf <= DCS_LDS_MAX_FLOATS) {
         const size_t lds = (size_t)(nf > 24 ? nf : 24) * sizeof(float);
         const int nbx = (int)((n1 + DTX - 1) / DTX), nby = (int)((n2 + DTY - 1) / DTY);
+        // the default rays at a compile-time r: constant LDS offsets
+        const bool axis = a.rays[0] == (SAL_RAY_PT | SAL_RAY_MT) && a.rays[1] == (SAL_RAY_PX | SAL_RAY_MX) &&
+                          a.rays[2] == (SAL_RAY_PY | SAL_RAY_MY);
+#define SAL_DCS_A(RR)                                                                                            \
+    case RR:                                                                                                      \
+        hipLaunchKernelGGL(k_dcs_axis<RR>, dim3(nb), dim3(256), 0, s, E, (int)n0, (int)n1, (int)n2, a, nbx, nby,  \
+                           S_raw, minmax_part);                                                                   \
+        return hipGetLastError();
+        if (axis) {
+            switch (c->r) {
+                SAL_DCS_A(1)
+                SAL_DCS_A(2)
+                SAL_DCS_A(3)
+                SAL_DCS_A(4)
+                SAL_DCS_A(8)
+            default: break;
+            }
+        }
+#undef SAL_DCS_A
 #define SAL_DCS_T(RR)                                                                                            \
     do {                                                                                                          \
         if (lds > 65536)                                                                                          \
