@@ -758,22 +758,20 @@ __global__ __launch_bounds__(256) void k_dcs_tiled(const float *__restrict__ E, 
 }
 
 // Step 4, Eq. (5), for the default rays (map m compared along its own axis, both ways) at a
-// compile-time r: the walk of k_dcs_tiled with every LDS offset a constant.  The t ring
-// holds each plane twice (slots p and p + D, D = 2r + 1), so the 2r + 1 planes of step t sit
-// in consecutive slots from (t - r) mod D and no read wraps; the x and y maps keep one plane
-// with its halo.  The sums run in the order of k_dcs_tiled and dcs_box_at (the + ray before
-// the - ray, s = 1..r), so all three give the same bits.
+// compile-time r, on the tiles and t walk of k_dcs_tiled.  Map t compares a voxel with its
+// own column along t only: each thread keeps the 2r + 1 values of its column in registers
+// and shifts them by one per step.  Maps x and y keep one plane each in LDS with its halo,
+// read at constant offsets.  The sums run in the order of k_dcs_tiled and dcs_box_at (the
+// + ray before the - ray, s = 1..r), so all three give the same bits.
 template <int R>
 __global__ __launch_bounds__(256) void k_dcs_axis(const float *__restrict__ E, int n0, int n1, int n2,
                                                   dcs_args a, int nbx, int nby, float *__restrict__ S,
                                                   float *__restrict__ mm_part)
 {
     constexpr int D = 2 * R + 1;
-    constexpr int HW0 = DTX * DTY;                        // map t: the tile
     constexpr int W1 = DTY, HW1 = (DTX + 2 * R) * W1;     // map x: halo along x
     constexpr int W2 = DTY + 2 * R, HW2 = DTX * W2;       // map y: halo along y
-    constexpr int N0 = (HW0 + 255) / 256, N1 = (HW1 + 255) / 256, N2 = (HW2 + 255) / 256;
-    __shared__ float ring0[2 * D * HW0];
+    constexpr int N1 = (HW1 + 255) / 256, N2 = (HW2 + 255) / 256;
     __shared__ float pl1[HW1];
     __shared__ float pl2[HW2];
     __shared__ float red[4 * 6];
@@ -790,13 +788,8 @@ __global__ __launch_bounds__(256) void k_dcs_axis(const float *__restrict__ E, i
 #pragma unroll
     for (int s = 0; s < R; ++s) g[s] = a.g[s];
 
-    // this thread's samples of each plane: volume offset (reflected), or -1
-    int o0[N0], o1[N1], o2[N2];
-#pragma unroll
-    for (int e = 0; e < N0; ++e) {
-        const int i = tid + 256 * e, ix = i / DTY, iy = i % DTY;
-        o0[e] = i < HW0 ? refl_idx(x_base + ix, n1) * n2 + refl_idx(y_base + iy, n2) : -1;
-    }
+    // this thread's samples of the x and y planes: volume offset (reflected), or -1
+    int o1[N1], o2[N2];
 #pragma unroll
     for (int e = 0; e < N1; ++e) {
         const int i = tid + 256 * e, ix = i / W1, iy = i % W1;
@@ -807,12 +800,9 @@ __global__ __launch_bounds__(256) void k_dcs_axis(const float *__restrict__ E, i
         const int i = tid + 256 * e, ix = i / W2, iy = i % W2;
         o2[e] = i < HW2 ? refl_idx(x_base + ix, n1) * n2 + refl_idx(y_base - R + iy, n2) : -1;
     }
-    float p0[N0], p1[N1], p2[N2];
-    auto fetch0 = [&](int tl) {
-        const float *src = E + (int64_t)refl_idx(tl, n0) * plane;
-#pragma unroll
-        for (int e = 0; e < N0; ++e) p0[e] = o0[e] >= 0 ? src[o0[e]] : 0.f;
-    };
+    const int o0 = valid ? x * n2 + y : 0;
+    float col[D], nxt = 0.f, p1[N1], p2[N2];
+    auto at0 = [&](int tl) { return E[(int64_t)refl_idx(tl, n0) * plane + o0]; };
     auto fetch12 = [&](int tl) {
         const float *src1 = E + N + (int64_t)refl_idx(tl, n0) * plane, *src2 = src1 + N;
 #pragma unroll
@@ -820,50 +810,36 @@ __global__ __launch_bounds__(256) void k_dcs_axis(const float *__restrict__ E, i
 #pragma unroll
         for (int e = 0; e < N2; ++e) p2[e] = o2[e] >= 0 ? src2[o2[e]] : 0.f;
     };
-    auto store0 = [&](int tl) {  // tl >= -R
-        float *pl = ring0 + ((tl + D) % D) * HW0;
+    // column values t_begin - R .. t_begin + R - 1, then the next one in flight
 #pragma unroll
-        for (int e = 0; e < N0; ++e)
-            if (o0[e] >= 0) {
-                pl[tid + 256 * e] = p0[e];
-                pl[D * HW0 + tid + 256 * e] = p0[e];
-            }
-    };
-    auto store12 = [&]() {
+    for (int i = 0; i < D - 1; ++i) col[i] = valid ? at0(t_begin - R + i) : 0.f;
+    if (valid) nxt = at0(t_begin + R);
+    fetch12(t_begin);
+
+    float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    for (int t = t_begin; t < t_end; ++t) {
+        col[D - 1] = nxt;  // plane t + R
 #pragma unroll
         for (int e = 0; e < N1; ++e)
             if (o1[e] >= 0) pl1[tid + 256 * e] = p1[e];
 #pragma unroll
         for (int e = 0; e < N2; ++e)
             if (o2[e] >= 0) pl2[tid + 256 * e] = p2[e];
-    };
-    for (int tl = t_begin - R; tl < t_begin + R; ++tl) {
-        fetch0(tl);
-        store0(tl);
-    }
-    fetch0(t_begin + R);
-    fetch12(t_begin);
-
-    float mn[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, mx[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
-    for (int t = t_begin; t < t_end; ++t) {
-        store0(t + R);
-        store12();
         if (t + 1 < t_end) {
-            fetch0(t + 1 + R);
+            if (valid) nxt = at0(t + 1 + R);
             fetch12(t + 1);
         }
         __syncthreads();
         if (valid) {
             const int64_t ov = ((int64_t)t * n1 + x) * n2 + y;
             float sum[3];
-            {   // map t: plane t at slot (t - R) mod D + R
-                const float *b = ring0 + ((t - R + D) % D + R) * HW0 + lx * DTY + ly;
-                const float c = b[0];
+            {   // map t: plane t + d in col[R + d]
+                const float c = col[R];
                 float su = 0.f;
 #pragma unroll
-                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[s * HW0]);
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * col[R + s]);
 #pragma unroll
-                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * b[-s * HW0]);
+                for (int s = 1; s <= R; ++s) su += fabsf(c - g[s - 1] * col[R - s]);
                 sum[0] = su;
             }
             {   // map x
@@ -894,6 +870,8 @@ __global__ __launch_bounds__(256) void k_dcs_axis(const float *__restrict__ E, i
                 mx[m] = fmaxf(mx[m], sv);
             }
         }
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) col[i] = col[i + 1];
         __syncthreads();
     }
     if (mm_part == nullptr) return;
